@@ -1,0 +1,175 @@
+/* libsisph: the per-timestep hot path of the simple iterative ISPH (SISPH)
+ * scheme of Muta, Ramachandran & Negi (arXiv:1908.01762) on one AMD MI355X
+ * (gfx950).
+ *
+ * One SISPH time step (Algorithm 1, section 3.1) is split the way the
+ * paper's implementation notes split it into two stages (section 3.3):
+ *
+ *   sisph_bin       cell binning of the particles at r^n and the neighbour
+ *                   sets N^n = { j : |r_ij|^2 < R^2 } (R = kernel support)
+ *   sisph_predict   summation density (eq. summation_density), free-surface
+ *                   flags (section 3), wall ghost velocity (eqs. vf,
+ *                   vg-adami, vg-no-normal), predictor accelerations
+ *                   (eqs. mom:sph:visc, mom:sph:av, mom:sph:gtvf:stress, body
+ *                   force), r* and u* (eqs. int:rnp1, int:vint), then the
+ *                   binning and neighbour sets N* at r*, and the wall u*
+ *   sisph_ppe_solve PPE right-hand side and coefficients (eqs. sph-ppe,
+ *                   coeff, coeff1), the damped-Jacobi iteration
+ *                   (eq. p-sor) with the wall pressure of eq. p-shepard
+ *                   re-extrapolated before every sweep, and the convergence
+ *                   test of eq. convergence (min 2 sweeps)
+ *   sisph_correct   pressure acceleration (eq. mom:sph:press:pij or
+ *                   mom:sph:press:symm) and u^{n+1} (eq. int:vnp1), K GTVF
+ *                   sub-steps on the frozen N* (eqs. mom:sph:gtvf,
+ *                   int:gtvf:pos, int:gtvf:vel:tmp), the transport velocity
+ *                   and the position update (eqs. int:vhatnp2, int:rnp2)
+ *   sisph_step      all four, nsteps times
+ *
+ * Units are SI.  Arrays crossing this boundary are host memory, float64,
+ * row-major [n][dim], in the caller's original particle order with fluid
+ * rows first and wall rows after them.  The device workspace is device
+ * memory owned by the caller (for instance a torch uint8 tensor); the
+ * library sub-allocates it and never frees it.  A context is not
+ * thread-safe; distinct contexts on distinct streams are independent.
+ * Every function returns a status code and never throws.
+ */
+#ifndef SISPH_H
+#define SISPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+    SISPH_OK = 0,
+    SISPH_WARN_MAXITER = 1,   /* PPE stopped at max_iter; fields valid       */
+    SISPH_E_INVAL = -1,       /* invalid descriptor or argument              */
+    SISPH_E_NOMEM = -2,       /* workspace or neighbour capacity too small   */
+    SISPH_E_DEVICE = -3,      /* HIP runtime error                           */
+    SISPH_E_STATE = -4,       /* call out of order                           */
+    SISPH_E_NONFINITE = -5    /* NaN/Inf found by the PPE residual reduction */
+};
+
+/* ----------------------------------------------------------- enumerations */
+enum { SISPH_QUINTIC = 0, SISPH_WENDLAND_C2 = 1 };      /* support 3h / 2h  */
+enum { SISPH_FP64 = 0, SISPH_MIXED = 1 };                /* see precision    */
+enum { SISPH_ASYMM = 0, SISPH_SYMM = 1 };                /* pressure gradient */
+enum { SISPH_GTVF_OFF = 0, SISPH_GTVF_INTERNAL = 1, SISPH_GTVF_EXTERNAL = 2 };
+enum { SISPH_PREF_FIXED = 0, SISPH_PREF_TWICE_MAX = 1 };
+enum { SISPH_CONV_SUM = 0, SISPH_CONV_MEAN = 1 };
+
+/* One case.  Parameters follow the paper's statement of the problem.
+ *  precision   SISPH_FP64: every sum in FP64.  SISPH_MIXED: neighbour sums,
+ *              kernel values and the cached PPE coefficients in FP32 (pair
+ *              differences formed in FP64 first); PPE residual, convergence
+ *              test, per-particle results and positions in FP64.
+ *  pgrad       "asymm" (eq. mom:sph:press:pij) or "symm" (eq. ...:symm).
+ *  gtvf        OFF; INTERNAL: h~ = h, p0 = p_ref; EXTERNAL: h~ = h/2,
+ *              p0 = min(10 |p_i|, p_ref) (section 2.1).
+ *  free_surface  enables the rho/rho0 < fs_ratio flag (p = 0) and the
+ *              clamp p_wall >= 0 (sections 3 and 3.4).
+ *  p_ref_mode  FIXED: p_ref as given; TWICE_MAX: 2 max_i p_i after the first
+ *              step's solve, then held.
+ *  conv_norm   SUM: sum|dp| / max(Lambda, sum|p|) as printed; MEAN: Lambda
+ *              scaled by the fluid count.
+ *  forced_iters  > 0: run exactly that many sweeps (ignores tol).
+ *  eta         the 0.01 of r^2 + eta h^2.
+ *  dx          initial particle spacing; sizes the neighbour storage.
+ *  nbr_cap     neighbour slots per particle (0: derived from h and dx).
+ *  periodic    per axis; the box is [box_lo, box_hi) on periodic axes and
+ *              the binning range (particles outside are clamped to the edge
+ *              cells) on the others.                                         */
+typedef struct {
+    int32_t dim, kernel, precision, pgrad, gtvf, free_surface;
+    int32_t p_ref_mode, conv_norm, min_iter, max_iter, gtvf_K, forced_iters;
+    int32_t periodic[3], nbr_cap;
+    int64_t n_fluid, n_wall;
+    double h, dx, rho0, nu, alpha, c_ref, dt, eta, fs_ratio, omega, tol, p_ref;
+    double gravity[3], box_lo[3], box_hi[3];
+} sisph_case_desc;
+
+typedef struct {
+    int32_t iters;       /* Jacobi sweeps done                              */
+    int32_t converged;   /* final ratio < tol                               */
+    int32_t nonfinite;   /* a non-finite pressure sum was seen              */
+    int32_t reserved;
+    double ratio;        /* eq. convergence at the last sweep               */
+    double lambda;       /* max |RHS_i / D_ii| over non-free-surface fluid   */
+    double p_ref;        /* GTVF reference pressure in use                  */
+} sisph_ppe_stats;
+
+typedef sisph_ppe_stats sisph_step_stats;
+
+typedef struct sisph_ctx sisph_ctx;
+
+/* Exact device-workspace bytes a case needs (0 for an invalid descriptor). */
+size_t sisph_workspace_bytes(const sisph_case_desc *desc);
+
+/* Creates a context.  d_workspace: device memory of ws_bytes >=
+ * sisph_workspace_bytes(desc), 256-byte aligned, owned by the caller and
+ * kept alive until sisph_destroy.  x [n][dim], p [n], m [n] cover fluid and
+ * walls; u [n_fluid][dim]; wall_u [n_wall][dim] is the prescribed (constant)
+ * wall velocity or NULL for static walls.  Host arrays are copied; the
+ * transport velocity starts equal to u.  hip_stream: the stream all work is
+ * queued on (NULL: the default stream).  Wall normals are computed here. */
+int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, size_t ws_bytes,
+                     const double *x, const double *u, const double *p, const double *m,
+                     const double *wall_u, void *hip_stream, sisph_ctx **out);
+
+int32_t sisph_bin(sisph_ctx *ctx);
+int32_t sisph_predict(sisph_ctx *ctx);
+int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out /* nullable */);
+int32_t sisph_correct(sisph_ctx *ctx);
+/* nsteps full steps; out: nsteps entries or NULL.  Returns the worst status
+ * (errors stop the loop; SISPH_WARN_MAXITER does not). */
+int32_t sisph_step(sisph_ctx *ctx, int32_t nsteps, sisph_step_stats *out);
+
+/* State in the caller's original order: x [n][dim] (fluid then walls),
+ * u and u_tilde [n_fluid][dim], p [n] (fluid then walls), rho [n_fluid].
+ * Any pointer may be NULL.  Valid between steps. */
+int32_t sisph_read_state(sisph_ctx *ctx, double *x, double *u, double *u_tilde,
+                         double *p, double *rho);
+/* Replaces the fluid state between steps (same layouts; NULL keeps). */
+int32_t sisph_write_state(sisph_ctx *ctx, const double *x, const double *u,
+                          const double *u_tilde, const double *p);
+
+/* Diagnostic fields of the last step in original order (tests, reports). */
+enum {
+    SISPH_FIELD_RHO = 0,      /* [n_fluid]        at r^n                   */
+    SISPH_FIELD_XSTAR = 1,    /* [n_fluid][dim]   r*                       */
+    SISPH_FIELD_USTAR = 2,    /* [n_fluid][dim]   u*                       */
+    SISPH_FIELD_RHS = 3,      /* [n_fluid]                                 */
+    SISPH_FIELD_DII = 4,      /* [n_fluid]                                 */
+    SISPH_FIELD_UNEW = 5,     /* [n_fluid][dim]   u^{n+1}                  */
+    SISPH_FIELD_WALL_U = 6,   /* [n_wall][dim]    stage-1 ghost velocity   */
+    SISPH_FIELD_WALL_USTAR = 7, /* [n_wall][dim]  stage-2 slip ghost u*    */
+    SISPH_FIELD_FS = 8,       /* [n_fluid]        free-surface flag (0/1)  */
+    SISPH_FIELD_NORMAL = 9,   /* [n_wall][dim]    wall unit normals        */
+    SISPH_FIELD_PRESSURE = 10 /* [n]              current pressure         */
+};
+int32_t sisph_read_field(sisph_ctx *ctx, int32_t field, double *out);
+
+/* Neighbour sets as CSR in original ids, each row ascending.
+ * stage 0: N^n (valid after sisph_bin), stage 1: N* (after sisph_predict);
+ * dest 0: fluid rows over fluid+wall sources, dest 1: wall rows over fluid
+ * sources.  offsets [rows+1]; ids up to cap entries. */
+int32_t sisph_debug_neighbors(sisph_ctx *ctx, int32_t stage, int32_t dest,
+                              int64_t *offsets, int32_t *ids, int64_t cap);
+
+/* Wall-clock of the last sisph_ppe_solve measured with HIP events on the
+ * context's stream, and of the whole last step (milliseconds). */
+int32_t sisph_last_timings(sisph_ctx *ctx, double *ppe_ms, double *step_ms);
+
+int32_t sisph_destroy(sisph_ctx *ctx);
+const char *sisph_status_string(int32_t status);
+/* Last error message of this context (or of the last failed create). */
+const char *sisph_last_error(sisph_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

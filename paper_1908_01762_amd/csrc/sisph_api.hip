@@ -1,0 +1,732 @@
+// Host runtime of libsisph: descriptor checks, workspace carving, the step
+// state machine and the C ABI declared in sisph.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sisph_internal.h"
+
+using namespace sisph;
+
+enum { ST_READY = 0, ST_BINNED = 1, ST_PREDICTED = 2, ST_SOLVED = 3 };
+
+struct sisph_ctx {
+    sisph_case_desc desc;
+    Params P;
+    State S;
+    hipStream_t stream;
+    int state;
+    int nbr_stage;      // which neighbour lists are held: -1, 0 (r^n), 1 (r*)
+    int final_parity;   // iterate holding the last solve's pressure
+    int last_iters;
+    Control *h_ctl;     // pinned mirror of the control block
+    hipEvent_t ev[4];
+    double ppe_ms, step_ms;
+    bool step_timed;
+    std::string err;
+};
+
+static thread_local std::string g_create_err;
+
+#define HIPCHK(ctx, expr)                                                               \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);             \
+            return SISPH_E_DEVICE;                                                      \
+        }                                                                               \
+    } while (0)
+
+// ----------------------------------------------------------- descriptor
+static double support_of(int kernel) { return kernel == SISPH_QUINTIC ? 3.0 : 2.0; }
+
+static const char *check_desc(const sisph_case_desc *d) {
+    if (!d) return "null descriptor";
+    if (d->dim != 2 && d->dim != 3) return "dim must be 2 or 3";
+    if (d->kernel != SISPH_QUINTIC && d->kernel != SISPH_WENDLAND_C2) return "unknown kernel";
+    if (d->precision != SISPH_FP64 && d->precision != SISPH_MIXED) return "unknown precision";
+    if (d->pgrad != SISPH_ASYMM && d->pgrad != SISPH_SYMM) return "unknown pressure-gradient form";
+    if (d->gtvf < SISPH_GTVF_OFF || d->gtvf > SISPH_GTVF_EXTERNAL) return "unknown gtvf mode";
+    if (d->p_ref_mode != SISPH_PREF_FIXED && d->p_ref_mode != SISPH_PREF_TWICE_MAX) return "unknown p_ref mode";
+    if (d->conv_norm != SISPH_CONV_SUM && d->conv_norm != SISPH_CONV_MEAN) return "unknown conv_norm";
+    if (d->n_fluid <= 0) return "n_fluid must be positive";
+    if (d->n_wall < 0) return "n_wall must be >= 0";
+    if (d->n_fluid + d->n_wall >= (int64_t)1 << 31) return "particle count exceeds 2^31";
+    if (!(d->h > 0) || !(d->dx > 0) || !(d->rho0 > 0) || !(d->dt > 0)) return "h, dx, rho0, dt must be positive";
+    if (!(d->omega > 0) || !(d->omega <= 1.0)) return "omega must be in (0, 1]";
+    if (d->min_iter < 1 || d->max_iter < d->min_iter) return "need 1 <= min_iter <= max_iter";
+    if (d->forced_iters < 0) return "forced_iters must be >= 0";
+    if (d->gtvf != SISPH_GTVF_OFF && d->gtvf_K < 1) return "gtvf_K must be >= 1";
+    if (d->nbr_cap < 0) return "nbr_cap must be >= 0";
+    double R = support_of(d->kernel) * d->h;
+    for (int k = 0; k < d->dim; ++k) {
+        double L = d->box_hi[k] - d->box_lo[k];
+        if (!(L > 0)) return "box_hi must exceed box_lo";
+        if (d->periodic[k] && L < 2.0 * R) return "a periodic axis must be at least two supports long";
+    }
+    return nullptr;
+}
+
+static Grid make_grid(const sisph_case_desc *d) {
+    Grid g{};
+    const double R = support_of(d->kernel) * d->h, Rm = R * 1.000001;
+    g.ncell = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (k < d->dim) {
+            g.lo[k] = d->box_lo[k];
+            g.hi[k] = d->box_hi[k];
+            g.L[k] = g.hi[k] - g.lo[k];
+            g.Lh[k] = 0.5 * g.L[k];
+            int64_t n = (int64_t)std::floor(g.L[k] / Rm);
+            if (n < 1) n = 1;
+            g.nc[k] = (int32_t)n;
+            g.edge[k] = g.L[k] / (double)n;
+            if (g.edge[k] < Rm) g.edge[k] = Rm;
+            g.per[k] = d->periodic[k] ? 1 : 0;
+        } else {
+            g.lo[k] = 0.0;
+            g.hi[k] = 1.0;
+            g.L[k] = 1.0;
+            g.Lh[k] = 0.5;
+            g.nc[k] = 1;
+            g.edge[k] = 1.0;
+            g.per[k] = 0;
+        }
+        g.ncell *= g.nc[k];
+    }
+    return g;
+}
+
+static int32_t neighbour_cap(const sisph_case_desc *d) {
+    if (d->nbr_cap > 0) return d->nbr_cap;
+    const double R = support_of(d->kernel) * d->h / d->dx;
+    const double pi = 3.14159265358979323846;
+    double n = d->dim == 2 ? pi * R * R : 4.0 / 3.0 * pi * R * R * R;
+    int32_t c = (int32_t)std::ceil(1.6 * n) + 8;
+    return (c + 3) / 4 * 4;
+}
+
+static Params make_params(const sisph_case_desc *d) {
+    Params P{};
+    P.dim = d->dim;
+    P.kernel = d->kernel;
+    P.precision = d->precision;
+    P.pgrad = d->pgrad;
+    P.gtvf = d->gtvf;
+    P.free_surface = d->free_surface ? 1 : 0;
+    P.conv_norm = d->conv_norm;
+    P.min_iter = d->min_iter;
+    P.max_iter = d->max_iter;
+    P.forced_iters = d->forced_iters;
+    P.gtvf_K = d->gtvf_K;
+    P.cap = neighbour_cap(d);
+    P.nf = d->n_fluid;
+    P.nw = d->n_wall;
+    P.ntot = d->n_fluid + d->n_wall;
+    P.h = d->h;
+    P.rho0 = d->rho0;
+    P.nu = d->nu;
+    P.alpha = d->alpha;
+    P.c_ref = d->c_ref;
+    P.dt = d->dt;
+    P.eps_h = d->eta * d->h * d->h;
+    P.fs_ratio = d->fs_ratio;
+    P.omega = d->omega;
+    P.tol = d->tol;
+    const double R = support_of(d->kernel) * d->h;
+    P.R2 = R * R;
+    for (int k = 0; k < 3; ++k) P.g[k] = k < d->dim ? d->gravity[k] : 0.0;
+    P.grid = make_grid(d);
+    return P;
+}
+
+// ------------------------------------------------------------- workspace
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(int64_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += sizeof(T) * (size_t)(count > 0 ? count : 1);
+        return p;
+    }
+};
+
+static void carve(const Params &P, Carver &c, State &S) {
+    const int64_t nf = P.nf, nw = P.nw, nt = P.ntot, D = P.dim;
+    auto vec = [&](double **dst, int64_t n) {
+        for (int k = 0; k < 3; ++k) dst[k] = nullptr;
+        for (int k = 0; k < D; ++k) dst[k] = c.take<double>(n);
+    };
+    vec(S.x, nt);
+    vec(S.u, nt);
+    vec(S.ut, nf);
+    vec(S.xs, nt);
+    vec(S.us, nt);
+    vec(S.un, nf);
+    vec(S.xk[0], nt);
+    vec(S.xk[1], nt);
+    vec(S.vk, nf);
+    vec(S.nrm, nw);
+    vec(S.wallu, nw);
+    S.p[0] = c.take<double>(nt);
+    S.p[1] = c.take<double>(nt);
+    S.p32 = c.take<float>(2 * nt);
+    S.m = c.take<double>(nt);
+    S.rho = c.take<double>(nt);
+    S.rhs = c.take<double>(nf);
+    S.dii = c.take<double>(nf);
+    S.fs = c.take<int32_t>(nf);
+    S.id = c.take<int32_t>(nf);
+    S.wid = c.take<int32_t>(nw);
+    const int64_t nmax = nf > nw ? nf : nw;
+    S.key = c.take<uint32_t>(nmax);
+    S.rank = c.take<uint32_t>(nmax);
+    S.count = c.take<uint32_t>(P.grid.ncell);
+    S.fstart = c.take<uint32_t>(P.grid.ncell + 1);
+    S.wstart = c.take<uint32_t>(P.grid.ncell + 1);
+    S.scan_tmp = c.take<uint32_t>(P.grid.ncell / 1024 + 2);
+    S.perm = c.take<int32_t>(nmax);
+    S.items = nullptr;
+    S.nbr = c.take<int32_t>((int64_t)P.cap * nf);
+    S.cnt = c.take<int32_t>(nf);
+    S.wnbr = c.take<int32_t>((int64_t)P.cap * nw);
+    S.wcnt = c.take<int32_t>(nw);
+    const size_t csz = P.precision == SISPH_MIXED ? sizeof(float) : sizeof(double);
+    S.coef = c.take<char>((int64_t)csz * P.cap * nf);
+    S.nblk_f = (nf + kBlock - 1) / kBlock;
+    S.partial = c.take<double>(2 * S.nblk_f);
+    S.tmp = c.take<double>(16 * nmax);
+    S.ctl = c.take<Control>(1);
+}
+
+extern "C" size_t sisph_workspace_bytes(const sisph_case_desc *desc) {
+    if (check_desc(desc)) return 0;
+    Params P = make_params(desc);
+    if (P.grid.ncell > ((int64_t)1 << 31) - 2) return 0;
+    Carver c{nullptr};
+    State S{};
+    carve(P, c, S);
+    return (c.off + 255) & ~(size_t)255;
+}
+
+// ------------------------------------------------------------ utilities
+static int32_t h2d(sisph_ctx *ctx, double *dst, const double *src, int64_t n) {
+    HIPCHK(ctx, hipMemcpyAsync(dst, src, sizeof(double) * (size_t)n, hipMemcpyHostToDevice, ctx->stream));
+    return SISPH_OK;
+}
+
+// Host row-major [n][dim] -> device SoA component arrays (offset `at`).
+static int32_t upload_vec(sisph_ctx *ctx, double *const dst[3], int64_t at, const double *src, int64_t n) {
+    const int D = ctx->P.dim;
+    std::vector<double> col((size_t)n);
+    for (int k = 0; k < D; ++k) {
+        for (int64_t i = 0; i < n; ++i) col[(size_t)i] = src[i * D + k];
+        HIPCHK(ctx, hipMemcpyAsync(dst[k] + at, col.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice,
+                                   ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return SISPH_OK;
+}
+
+static int32_t read_ctl(sisph_ctx *ctx) {
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_ctl, ctx->S.ctl, sizeof(Control), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SISPH_OK;
+}
+
+static int32_t fail(sisph_ctx *ctx, int32_t code, const std::string &msg) {
+    ctx->err = msg;
+    return code;
+}
+
+// ---------------------------------------------------------------- create
+extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, size_t ws_bytes, const double *x,
+                                const double *u, const double *p, const double *m, const double *wall_u,
+                                void *hip_stream, sisph_ctx **out) {
+    if (!out) return SISPH_E_INVAL;
+    *out = nullptr;
+    if (const char *why = check_desc(desc)) {
+        g_create_err = why;
+        return SISPH_E_INVAL;
+    }
+    if (!x || !u || !p || !m || !d_workspace) {
+        g_create_err = "null array argument";
+        return SISPH_E_INVAL;
+    }
+    if (((uintptr_t)d_workspace & 255) != 0) {
+        g_create_err = "workspace must be 256-byte aligned";
+        return SISPH_E_INVAL;
+    }
+    size_t need = sisph_workspace_bytes(desc);
+    if (need == 0) {
+        g_create_err = "binning grid too large";
+        return SISPH_E_INVAL;
+    }
+    if (ws_bytes < need) {
+        g_create_err = "workspace too small: need " + std::to_string(need) + " bytes";
+        return SISPH_E_NOMEM;
+    }
+    sisph_ctx *ctx = new sisph_ctx();
+    ctx->desc = *desc;
+    ctx->P = make_params(desc);
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->state = ST_READY;
+    ctx->nbr_stage = -1;
+    ctx->final_parity = 0;
+    ctx->last_iters = desc->min_iter;
+    ctx->ppe_ms = ctx->step_ms = 0.0;
+    ctx->step_timed = false;
+    Carver c{(char *)d_workspace};
+    carve(ctx->P, c, ctx->S);
+    auto bail = [&](int32_t code) {
+        g_create_err = ctx->err;
+        if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
+        for (auto &e : ctx->ev)
+            if (e) (void)hipEventDestroy(e);
+        delete ctx;
+        return code;
+    };
+    if (hipHostMalloc((void **)&ctx->h_ctl, sizeof(Control), hipHostMallocDefault) != hipSuccess) {
+        ctx->err = "hipHostMalloc failed";
+        ctx->h_ctl = nullptr;
+        return bail(SISPH_E_DEVICE);
+    }
+    for (auto &e : ctx->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            ctx->err = "hipEventCreate failed";
+            return bail(SISPH_E_DEVICE);
+        }
+    }
+    const Params &P = ctx->P;
+    State &S = ctx->S;
+    const int64_t nf = P.nf, nw = P.nw, nt = P.ntot, D = P.dim;
+    hipStream_t s = ctx->stream;
+    int32_t st;
+    // state in caller order; fluid ids are 0..nf-1, wall ids 0..nw-1
+    if ((st = upload_vec(ctx, S.x, 0, x, nt)) != SISPH_OK) return bail(st);
+    if ((st = upload_vec(ctx, S.u, 0, u, nf)) != SISPH_OK) return bail(st);
+    if ((st = upload_vec(ctx, S.ut, 0, u, nf)) != SISPH_OK) return bail(st);
+    if ((st = h2d(ctx, S.p[0], p, nt)) != SISPH_OK) return bail(st);
+    if ((st = h2d(ctx, S.m, m, nt)) != SISPH_OK) return bail(st);
+    if (nw > 0) {
+        if (wall_u) {
+            if ((st = upload_vec(ctx, S.wallu, 0, wall_u, nw)) != SISPH_OK) return bail(st);
+        } else {
+            for (int k = 0; k < D; ++k) fill_f64(S.wallu[k], 0.0, nw, s);
+        }
+    }
+    iota_i32(S.id, nf, s);
+    iota_i32(S.wid, nw, s);
+    reset_control(S.ctl, RESET_PPE | RESET_NEIGHBOURS | RESET_PREF, s);
+    if (desc->p_ref_mode == SISPH_PREF_FIXED) {
+        Control c0{};
+        c0.p_ref = desc->p_ref;
+        c0.p_ref_set = 1;
+        // set p_ref / p_ref_set only (a fill of the two fields)
+        if (hipMemcpyAsync(&S.ctl->p_ref, &c0.p_ref, sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(&S.ctl->p_ref_set, &c0.p_ref_set, sizeof(int32_t), hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            ctx->err = "control upload failed";
+            return bail(SISPH_E_DEVICE);
+        }
+    }
+    // walls: one stable sort into cell order (they never move)
+    fill_u32(S.wstart, 0u, P.grid.ncell + 1, s);
+    if (nw > 0) {
+        bin_particles(P, S.x, nf, nw, S.wid, S, S.wstart, S.perm, s);
+        std::vector<double *> arrs;
+        for (int k = 0; k < D; ++k) arrs.push_back(S.x[k] + nf);
+        arrs.push_back(S.m + nf);
+        for (int k = 0; k < D; ++k) arrs.push_back(S.wallu[k]);
+        reorder_f64(S.perm, nw, arrs.data(), (int)arrs.size(), S.tmp, s);
+        reorder_i32(S.perm, nw, S.wid, (int32_t *)S.tmp, s);
+        fill_f64(S.rho + nf, P.rho0, nw, s);
+        fill_f64(S.p[0] + nf, 0.0, nw, s);
+        fill_f64(S.p[1] + nf, 0.0, nw, s);
+        for (int k = 0; k < D; ++k) {
+            if (hipMemcpyAsync(S.xs[k] + nf, S.x[k] + nf, sizeof(double) * nw, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess ||
+                hipMemcpyAsync(S.xk[0][k] + nf, S.x[k] + nf, sizeof(double) * nw, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess ||
+                hipMemcpyAsync(S.xk[1][k] + nf, S.x[k] + nf, sizeof(double) * nw, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess) {
+                ctx->err = "wall copy failed";
+                return bail(SISPH_E_DEVICE);
+            }
+            fill_f64(S.u[k] + nf, 0.0, nw, s);
+            fill_f64(S.us[k] + nf, 0.0, nw, s);
+        }
+        wall_normals(P, S, s);
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        ctx->err = "device error during create";
+        return bail(SISPH_E_DEVICE);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        ctx->err = std::string("kernel launch failed: ") + hipGetErrorString(e);
+        return bail(SISPH_E_DEVICE);
+    }
+    *out = ctx;
+    return SISPH_OK;
+}
+
+// ------------------------------------------------------------ the stages
+extern "C" int32_t sisph_bin(sisph_ctx *ctx) {
+    if (!ctx) return SISPH_E_INVAL;
+    if (ctx->state != ST_READY) return fail(ctx, SISPH_E_STATE, "sisph_bin needs a completed step");
+    const Params &P = ctx->P;
+    State &S = ctx->S;
+    hipStream_t s = ctx->stream;
+    HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
+    reset_control(S.ctl, RESET_NEIGHBOURS, s);
+    bin_particles(P, S.x, 0, P.nf, S.id, S, S.fstart, S.perm, s);
+    std::vector<double *> arrs;
+    for (int k = 0; k < P.dim; ++k) arrs.push_back(S.x[k]);
+    for (int k = 0; k < P.dim; ++k) arrs.push_back(S.u[k]);
+    for (int k = 0; k < P.dim; ++k) arrs.push_back(S.ut[k]);
+    arrs.push_back(S.p[0]);
+    arrs.push_back(S.m);
+    reorder_f64(S.perm, P.nf, arrs.data(), (int)arrs.size(), S.tmp, s);
+    reorder_i32(S.perm, P.nf, S.id, (int32_t *)S.tmp, s);
+    S.items = nullptr;
+    build_neighbors(P, S.x, S, s);
+    HIPCHK(ctx, hipGetLastError());
+    ctx->state = ST_BINNED;
+    ctx->nbr_stage = 0;
+    ctx->step_timed = true;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_predict(sisph_ctx *ctx) {
+    if (!ctx) return SISPH_E_INVAL;
+    if (ctx->state != ST_BINNED) return fail(ctx, SISPH_E_STATE, "sisph_predict needs sisph_bin first");
+    const Params &P = ctx->P;
+    State &S = ctx->S;
+    hipStream_t s = ctx->stream;
+    density(P, S, s);
+    wall_velocity(P, S.x, S.u, S.u, 0, S, s);
+    predictor(P, S, s);
+    // N*: bin r* without moving data; lists index the r^n cell order
+    bin_particles(P, S.xs, 0, P.nf, nullptr, S, S.fstart, S.perm, s);
+    S.items = S.perm;
+    build_neighbors(P, S.xs, S, s);
+    wall_velocity(P, S.xs, S.us, S.us, 1, S, s);
+    HIPCHK(ctx, hipGetLastError());
+    ctx->state = ST_PREDICTED;
+    ctx->nbr_stage = 1;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out) {
+    if (!ctx) return SISPH_E_INVAL;
+    if (ctx->state != ST_PREDICTED) return fail(ctx, SISPH_E_STATE, "sisph_ppe_solve needs sisph_predict first");
+    const Params &P = ctx->P;
+    State &S = ctx->S;
+    hipStream_t s = ctx->stream;
+    HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
+    reset_control(S.ctl, RESET_PPE, s);
+    rhs_coef(P, S, s);
+    if (P.precision == SISPH_MIXED) copy_p32(P, S, s);
+    int chunk = P.forced_iters > 0 ? P.forced_iters : std::max(P.min_iter, ctx->last_iters);
+    chunk = std::min(chunk, P.forced_iters > 0 ? P.forced_iters : P.max_iter);
+    int64_t launched = 0;
+    const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter);
+    for (;;) {
+        for (int c = 0; c < chunk; ++c) ppe_iteration(P, S, s);
+        launched += chunk;
+        HIPCHK(ctx, hipGetLastError());
+        int32_t st = read_ctl(ctx);
+        if (st != SISPH_OK) return st;
+        if (ctx->h_ctl->done || launched >= limit) break;
+        int64_t left = limit - ctx->h_ctl->iter;
+        chunk = (int)std::min<int64_t>(std::min<int64_t>(2 * (int64_t)chunk, 64), left);
+        if (chunk < 1) chunk = 1;
+    }
+    const int iters = ctx->h_ctl->iter;
+    wall_pressure_final(P, S, s);
+    ctx->final_parity = iters & 1;
+    if (ctx->desc.p_ref_mode == SISPH_PREF_TWICE_MAX) pressure_max(P, S, ctx->final_parity, s);
+    HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+    int32_t st = read_ctl(ctx);
+    if (st != SISPH_OK) return st;
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+    ctx->ppe_ms = ms;
+    const Control &C = *ctx->h_ctl;
+    ctx->last_iters = std::max(iters, 1);
+    if (out) {
+        out->iters = C.iter;
+        out->converged = C.ratio < P.tol ? 1 : 0;
+        out->nonfinite = C.nonfinite;
+        out->reserved = 0;
+        out->ratio = C.ratio;
+        union {
+            unsigned long long u;
+            double d;
+        } cv;
+        cv.u = C.lambda_bits;
+        out->lambda = cv.d;
+        out->p_ref = C.p_ref;
+    }
+    ctx->state = ST_SOLVED;
+    if (C.overflow)
+        return fail(ctx, SISPH_E_NOMEM,
+                    "neighbour capacity exceeded: " + std::to_string(C.maxcnt) + " > nbr_cap " +
+                        std::to_string(P.cap));
+    if (C.nonfinite) return fail(ctx, SISPH_E_NONFINITE, "non-finite pressure in the PPE residual");
+    if (P.forced_iters == 0 && !(C.ratio < P.tol)) return SISPH_WARN_MAXITER;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_correct(sisph_ctx *ctx) {
+    if (!ctx) return SISPH_E_INVAL;
+    if (ctx->state != ST_SOLVED) return fail(ctx, SISPH_E_STATE, "sisph_correct needs sisph_ppe_solve first");
+    const Params &P = ctx->P;
+    State &S = ctx->S;
+    hipStream_t s = ctx->stream;
+    const int fp = ctx->final_parity;
+    correct(P, S, fp, s);
+    int kfinal = -1;
+    if (P.gtvf != SISPH_GTVF_OFF) {
+        for (int k = 0; k < P.gtvf_K; ++k) gtvf_substep(P, S, fp, k, s);
+        kfinal = P.gtvf_K - 1;
+    }
+    advance(P, S, kfinal, s);
+    HIPCHK(ctx, hipGetLastError());
+    if (fp == 1) {
+        // keep the current pressure in iterate 0 for the next solve
+        std::swap(S.p[0], S.p[1]);
+    }
+    ctx->final_parity = 0;
+    HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
+    if (ctx->step_timed) {
+        HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
+        float ms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
+        ctx->step_ms = ms;
+    }
+    ctx->state = ST_READY;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_step(sisph_ctx *ctx, int32_t nsteps, sisph_step_stats *out) {
+    if (!ctx || nsteps < 0) return SISPH_E_INVAL;
+    int32_t worst = SISPH_OK;
+    for (int32_t n = 0; n < nsteps; ++n) {
+        int32_t st = sisph_bin(ctx);
+        if (st < 0) return st;
+        if ((st = sisph_predict(ctx)) < 0) return st;
+        int32_t sp = sisph_ppe_solve(ctx, out ? out + n : nullptr);
+        if (sp < 0) return sp;
+        if ((st = sisph_correct(ctx)) < 0) return st;
+        if (sp > worst) worst = sp;
+    }
+    return worst;
+}
+
+// --------------------------------------------------------- state access
+template <typename T>
+static int32_t d2h(sisph_ctx *ctx, std::vector<T> &dst, const T *src, int64_t n) {
+    dst.resize((size_t)(n > 0 ? n : 0));
+    if (n <= 0) return SISPH_OK;
+    HIPCHK(ctx, hipMemcpyAsync(dst.data(), src, sizeof(T) * (size_t)n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SISPH_OK;
+}
+
+// Device SoA (sorted) -> host row-major in original order via the id map.
+static int32_t download_vec(sisph_ctx *ctx, double *dst, double *const src[3], int64_t at, int64_t n,
+                            const std::vector<int32_t> &ids, int64_t dst_off) {
+    const int D = ctx->P.dim;
+    std::vector<double> col;
+    for (int k = 0; k < D; ++k) {
+        int32_t st = d2h(ctx, col, src[k] + at, n);
+        if (st != SISPH_OK) return st;
+        for (int64_t i = 0; i < n; ++i) dst[(dst_off + ids[(size_t)i]) * D + k] = col[(size_t)i];
+    }
+    return SISPH_OK;
+}
+
+static int32_t download_scalar(sisph_ctx *ctx, double *dst, const double *src, int64_t n,
+                               const std::vector<int32_t> &ids, int64_t dst_off) {
+    std::vector<double> col;
+    int32_t st = d2h(ctx, col, src, n);
+    if (st != SISPH_OK) return st;
+    for (int64_t i = 0; i < n; ++i) dst[dst_off + ids[(size_t)i]] = col[(size_t)i];
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_read_state(sisph_ctx *ctx, double *x, double *u, double *u_tilde, double *p,
+                                    double *rho) {
+    if (!ctx) return SISPH_E_INVAL;
+    if (ctx->state != ST_READY && ctx->state != ST_BINNED)
+        return fail(ctx, SISPH_E_STATE, "state is readable between steps only");
+    const Params &P = ctx->P;
+    State &S = ctx->S;
+    std::vector<int32_t> id, wid;
+    int32_t st;
+    if ((st = d2h(ctx, id, S.id, P.nf)) != SISPH_OK) return st;
+    if ((st = d2h(ctx, wid, S.wid, P.nw)) != SISPH_OK) return st;
+    if (x) {
+        if ((st = download_vec(ctx, x, S.x, 0, P.nf, id, 0)) != SISPH_OK) return st;
+        if (P.nw && (st = download_vec(ctx, x, S.x, P.nf, P.nw, wid, P.nf)) != SISPH_OK) return st;
+    }
+    if (u && (st = download_vec(ctx, u, S.u, 0, P.nf, id, 0)) != SISPH_OK) return st;
+    if (u_tilde && (st = download_vec(ctx, u_tilde, S.ut, 0, P.nf, id, 0)) != SISPH_OK) return st;
+    if (p) {
+        if ((st = download_scalar(ctx, p, S.p[0], P.nf, id, 0)) != SISPH_OK) return st;
+        if (P.nw && (st = download_scalar(ctx, p, S.p[0] + P.nf, P.nw, wid, P.nf)) != SISPH_OK) return st;
+    }
+    if (rho && (st = download_scalar(ctx, rho, S.rho, P.nf, id, 0)) != SISPH_OK) return st;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_write_state(sisph_ctx *ctx, const double *x, const double *u, const double *u_tilde,
+                                     const double *p) {
+    if (!ctx) return SISPH_E_INVAL;
+    if (ctx->state != ST_READY) return fail(ctx, SISPH_E_STATE, "state is writable between steps only");
+    const Params &P = ctx->P;
+    State &S = ctx->S;
+    const int D = P.dim;
+    std::vector<int32_t> id;
+    int32_t st;
+    if ((st = d2h(ctx, id, S.id, P.nf)) != SISPH_OK) return st;
+    // write in the current sorted order so that fields stay aligned
+    auto put_vec = [&](double *const dst[3], const double *src) -> int32_t {
+        std::vector<double> col((size_t)P.nf);
+        for (int k = 0; k < D; ++k) {
+            for (int64_t i = 0; i < P.nf; ++i) col[(size_t)i] = src[(int64_t)id[(size_t)i] * D + k];
+            HIPCHK(ctx, hipMemcpyAsync(dst[k], col.data(), sizeof(double) * (size_t)P.nf, hipMemcpyHostToDevice,
+                                       ctx->stream));
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        }
+        return SISPH_OK;
+    };
+    if (x && (st = put_vec(S.x, x)) != SISPH_OK) return st;
+    if (u && (st = put_vec(S.u, u)) != SISPH_OK) return st;
+    if (u_tilde && (st = put_vec(S.ut, u_tilde)) != SISPH_OK) return st;
+    if (p) {
+        std::vector<double> col((size_t)P.nf);
+        for (int64_t i = 0; i < P.nf; ++i) col[(size_t)i] = p[id[(size_t)i]];
+        HIPCHK(ctx, hipMemcpyAsync(S.p[0], col.data(), sizeof(double) * (size_t)P.nf, hipMemcpyHostToDevice,
+                                   ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_read_field(sisph_ctx *ctx, int32_t field, double *out) {
+    if (!ctx || !out) return SISPH_E_INVAL;
+    const Params &P = ctx->P;
+    State &S = ctx->S;
+    std::vector<int32_t> id, wid;
+    int32_t st;
+    if ((st = d2h(ctx, id, S.id, P.nf)) != SISPH_OK) return st;
+    if ((st = d2h(ctx, wid, S.wid, P.nw)) != SISPH_OK) return st;
+    switch (field) {
+    case SISPH_FIELD_RHO: return download_scalar(ctx, out, S.rho, P.nf, id, 0);
+    case SISPH_FIELD_XSTAR: return download_vec(ctx, out, S.xs, 0, P.nf, id, 0);
+    case SISPH_FIELD_USTAR: return download_vec(ctx, out, S.us, 0, P.nf, id, 0);
+    case SISPH_FIELD_RHS: return download_scalar(ctx, out, S.rhs, P.nf, id, 0);
+    case SISPH_FIELD_DII: return download_scalar(ctx, out, S.dii, P.nf, id, 0);
+    case SISPH_FIELD_UNEW: return download_vec(ctx, out, S.un, 0, P.nf, id, 0);
+    case SISPH_FIELD_WALL_U: return download_vec(ctx, out, S.u, P.nf, P.nw, wid, 0);
+    case SISPH_FIELD_WALL_USTAR: return download_vec(ctx, out, S.us, P.nf, P.nw, wid, 0);
+    case SISPH_FIELD_NORMAL: return download_vec(ctx, out, S.nrm, 0, P.nw, wid, 0);
+    case SISPH_FIELD_FS: {
+        std::vector<int32_t> f;
+        if ((st = d2h(ctx, f, S.fs, P.nf)) != SISPH_OK) return st;
+        for (int64_t i = 0; i < P.nf; ++i) out[id[(size_t)i]] = (double)f[(size_t)i];
+        return SISPH_OK;
+    }
+    case SISPH_FIELD_PRESSURE: {
+        const double *pc = S.p[ctx->state == ST_SOLVED ? ctx->final_parity : 0];
+        if ((st = download_scalar(ctx, out, pc, P.nf, id, 0)) != SISPH_OK) return st;
+        if (P.nw) return download_scalar(ctx, out, pc + P.nf, P.nw, wid, P.nf);
+        return SISPH_OK;
+    }
+    default: return fail(ctx, SISPH_E_INVAL, "unknown field");
+    }
+}
+
+extern "C" int32_t sisph_debug_neighbors(sisph_ctx *ctx, int32_t stage, int32_t dest, int64_t *offsets,
+                                         int32_t *ids, int64_t cap) {
+    if (!ctx || !offsets || (dest != 0 && dest != 1)) return SISPH_E_INVAL;
+    if (stage != ctx->nbr_stage) return fail(ctx, SISPH_E_STATE, "requested neighbour stage is not held");
+    const Params &P = ctx->P;
+    State &S = ctx->S;
+    int32_t st = read_ctl(ctx);
+    if (st != SISPH_OK) return st;
+    if (ctx->h_ctl->overflow)
+        return fail(ctx, SISPH_E_NOMEM, "neighbour capacity exceeded: " + std::to_string(ctx->h_ctl->maxcnt));
+    std::vector<int32_t> id, wid, nbr, cnt;
+    if ((st = d2h(ctx, id, S.id, P.nf)) != SISPH_OK) return st;
+    if ((st = d2h(ctx, wid, S.wid, P.nw)) != SISPH_OK) return st;
+    const int64_t rows = dest == 0 ? P.nf : P.nw;
+    if ((st = d2h(ctx, nbr, dest == 0 ? S.nbr : S.wnbr, (int64_t)P.cap * rows)) != SISPH_OK) return st;
+    if ((st = d2h(ctx, cnt, dest == 0 ? S.cnt : S.wcnt, rows)) != SISPH_OK) return st;
+    auto orig = [&](int64_t j) -> int32_t {
+        return j < P.nf ? id[(size_t)j] : (int32_t)(P.nf + wid[(size_t)(j - P.nf)]);
+    };
+    std::vector<std::vector<int32_t>> out((size_t)rows);
+    for (int64_t r = 0; r < rows; ++r) {
+        int64_t orow = dest == 0 ? id[(size_t)r] : wid[(size_t)r];
+        auto &v = out[(size_t)orow];
+        for (int k = 0; k < cnt[(size_t)r]; ++k) v.push_back(orig(nbr[(size_t)((int64_t)k * rows + r)]));
+        std::sort(v.begin(), v.end());
+    }
+    int64_t tot = 0;
+    offsets[0] = 0;
+    for (int64_t r = 0; r < rows; ++r) {
+        for (int32_t j : out[(size_t)r]) {
+            if (tot < cap && ids) ids[tot] = j;
+            ++tot;
+        }
+        offsets[r + 1] = tot;
+    }
+    if (tot > cap) return fail(ctx, SISPH_E_NOMEM, "ids buffer too small");
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_last_timings(sisph_ctx *ctx, double *ppe_ms, double *step_ms) {
+    if (!ctx) return SISPH_E_INVAL;
+    if (ppe_ms) *ppe_ms = ctx->ppe_ms;
+    if (step_ms) *step_ms = ctx->step_ms;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_destroy(sisph_ctx *ctx) {
+    if (!ctx) return SISPH_E_INVAL;
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+    return SISPH_OK;
+}
+
+extern "C" const char *sisph_status_string(int32_t status) {
+    switch (status) {
+    case SISPH_OK: return "ok";
+    case SISPH_WARN_MAXITER: return "PPE stopped at max_iter before reaching the tolerance";
+    case SISPH_E_INVAL: return "invalid descriptor or argument";
+    case SISPH_E_NOMEM: return "workspace or neighbour capacity too small";
+    case SISPH_E_DEVICE: return "HIP runtime error";
+    case SISPH_E_STATE: return "call out of order";
+    case SISPH_E_NONFINITE: return "non-finite value in the PPE residual";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *sisph_last_error(sisph_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}

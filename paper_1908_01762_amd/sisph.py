@@ -1,0 +1,250 @@
+"""Thin Python binding of libsisph (the C ABI of include/sisph.h).
+
+Argument marshalling only: every step of the SISPH path runs in the HIP
+kernels of libsisph.so.  PyTorch provides the device workspace (a uint8
+tensor the caller owns) and the stream.  If the library is missing this
+module raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import cases as _cases
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsisph.so")
+
+OK, WARN_MAXITER = 0, 1
+E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_NONFINITE = -1, -2, -3, -4, -5
+
+FIELDS = {"rho": 0, "xstar": 1, "ustar": 2, "rhs": 3, "dii": 4, "unew": 5, "wall_u": 6,
+          "wall_ustar": 7, "fs": 8, "normal": 9, "pressure": 10}
+_VECTOR = {"xstar", "ustar", "unew", "wall_u", "wall_ustar", "normal"}
+_WALL = {"wall_u", "wall_ustar", "normal"}
+
+
+class SisphError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sisph status {code}: {msg}")
+        self.code = code
+
+
+class CaseDesc(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in (
+        "dim", "kernel", "precision", "pgrad", "gtvf", "free_surface",
+        "p_ref_mode", "conv_norm", "min_iter", "max_iter", "gtvf_K", "forced_iters")] + \
+        [("periodic", C.c_int32 * 3), ("nbr_cap", C.c_int32),
+         ("n_fluid", C.c_int64), ("n_wall", C.c_int64)] + \
+        [(n, C.c_double) for n in (
+            "h", "dx", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio",
+            "omega", "tol", "p_ref")] + \
+        [("gravity", C.c_double * 3), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3)]
+
+
+class PPEStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("nonfinite", C.c_int32),
+                ("reserved", C.c_int32), ("ratio", C.c_double), ("lambda_", C.c_double),
+                ("p_ref", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return dict(iters=self.iters, converged=bool(self.converged), nonfinite=bool(self.nonfinite),
+                    ratio=self.ratio, lam=self.lambda_, p_ref=self.p_ref)
+
+
+_lib = None
+_DP = C.POINTER(C.c_double)
+
+
+def lib():
+    """Loads libsisph.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1908_01762_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        L.sisph_workspace_bytes.restype = C.c_size_t
+        L.sisph_workspace_bytes.argtypes = [C.POINTER(CaseDesc)]
+        L.sisph_create.restype = C.c_int32
+        L.sisph_create.argtypes = [C.POINTER(CaseDesc), C.c_void_p, C.c_size_t, _DP, _DP, _DP, _DP, _DP,
+                                   C.c_void_p, C.POINTER(C.c_void_p)]
+        for f in ("sisph_bin", "sisph_predict", "sisph_correct", "sisph_destroy"):
+            getattr(L, f).restype = C.c_int32
+            getattr(L, f).argtypes = [C.c_void_p]
+        L.sisph_ppe_solve.restype = C.c_int32
+        L.sisph_ppe_solve.argtypes = [C.c_void_p, C.POINTER(PPEStats)]
+        L.sisph_step.restype = C.c_int32
+        L.sisph_step.argtypes = [C.c_void_p, C.c_int32, C.POINTER(PPEStats)]
+        L.sisph_read_state.restype = C.c_int32
+        L.sisph_read_state.argtypes = [C.c_void_p, _DP, _DP, _DP, _DP, _DP]
+        L.sisph_write_state.restype = C.c_int32
+        L.sisph_write_state.argtypes = [C.c_void_p, _DP, _DP, _DP, _DP]
+        L.sisph_read_field.restype = C.c_int32
+        L.sisph_read_field.argtypes = [C.c_void_p, C.c_int32, _DP]
+        L.sisph_debug_neighbors.restype = C.c_int32
+        L.sisph_debug_neighbors.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
+                                            C.POINTER(C.c_int32), C.c_int64]
+        L.sisph_last_timings.restype = C.c_int32
+        L.sisph_last_timings.argtypes = [C.c_void_p, _DP, _DP]
+        L.sisph_status_string.restype = C.c_char_p
+        L.sisph_status_string.argtypes = [C.c_int32]
+        L.sisph_last_error.restype = C.c_char_p
+        L.sisph_last_error.argtypes = [C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_DP)
+
+
+def describe(case: "_cases.Case") -> CaseDesc:
+    """sisph_case_desc of a seeded case."""
+    d = CaseDesc()
+    d.dim = case.dim
+    d.kernel = _cases.KERNELS[case.kernel]
+    d.precision = _cases.PRECISION[case.precision]
+    d.pgrad = _cases.PGRAD[case.pgrad]
+    d.gtvf = _cases.GTVF[case.gtvf]
+    d.free_surface = int(bool(case.free_surface))
+    d.p_ref_mode = _cases.PREF[case.p_ref_mode]
+    d.conv_norm = _cases.CONV[case.conv_norm]
+    d.min_iter = case.min_iter
+    d.max_iter = case.max_iter
+    d.gtvf_K = case.gtvf_K
+    d.forced_iters = case.forced_iters
+    for k in range(3):
+        d.periodic[k] = int(case.periodic[k])
+        d.gravity[k] = case.gravity[k]
+        d.box_lo[k] = case.box_lo[k]
+        d.box_hi[k] = case.box_hi[k]
+    d.nbr_cap = int(case.meta.get("nbr_cap", 0))
+    d.n_fluid = case.n_fluid
+    d.n_wall = case.n_wall
+    for k in ("h", "dx", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio", "omega", "tol", "p_ref"):
+        setattr(d, k, float(getattr(case, k)))
+    return d
+
+
+def workspace_bytes(case) -> int:
+    return int(lib().sisph_workspace_bytes(C.byref(describe(case))))
+
+
+def status_string(code: int) -> str:
+    return lib().sisph_status_string(code).decode()
+
+
+def _check(code: int, ctx=None, allow_warn: bool = True) -> int:
+    if code < 0 or (code > 0 and not allow_warn):
+        msg = lib().sisph_last_error(ctx).decode()
+        raise SisphError(code, f"{status_string(code)} ({msg})")
+    return code
+
+
+class Context:
+    """One SISPH case resident on the GPU."""
+
+    def __init__(self, case, device: str = "cuda", stream=None):
+        import torch
+        self.case = case
+        self.desc = describe(case)
+        L = lib()
+        nbytes = int(L.sisph_workspace_bytes(C.byref(self.desc)))
+        if nbytes == 0:
+            raise SisphError(E_INVAL, "invalid case descriptor")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        h = C.c_void_p()
+        x = np.ascontiguousarray(case.x, dtype=np.float64)
+        u = np.ascontiguousarray(case.u, dtype=np.float64)
+        p = np.ascontiguousarray(case.p, dtype=np.float64)
+        m = np.ascontiguousarray(case.m, dtype=np.float64)
+        wu = None if case.wall_u is None or case.n_wall == 0 else np.ascontiguousarray(case.wall_u, dtype=np.float64)
+        code = L.sisph_create(C.byref(self.desc), C.c_void_p(aligned), C.c_size_t(nbytes), _p(x), _p(u), _p(p),
+                              _p(m), _p(wu), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        _check(code, None)
+        self.h = h
+        self.nbytes = nbytes
+
+    # -- stages -----------------------------------------------------------
+    def bin(self):
+        _check(lib().sisph_bin(self.h), self.h)
+
+    def predict(self):
+        _check(lib().sisph_predict(self.h), self.h)
+
+    def ppe_solve(self) -> dict:
+        st = PPEStats()
+        code = _check(lib().sisph_ppe_solve(self.h, C.byref(st)), self.h)
+        d = st.as_dict()
+        d["status"] = code
+        return d
+
+    def correct(self):
+        _check(lib().sisph_correct(self.h), self.h)
+
+    def step(self, nsteps: int = 1) -> List[dict]:
+        st = (PPEStats * max(nsteps, 1))()
+        code = _check(lib().sisph_step(self.h, nsteps, st), self.h)
+        out = [st[k].as_dict() for k in range(nsteps)]
+        for o in out:
+            o["status"] = code
+        return out
+
+    # -- state ------------------------------------------------------------
+    def read_state(self) -> Dict[str, np.ndarray]:
+        c = self.case
+        x = np.zeros((c.n, c.dim))
+        u = np.zeros((c.n_fluid, c.dim))
+        ut = np.zeros((c.n_fluid, c.dim))
+        p = np.zeros(c.n)
+        rho = np.zeros(c.n_fluid)
+        _check(lib().sisph_read_state(self.h, _p(x), _p(u), _p(ut), _p(p), _p(rho)), self.h)
+        return dict(x=x, u=u, ut=ut, p=p, rho=rho)
+
+    def write_state(self, x=None, u=None, ut=None, p=None):
+        conv = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        x, u, ut, p = conv(x), conv(u), conv(ut), conv(p)
+        _check(lib().sisph_write_state(self.h, _p(x), _p(u), _p(ut), _p(p)), self.h)
+
+    def field(self, name: str) -> np.ndarray:
+        c = self.case
+        rows = c.n_wall if name in _WALL else (c.n if name == "pressure" else c.n_fluid)
+        shape = (rows, c.dim) if name in _VECTOR else (rows,)
+        out = np.zeros(shape)
+        _check(lib().sisph_read_field(self.h, FIELDS[name], _p(out)), self.h)
+        return out
+
+    def neighbors(self, stage: int, dest: int = 0):
+        c = self.case
+        rows = c.n_fluid if dest == 0 else c.n_wall
+        off = np.zeros(rows + 1, dtype=np.int64)
+        cap = max(1, 300 * rows)
+        ids = np.zeros(cap, dtype=np.int32)
+        _check(lib().sisph_debug_neighbors(self.h, stage, dest, off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                            ids.ctypes.data_as(C.POINTER(C.c_int32)), cap), self.h)
+        return off, ids[:off[-1]].copy()
+
+    def timings(self):
+        a, b = C.c_double(), C.c_double()
+        _check(lib().sisph_last_timings(self.h, C.byref(a), C.byref(b)), self.h)
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sisph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,236 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Every case is seeded and synthetic; the oracle and the GPU read the same
+arrays.  Neighbour sets must match bit-exactly (same FP64 predicate, no
+contraction); FP64 fields must agree within 1e-5 relative L2 (they agree
+to ~1e-12: only the summation order differs); iteration counts must be
+equal.  Mixed-precision errors are checked against bounds derived from
+FP32 rounding (unit roundoff 6e-8 times the neighbour count and the
+conditioning of each quantity).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_01762_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-5
+
+
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1908_01762_amd import sisph
+    return sisph
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0))
+
+
+def _cases_small():
+    return {
+        "tg50_quintic": cases.taylor_green(50),
+        "tg40_wendland_jitter": cases.taylor_green(40, kernel="wendland", hdx=1.3, jitter=0.2, seed=3),
+        "db2d_dx0.05": cases.dam_break_2d(dx=0.05, precision="fp64"),
+        "db3d_small": cases.dam_break_3d(dx=0.1, lx=0.5, ly=0.5, lz=0.6, tank_x=1.5, tank_y=0.5, tank_z=1.0,
+                                         precision="fp64"),
+    }
+
+
+def _same_sets(off_a, ids_a, off_b, ids_b):
+    return np.array_equal(off_a, off_b) and np.array_equal(ids_a, ids_b)
+
+
+@pytest.mark.parametrize("name", list(_cases_small().keys()))
+def test_neighbour_sets_bit_exact(name):
+    sisph = _gpu()
+    case = _cases_small()[name]
+    say("case", name, case.n_fluid, case.n_wall)
+    ctx = sisph.Context(case)
+    ctx.bin()
+    off, ids = ctx.neighbors(0, 0)
+    roff, rids = oracle.neighbors(case)
+    assert _same_sets(off, ids, roff, rids)
+    if case.n_wall:
+        off, ids = ctx.neighbors(0, 1)
+        roff, rids = oracle.neighbors(case, dest=(case.n_fluid, case.n), src=(0, case.n_fluid))
+        assert _same_sets(off, ids, roff, rids)
+    # stage 1: r* = r^n + dt u~^n is formed with the same FP64 operations
+    ctx.predict()
+    out = oracle.Sim(case).step(capture=True)
+    xs_all = case.x.copy()
+    xs_all[:case.n_fluid] = out["xs"]
+    assert np.array_equal(ctx.field("xstar"), out["xs"])
+    off, ids = ctx.neighbors(1, 0)
+    roff, rids = oracle.neighbors(case, x=xs_all)
+    assert _same_sets(off, ids, roff, rids)
+    if case.n_wall:
+        off, ids = ctx.neighbors(1, 1)
+        roff, rids = oracle.neighbors(case, x=xs_all, dest=(case.n_fluid, case.n), src=(0, case.n_fluid))
+        assert _same_sets(off, ids, roff, rids)
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", list(_cases_small().keys()))
+def test_single_step_fields_fp64(name):
+    sisph = _gpu()
+    case = _cases_small()[name]
+    say("case", name)
+    ref = oracle.Sim(case)
+    out = ref.step(capture=True)
+    ctx = sisph.Context(case)
+    ctx.bin()
+    ctx.predict()
+    st = ctx.ppe_solve()
+    fields = {
+        "rho": (ctx.field("rho"), out["rho"]),
+        "ustar": (ctx.field("ustar"), out["us"]),
+        "rhs": (ctx.field("rhs"), out["rhs"]),
+        "dii": (ctx.field("dii"), out["diag"]),
+    }
+    if case.n_wall:
+        fields["wall_u_slip"] = (ctx.field("wall_ustar"), out["usw"])
+        fields["normals"] = (ctx.field("normal"), ref.nrm)
+    ctx.correct()
+    fields["unew"] = (ctx.field("unew"), out["unew"])
+    s = ctx.read_state()
+    fields["p"] = (s["p"], ref.p)
+    fields["u_tilde"] = (s["ut"], ref.ut)
+    fields["displacement"] = (s["x"][:case.n_fluid] - case.x[:case.n_fluid], ref.x[:case.n_fluid] - case.x[:case.n_fluid])
+    for k, (g, o) in fields.items():
+        e = rel(g, o)
+        say(f"  {k:14s} rel L2 {e:.3e}")
+        assert e < FP64_TOL, k
+    assert st["iters"] == out["iters"]
+    assert math.isclose(st["lam"], out["lam"], rel_tol=1e-9)
+    assert np.array_equal(ctx.field("fs"), out["fs"].astype(float))
+    ctx.close()
+
+
+def test_taylor_green_50_steps_fp64():
+    """C1: 50x50, quintic h = dx, Re = 100, tol 1e-4, 50 steps, FP64."""
+    sisph = _gpu()
+    case = cases.taylor_green(50)
+    ref = oracle.Sim(case)
+    ctx = sisph.Context(case)
+    u0 = np.linalg.norm(case.u, axis=1).max()
+    worst = 0.0
+    for k in range(50):
+        o = ref.step()
+        g = ctx.step(1)[0]
+        assert g["iters"] == o["iters"], f"step {k}"
+        s = ctx.read_state()
+        a = np.linalg.norm(s["u"], axis=1).max() / u0
+        b = np.linalg.norm(ref.u, axis=1).max() / u0
+        worst = max(worst, abs(a - b) / b)
+    say("  |u|max series worst rel diff", worst)
+    assert worst < 1e-4
+    s = ctx.read_state()
+    assert rel(s["u"], ref.u) < FP64_TOL
+    ctx.close()
+
+
+def test_dam_break_steps_fp64():
+    sisph = _gpu()
+    case = cases.dam_break_2d(dx=0.05, precision="fp64")
+    ref = oracle.Sim(case)
+    ctx = sisph.Context(case)
+    for k in range(20):
+        o = ref.step()
+        g = ctx.step(1)[0]
+        assert g["iters"] == o["iters"], f"step {k}"
+    s = ctx.read_state()
+    assert rel(s["p"], ref.p) < FP64_TOL
+    assert rel(s["u"], ref.u) < FP64_TOL
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["tg50_quintic", "db2d_dx0.05"])
+def test_mixed_precision_single_step(name):
+    """Mixed mode against the FP64 oracle with the oracle run on the GPU's
+    sweep count (the ratio test may flip one sweep earlier or later)."""
+    sisph = _gpu()
+    case = _cases_small()[name].replace(precision="mixed")
+    ctx = sisph.Context(case)
+    g = ctx.step(1)[0]
+    ref = oracle.Sim(case, forced_iters=g["iters"])
+    out = ref.step(capture=True)
+    s = ctx.read_state()
+    errs = {
+        "rho": rel(ctx.field("rho"), out["rho"]),
+        "rhs": rel(ctx.field("rhs"), out["rhs"]),
+        "dii": rel(ctx.field("dii"), out["diag"]),
+        "p": rel(s["p"], ref.p),
+        "u": rel(s["u"], ref.u),
+        "displacement": rel(s["x"][:case.n_fluid] - case.x[:case.n_fluid],
+                            ref.x[:case.n_fluid] - case.x[:case.n_fluid]),
+    }
+    for k, e in errs.items():
+        say(f"  mixed {name} {k:12s} rel L2 {e:.3e}")
+    assert errs["rho"] < 1e-6 and errs["dii"] < 1e-5
+    assert errs["u"] < 1e-4 and errs["displacement"] < 1e-4
+    assert errs["rhs"] < 1e-3 and errs["p"] < 1e-3
+    ctx.close()
+
+
+def test_error_paths():
+    sisph = _gpu()
+    case = cases.taylor_green(16)
+    ctx = sisph.Context(case)
+    with pytest.raises(sisph.SisphError) as e:
+        ctx.predict()
+    assert e.value.code == sisph.E_STATE
+    ctx.close()
+    ctx = sisph.Context(case.replace(tol=1e-300, max_iter=3))
+    st = ctx.step(1)[0]
+    assert st["iters"] == 3 and st["status"] == sisph.WARN_MAXITER
+    ctx.close()
+    bad = case.copy()
+    bad.u[5, 0] = np.nan
+    ctx = sisph.Context(bad)
+    with pytest.raises(sisph.SisphError) as e:
+        ctx.step(1)
+    assert e.value.code == sisph.E_NONFINITE
+    ctx.close()
+
+
+def test_eisph_single_sweep_matches_oracle():
+    """forced one sweep (EISPH) on both sides."""
+    sisph = _gpu()
+    case = cases.taylor_green(30, jitter=0.1, seed=4).replace(forced_iters=1)
+    ref = oracle.Sim(case)
+    ctx = sisph.Context(case)
+    for _ in range(3):
+        assert ref.step()["iters"] == 1 and ctx.step(1)[0]["iters"] == 1
+    s = ctx.read_state()
+    assert rel(s["p"], ref.p) < FP64_TOL and rel(s["u"], ref.u) < FP64_TOL
+    ctx.close()
+
+
+def test_save_restore_bitwise():
+    """20 steps == 10 steps, read_state, write_state, 10 steps (same context)."""
+    sisph = _gpu()
+    case = cases.dam_break_2d(dx=0.05, precision="mixed")
+    a = sisph.Context(case)
+    a.step(20)
+    b = sisph.Context(case)
+    b.step(10)
+    s = b.read_state()
+    b.write_state(x=s["x"], u=s["u"], ut=s["ut"], p=s["p"])
+    b.step(10)
+    sa, sb = a.read_state(), b.read_state()
+    for k in ("x", "u", "ut", "p"):
+        assert np.array_equal(sa[k], sb[k]), k
+    a.close()
+    b.close()
