@@ -568,8 +568,11 @@ void orc_wall_normals(const orc_params *P, const double *x, const double *m, dou
             double W = orc_W(P->kernel, dim, sqrt(norm2(dim, d)), P->h);
             for (int k = 0; k < dim; ++k) a[k] += m[j] / P->rho0 * ns[(j - nf) * dim + k] * W;
         }
+        /* a smoothed normal that is only the rounding residue of opposite
+         * layers cancelling (length below 1e-9, against ~1 for a real
+         * surface) has no direction: it is set to zero (reading R7) */
         double mag = sqrt(dot(dim, a, a));
-        for (int k = 0; k < dim; ++k) nrm[w * dim + k] = mag > 0.0 ? a[k] / mag : 0.0;
+        for (int k = 0; k < dim; ++k) nrm[w * dim + k] = mag > 1e-9 ? a[k] / mag : 0.0;
     }
     free(ns);
     csr_free(&N);
