@@ -454,7 +454,7 @@ __global__ void k_wall_normals(Params P, Pos x, const double *m, const uint32_t 
     for (int k = 0; k < D; ++k) {
         double v;
         if (pass == 0) v = mag < 1.0 / (4.0 * P.h) ? 0.0 : a[k] / mag;
-        else v = mag > 0.0 ? a[k] / mag : 0.0;
+        else v = mag > 1e-9 ? a[k] / mag : 0.0;   // cancellation residue: no direction
         out.c[k][w] = v;
     }
 }
