@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the SISPH hot path on one MI355X.
+
+A step is one full SISPH time step (binning, predictor, PPE solve,
+correction, GTVF, advance) through the C ABI on a seeded synthetic case whose
+particles are already resident in HBM.  The headline value is whole-job PPE
+throughput: fluid particles x Jacobi sweeps done in the timed steps, divided
+by the wall-clock of those steps (bracketed by device synchronisation).
+
+The JSON line also carries the roofline of the dominant kernel (the Jacobi
+sweep), timed live with HIP events on the library's stream, and the CPU
+oracle's rate on a bounded sample of the same case.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PPE particle-iters/s + HBM GB/s frac; batched vs plain at equal tol; p99 step"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (builder, description)
+    "tg400_wendland_mixed": "2D Taylor-Green, periodic unit square, 400x400 lattice (160,000 particles), "
+                            "+-1% seeded jitter, Wendland C2 h=1.3dx, Re=100, tol 1e-4, FP32 sums / FP64 "
+                            "residual and positions",
+    "tg400_wendland_fp64": "same case, all sums FP64",
+    "tg50_quintic_fp64": "2D Taylor-Green 50x50, quintic h=dx, Re=100, tol 1e-4, FP64",
+    "db2d_dx0.005_mixed": "2D dam break 1x2 column in a 4x4 tank, dx=0.005 (80,000 fluid + 7,218 wall), "
+                          "Wendland h=1.3dx, tol 1e-3, mixed",
+}
+
+
+def make_case(name: str):
+    from paper_1908_01762_amd import cases
+    if name == "tg400_wendland_mixed":
+        return cases.taylor_green(400, kernel="wendland", hdx=1.3, precision="mixed", tol=1e-4)
+    if name == "tg400_wendland_fp64":
+        return cases.taylor_green(400, kernel="wendland", hdx=1.3, precision="fp64", tol=1e-4)
+    if name == "tg50_quintic_fp64":
+        return cases.taylor_green(50)
+    if name == "db2d_dx0.005_mixed":
+        return cases.dam_break_2d(dx=0.005, precision="mixed", tol=1e-3)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def sweep_bytes(case, slots: int) -> dict:
+    """Algorithmic HBM bytes of one Jacobi sweep over the whole case.
+
+    Per fluid row: neighbour count (4 B), RHS and D_ii (8 + 8), free-surface
+    flag (4), own iterate (8), new iterate (8); mixed adds the FP32 copy of
+    the new iterate (4) and reads neighbours' FP32 iterate once (4), FP64
+    reads it once (8).  Per stored pair (self slot excluded): neighbour index
+    (4) and cached coefficient (4 mixed, 8 FP64).  Walls: per wall row, count,
+    its pressure written; per wall pair, index (4).
+    """
+    nf = case.n_fluid
+    pairs = slots - nf
+    mixed = case.precision == "mixed"
+    row = 4 + 8 + 8 + 4 + 8 + 8 + (4 + 4 if mixed else 8)
+    pair = 4 + (4 if mixed else 8)
+    total = nf * row + pairs * pair
+    return dict(per_row=row, per_pair=pair, pairs=int(pairs), bytes=int(total))
+
+
+def traffic_from_profiles(kernel_src_sha: str, workload: str):
+    """HBM traffic per sweep from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"ppe_sweep_{workload}_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    t = re.search(r"hbm_bytes_per_sweep:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != kernel_src_sha:
+        return None
+    return float(t.group(1))
+
+
+def kernel_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1908_01762_amd", "csrc", "sisph_kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def cpu_baseline(case, budget_s: float) -> dict:
+    """The FP64 oracle (serial C) on the first steps of the same case, for
+    about budget_s seconds of CPU work (at least one step)."""
+    import oracle
+    sim = oracle.Sim(case)
+    t0 = time.perf_counter()
+    iters = steps = 0
+    while True:
+        out = sim.step()
+        iters += out["iters"]
+        steps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": case.n_fluid * iters / dt, "unit": "particle-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {steps} step(s) of the same case ({iters} Jacobi sweeps, {case.n_fluid} fluid "
+                      f"particles), {dt:.1f} s on one host core; serial FP64 C oracle",
+            "particle_steps_per_s": case.n_fluid * steps / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=195)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="tg400_wendland_mixed", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1908_01762_amd import sisph
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    sisph.lib()
+    case = make_case(args.workload)
+    ctx = sisph.Context(case, device="cuda:0")
+    print(f"[bench] workload {args.workload}: {case.n_fluid} fluid + {case.n_wall} wall particles, "
+          f"workspace {ctx.nbytes / 1e6:.1f} MB", file=sys.stderr, flush=True)
+    if args.warmup:
+        ctx.step(args.warmup)
+    torch.cuda.synchronize()
+    ctx.sweep_counters(reset=True)
+    t0 = time.perf_counter()
+    stats = ctx.step(args.steps) if args.steps > 0 else []
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    iters = sum(s["iters"] for s in stats)
+    value = case.n_fluid * iters / elapsed if elapsed > 0 else 0.0
+    cnt = ctx.sweep_counters()
+    off, _ = ctx.neighbors(1, 0)
+    sb = sweep_bytes(case, int(off[-1]))
+    avg_launch_s = cnt["sweep_ms"] / 1e3 / max(cnt["launches"], 1)
+    achieved = sb["bytes"] * cnt["effective"] / (cnt["sweep_ms"] / 1e3) / 1e9 if cnt["sweep_ms"] > 0 else 0.0
+    traffic = traffic_from_profiles(kernel_sha(), args.workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_ppe_sweep", "avg_launch_us": round(avg_launch_s * 1e6, 3),
+                "launches": cnt["launches"], "effective_launches": cnt["effective"],
+                "algorithmic_bytes_per_launch": sb["bytes"], "bytes_per_row": sb["per_row"],
+                "bytes_per_pair": sb["per_pair"], "pairs": sb["pairs"]}
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / max(args.steps, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if case.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
+                   "fluid_particles": case.n_fluid, "wall_particles": case.n_wall,
+                   "parallelism": "single GPU"},
+        "mean_ppe_iters": iters / max(len(stats), 1),
+        "particle_steps_per_s": case.n_fluid * args.steps / elapsed if elapsed > 0 else 0.0,
+        "sweep_time_frac": cnt["sweep_ms"] / 1e3 / elapsed if elapsed > 0 else 0.0,
+        "roofline": roofline,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(make_case(args.workload), args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -164,6 +164,14 @@ int32_t sisph_debug_neighbors(sisph_ctx *ctx, int32_t stage, int32_t dest,
  * context's stream, and of the whole last step (milliseconds). */
 int32_t sisph_last_timings(sisph_ctx *ctx, double *ppe_ms, double *step_ms);
 
+/* Accumulated since the last reset: HIP-event time of the Jacobi sweep
+ * chunks (each chunk = sweeps queued back to back, with the wall-pressure
+ * kernel of each sweep when the case has walls), the number of sweep
+ * launches, and the number of launches that did a sweep (the rest found
+ * the solve already finished).  reset != 0 clears after reading. */
+int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_t *launches,
+                             int64_t *effective, int32_t reset);
+
 int32_t sisph_destroy(sisph_ctx *ctx);
 const char *sisph_status_string(int32_t status);
 /* Last error message of this context (or of the last failed create). */

@@ -228,7 +228,7 @@ def wall_velocity(case, x, u_fluid, nrm, slip: bool, wall_u=None) -> np.ndarray:
 class Sim:
     """Oracle state of one case, advanced one SISPH step at a time."""
 
-    def __init__(self, case, forced_iters: int = 0):
+    def __init__(self, case, forced_iters: Optional[int] = None):
         self.case = case
         self.x = case.x.copy()
         self.u = case.u.copy()
@@ -239,7 +239,7 @@ class Sim:
         self.nrm = wall_normals(case) if case.n_wall else np.zeros((0, case.dim))
         self.p_ref = C.c_double(case.p_ref)
         self.p_ref_set = C.c_int64(1 if case.p_ref_mode == "fixed" else 0)
-        self.forced_iters = forced_iters
+        self.forced_iters = case.forced_iters if forced_iters is None else forced_iters
         self.t = 0.0
         self.steps = 0
 

@@ -26,7 +26,10 @@ struct sisph_ctx {
     int last_iters;
     Control *h_ctl;     // pinned mirror of the control block
     hipEvent_t ev[4];
+    hipEvent_t evc[2];  // brackets one chunk of back-to-back sweeps
     double ppe_ms, step_ms;
+    double sweep_ms;
+    int64_t sweep_launches, sweep_effective;
     bool step_timed;
     std::string err;
 };
@@ -198,10 +201,11 @@ static void carve(const Params &P, Carver &c, State &S) {
     S.cnt = c.take<int32_t>(nf);
     S.wnbr = c.take<int32_t>((int64_t)P.cap * nw);
     S.wcnt = c.take<int32_t>(nw);
-    const size_t csz = P.precision == SISPH_MIXED ? sizeof(float) : sizeof(double);
+    // mixed: (index, FP32 c_ij) 8-byte words; FP64: FP64 c_ij (indices from nbr)
+    const size_t csz = 8;
     S.coef = c.take<char>((int64_t)csz * P.cap * nf);
     S.nblk_f = (nf + kBlock - 1) / kBlock;
-    S.partial = c.take<double>(2 * S.nblk_f);
+    S.partial = c.take<double>(4 * S.nblk_f);
     S.tmp = c.take<double>(16 * nmax);
     S.ctl = c.take<Control>(1);
 }
@@ -282,6 +286,8 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
     ctx->final_parity = 0;
     ctx->last_iters = desc->min_iter;
     ctx->ppe_ms = ctx->step_ms = 0.0;
+    ctx->sweep_ms = 0.0;
+    ctx->sweep_launches = ctx->sweep_effective = 0;
     ctx->step_timed = false;
     Carver c{(char *)d_workspace};
     carve(ctx->P, c, ctx->S);
@@ -290,6 +296,8 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
         if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
         for (auto &e : ctx->ev)
             if (e) (void)hipEventDestroy(e);
+        for (auto &e : ctx->evc)
+            if (e) (void)hipEventDestroy(e);
         delete ctx;
         return code;
     };
@@ -297,6 +305,12 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
         ctx->err = "hipHostMalloc failed";
         ctx->h_ctl = nullptr;
         return bail(SISPH_E_DEVICE);
+    }
+    for (auto &e : ctx->evc) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            ctx->err = "hipEventCreate failed";
+            return bail(SISPH_E_DEVICE);
+        }
     }
     for (auto &e : ctx->ev) {
         if (hipEventCreate(&e) != hipSuccess) {
@@ -436,19 +450,29 @@ extern "C" int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out) {
     reset_control(S.ctl, RESET_PPE, s);
     rhs_coef(P, S, s);
     if (P.precision == SISPH_MIXED) copy_p32(P, S, s);
-    int chunk = P.forced_iters > 0 ? P.forced_iters : std::max(P.min_iter, ctx->last_iters);
-    chunk = std::min(chunk, P.forced_iters > 0 ? P.forced_iters : P.max_iter);
+    // Launch L sweeps iterate L (L = 0, 1, ...) unless the solve already
+    // stopped; the stopping decision for L sweeps is taken at the start of
+    // launch L, so a chunk ends with one launch beyond the predicted count.
+    const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1;
+    int64_t chunk = (P.forced_iters > 0 ? P.forced_iters : std::max(P.min_iter, ctx->last_iters)) + 1;
+    chunk = std::min(chunk, limit);
     int64_t launched = 0;
-    const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter);
     for (;;) {
-        for (int c = 0; c < chunk; ++c) ppe_iteration(P, S, s);
+        const int before = launched == 0 ? 0 : ctx->h_ctl->iter;
+        HIPCHK(ctx, hipEventRecord(ctx->evc[0], s));
+        for (int64_t c = 0; c < chunk; ++c) ppe_iteration(P, S, (int)(launched + c), s);
+        HIPCHK(ctx, hipEventRecord(ctx->evc[1], s));
         launched += chunk;
         HIPCHK(ctx, hipGetLastError());
         int32_t st = read_ctl(ctx);
         if (st != SISPH_OK) return st;
+        float cms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&cms, ctx->evc[0], ctx->evc[1]));
+        ctx->sweep_ms += cms;
+        ctx->sweep_launches += chunk;
+        ctx->sweep_effective += ctx->h_ctl->iter - before;
         if (ctx->h_ctl->done || launched >= limit) break;
-        int64_t left = limit - ctx->h_ctl->iter;
-        chunk = (int)std::min<int64_t>(std::min<int64_t>(2 * (int64_t)chunk, 64), left);
+        chunk = std::min<int64_t>(std::min<int64_t>(2 * chunk, 64), limit - launched);
         if (chunk < 1) chunk = 1;
     }
     const int iters = ctx->h_ctl->iter;
@@ -704,11 +728,26 @@ extern "C" int32_t sisph_last_timings(sisph_ctx *ctx, double *ppe_ms, double *st
     return SISPH_OK;
 }
 
+extern "C" int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_t *launches, int64_t *effective,
+                                        int32_t reset) {
+    if (!ctx) return SISPH_E_INVAL;
+    if (sweep_ms) *sweep_ms = ctx->sweep_ms;
+    if (launches) *launches = ctx->sweep_launches;
+    if (effective) *effective = ctx->sweep_effective;
+    if (reset) {
+        ctx->sweep_ms = 0.0;
+        ctx->sweep_launches = ctx->sweep_effective = 0;
+    }
+    return SISPH_OK;
+}
+
 extern "C" int32_t sisph_destroy(sisph_ctx *ctx) {
     if (!ctx) return SISPH_E_INVAL;
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
     for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : ctx->evc)
         if (e) (void)hipEventDestroy(e);
     delete ctx;
     return SISPH_OK;

@@ -78,7 +78,7 @@ struct State {
     int32_t *nbr, *cnt;     // fluid rows: fluid + wall sources
     int32_t *wnbr, *wcnt;   // wall rows: fluid sources
     void *coef;             // cached PPE c_ij, float (mixed) or double [cap][nf]
-    double *partial;        // per-workgroup partial sums [2 * nblk]
+    double *partial;        // per-workgroup partial sums, two sweeps [2][2][nblk]
     double *tmp;            // reorder scratch [ntot]
     Control *ctl;
     int64_t nblk_f;         // workgroups of a fluid launch
@@ -109,7 +109,7 @@ void wall_velocity(const Params &P, const double *const pos[3], const double *co
                    double *const uw[3], int slip, State &S, hipStream_t s);
 void predictor(const Params &P, State &S, hipStream_t s);
 void rhs_coef(const Params &P, State &S, hipStream_t s);
-void ppe_iteration(const Params &P, State &S, hipStream_t s);
+void ppe_iteration(const Params &P, State &S, int launch, hipStream_t s);
 void wall_pressure_final(const Params &P, State &S, hipStream_t s);
 void pressure_max(const Params &P, State &S, int final_parity, hipStream_t s);
 void correct(const Params &P, State &S, int final_parity, hipStream_t s);

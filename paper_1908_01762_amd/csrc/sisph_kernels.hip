@@ -200,6 +200,16 @@ __global__ void k_reset_control(Control *c, int what) {
     }
 }
 
+// atomicMax that skips the atomic when a (possibly stale) read of the
+// monotonically growing target already covers v: most threads then issue a
+// plain load instead of contending on one address.
+__device__ __forceinline__ void max_if_larger(int32_t *t, int32_t v) {
+    if (v > __hip_atomic_load(t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(t, v);
+}
+__device__ __forceinline__ void max_if_larger(unsigned long long *t, unsigned long long v) {
+    if (v > __hip_atomic_load(t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(t, v);
+}
+
 // ----------------------------------------------------------------- binning
 template <int D>
 __global__ void k_bin_keys(Grid g, Pos x, int64_t base, int64_t n, uint32_t *count, uint32_t *key,
@@ -365,8 +375,10 @@ __global__ void k_build_fluid(Params P, Pos x, const int32_t *items, const uint3
                     }
                 }
             }
-    if (c > cap) atomicOr(&ctl->overflow, 1);
-    atomicMax(&ctl->maxcnt, c);
+    if (c > cap) {
+        atomicOr(&ctl->overflow, 1);
+        atomicMax(&ctl->maxcnt, c);
+    }
     cnt[i] = c < cap ? c : cap;
 }
 
@@ -402,8 +414,10 @@ __global__ void k_build_wall(Params P, Pos x, const int32_t *items, const uint32
                     }
                 }
             }
-    if (c > cap) atomicOr(&ctl->overflow, 1);
-    atomicMax(&ctl->maxcnt, c);
+    if (c > cap) {
+        atomicOr(&ctl->overflow, 1);
+        atomicMax(&ctl->maxcnt, c);
+    }
     cnt[w] = c < cap ? c : cap;
 }
 
@@ -593,49 +607,78 @@ __global__ void k_predictor(Params P, Pos x, Pos u, Pos ut, const double *m, con
     }
 }
 
+// ------------------------------------------------------- wave reductions
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Cached pair of the mixed-precision sweep: neighbour index and FP32 c_ij
+// in one 8-byte word, slot-major [cap][nf] like the neighbour lists.
+struct PairF {
+    int32_t j;
+    float c;
+};
+template <typename R>
+struct CoefSlot;
+template <>
+struct CoefSlot<float> {
+    using T = PairF;
+};
+template <>
+struct CoefSlot<double> {
+    using T = double;
+};
+
 // ------------------------------------------------- PPE RHS and coefficients
 // eq. sph-ppe / coeff / coeff1 at r*: RHS_i = sum -m_j/(rho_j dt) u*_ij.gradW,
 // c_ij = 4 m_j / (rho_i (rho_i + rho_j)) (r_ij.gradW) / (r^2 + eta h^2),
 // D_ii = sum_j c_ij (r^2 + eta h^2, not "+ eta^2").  c_ij is stored in list
-// order for the sweeps; Lambda = max |RHS/D| over non-free-surface rows.
+// order for the sweeps (with its neighbour index in the mixed mode);
+// Lambda = max |RHS/D| over non-free-surface rows (wave max, then one
+// atomic per wavefront).
 template <int KER, int D, typename R>
 __global__ void k_rhs_coef(Params P, Pos xs, Pos us, const double *m, const double *rho, const int32_t *fs,
-                           const int32_t *nbr, const int32_t *cnt, R *coef, double *rhs, double *dii,
-                           Control *ctl) {
+                           const int32_t *nbr, const int32_t *cnt, typename CoefSlot<R>::T *coef, double *rhs,
+                           double *dii, Control *ctl) {
     const int64_t i = gid_xcd();
-    if (i >= P.nf) return;
-    Kern<KER, D, R> K(P.h);
     const int64_t nf = P.nf;
-    double xi[3] = {0, 0, 0};
-    R usi[3] = {0, 0, 0};
-    for (int k = 0; k < D; ++k) {
-        xi[k] = xs.c[k][i];
-        usi[k] = (R)us.c[k][i];
+    unsigned long long lam = 0ull;
+    if (i < nf) {
+        Kern<KER, D, R> K(P.h);
+        double xi[3] = {0, 0, 0};
+        R usi[3] = {0, 0, 0};
+        for (int k = 0; k < D; ++k) {
+            xi[k] = xs.c[k][i];
+            usi[k] = (R)us.c[k][i];
+        }
+        const R rhoi = (R)rho[i], eps = (R)P.eps_h, inv_dt = (R)(1.0 / P.dt);
+        R s = R(0), Dg = R(0);
+        const int c = cnt[i];
+        for (int k = 1; k < c; ++k) {
+            int64_t j = nbr[(int64_t)k * nf + i];
+            R d[3], r2;
+            pair_diff<D, R>(P.grid, xi, xs, j, d, r2);
+            R dw = K.dwr(sqrt(r2));
+            R mj = (R)m[j], rhoj = (R)rho[j];
+            R dot = R(0);
+            for (int a = 0; a < D; ++a) dot += (usi[a] - (R)us.c[a][j]) * d[a];
+            s -= mj / rhoj * inv_dt * dw * dot;
+            R cij = R(4) * mj / (rhoi * (rhoi + rhoj)) * (dw * r2) / (r2 + eps);
+            if constexpr (sizeof(R) == 4) coef[(int64_t)k * nf + i] = PairF{(int32_t)j, cij};
+            else coef[(int64_t)k * nf + i] = cij;
+            Dg += cij;
+        }
+        double rr = (double)s, dd = (double)Dg;
+        rhs[i] = rr;
+        dii[i] = dd;
+        if (dd != 0.0 && !fs[i]) lam = (unsigned long long)__double_as_longlong(fabs(rr / dd));
     }
-    const R rhoi = (R)rho[i], eps = (R)P.eps_h, inv_dt = (R)(1.0 / P.dt);
-    R s = R(0), Dg = R(0);
-    const int c = cnt[i];
-    coef[i] = R(0);
-    for (int k = 1; k < c; ++k) {
-        int64_t j = nbr[(int64_t)k * nf + i];
-        R d[3], r2;
-        pair_diff<D, R>(P.grid, xi, xs, j, d, r2);
-        R dw = K.dwr(sqrt(r2));
-        R mj = (R)m[j], rhoj = (R)rho[j];
-        R dot = R(0);
-        for (int a = 0; a < D; ++a) dot += (usi[a] - (R)us.c[a][j]) * d[a];
-        s -= mj / rhoj * inv_dt * dw * dot;
-        R cij = R(4) * mj / (rhoi * (rhoi + rhoj)) * (dw * r2) / (r2 + eps);
-        coef[(int64_t)k * nf + i] = cij;
-        Dg += cij;
-    }
-    double rr = (double)s, dd = (double)Dg;
-    rhs[i] = rr;
-    dii[i] = dd;
-    if (dd != 0.0 && !fs[i]) {
-        double v = fabs(rr / dd);
-        atomicMax(&ctl->lambda_bits, (unsigned long long)__double_as_longlong(v));
-    }
+    lam = wave_max_u64(lam);   // non-negative doubles order like their bits
+    if ((threadIdx.x & 63) == 0 && lam) max_if_larger(&ctl->lambda_bits, lam);
 }
 
 // ------------------------------------------------------- block reductions
@@ -665,91 +708,203 @@ __device__ __forceinline__ void block_sum2(double &a, double &b) {
     }
 }
 
-// The last workgroup to arrive sums the per-workgroup partials in index
-// order (deterministic) and applies the stopping rule of eq. convergence.
-__device__ void finish_sweep(const Params &P, double *partial, int64_t nblk, Control *ctl, int iter) {
-    __shared__ bool last;
-    __threadfence();
-    if (threadIdx.x == 0) {
-        uint32_t t = atomicAdd(&ctl->ticket, 1u);
-        last = (t == (uint32_t)(nblk - 1));
+// Stopping rule of eq. convergence after L sweeps, from the per-workgroup
+// partial sums of sweep L-1.  Every workgroup of the next launch sums the
+// same partials in the same order, so all reach the same decision without
+// any cross-workgroup synchronisation (the kernel boundary makes the
+// partials visible).  The partials are loaded into registers before the
+// workgroup's own row work (kPartialRegs per thread and array when they fit)
+// so their latency overlaps it; stopped_after() then reduces and decides.
+// Workgroup 0 records the result.
+constexpr int kPartialRegs = 8;
+
+struct PartialLoad {
+    double a[kPartialRegs], b[kPartialRegs];
+};
+
+__device__ __forceinline__ void load_partials(const double *partial, int64_t nblk, int L, PartialLoad &pl) {
+    const double *pa = partial + (int64_t)((L - 1) & 1) * 2 * nblk;
+#pragma unroll
+    for (int t = 0; t < kPartialRegs; ++t) {
+        const int64_t k = threadIdx.x + (int64_t)t * kBlock;
+        pl.a[t] = k < nblk ? pa[k] : 0.0;
+        pl.b[t] = k < nblk ? pa[nblk + k] : 0.0;
+    }
+}
+
+__device__ bool stopped_after(const Params &P, const double *partial, int64_t nblk, int L, const PartialLoad &pl,
+                              int done0, double lam, Control *ctl) {
+    __shared__ double sh[2][kBlock / 64];
+    __shared__ int stop_sh;
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int t = 0; t < kPartialRegs; ++t) {
+        a += pl.a[t];
+        b += pl.b[t];
+    }
+    if (nblk > (int64_t)kPartialRegs * kBlock) {   // large grids: the rest, in order
+        const double *pa = partial + (int64_t)((L - 1) & 1) * 2 * nblk;
+        for (int64_t k = threadIdx.x + (int64_t)kPartialRegs * kBlock; k < nblk; k += kBlock) {
+            a += pa[k];
+            b += pa[nblk + k];
+        }
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[0][wv] = a;
+        sh[1][wv] = b;
     }
     __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double a = 0.0, b = 0.0;
-    for (int64_t k = threadIdx.x; k < nblk; k += kBlock) {
-        a += __hip_atomic_load(&partial[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        b += __hip_atomic_load(&partial[nblk + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    block_sum2(a, b);
-    if (threadIdx.x == 0) {
-        double lam = __longlong_as_double((long long)ctl->lambda_bits);
-        if (P.conv_norm == SISPH_CONV_MEAN) lam *= (double)P.nf;
-        double scale = lam > b ? lam : b;
-        double ratio = scale > 0.0 ? a / scale : (a > 0.0 ? INFINITY : 0.0);
-        int k = iter + 1;
-        bool bad = !isfinite(a) || !isfinite(b);
-        bool stop;
-        if (P.forced_iters > 0) stop = k >= P.forced_iters;
-        else stop = (k >= P.min_iter && ratio < P.tol) || k >= P.max_iter;
-        if (bad) {
-            ctl->nonfinite = 1;
-            stop = true;
+    if (threadIdx.x == 0 && done0) {
+        stop_sh = 1;   // sticky: an earlier launch stopped the solve
+    } else if (threadIdx.x == 0) {
+        a = 0.0;
+        b = 0.0;
+        for (int t = 0; t < kBlock / 64; ++t) {
+            a += sh[0][t];
+            b += sh[1][t];
         }
-        ctl->num = a;
-        ctl->den = b;
-        ctl->ratio = ratio;
-        ctl->iter = k;
-        ctl->done = stop ? 1 : 0;
-        ctl->ticket = 0u;
-        __threadfence();
+        if (P.conv_norm == SISPH_CONV_MEAN) lam *= (double)P.nf;
+        const double scale = lam > b ? lam : b;
+        const double ratio = scale > 0.0 ? a / scale : (a > 0.0 ? INFINITY : 0.0);
+        const bool bad = !isfinite(a) || !isfinite(b);
+        bool stop;
+        if (P.forced_iters > 0) stop = L >= P.forced_iters;
+        else stop = (L >= P.min_iter && ratio < P.tol) || L >= P.max_iter;
+        stop = stop || bad;
+        stop_sh = stop ? 1 : 0;
+        if (blockIdx.x == 0) {
+            ctl->num = a;
+            ctl->den = b;
+            ctl->ratio = ratio;
+            if (bad) ctl->nonfinite = 1;
+            if (stop) {
+                ctl->iter = L;
+                ctl->done = 1;
+            }
+        }
     }
+    __syncthreads();
+    return stop_sh != 0;
 }
 
 // ------------------------------------------------------------- PPE sweep
 // eq. p-sor with omega: p_i^{k+1} = w (RHS_i + sum_j c_ij p_j^k) / D_ii
 // + (1 - w) p_i^k; p = 0 where D_ii = 0 or on free-surface rows (section 3).
-// Double-buffered (Jacobi): reads iterate k, writes k+1.  In the mixed
-// mode the neighbour sum reads the FP32 copy of iterate k.
+// Double-buffered (Jacobi): reads iterate k, writes k+1.  The neighbour sum
+// is taken in batches of kSweepBatch slots whose loads are all issued
+// before the first is used (the sum still runs in slot order).  Mixed: the
+// cached (j, c_ij) words and the FP32 copy of iterate k; FP64: indices,
+// FP64 coefficients and iterate k.
+// First batch: slots 1..kSweepFirst loaded without waiting for the row's
+// count (every slot below cap is inside the list storage; slots past the
+// count hold stale words and are discarded by the select), so the row loads,
+// these loads and the partial-sum loads form one round trip.  Longer rows
+// continue in batches of kSweepBatch.
+constexpr int kSweepFirst = 24;
+constexpr int kSweepBatch = 8;
+
+template <typename R, int NB>
+__device__ __forceinline__ void load_batch(int64_t i, int64_t nf, int k0, int c, int cap, bool blind,
+                                           const typename CoefSlot<R>::T *coef, const int32_t *nbr,
+                                           int32_t (&jj)[NB], R (&cc)[NB]) {
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        const int k = k0 + t;
+        int ks = blind ? (k < cap ? k : cap - 1) : (k < c ? k : c - 1);
+        const int64_t at = (int64_t)ks * nf + i;
+        int32_t j;
+        R cf;
+        if constexpr (sizeof(R) == 4) {
+            const PairF w = coef[at];
+            j = w.j;
+            cf = w.c;
+        } else {
+            j = nbr[at];
+            cf = coef[at];
+        }
+        jj[t] = j;
+        cc[t] = cf;
+    }
+}
+
+template <typename R, int NB>
+__device__ __forceinline__ R gather_sum(int64_t i, int k0, int c, const int32_t (&jj)[NB], const R (&cc)[NB],
+                                        const double *pc, const float *qc, R s) {
+    R pv[NB];
+    int32_t js[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) js[t] = (k0 + t < c) ? jj[t] : (int32_t)i;
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        if constexpr (sizeof(R) == 4) pv[t] = qc[js[t]];
+        else pv[t] = pc[js[t]];
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) s += ((k0 + t < c) ? cc[t] : R(0)) * pv[t];
+    return s;
+}
+
 template <typename R>
-__global__ void k_ppe_sweep(Params P, double *p0, double *p1, float *q0, float *q1, const R *coef,
-                            const int32_t *nbr, const int32_t *cnt, const double *rhs, const double *dii,
-                            const int32_t *fs, double *partial, Control *ctl) {
-    if (ctl->done) return;
-    const int iter = ctl->iter;
-    const double *pc = (iter & 1) ? p1 : p0;
-    double *pn = (iter & 1) ? p0 : p1;
-    const float *qc = (iter & 1) ? q1 : q0;
-    float *qn = (iter & 1) ? q0 : q1;
+__global__ void k_ppe_sweep(Params P, int L, double *p0, double *p1, float *q0, float *q1,
+                            const typename CoefSlot<R>::T *coef, const int32_t *nbr, const int32_t *cnt,
+                            const double *rhs, const double *dii, const int32_t *fs, double *partial,
+                            Control *ctl) {
+    // L = sweeps completed before this launch (the host counts launches).
+    // Whether the solve has already stopped is decided per workgroup behind
+    // a barrier (stopped_after), never per wavefront.
+    const int64_t nblk = gridDim.x;
+    // control values the decision needs, loaded up front: done (set by an
+    // earlier launch, or by workgroup 0 of this one from the same partials,
+    // which gives the same answer) and Lambda (fixed during the solve)
+    const int done0 = __hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double lam = __longlong_as_double((long long)ctl->lambda_bits);
+    PartialLoad pl;
+    if (L > 0) load_partials(partial, nblk, L, pl);
+    const double *pc = (L & 1) ? p1 : p0;
+    double *pn = (L & 1) ? p0 : p1;
+    const float *qc = (L & 1) ? q1 : q0;
+    float *qn = (L & 1) ? q0 : q1;
     const int64_t blk = xcd_block();
     const int64_t i = blk * kBlock + threadIdx.x;
     const int64_t nf = P.nf;
+    double v = 0.0, pold = 0.0;
+    if (i < nf) {
+        // one round trip: row values, the first batch of (j, c) words and
+        // (above) the partial sums
+        int32_t jj[kSweepFirst];
+        R cc[kSweepFirst];
+        load_batch<R, kSweepFirst>(i, nf, 1, 0, P.cap, true, coef, nbr, jj, cc);
+        const double D = dii[i], r = rhs[i];
+        const int32_t f = fs[i], c = cnt[i];
+        pold = pc[i];
+        R s = gather_sum<R, kSweepFirst>(i, 1, c, jj, cc, pc, qc, R(0));
+        for (int k0 = 1 + kSweepFirst; k0 < c; k0 += kSweepBatch) {
+            int32_t jb[kSweepBatch];
+            R cb[kSweepBatch];
+            load_batch<R, kSweepBatch>(i, nf, k0, c, P.cap, false, coef, nbr, jb, cb);
+            s = gather_sum<R, kSweepBatch>(i, k0, c, jb, cb, pc, qc, s);
+        }
+        if (D != 0.0 && !f) v = P.omega * (r + (double)s) / D + (1.0 - P.omega) * pold;
+    }
+    // the decision for L sweeps gates every write of this launch
+    if (L > 0 && stopped_after(P, partial, nblk, L, pl, done0, lam, ctl)) return;
     double a = 0.0, b = 0.0;
     if (i < nf) {
-        const double pold = pc[i], D = dii[i];
-        double v = 0.0;
-        if (D != 0.0 && !fs[i]) {
-            R s = R(0);
-            const int c = cnt[i];
-            for (int k = 1; k < c; ++k) {
-                int64_t j = nbr[(int64_t)k * nf + i];
-                R pj = sizeof(R) == 4 ? (R)qc[j] : (R)pc[j];
-                s += coef[(int64_t)k * nf + i] * pj;
-            }
-            v = P.omega * (rhs[i] + (double)s) / D + (1.0 - P.omega) * pold;
-        }
         pn[i] = v;
-        if (sizeof(R) == 4) qn[i] = (float)v;
+        if constexpr (sizeof(R) == 4) qn[i] = (float)v;
         a = fabs(v - pold);
         b = fabs(v);
     }
     block_sum2(a, b);
     if (threadIdx.x == 0) {
-        partial[blk] = a;
-        partial[gridDim.x + blk] = b;
+        double *pw = partial + (int64_t)(L & 1) * 2 * nblk;
+        pw[blk] = a;
+        pw[nblk + blk] = b;
+        if (blk == 0) ctl->iter = L + 1;
     }
-    finish_sweep(P, partial, gridDim.x, ctl, iter);
 }
 
 // eq. p-shepard: p_w = [sum_f p_f W_wf + (g - a_w) . sum_f rho_f r_wf W_wf]
@@ -757,11 +912,13 @@ __global__ void k_ppe_sweep(Params P, double *p0, double *p1, float *q0, float *
 // neighbours; clamped at 0 on free-surface problems.  Writes the wall slots
 // of the iterate the next sweep reads.
 template <int KER, int D, typename R>
-__global__ void k_wall_pressure(Params P, Pos xs, double *p0, double *p1, float *q0, float *q1,
+__global__ void k_wall_pressure(Params P, int L, Pos xs, double *p0, double *p1, float *q0, float *q1,
                                 const double *rho, const int32_t *wnbr, const int32_t *wcnt, Control *ctl,
                                 int force) {
+    // L: sweeps completed (the iterate the next sweep reads); with force the
+    // final count recorded in the control block is used instead
     if (!force && ctl->done) return;
-    const int iter = ctl->iter;
+    const int iter = force ? ctl->iter : L;
     double *pc = (iter & 1) ? p1 : p0;
     float *qc = (iter & 1) ? q1 : q0;
     const int64_t w = gid_xcd();
@@ -805,7 +962,9 @@ __device__ __forceinline__ double order_val(unsigned long long k) {
 
 __global__ void k_pmax(Params P, const double *p, Control *ctl) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < P.nf) atomicMax(&ctl->pmax_key, order_key(p[i]));
+    unsigned long long k = i < P.nf ? order_key(p[i]) : 0ull;
+    k = wave_max_u64(k);
+    if ((threadIdx.x & 63) == 0 && k) max_if_larger(&ctl->pmax_key, k);
 }
 // p_ref for internal flows: twice the largest pressure after the first
 // solve, then held (section 2.1).
@@ -1029,20 +1188,21 @@ void predictor(const Params &P, State &S, hipStream_t s) {
 
 void rhs_coef(const Params &P, State &S, hipStream_t s) {
     SISPH_DISPATCH_KDR(P, (k_rhs_coef<KER, D, R><<<nblocks(P.nf), kBlock, 0, s>>>(
-                              P, mkpos(S.xs), mkpos(S.us), S.m, S.rho, S.fs, S.nbr, S.cnt, (R *)S.coef, S.rhs,
+                              P, mkpos(S.xs), mkpos(S.us), S.m, S.rho, S.fs, S.nbr, S.cnt,
+                              (typename CoefSlot<R>::T *)S.coef, S.rhs,
                               S.dii, S.ctl)));
 }
 
-void ppe_iteration(const Params &P, State &S, hipStream_t s) {
+void ppe_iteration(const Params &P, State &S, int L, hipStream_t s) {
     float *q0 = S.p32, *q1 = S.p32 + P.ntot;
     if (P.nw > 0)
         SISPH_DISPATCH_KDR(P, (k_wall_pressure<KER, D, R><<<nblocks(P.nw), kBlock, 0, s>>>(
-                                  P, mkpos(S.xs), S.p[0], S.p[1], q0, q1, S.rho, S.wnbr, S.wcnt, S.ctl, 0)));
+                                  P, L, mkpos(S.xs), S.p[0], S.p[1], q0, q1, S.rho, S.wnbr, S.wcnt, S.ctl, 0)));
     if (P.precision == SISPH_MIXED)
-        k_ppe_sweep<float><<<S.nblk_f, kBlock, 0, s>>>(P, S.p[0], S.p[1], q0, q1, (const float *)S.coef, S.nbr,
+        k_ppe_sweep<float><<<S.nblk_f, kBlock, 0, s>>>(P, L, S.p[0], S.p[1], q0, q1, (const PairF *)S.coef, S.nbr,
                                                       S.cnt, S.rhs, S.dii, S.fs, S.partial, S.ctl);
     else
-        k_ppe_sweep<double><<<S.nblk_f, kBlock, 0, s>>>(P, S.p[0], S.p[1], q0, q1, (const double *)S.coef,
+        k_ppe_sweep<double><<<S.nblk_f, kBlock, 0, s>>>(P, L, S.p[0], S.p[1], q0, q1, (const double *)S.coef,
                                                        S.nbr, S.cnt, S.rhs, S.dii, S.fs, S.partial, S.ctl);
 }
 
@@ -1050,7 +1210,7 @@ void wall_pressure_final(const Params &P, State &S, hipStream_t s) {
     if (P.nw <= 0) return;
     float *q0 = S.p32, *q1 = S.p32 + P.ntot;
     SISPH_DISPATCH_KDR(P, (k_wall_pressure<KER, D, R><<<nblocks(P.nw), kBlock, 0, s>>>(
-                              P, mkpos(S.xs), S.p[0], S.p[1], q0, q1, S.rho, S.wnbr, S.wcnt, S.ctl, 1)));
+                              P, 0, mkpos(S.xs), S.p[0], S.p[1], q0, q1, S.rho, S.wnbr, S.wcnt, S.ctl, 1)));
 }
 
 void pressure_max(const Params &P, State &S, int final_parity, hipStream_t s) {

@@ -89,6 +89,8 @@ def lib():
                                             C.POINTER(C.c_int32), C.c_int64]
         L.sisph_last_timings.restype = C.c_int32
         L.sisph_last_timings.argtypes = [C.c_void_p, _DP, _DP]
+        L.sisph_sweep_counters.restype = C.c_int32
+        L.sisph_sweep_counters.argtypes = [C.c_void_p, _DP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int32]
         L.sisph_status_string.restype = C.c_char_p
         L.sisph_status_string.argtypes = [C.c_int32]
         L.sisph_last_error.restype = C.c_char_p
@@ -237,6 +239,11 @@ class Context:
         a, b = C.c_double(), C.c_double()
         _check(lib().sisph_last_timings(self.h, C.byref(a), C.byref(b)), self.h)
         return a.value, b.value
+
+    def sweep_counters(self, reset: bool = False):
+        ms, n, e = C.c_double(), C.c_int64(), C.c_int64()
+        _check(lib().sisph_sweep_counters(self.h, C.byref(ms), C.byref(n), C.byref(e), int(reset)), self.h)
+        return dict(sweep_ms=ms.value, launches=n.value, effective=e.value)
 
     def close(self):
         if getattr(self, "h", None):
