@@ -173,6 +173,31 @@ int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_t *launches
                              int64_t *effective, int32_t reset);
 
 int32_t sisph_destroy(sisph_ctx *ctx);
+
+/* ------------------------------------------------------------- batching
+ * Many independent cases stepped together: every kernel of a step is one
+ * launch over all attached cases that share dimension, kernel and
+ * precision (each workgroup finds its case in a device table), and each
+ * case keeps its own PPE convergence (a converged case's sweeps return at
+ * once).  A case gives the same results alone and in a batch, bit for bit:
+ * its workgroups, sums and decisions do not depend on the other cases.
+ * The batch owns small device tables (allocated here, freed by
+ * sisph_batch_destroy); the cases' workspaces stay with their callers.
+ * Attached contexts must be between steps and on the batch's stream; while
+ * attached they are stepped only through the batch.  Not thread-safe. */
+typedef struct sisph_batch sisph_batch;
+
+int32_t sisph_batch_create(int32_t max_cases, void *hip_stream, sisph_batch **out);
+int32_t sisph_batch_attach(sisph_batch *b, sisph_ctx *ctx);
+int32_t sisph_batch_detach(sisph_batch *b, sisph_ctx *ctx);
+int32_t sisph_batch_size(sisph_batch *b);
+/* One SISPH step of every attached case.  per_case: sisph_batch_size(b)
+ * entries in attach order (or NULL).  Returns the worst status over the
+ * cases (errors of single cases are reported in their entries' nonfinite
+ * flag and in the return value). */
+int32_t sisph_batch_step(sisph_batch *b, sisph_step_stats *per_case);
+int32_t sisph_batch_destroy(sisph_batch *b);
+
 const char *sisph_status_string(int32_t status);
 /* Last error message of this context (or of the last failed create). */
 const char *sisph_last_error(sisph_ctx *ctx);

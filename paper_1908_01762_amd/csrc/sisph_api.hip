@@ -1,8 +1,9 @@
 // Host runtime of libsisph: descriptor checks, workspace carving, the step
-// state machine and the C ABI declared in sisph.h.
+// state machine, batching and the C ABI declared in sisph.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -19,18 +20,19 @@ struct sisph_ctx {
     sisph_case_desc desc;
     Params P;
     State S;
+    Target T;            // single-case launch target
     hipStream_t stream;
     int state;
-    int nbr_stage;      // which neighbour lists are held: -1, 0 (r^n), 1 (r*)
-    int final_parity;   // iterate holding the last solve's pressure
+    int nbr_stage;       // which neighbour lists are held: -1, 0 (r^n), 1 (r*)
     int last_iters;
-    Control *h_ctl;     // pinned mirror of the control block
+    Control *h_ctl;      // pinned mirror of the control block
     hipEvent_t ev[4];
-    hipEvent_t evc[2];  // brackets one chunk of back-to-back sweeps
+    hipEvent_t evc[2];   // brackets one chunk of back-to-back sweeps
     double ppe_ms, step_ms;
     double sweep_ms;
     int64_t sweep_launches, sweep_effective;
     bool step_timed;
+    sisph_batch *batch;  // non-null while attached
     std::string err;
 };
 
@@ -63,7 +65,8 @@ static const char *check_desc(const sisph_case_desc *d) {
     if (!(d->h > 0) || !(d->dx > 0) || !(d->rho0 > 0) || !(d->dt > 0)) return "h, dx, rho0, dt must be positive";
     if (!(d->omega > 0) || !(d->omega <= 1.0)) return "omega must be in (0, 1]";
     if (d->min_iter < 1 || d->max_iter < d->min_iter) return "need 1 <= min_iter <= max_iter";
-    if (d->forced_iters < 0) return "forced_iters must be >= 0";
+    if (d->max_iter >= INT32_MAX - 1) return "max_iter too large";
+    if (d->forced_iters < 0 || d->forced_iters >= INT32_MAX - 1) return "forced_iters out of range";
     if (d->gtvf != SISPH_GTVF_OFF && d->gtvf_K < 1) return "gtvf_K must be >= 1";
     if (d->nbr_cap < 0) return "nbr_cap must be >= 0";
     double R = support_of(d->kernel) * d->h;
@@ -87,8 +90,8 @@ static Grid make_grid(const sisph_case_desc *d) {
             g.Lh[k] = 0.5 * g.L[k];
             int64_t n = (int64_t)std::floor(g.L[k] / Rm);
             if (n < 1) n = 1;
-            g.nc[k] = (int32_t)n;
-            g.edge[k] = g.L[k] / (double)n;
+            g.nc[k] = (int32_t)std::min<int64_t>(n, INT32_MAX);
+            g.edge[k] = g.L[k] / (double)g.nc[k];
             if (g.edge[k] < Rm) g.edge[k] = Rm;
             g.per[k] = d->periodic[k] ? 1 : 0;
         } else {
@@ -126,7 +129,7 @@ static Params make_params(const sisph_case_desc *d) {
     P.min_iter = d->min_iter;
     P.max_iter = d->max_iter;
     P.forced_iters = d->forced_iters;
-    P.gtvf_K = d->gtvf_K;
+    P.gtvf_K = d->gtvf == SISPH_GTVF_OFF ? 0 : d->gtvf_K;
     P.cap = neighbour_cap(d);
     P.nf = d->n_fluid;
     P.nw = d->n_wall;
@@ -194,18 +197,15 @@ static void carve(const Params &P, Carver &c, State &S) {
     S.count = c.take<uint32_t>(P.grid.ncell);
     S.fstart = c.take<uint32_t>(P.grid.ncell + 1);
     S.wstart = c.take<uint32_t>(P.grid.ncell + 1);
-    S.scan_tmp = c.take<uint32_t>(P.grid.ncell / 1024 + 2);
+    S.scan_tmp = c.take<uint32_t>(kind_blocks(P, K_TILE) + 1);
     S.perm = c.take<int32_t>(nmax);
-    S.items = nullptr;
     S.nbr = c.take<int32_t>((int64_t)P.cap * nf);
     S.cnt = c.take<int32_t>(nf);
     S.wnbr = c.take<int32_t>((int64_t)P.cap * nw);
     S.wcnt = c.take<int32_t>(nw);
     // mixed: (index, FP32 c_ij) 8-byte words; FP64: FP64 c_ij (indices from nbr)
-    const size_t csz = 8;
-    S.coef = c.take<char>((int64_t)csz * P.cap * nf);
-    S.nblk_f = (nf + kBlock - 1) / kBlock;
-    S.partial = c.take<double>(4 * S.nblk_f);
+    S.coef = c.take<char>((int64_t)8 * P.cap * nf);
+    S.partial = c.take<double>(4 * kind_blocks(P, K_FLUID));
     S.tmp = c.take<double>(16 * nmax);
     S.ctl = c.take<Control>(1);
 }
@@ -220,9 +220,23 @@ extern "C" size_t sisph_workspace_bytes(const sisph_case_desc *desc) {
     return (c.off + 255) & ~(size_t)255;
 }
 
+static Target single_target(sisph_ctx *ctx) {
+    Target T{};
+    T.P = &ctx->P;
+    T.S = &ctx->S;
+    T.batched = false;
+    T.ncase = 1;
+    T.dim = ctx->P.dim;
+    T.kernel = ctx->P.kernel;
+    T.precision = ctx->P.precision;
+    T.s = ctx->stream;
+    return T;
+}
+
 // ------------------------------------------------------------ utilities
 static int32_t h2d(sisph_ctx *ctx, double *dst, const double *src, int64_t n) {
     HIPCHK(ctx, hipMemcpyAsync(dst, src, sizeof(double) * (size_t)n, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return SISPH_OK;
 }
 
@@ -248,6 +262,35 @@ static int32_t read_ctl(sisph_ctx *ctx) {
 static int32_t fail(sisph_ctx *ctx, int32_t code, const std::string &msg) {
     ctx->err = msg;
     return code;
+}
+
+static void fill_stats(const Control &C, const Params &P, sisph_ppe_stats *out) {
+    out->iters = C.iter;
+    out->converged = C.ratio < P.tol ? 1 : 0;
+    out->nonfinite = C.nonfinite;
+    out->reserved = 0;
+    out->ratio = C.ratio;
+    union {
+        unsigned long long u;
+        double d;
+    } cv;
+    cv.u = C.lambda_bits;
+    out->lambda = cv.d;
+    out->p_ref = C.p_ref;
+}
+
+static int32_t status_of(const Control &C, const Params &P, std::string *msg) {
+    if (C.overflow) {
+        if (msg)
+            *msg = "neighbour capacity exceeded: " + std::to_string(C.maxcnt) + " > nbr_cap " + std::to_string(P.cap);
+        return SISPH_E_NOMEM;
+    }
+    if (C.nonfinite) {
+        if (msg) *msg = "non-finite pressure in the PPE residual";
+        return SISPH_E_NONFINITE;
+    }
+    if (P.forced_iters == 0 && !(C.ratio < P.tol)) return SISPH_WARN_MAXITER;
+    return SISPH_OK;
 }
 
 // ---------------------------------------------------------------- create
@@ -283,14 +326,18 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
     ctx->stream = (hipStream_t)hip_stream;
     ctx->state = ST_READY;
     ctx->nbr_stage = -1;
-    ctx->final_parity = 0;
     ctx->last_iters = desc->min_iter;
     ctx->ppe_ms = ctx->step_ms = 0.0;
     ctx->sweep_ms = 0.0;
     ctx->sweep_launches = ctx->sweep_effective = 0;
     ctx->step_timed = false;
+    ctx->batch = nullptr;
+    ctx->h_ctl = nullptr;
+    for (auto &e : ctx->ev) e = nullptr;
+    for (auto &e : ctx->evc) e = nullptr;
     Carver c{(char *)d_workspace};
     carve(ctx->P, c, ctx->S);
+    ctx->T = single_target(ctx);
     auto bail = [&](int32_t code) {
         g_create_err = ctx->err;
         if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
@@ -306,18 +353,16 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
         ctx->h_ctl = nullptr;
         return bail(SISPH_E_DEVICE);
     }
-    for (auto &e : ctx->evc) {
+    for (auto &e : ctx->ev)
         if (hipEventCreate(&e) != hipSuccess) {
             ctx->err = "hipEventCreate failed";
             return bail(SISPH_E_DEVICE);
         }
-    }
-    for (auto &e : ctx->ev) {
+    for (auto &e : ctx->evc)
         if (hipEventCreate(&e) != hipSuccess) {
             ctx->err = "hipEventCreate failed";
             return bail(SISPH_E_DEVICE);
         }
-    }
     const Params &P = ctx->P;
     State &S = ctx->S;
     const int64_t nf = P.nf, nw = P.nw, nt = P.ntot, D = P.dim;
@@ -338,12 +383,11 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
     }
     iota_i32(S.id, nf, s);
     iota_i32(S.wid, nw, s);
-    reset_control(S.ctl, RESET_PPE | RESET_NEIGHBOURS | RESET_PREF, s);
+    reset_control(ctx->T, RESET_PPE | RESET_NEIGHBOURS | RESET_PREF);
     if (desc->p_ref_mode == SISPH_PREF_FIXED) {
         Control c0{};
         c0.p_ref = desc->p_ref;
         c0.p_ref_set = 1;
-        // set p_ref / p_ref_set only (a fill of the two fields)
         if (hipMemcpyAsync(&S.ctl->p_ref, &c0.p_ref, sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(&S.ctl->p_ref_set, &c0.p_ref_set, sizeof(int32_t), hipMemcpyHostToDevice, s) !=
                 hipSuccess ||
@@ -355,13 +399,7 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
     // walls: one stable sort into cell order (they never move)
     fill_u32(S.wstart, 0u, P.grid.ncell + 1, s);
     if (nw > 0) {
-        bin_particles(P, S.x, nf, nw, S.wid, S, S.wstart, S.perm, s);
-        std::vector<double *> arrs;
-        for (int k = 0; k < D; ++k) arrs.push_back(S.x[k] + nf);
-        arrs.push_back(S.m + nf);
-        for (int k = 0; k < D; ++k) arrs.push_back(S.wallu[k]);
-        reorder_f64(S.perm, nw, arrs.data(), (int)arrs.size(), S.tmp, s);
-        reorder_i32(S.perm, nw, S.wid, (int32_t *)S.tmp, s);
+        bin_walls_once(ctx->T);
         fill_f64(S.rho + nf, P.rho0, nw, s);
         fill_f64(S.p[0] + nf, 0.0, nw, s);
         fill_f64(S.p[1] + nf, 0.0, nw, s);
@@ -378,7 +416,7 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
             fill_f64(S.u[k] + nf, 0.0, nw, s);
             fill_f64(S.us[k] + nf, 0.0, nw, s);
         }
-        wall_normals(P, S, s);
+        wall_normals(ctx->T);
     }
     if (hipStreamSynchronize(s) != hipSuccess) {
         ctx->err = "device error during create";
@@ -393,26 +431,50 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
     return SISPH_OK;
 }
 
+// ------------------------------------------------------- step sequences
+// The same launch sequences serve one case and a batch (Target).
+static void seq_bin(const Target &T) {
+    reset_control(T, RESET_NEIGHBOURS);
+    bin_fluid(T, POS_X);
+    build_neighbors(T, POS_X);
+}
+
+static void seq_predict(const Target &T) {
+    density(T);
+    wall_velocity(T, POS_X, 0);
+    predictor(T);
+    bin_fluid(T, POS_XS);
+    build_neighbors(T, POS_XS);
+    wall_velocity(T, POS_XS, 1);
+}
+
+static void seq_ppe_begin(const Target &T) {
+    reset_control(T, RESET_PPE);
+    rhs_coef(T);
+    if (T.precision == SISPH_MIXED) copy_p32(T);
+}
+
+static void seq_ppe_end(const Target &T) {
+    settle_pressure(T);
+    wall_pressure_final(T);
+    pressure_max(T);
+}
+
+static void seq_correct(const Target &T, int maxK) {
+    correct(T);
+    for (int k = 0; k < maxK; ++k) gtvf_substep(T, k);
+    advance(T);
+}
+
 // ------------------------------------------------------------ the stages
+static bool attached(sisph_ctx *ctx) { return ctx->batch != nullptr; }
+
 extern "C" int32_t sisph_bin(sisph_ctx *ctx) {
     if (!ctx) return SISPH_E_INVAL;
+    if (attached(ctx)) return fail(ctx, SISPH_E_STATE, "context is attached to a batch");
     if (ctx->state != ST_READY) return fail(ctx, SISPH_E_STATE, "sisph_bin needs a completed step");
-    const Params &P = ctx->P;
-    State &S = ctx->S;
-    hipStream_t s = ctx->stream;
-    HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
-    reset_control(S.ctl, RESET_NEIGHBOURS, s);
-    bin_particles(P, S.x, 0, P.nf, S.id, S, S.fstart, S.perm, s);
-    std::vector<double *> arrs;
-    for (int k = 0; k < P.dim; ++k) arrs.push_back(S.x[k]);
-    for (int k = 0; k < P.dim; ++k) arrs.push_back(S.u[k]);
-    for (int k = 0; k < P.dim; ++k) arrs.push_back(S.ut[k]);
-    arrs.push_back(S.p[0]);
-    arrs.push_back(S.m);
-    reorder_f64(S.perm, P.nf, arrs.data(), (int)arrs.size(), S.tmp, s);
-    reorder_i32(S.perm, P.nf, S.id, (int32_t *)S.tmp, s);
-    S.items = nullptr;
-    build_neighbors(P, S.x, S, s);
+    HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    seq_bin(ctx->T);
     HIPCHK(ctx, hipGetLastError());
     ctx->state = ST_BINNED;
     ctx->nbr_stage = 0;
@@ -422,115 +484,92 @@ extern "C" int32_t sisph_bin(sisph_ctx *ctx) {
 
 extern "C" int32_t sisph_predict(sisph_ctx *ctx) {
     if (!ctx) return SISPH_E_INVAL;
+    if (attached(ctx)) return fail(ctx, SISPH_E_STATE, "context is attached to a batch");
     if (ctx->state != ST_BINNED) return fail(ctx, SISPH_E_STATE, "sisph_predict needs sisph_bin first");
-    const Params &P = ctx->P;
-    State &S = ctx->S;
-    hipStream_t s = ctx->stream;
-    density(P, S, s);
-    wall_velocity(P, S.x, S.u, S.u, 0, S, s);
-    predictor(P, S, s);
-    // N*: bin r* without moving data; lists index the r^n cell order
-    bin_particles(P, S.xs, 0, P.nf, nullptr, S, S.fstart, S.perm, s);
-    S.items = S.perm;
-    build_neighbors(P, S.xs, S, s);
-    wall_velocity(P, S.xs, S.us, S.us, 1, S, s);
+    seq_predict(ctx->T);
     HIPCHK(ctx, hipGetLastError());
     ctx->state = ST_PREDICTED;
     ctx->nbr_stage = 1;
     return SISPH_OK;
 }
 
-extern "C" int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out) {
-    if (!ctx) return SISPH_E_INVAL;
-    if (ctx->state != ST_PREDICTED) return fail(ctx, SISPH_E_STATE, "sisph_ppe_solve needs sisph_predict first");
-    const Params &P = ctx->P;
-    State &S = ctx->S;
-    hipStream_t s = ctx->stream;
-    HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
-    reset_control(S.ctl, RESET_PPE, s);
-    rhs_coef(P, S, s);
-    if (P.precision == SISPH_MIXED) copy_p32(P, S, s);
-    // Launch L sweeps iterate L (L = 0, 1, ...) unless the solve already
-    // stopped; the stopping decision for L sweeps is taken at the start of
-    // launch L, so a chunk ends with one launch beyond the predicted count.
-    const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1;
-    int64_t chunk = (P.forced_iters > 0 ? P.forced_iters : std::max(P.min_iter, ctx->last_iters)) + 1;
-    chunk = std::min(chunk, limit);
+// Launch L performs sweep L unless its case stopped earlier; the decision
+// for L sweeps is taken at the start of launch L, so each chunk of launches
+// ends one beyond the predicted count.  poll() reads the control state and
+// reports whether every case has stopped.
+template <class Poll>
+static int32_t ppe_loop(const Target &T, int64_t predicted, int64_t limit, hipEvent_t e0, hipEvent_t e1,
+                        double &sweep_ms, int64_t &launches, Poll poll, std::string &err) {
+    int64_t chunk = std::min<int64_t>(predicted + 1, limit);
     int64_t launched = 0;
     for (;;) {
-        const int before = launched == 0 ? 0 : ctx->h_ctl->iter;
-        HIPCHK(ctx, hipEventRecord(ctx->evc[0], s));
-        for (int64_t c = 0; c < chunk; ++c) ppe_iteration(P, S, (int)(launched + c), s);
-        HIPCHK(ctx, hipEventRecord(ctx->evc[1], s));
+        if (hipEventRecord(e0, T.s) != hipSuccess) return SISPH_E_DEVICE;
+        for (int64_t c = 0; c < chunk; ++c) ppe_iteration(T, (int)(launched + c));
+        if (hipEventRecord(e1, T.s) != hipSuccess) return SISPH_E_DEVICE;
         launched += chunk;
-        HIPCHK(ctx, hipGetLastError());
-        int32_t st = read_ctl(ctx);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            err = std::string("sweep launch failed: ") + hipGetErrorString(e);
+            return SISPH_E_DEVICE;
+        }
+        bool all_done = false;
+        int32_t st = poll(all_done);
         if (st != SISPH_OK) return st;
         float cms = 0.f;
-        HIPCHK(ctx, hipEventElapsedTime(&cms, ctx->evc[0], ctx->evc[1]));
-        ctx->sweep_ms += cms;
-        ctx->sweep_launches += chunk;
-        ctx->sweep_effective += ctx->h_ctl->iter - before;
-        if (ctx->h_ctl->done || launched >= limit) break;
+        if (hipEventElapsedTime(&cms, e0, e1) != hipSuccess) return SISPH_E_DEVICE;
+        sweep_ms += cms;
+        launches += chunk;
+        if (all_done || launched >= limit) break;
         chunk = std::min<int64_t>(std::min<int64_t>(2 * chunk, 64), limit - launched);
         if (chunk < 1) chunk = 1;
     }
-    const int iters = ctx->h_ctl->iter;
-    wall_pressure_final(P, S, s);
-    ctx->final_parity = iters & 1;
-    if (ctx->desc.p_ref_mode == SISPH_PREF_TWICE_MAX) pressure_max(P, S, ctx->final_parity, s);
-    HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
-    int32_t st = read_ctl(ctx);
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out) {
+    if (!ctx) return SISPH_E_INVAL;
+    if (attached(ctx)) return fail(ctx, SISPH_E_STATE, "context is attached to a batch");
+    if (ctx->state != ST_PREDICTED) return fail(ctx, SISPH_E_STATE, "sisph_ppe_solve needs sisph_predict first");
+    const Params &P = ctx->P;
+    hipStream_t s = ctx->stream;
+    HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
+    seq_ppe_begin(ctx->T);
+    const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1;
+    const int64_t predicted = P.forced_iters > 0 ? P.forced_iters : std::max(P.min_iter, ctx->last_iters);
+    const int before = 0;
+    auto poll = [&](bool &done) -> int32_t {
+        int32_t st = read_ctl(ctx);
+        if (st != SISPH_OK) return st;
+        done = ctx->h_ctl->done != 0;
+        return SISPH_OK;
+    };
+    int32_t st = ppe_loop(ctx->T, predicted, limit, ctx->evc[0], ctx->evc[1], ctx->sweep_ms, ctx->sweep_launches,
+                          poll, ctx->err);
     if (st != SISPH_OK) return st;
+    seq_ppe_end(ctx->T);
+    HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+    if ((st = read_ctl(ctx)) != SISPH_OK) return st;
     float ms = 0.f;
     HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
     ctx->ppe_ms = ms;
     const Control &C = *ctx->h_ctl;
-    ctx->last_iters = std::max(iters, 1);
-    if (out) {
-        out->iters = C.iter;
-        out->converged = C.ratio < P.tol ? 1 : 0;
-        out->nonfinite = C.nonfinite;
-        out->reserved = 0;
-        out->ratio = C.ratio;
-        union {
-            unsigned long long u;
-            double d;
-        } cv;
-        cv.u = C.lambda_bits;
-        out->lambda = cv.d;
-        out->p_ref = C.p_ref;
-    }
+    ctx->sweep_effective += C.iter - before;
+    ctx->last_iters = std::max(C.iter, 1);
+    if (out) fill_stats(C, P, out);
     ctx->state = ST_SOLVED;
-    if (C.overflow)
-        return fail(ctx, SISPH_E_NOMEM,
-                    "neighbour capacity exceeded: " + std::to_string(C.maxcnt) + " > nbr_cap " +
-                        std::to_string(P.cap));
-    if (C.nonfinite) return fail(ctx, SISPH_E_NONFINITE, "non-finite pressure in the PPE residual");
-    if (P.forced_iters == 0 && !(C.ratio < P.tol)) return SISPH_WARN_MAXITER;
-    return SISPH_OK;
+    std::string msg;
+    st = status_of(C, P, &msg);
+    if (st < 0) return fail(ctx, st, msg);
+    return st;
 }
 
 extern "C" int32_t sisph_correct(sisph_ctx *ctx) {
     if (!ctx) return SISPH_E_INVAL;
+    if (attached(ctx)) return fail(ctx, SISPH_E_STATE, "context is attached to a batch");
     if (ctx->state != ST_SOLVED) return fail(ctx, SISPH_E_STATE, "sisph_correct needs sisph_ppe_solve first");
-    const Params &P = ctx->P;
-    State &S = ctx->S;
     hipStream_t s = ctx->stream;
-    const int fp = ctx->final_parity;
-    correct(P, S, fp, s);
-    int kfinal = -1;
-    if (P.gtvf != SISPH_GTVF_OFF) {
-        for (int k = 0; k < P.gtvf_K; ++k) gtvf_substep(P, S, fp, k, s);
-        kfinal = P.gtvf_K - 1;
-    }
-    advance(P, S, kfinal, s);
+    seq_correct(ctx->T, ctx->P.gtvf_K);
     HIPCHK(ctx, hipGetLastError());
-    if (fp == 1) {
-        // keep the current pressure in iterate 0 for the next solve
-        std::swap(S.p[0], S.p[1]);
-    }
-    ctx->final_parity = 0;
     HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
     if (ctx->step_timed) {
         HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
@@ -673,9 +712,8 @@ extern "C" int32_t sisph_read_field(sisph_ctx *ctx, int32_t field, double *out) 
         return SISPH_OK;
     }
     case SISPH_FIELD_PRESSURE: {
-        const double *pc = S.p[ctx->state == ST_SOLVED ? ctx->final_parity : 0];
-        if ((st = download_scalar(ctx, out, pc, P.nf, id, 0)) != SISPH_OK) return st;
-        if (P.nw) return download_scalar(ctx, out, pc + P.nf, P.nw, wid, P.nf);
+        if ((st = download_scalar(ctx, out, S.p[0], P.nf, id, 0)) != SISPH_OK) return st;
+        if (P.nw) return download_scalar(ctx, out, S.p[0] + P.nf, P.nw, wid, P.nf);
         return SISPH_OK;
     }
     default: return fail(ctx, SISPH_E_INVAL, "unknown field");
@@ -741,8 +779,259 @@ extern "C" int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_
     return SISPH_OK;
 }
 
+// ================================================================ batches
+// Cases of one (dim, kernel, precision) share a device table and one launch
+// per kernel; the per-kind maps give each workgroup its case.
+struct Group {
+    int32_t dim, kernel, precision;
+    std::vector<sisph_ctx *> members;
+    CaseEntry *d_tab = nullptr;
+    int32_t *d_owner[K_COUNT] = {};
+    int64_t *d_first[K_COUNT] = {};
+    Control *d_ctl = nullptr;   // gathered control blocks [members]
+    Control *h_ctl = nullptr;   // pinned mirror
+    size_t owner_cap[K_COUNT] = {};
+    size_t case_cap = 0;
+    bool dirty = true;
+    Target T{};
+};
+
+struct sisph_batch {
+    int32_t max_cases;
+    hipStream_t stream;
+    std::vector<sisph_ctx *> cases;   // attach order
+    std::vector<Group> groups;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::string err;
+};
+
+static void free_group(Group &g) {
+    if (g.d_tab) (void)hipFree(g.d_tab);
+    for (int k = 0; k < K_COUNT; ++k) {
+        if (g.d_owner[k]) (void)hipFree(g.d_owner[k]);
+        if (g.d_first[k]) (void)hipFree(g.d_first[k]);
+        g.d_owner[k] = nullptr;
+        g.d_first[k] = nullptr;
+        g.owner_cap[k] = 0;
+    }
+    if (g.d_ctl) (void)hipFree(g.d_ctl);
+    if (g.h_ctl) (void)hipHostFree(g.h_ctl);
+    g.d_tab = nullptr;
+    g.d_ctl = nullptr;
+    g.h_ctl = nullptr;
+    g.case_cap = 0;
+}
+
+#define BCHK(b, expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            (b)->err = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+            return SISPH_E_DEVICE;                                                      \
+        }                                                                               \
+    } while (0)
+
+// Rebuilds a group's device table and workgroup maps after membership changed.
+static int32_t rebuild_group(sisph_batch *b, Group &g) {
+    const size_t n = g.members.size();
+    if (n > g.case_cap) {
+        if (g.d_tab) (void)hipFree(g.d_tab);
+        if (g.d_ctl) (void)hipFree(g.d_ctl);
+        if (g.h_ctl) (void)hipHostFree(g.h_ctl);
+        g.d_tab = nullptr;
+        g.d_ctl = nullptr;
+        g.h_ctl = nullptr;
+        BCHK(b, hipMalloc((void **)&g.d_tab, sizeof(CaseEntry) * n));
+        BCHK(b, hipMalloc((void **)&g.d_ctl, sizeof(Control) * n));
+        BCHK(b, hipHostMalloc((void **)&g.h_ctl, sizeof(Control) * n, hipHostMallocDefault));
+        g.case_cap = n;
+    }
+    std::vector<CaseEntry> tab(n);
+    Target &T = g.T;
+    T = Target{};
+    T.batched = true;
+    T.ncase = (int32_t)n;
+    T.dim = g.dim;
+    T.kernel = g.kernel;
+    T.precision = g.precision;
+    T.s = b->stream;
+    for (int k = 0; k < K_COUNT; ++k) {
+        std::vector<int32_t> owner;
+        std::vector<int64_t> first(n);
+        for (size_t c = 0; c < n; ++c) {
+            const int64_t nb = kind_blocks(g.members[c]->P, k);
+            tab[c].nblk[k] = nb;
+            first[c] = (int64_t)owner.size();
+            owner.insert(owner.end(), (size_t)nb, (int32_t)c);
+        }
+        T.total[k] = (int64_t)owner.size();
+        if (owner.size() > g.owner_cap[k] || !g.d_first[k]) {
+            if (g.d_owner[k]) (void)hipFree(g.d_owner[k]);
+            if (g.d_first[k]) (void)hipFree(g.d_first[k]);
+            g.d_owner[k] = nullptr;
+            g.d_first[k] = nullptr;
+            BCHK(b, hipMalloc((void **)&g.d_owner[k], sizeof(int32_t) * std::max<size_t>(owner.size(), 1)));
+            BCHK(b, hipMalloc((void **)&g.d_first[k], sizeof(int64_t) * std::max<size_t>(g.case_cap, 1)));
+            g.owner_cap[k] = owner.size();
+        }
+        if (!owner.empty())
+            BCHK(b, hipMemcpyAsync(g.d_owner[k], owner.data(), sizeof(int32_t) * owner.size(),
+                                   hipMemcpyHostToDevice, b->stream));
+        BCHK(b, hipMemcpyAsync(g.d_first[k], first.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, b->stream));
+        T.owner[k] = g.d_owner[k];
+        T.first[k] = g.d_first[k];
+    }
+    for (size_t c = 0; c < n; ++c) {
+        tab[c].P = g.members[c]->P;
+        tab[c].S = g.members[c]->S;
+    }
+    BCHK(b, hipMemcpyAsync(g.d_tab, tab.data(), sizeof(CaseEntry) * n, hipMemcpyHostToDevice, b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));
+    T.tab = g.d_tab;
+    g.dirty = false;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_batch_create(int32_t max_cases, void *hip_stream, sisph_batch **out) {
+    if (!out || max_cases < 1) return SISPH_E_INVAL;
+    sisph_batch *b = new sisph_batch();
+    b->max_cases = max_cases;
+    b->stream = (hipStream_t)hip_stream;
+    if (hipEventCreate(&b->e0) != hipSuccess || hipEventCreate(&b->e1) != hipSuccess) {
+        if (b->e0) (void)hipEventDestroy(b->e0);
+        delete b;
+        return SISPH_E_DEVICE;
+    }
+    *out = b;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_batch_attach(sisph_batch *b, sisph_ctx *ctx) {
+    if (!b || !ctx) return SISPH_E_INVAL;
+    if (ctx->batch) return fail(ctx, SISPH_E_STATE, "context already attached to a batch");
+    if (ctx->state != ST_READY) return fail(ctx, SISPH_E_STATE, "attach between steps only");
+    if (ctx->stream != b->stream) return fail(ctx, SISPH_E_INVAL, "context and batch must share a stream");
+    if ((int32_t)b->cases.size() >= b->max_cases) return fail(ctx, SISPH_E_NOMEM, "batch is full");
+    Group *g = nullptr;
+    for (auto &x : b->groups)
+        if (x.dim == ctx->P.dim && x.kernel == ctx->P.kernel && x.precision == ctx->P.precision) g = &x;
+    if (!g) {
+        b->groups.emplace_back();
+        g = &b->groups.back();
+        g->dim = ctx->P.dim;
+        g->kernel = ctx->P.kernel;
+        g->precision = ctx->P.precision;
+    }
+    g->members.push_back(ctx);
+    g->dirty = true;
+    b->cases.push_back(ctx);
+    ctx->batch = b;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_batch_detach(sisph_batch *b, sisph_ctx *ctx) {
+    if (!b || !ctx) return SISPH_E_INVAL;
+    if (ctx->batch != b) return fail(ctx, SISPH_E_INVAL, "context is not attached to this batch");
+    b->cases.erase(std::remove(b->cases.begin(), b->cases.end(), ctx), b->cases.end());
+    for (auto &g : b->groups) {
+        auto it = std::find(g.members.begin(), g.members.end(), ctx);
+        if (it != g.members.end()) {
+            g.members.erase(it);
+            g.dirty = true;
+        }
+    }
+    ctx->batch = nullptr;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_batch_size(sisph_batch *b) { return b ? (int32_t)b->cases.size() : SISPH_E_INVAL; }
+
+// One full step of one group; per-case results into the members' contexts.
+static int32_t group_step(sisph_batch *b, Group &g) {
+    if (g.members.empty()) return SISPH_OK;
+    if (g.dirty) {
+        int32_t st = rebuild_group(b, g);
+        if (st != SISPH_OK) return st;
+    }
+    const Target &T = g.T;
+    const size_t n = g.members.size();
+    int64_t limit = 1, predicted = 1;
+    int maxK = 0;
+    for (auto *c : g.members) {
+        const Params &P = c->P;
+        limit = std::max<int64_t>(limit, (P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1);
+        predicted = std::max<int64_t>(predicted, P.forced_iters > 0 ? P.forced_iters
+                                                                   : std::max(P.min_iter, c->last_iters));
+        maxK = std::max(maxK, P.gtvf_K);
+    }
+    seq_bin(T);
+    seq_predict(T);
+    seq_ppe_begin(T);
+    auto poll = [&](bool &done) -> int32_t {
+        gather_control(T, g.d_ctl);
+        BCHK(b, hipMemcpyAsync(g.h_ctl, g.d_ctl, sizeof(Control) * n, hipMemcpyDeviceToHost, b->stream));
+        BCHK(b, hipStreamSynchronize(b->stream));
+        done = true;
+        for (size_t c = 0; c < n; ++c) done = done && g.h_ctl[c].done;
+        return SISPH_OK;
+    };
+    double sweep_ms = 0.0;
+    int64_t launches = 0;
+    int32_t st = ppe_loop(T, predicted, limit, b->e0, b->e1, sweep_ms, launches, poll, b->err);
+    if (st != SISPH_OK) return st;
+    seq_ppe_end(T);
+    seq_correct(T, maxK);
+    gather_control(T, g.d_ctl);
+    BCHK(b, hipMemcpyAsync(g.h_ctl, g.d_ctl, sizeof(Control) * n, hipMemcpyDeviceToHost, b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));
+    BCHK(b, hipGetLastError());
+    for (size_t c = 0; c < n; ++c) {
+        sisph_ctx *ctx = g.members[c];
+        *ctx->h_ctl = g.h_ctl[c];
+        ctx->last_iters = std::max(g.h_ctl[c].iter, 1);
+        ctx->sweep_effective += g.h_ctl[c].iter;
+        ctx->nbr_stage = 1;
+    }
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_batch_step(sisph_batch *b, sisph_step_stats *per_case) {
+    if (!b) return SISPH_E_INVAL;
+    for (auto &g : b->groups) {
+        int32_t st = group_step(b, g);
+        if (st != SISPH_OK) return st;
+    }
+    // errors first (the most negative), else the largest warning
+    int32_t err = SISPH_OK, warn = SISPH_OK;
+    for (size_t c = 0; c < b->cases.size(); ++c) {
+        sisph_ctx *ctx = b->cases[c];
+        if (per_case) fill_stats(*ctx->h_ctl, ctx->P, per_case + c);
+        std::string msg;
+        const int32_t st = status_of(*ctx->h_ctl, ctx->P, &msg);
+        if (st < 0) {
+            ctx->err = msg;
+            err = std::min(err, st);
+        } else {
+            warn = std::max(warn, st);
+        }
+    }
+    return err < 0 ? err : warn;
+}
+
+extern "C" int32_t sisph_batch_destroy(sisph_batch *b) {
+    if (!b) return SISPH_E_INVAL;
+    (void)hipStreamSynchronize(b->stream);
+    for (auto *c : b->cases) c->batch = nullptr;
+    for (auto &g : b->groups) free_group(g);
+    if (b->e0) (void)hipEventDestroy(b->e0);
+    if (b->e1) (void)hipEventDestroy(b->e1);
+    delete b;
+    return SISPH_OK;
+}
+
 extern "C" int32_t sisph_destroy(sisph_ctx *ctx) {
     if (!ctx) return SISPH_E_INVAL;
+    if (ctx->batch) (void)sisph_batch_detach(ctx->batch, ctx);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
     for (auto &e : ctx->ev)

@@ -1,6 +1,6 @@
 // Internal types of libsisph: device-side parameter blocks, the per-case
-// state (pointers carved out of the caller's workspace) and the launchers the
-// host runtime calls.  gfx950 only.
+// state (pointers carved out of the caller's workspace) and the launch
+// interface the host runtime uses.  gfx950 only.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,6 +12,8 @@ namespace sisph {
 
 constexpr int kBlock = 256;   // threads per workgroup for particle kernels
 constexpr int kXcd = 8;       // MI355X: 8 XCDs, workgroups dealt round-robin
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
 
 // Binning grid and periodic box.  Cell edge >= R (with a 1e-6 margin), so
 // two particles closer than R are never more than one cell apart.
@@ -23,7 +25,7 @@ struct Grid {
     int64_t ncell;
 };
 
-// Scalar parameters of one case as kernels see them (passed by value).
+// Scalar parameters of one case as kernels see them.
 struct Params {
     int32_t dim, kernel, precision, pgrad, gtvf, free_surface;
     int32_t conv_norm, min_iter, max_iter, forced_iters, gtvf_K, cap;
@@ -38,10 +40,10 @@ struct Params {
 struct Control {
     int32_t iter;          // sweeps done in the current solve
     int32_t done;          // solve finished (converged, max_iter, forced)
+    int32_t stopped_at;    // sweep count at which the solve stopped (INT32_MAX: running)
     int32_t nonfinite;     // a non-finite pressure sum was seen
     int32_t overflow;      // neighbour capacity exceeded
-    int32_t maxcnt;        // largest neighbour count seen
-    uint32_t ticket;       // last-workgroup-done counter
+    int32_t maxcnt;        // largest neighbour count seen (on overflow)
     int32_t p_ref_set;
     int32_t pad;
     double ratio, num, den;
@@ -63,8 +65,8 @@ struct State {
     double *vk[3];     // GTVF sub-step velocity     [nf]
     double *nrm[3];    // wall unit normals          [nw]
     double *wallu[3];  // prescribed wall velocity   [nw]
-    double *p[2];      // pressure iterates          [ntot] x2
-    float *p32;        // FP32 copy of the current iterate (mixed) [ntot]
+    double *p[2];      // pressure iterates; p[0] holds p^n between steps [ntot] x2
+    float *p32;        // FP32 copies of the iterates (mixed) [2][ntot]
     double *m;         // mass                       [ntot]
     double *rho;       // density (walls rho0)       [ntot]
     double *rhs, *dii; //                            [nf]
@@ -73,48 +75,81 @@ struct State {
     int32_t *wid;      // original wall index of sorted wall slot [nw]
     // binning
     uint32_t *key, *rank, *count, *fstart, *wstart, *scan_tmp;
-    int32_t *perm, *items;
+    int32_t *perm;          // sorted slot -> source index (at r*: cell slot -> particle)
     // neighbour lists, slot-major [cap][n]: slot 0 is the particle itself
     int32_t *nbr, *cnt;     // fluid rows: fluid + wall sources
     int32_t *wnbr, *wcnt;   // wall rows: fluid sources
-    void *coef;             // cached PPE c_ij, float (mixed) or double [cap][nf]
-    double *partial;        // per-workgroup partial sums, two sweeps [2][2][nblk]
-    double *tmp;            // reorder scratch [ntot]
+    void *coef;             // cached PPE c_ij: (j, FP32 c) words (mixed) or FP64 [cap][nf]
+    double *partial;        // per-workgroup partial sums of two sweeps [2][2][nblk]
+    double *tmp;            // reorder scratch [16][max(nf, nw)]
     Control *ctl;
-    int64_t nblk_f;         // workgroups of a fluid launch
 };
 
-// ---- launchers (sisph_kernels.hip) -------------------------------------
+// Launch-size kinds: how many workgroups one case needs for a kernel.
+enum Kind { K_FLUID = 0, K_WALL, K_TOT, K_CELL, K_TILE, K_ONE, K_COUNT };
+
+inline int64_t kind_blocks(const Params &P, int kind) {
+    switch (kind) {
+    case K_FLUID: return (P.nf + kBlock - 1) / kBlock;
+    case K_WALL: return (P.nw + kBlock - 1) / kBlock;
+    case K_TOT: return (P.ntot + kBlock - 1) / kBlock;
+    case K_CELL: return (P.grid.ncell + kBlock - 1) / kBlock;
+    case K_TILE: return (P.grid.ncell + kScanTile - 1) / kScanTile;
+    default: return 1;
+    }
+}
+
+// One case of a batch as the batched kernels see it.
+struct CaseEntry {
+    Params P;
+    State S;
+    int64_t nblk[K_COUNT];
+};
+
+// Where a group of launches goes: one case (parameters by value) or a batch
+// of cases of the same dimension, kernel and precision (a device table; a
+// per-kind map from workgroup to case and the case's first workgroup).
+struct Target {
+    const Params *P;
+    const State *S;
+    const CaseEntry *tab;            // device
+    const int32_t *owner[K_COUNT];   // device: case of each workgroup
+    const int64_t *first[K_COUNT];   // device: first workgroup of each case
+    int64_t total[K_COUNT];          // workgroups per kind over the batch
+    int32_t ncase;
+    int32_t dim, kernel, precision;
+    bool batched;
+    hipStream_t s;
+};
+
+enum { RESET_PPE = 1, RESET_NEIGHBOURS = 2, RESET_PREF = 4 };
+enum { POS_X = 0, POS_XS = 1 };
+
+// ---- launch sequences (sisph_kernels.hip) -------------------------------
+void reset_control(const Target &T, int what);
+// Stable counting sort of the fluid at r^n (POS_X, data reordered into cell
+// order) or at r* (POS_XS, cell slots map through perm).
+void bin_fluid(const Target &T, int which);
+// Walls of a single case, once at creation.
+void bin_walls_once(const Target &T);
+void build_neighbors(const Target &T, int which);
+void wall_normals(const Target &T);
+void density(const Target &T);
+void wall_velocity(const Target &T, int which, int slip);
+void predictor(const Target &T);
+void rhs_coef(const Target &T);
+void copy_p32(const Target &T);
+void ppe_iteration(const Target &T, int launch);
+void settle_pressure(const Target &T);
+void wall_pressure_final(const Target &T);
+void pressure_max(const Target &T);
+void correct(const Target &T);
+void gtvf_substep(const Target &T, int k);
+void advance(const Target &T);
+void gather_control(const Target &T, Control *out);
+
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void fill_f64(double *p, double v, int64_t n, hipStream_t s);
-enum { RESET_PPE = 1, RESET_NEIGHBOURS = 2, RESET_PREF = 4 };
-void reset_control(Control *c, int what, hipStream_t s);
-
-// Stable counting sort of [base, base+n) by cell of pos; perm gets, per
-// sorted slot, the source index (relative to base).  sortkey (nullable)
-// orders particles within a cell (otherwise the source index does).
-void bin_particles(const Params &P, const double *const pos[3], int64_t base, int64_t n,
-                   const int32_t *sortkey, State &S, uint32_t *start, int32_t *perm,
-                   hipStream_t s);
-void reorder_f64(const int32_t *perm, int64_t n, double *const *arrays, int narr,
-                 double *tmp, hipStream_t s);
-void reorder_i32(const int32_t *perm, int64_t n, int32_t *a, int32_t *tmp, hipStream_t s);
 void iota_i32(int32_t *p, int64_t n, hipStream_t s);
-
-void build_neighbors(const Params &P, const double *const pos[3], State &S, hipStream_t s);
-
-void wall_normals(const Params &P, State &S, hipStream_t s);
-void density(const Params &P, State &S, hipStream_t s);
-void wall_velocity(const Params &P, const double *const pos[3], const double *const uf[3],
-                   double *const uw[3], int slip, State &S, hipStream_t s);
-void predictor(const Params &P, State &S, hipStream_t s);
-void rhs_coef(const Params &P, State &S, hipStream_t s);
-void ppe_iteration(const Params &P, State &S, int launch, hipStream_t s);
-void wall_pressure_final(const Params &P, State &S, hipStream_t s);
-void pressure_max(const Params &P, State &S, int final_parity, hipStream_t s);
-void correct(const Params &P, State &S, int final_parity, hipStream_t s);
-void gtvf_substep(const Params &P, State &S, int final_parity, int k, hipStream_t s);
-void advance(const Params &P, State &S, int kfinal, hipStream_t s);
-void copy_p32(const Params &P, State &S, hipStream_t s);
 
 }  // namespace sisph

@@ -91,6 +91,17 @@ def lib():
         L.sisph_last_timings.argtypes = [C.c_void_p, _DP, _DP]
         L.sisph_sweep_counters.restype = C.c_int32
         L.sisph_sweep_counters.argtypes = [C.c_void_p, _DP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int32]
+        L.sisph_batch_create.restype = C.c_int32
+        L.sisph_batch_create.argtypes = [C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+        for f in ("sisph_batch_attach", "sisph_batch_detach"):
+            getattr(L, f).restype = C.c_int32
+            getattr(L, f).argtypes = [C.c_void_p, C.c_void_p]
+        L.sisph_batch_size.restype = C.c_int32
+        L.sisph_batch_size.argtypes = [C.c_void_p]
+        L.sisph_batch_step.restype = C.c_int32
+        L.sisph_batch_step.argtypes = [C.c_void_p, C.POINTER(PPEStats)]
+        L.sisph_batch_destroy.restype = C.c_int32
+        L.sisph_batch_destroy.argtypes = [C.c_void_p]
         L.sisph_status_string.restype = C.c_char_p
         L.sisph_status_string.argtypes = [C.c_int32]
         L.sisph_last_error.restype = C.c_char_p
@@ -249,6 +260,55 @@ class Context:
         if getattr(self, "h", None):
             lib().sisph_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent cases stepped together: one launch per kernel for all
+    attached cases (per (dim, kernel, precision) group), each case keeping
+    its own PPE convergence."""
+
+    def __init__(self, max_cases: int = 64, stream=None):
+        import torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        code = lib().sisph_batch_create(int(max_cases), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if code != OK:
+            raise SisphError(code, status_string(code))
+        self.h = h
+        self.members: List[Context] = []
+
+    def attach(self, ctx: Context):
+        _check(lib().sisph_batch_attach(self.h, ctx.h), ctx.h)
+        self.members.append(ctx)
+
+    def detach(self, ctx: Context):
+        _check(lib().sisph_batch_detach(self.h, ctx.h), ctx.h)
+        self.members.remove(ctx)
+
+    def step(self) -> List[dict]:
+        n = len(self.members)
+        st = (PPEStats * max(n, 1))()
+        code = lib().sisph_batch_step(self.h, st)
+        if code < 0:
+            bad = [m for m in self.members if lib().sisph_last_error(m.h)]
+            msg = "; ".join(lib().sisph_last_error(m.h).decode() for m in bad)
+            raise SisphError(code, f"{status_string(code)} ({msg})")
+        out = [st[k].as_dict() for k in range(n)]
+        for o in out:
+            o["status"] = code
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sisph_batch_destroy(self.h)
+            self.h = None
+            self.members = []
 
     def __del__(self):
         try:

@@ -1,0 +1,135 @@
+"""Batched stepping: a case gives bitwise the same state alone and inside a
+batch of uneven cases (its workgroups, sums and stopping decisions do not
+depend on the other cases), across groups of different dimension, kernel
+and precision, with cases attached and detached between steps."""
+import numpy as np
+import pytest
+
+from paper_1908_01762_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1908_01762_amd import sisph
+    return sisph
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _mix():
+    return [
+        cases.taylor_green(24, kernel="wendland", hdx=1.3, precision="mixed", seed=1),
+        cases.taylor_green(40, kernel="wendland", hdx=1.3, precision="mixed", seed=2, re=500.0),
+        cases.dam_break_2d(dx=0.1, precision="mixed"),
+        cases.taylor_green(17, kernel="wendland", hdx=1.3, precision="mixed", seed=3, tol=1e-2),
+        cases.taylor_green(30, precision="fp64", seed=4),                 # other group: quintic FP64
+        cases.dam_break_3d(dx=0.1, lx=0.4, ly=0.4, lz=0.5, tank_x=1.0, tank_y=0.4, tank_z=0.8,
+                           precision="mixed"),                            # other group: 3D
+    ]
+
+
+def _same(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in ("x", "u", "ut", "p"))
+
+
+def test_batch_equals_alone_bitwise():
+    sisph = _gpu()
+    steps = 6
+    alone = []
+    for c in _mix():
+        say("alone", c.name, c.n_fluid, c.n_wall)
+        ctx = sisph.Context(c)
+        its = [s["iters"] for s in ctx.step(steps)]
+        alone.append((ctx.read_state(), its))
+        ctx.close()
+    ctxs = [sisph.Context(c) for c in _mix()]
+    b = sisph.Batch(16)
+    for ctx in ctxs:
+        b.attach(ctx)
+    its_b = [[] for _ in ctxs]
+    for _ in range(steps):
+        for k, s in enumerate(b.step()):
+            its_b[k].append(s["iters"])
+    for k, ctx in enumerate(ctxs):
+        b.detach(ctx)
+        st = ctx.read_state()
+        say("case", k, "iters alone", alone[k][1], "batched", its_b[k])
+        assert its_b[k] == alone[k][1]
+        assert _same(st, alone[k][0]), k
+    b.close()
+    for ctx in ctxs:
+        ctx.close()
+
+
+def test_attach_detach_between_steps():
+    """Cases join and leave; each still matches its own solo run."""
+    sisph = _gpu()
+    mix = _mix()[:4]
+    ref = []
+    for c in mix:
+        ctx = sisph.Context(c)
+        ctx.step(5)
+        ref.append(ctx.read_state())
+        ctx.close()
+    ctxs = [sisph.Context(c) for c in mix]
+    b = sisph.Batch(8)
+    b.attach(ctxs[0])
+    b.attach(ctxs[1])
+    b.step()                   # batch step 1: cases 0, 1
+    b.step()                   # 2: 0, 1
+    b.attach(ctxs[2])          # joins two steps late
+    ctxs[3].step(2)            # runs alone meanwhile
+    b.attach(ctxs[3])
+    b.step()                   # 3: 0, 1, 2, 3
+    b.detach(ctxs[0])          # leaves after 3 steps, finishes alone
+    ctxs[0].step(2)
+    b.step()                   # 4: 1, 2, 3
+    b.step()                   # 5: 1, 2, 3
+    b.detach(ctxs[1])          # 5 steps
+    b.detach(ctxs[3])          # 2 alone + 3 batched
+    b.step()                   # 6: 2
+    b.step()                   # 7: 2
+    b.detach(ctxs[2])          # steps 3..7
+    for k, ctx in enumerate(ctxs):
+        st = ctx.read_state()
+        assert _same(st, ref[k]), k
+    b.close()
+
+
+def test_stepping_an_attached_context_directly_is_refused():
+    sisph = _gpu()
+    c = sisph.Context(cases.taylor_green(16))
+    b = sisph.Batch(2)
+    b.attach(c)
+    with pytest.raises(sisph.SisphError) as e:
+        c.step(1)
+    assert e.value.code == sisph.E_STATE
+    b.close()
+    c.step(1)   # usable again once the batch is gone
+    c.close()
+
+
+def test_a_failing_case_does_not_disturb_the_others():
+    sisph = _gpu()
+    good = cases.taylor_green(20, kernel="wendland", hdx=1.3, precision="mixed")
+    bad = good.copy()
+    bad.u[3, 1] = np.inf
+    solo = sisph.Context(good)
+    solo.step(1)
+    ref = solo.read_state()
+    b = sisph.Batch(4)
+    cg, cb = sisph.Context(good), sisph.Context(bad)
+    b.attach(cg)
+    b.attach(cb)
+    with pytest.raises(sisph.SisphError) as e:
+        b.step()
+    assert e.value.code == sisph.E_NONFINITE
+    b.detach(cg)
+    assert _same(cg.read_state(), ref)
+    b.close()
