@@ -113,6 +113,65 @@ def cpu_baseline(case, budget_s: float) -> dict:
             "particle_steps_per_s": case.n_fluid * steps / dt}
 
 
+def batched_vs_plain(n_cases: int, steps: int, seed: int) -> dict:
+    """The same uneven cases (serving mix: Taylor-Green or 2D dam break, N
+    log-uniform in 2.5k-160k, mixed precision, their own tolerances), first
+    stepped one case at a time with their own launches ("plain"), then all
+    together in one batch; both from the same initial state, same number of
+    steps, hence equal tolerance and equal results."""
+    import torch
+    from paper_1908_01762_amd import cases, sisph
+    mix = [c for _, c in cases.serving_mix(n_cases=n_cases, seed=seed)]
+    nf = sum(c.n_fluid for c in mix)
+    ctxs = [sisph.Context(c) for c in mix]
+    for ctx in ctxs:          # one warm step each (first-step p_ref, caches)
+        ctx.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_plain = 0
+    for ctx in ctxs:
+        it_plain += sum(s["iters"] * ctx.case.n_fluid for s in ctx.step(steps))
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    for ctx in ctxs:
+        ctx.close()
+    ctxs = [sisph.Context(c) for c in mix]
+    b = sisph.Batch(len(ctxs))
+    for ctx in ctxs:
+        b.attach(ctx)
+    b.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_batch = 0
+    for _ in range(steps):
+        it_batch += sum(s["iters"] * c.case.n_fluid for s, c in zip(b.step(), ctxs))
+    torch.cuda.synchronize()
+    batched = time.perf_counter() - t0
+    b.close()
+    for ctx in ctxs:
+        ctx.close()
+    return {"cases": len(mix), "fluid_particles": nf, "steps": steps,
+            "plain_s": plain, "batched_s": batched, "speedup": plain / batched,
+            "plain_ppe_particle_iters_per_s": it_plain / plain,
+            "batched_ppe_particle_iters_per_s": it_batch / batched,
+            "same_sweep_counts": it_plain == it_batch,
+            "workload": "serving mix (seed %d): Taylor-Green / 2D dam break, N log-uniform 2.5k-160k, "
+                        "mixed precision, tol 1e-4 (TG) / 1e-3 (dam break)" % seed}
+
+
+def serving(n_requests: int, steps: int, rate_hz: float, budget_gb: float, seed: int) -> dict:
+    """Continuous batching: Poisson arrivals, admission by workspace bytes."""
+    from paper_1908_01762_amd import cases
+    from paper_1908_01762_amd.serve import GpuBackend, Server, requests_from_mix
+    reqs = requests_from_mix(cases.serving_mix(n_cases=n_requests, seed=seed, rate_hz=rate_hz), steps)
+    backend = GpuBackend(max_slots=n_requests)
+    srv = Server(backend, budget_bytes=int(budget_gb * 1e9), max_slots=n_requests, keep_results=False)
+    rep = srv.run(reqs)
+    backend.close()
+    rep.update(requests_per_s_offered=rate_hz, steps_per_request=steps)
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +180,14 @@ def main():
     ap.add_argument("--workload", default="tg400_wendland_mixed", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch-compare", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--batch-cases", type=int, default=16)
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=20)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=1.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -183,6 +250,13 @@ def main():
         "roofline": roofline,
     }
     ctx.close()
+    if not args.no_batch_compare:
+        print("[bench] batched vs plain", file=sys.stderr, flush=True)
+        line["batched_vs_plain"] = batched_vs_plain(args.batch_cases, args.batch_steps, seed=0)
+    if not args.no_serving:
+        print("[bench] serving", file=sys.stderr, flush=True)
+        line["serving"] = serving(args.serve_requests, args.serve_steps, args.serve_rate,
+                                  args.serve_budget_gb, seed=1)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(make_case(args.workload), args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -96,7 +96,7 @@ typedef struct {
     int32_t iters;       /* Jacobi sweeps done                              */
     int32_t converged;   /* final ratio < tol                               */
     int32_t nonfinite;   /* a non-finite pressure sum was seen              */
-    int32_t reserved;
+    int32_t status;      /* this case's status code (SISPH_OK, ...)      */
     double ratio;        /* eq. convergence at the last sweep               */
     double lambda;       /* max |RHS_i / D_ii| over non-free-surface fluid   */
     double p_ref;        /* GTVF reference pressure in use                  */

@@ -264,11 +264,13 @@ static int32_t fail(sisph_ctx *ctx, int32_t code, const std::string &msg) {
     return code;
 }
 
+static int32_t status_of(const Control &C, const Params &P, std::string *msg);
+
 static void fill_stats(const Control &C, const Params &P, sisph_ppe_stats *out) {
     out->iters = C.iter;
     out->converged = C.ratio < P.tol ? 1 : 0;
     out->nonfinite = C.nonfinite;
-    out->reserved = 0;
+    out->status = status_of(C, P, nullptr);
     out->ratio = C.ratio;
     union {
         unsigned long long u;

@@ -47,11 +47,12 @@ class CaseDesc(C.Structure):
 
 class PPEStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("nonfinite", C.c_int32),
-                ("reserved", C.c_int32), ("ratio", C.c_double), ("lambda_", C.c_double),
+                ("status", C.c_int32), ("ratio", C.c_double), ("lambda_", C.c_double),
                 ("p_ref", C.c_double)]
 
     def as_dict(self) -> dict:
         return dict(iters=self.iters, converged=bool(self.converged), nonfinite=bool(self.nonfinite),
+                    case_status=self.status,
                     ratio=self.ratio, lam=self.lambda_, p_ref=self.p_ref)
 
 
@@ -291,15 +292,17 @@ class Batch:
         _check(lib().sisph_batch_detach(self.h, ctx.h), ctx.h)
         self.members.remove(ctx)
 
-    def step(self) -> List[dict]:
+    def step(self, raise_on_error: bool = True) -> List[dict]:
+        """One step of every attached case, stats in attach order.  Each
+        entry's case_status is that case's own status code."""
         n = len(self.members)
         st = (PPEStats * max(n, 1))()
         code = lib().sisph_batch_step(self.h, st)
-        if code < 0:
-            bad = [m for m in self.members if lib().sisph_last_error(m.h)]
-            msg = "; ".join(lib().sisph_last_error(m.h).decode() for m in bad)
-            raise SisphError(code, f"{status_string(code)} ({msg})")
         out = [st[k].as_dict() for k in range(n)]
+        if code < 0 and raise_on_error:
+            bad = [m for m, o in zip(self.members, out) if o["case_status"] < 0]
+            msg = "; ".join(lib().sisph_last_error(m.h).decode() for m in bad) or status_string(code)
+            raise SisphError(code, f"{status_string(code)} ({msg})")
         for o in out:
             o["status"] = code
         return out
