@@ -36,6 +36,8 @@ WORKLOADS = {
     "tg50_quintic_fp64": "2D Taylor-Green 50x50, quintic h=dx, Re=100, tol 1e-4, FP64",
     "db2d_dx0.005_mixed": "2D dam break 1x2 column in a 4x4 tank, dx=0.005 (80,000 fluid + 7,218 wall), "
                           "Wendland h=1.3dx, tol 1e-3, mixed",
+    "db3d_dx0.01_mixed": "3D dam break 1x1x2 block in a 4x1x4 tank, dx=0.01 (2,000,000 fluid + 1,343,508 wall), "
+                         "Wendland h=1.3dx, gravity, free surface, external GTVF, tol 1e-3, mixed",
 }
 
 
@@ -49,6 +51,8 @@ def make_case(name: str):
         return cases.taylor_green(50)
     if name == "db2d_dx0.005_mixed":
         return cases.dam_break_2d(dx=0.005, precision="mixed", tol=1e-3)
+    if name == "db3d_dx0.01_mixed":
+        return cases.dam_break_3d(dx=0.01, precision="mixed", tol=1e-3)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -188,6 +192,9 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=20)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gb", type=float, default=1.0)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a counter calibration "
+                         "reference for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -201,6 +208,16 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     sisph.lib()
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written",
+              file=sys.stderr, flush=True)
+        del src, dst
     case = make_case(args.workload)
     ctx = sisph.Context(case, device="cuda:0")
     print(f"[bench] workload {args.workload}: {case.n_fluid} fluid + {case.n_wall} wall particles, "

@@ -174,6 +174,22 @@ int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_t *launches
 
 int32_t sisph_destroy(sisph_ctx *ctx);
 
+/* ------------------------------------------------------------- autotuning
+ * The Jacobi sweep comes in SISPH_SWEEP_VARIANTS launch variants (how many
+ * neighbour slots are fetched in the first round trip, and whether
+ * workgroups are mapped to XCDs in contiguous ranges).  They differ in speed
+ * only: every variant computes the same sums in the same order.
+ * sisph_autotune times each variant `reps` times on the context's current
+ * state (it needs one completed step; it writes only the scratch iterate, so
+ * the simulation state is unchanged), selects the fastest and returns it in
+ * *best and the mean launch time of every variant in us[] (microseconds,
+ * SISPH_SWEEP_VARIANTS entries, nullable).  A batch launches its group with
+ * the variant of its largest case. */
+enum { SISPH_SWEEP_VARIANTS = 6 };
+int32_t sisph_autotune(sisph_ctx *ctx, int32_t reps, int32_t *best, double *us);
+int32_t sisph_set_variant(sisph_ctx *ctx, int32_t variant);
+int32_t sisph_get_variant(sisph_ctx *ctx);
+
 /* ------------------------------------------------------------- batching
  * Many independent cases stepped together: every kernel of a step is one
  * launch over all attached cases that share dimension, kernel and

@@ -33,6 +33,7 @@ struct sisph_ctx {
     int64_t sweep_launches, sweep_effective;
     bool step_timed;
     sisph_batch *batch;  // non-null while attached
+    int32_t variant;     // Jacobi-sweep launch variant
     std::string err;
 };
 
@@ -229,6 +230,7 @@ static Target single_target(sisph_ctx *ctx) {
     T.dim = ctx->P.dim;
     T.kernel = ctx->P.kernel;
     T.precision = ctx->P.precision;
+    T.variant = ctx->variant;
     T.s = ctx->stream;
     return T;
 }
@@ -334,6 +336,7 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
     ctx->sweep_launches = ctx->sweep_effective = 0;
     ctx->step_timed = false;
     ctx->batch = nullptr;
+    ctx->variant = kDefaultVariant;
     ctx->h_ctl = nullptr;
     for (auto &e : ctx->ev) e = nullptr;
     for (auto &e : ctx->evc) e = nullptr;
@@ -955,6 +958,11 @@ static int32_t group_step(sisph_batch *b, Group &g) {
         int32_t st = rebuild_group(b, g);
         if (st != SISPH_OK) return st;
     }
+    // the group's sweep variant is that of its largest case
+    const sisph_ctx *largest = g.members[0];
+    for (auto *c : g.members)
+        if (c->P.nf > largest->P.nf) largest = c;
+    g.T.variant = largest->variant;
     const Target &T = g.T;
     const size_t n = g.members.size();
     int64_t limit = 1, predicted = 1;
@@ -1030,6 +1038,46 @@ extern "C" int32_t sisph_batch_destroy(sisph_batch *b) {
     delete b;
     return SISPH_OK;
 }
+
+// ------------------------------------------------------------- autotune
+extern "C" int32_t sisph_autotune(sisph_ctx *ctx, int32_t reps, int32_t *best, double *us) {
+    if (!ctx || reps < 1) return SISPH_E_INVAL;
+    if (attached(ctx)) return fail(ctx, SISPH_E_STATE, "context is attached to a batch");
+    if (ctx->state != ST_READY || ctx->nbr_stage != 1)
+        return fail(ctx, SISPH_E_STATE, "sisph_autotune needs one completed step");
+    // launch 0 of a sweep reads the current pressure (iterate 0) and writes
+    // only iterate 1, the FP32 copy and the partial sums: scratch between steps
+    Target T = ctx->T;
+    double t_us[kSweepVariants];
+    int32_t win = 0;
+    for (int v = 0; v < kSweepVariants; ++v) {
+        T.variant = v;
+        sweep_only(T, 0);   // warm-up
+        HIPCHK(ctx, hipEventRecord(ctx->evc[0], ctx->stream));
+        for (int r = 0; r < reps; ++r) sweep_only(T, 0);
+        HIPCHK(ctx, hipEventRecord(ctx->evc[1], ctx->stream));
+        HIPCHK(ctx, hipEventSynchronize(ctx->evc[1]));
+        HIPCHK(ctx, hipGetLastError());
+        float ms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->evc[0], ctx->evc[1]));
+        t_us[v] = ms * 1e3 / reps;
+        if (us) us[v] = t_us[v];
+        if (v == 0 || t_us[v] < t_us[win]) win = v;
+    }
+    ctx->variant = win;
+    ctx->T.variant = win;
+    if (best) *best = win;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_set_variant(sisph_ctx *ctx, int32_t variant) {
+    if (!ctx || variant < 0 || variant >= kSweepVariants) return SISPH_E_INVAL;
+    ctx->variant = variant;
+    ctx->T.variant = variant;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_get_variant(sisph_ctx *ctx) { return ctx ? ctx->variant : SISPH_E_INVAL; }
 
 extern "C" int32_t sisph_destroy(sisph_ctx *ctx) {
     if (!ctx) return SISPH_E_INVAL;

@@ -118,6 +118,7 @@ struct Target {
     int64_t total[K_COUNT];          // workgroups per kind over the batch
     int32_t ncase;
     int32_t dim, kernel, precision;
+    int32_t variant;                 // Jacobi-sweep variant (speed only)
     bool batched;
     hipStream_t s;
 };
@@ -140,6 +141,10 @@ void predictor(const Target &T);
 void rhs_coef(const Target &T);
 void copy_p32(const Target &T);
 void ppe_iteration(const Target &T, int launch);
+// The sweep alone (no wall pressure), for timing variants.
+void sweep_only(const Target &T, int launch);
+constexpr int kSweepVariants = 6;
+constexpr int kDefaultVariant = 1;
 void settle_pressure(const Target &T);
 void wall_pressure_final(const Target &T);
 void pressure_max(const Target &T);

@@ -221,28 +221,37 @@ __device__ __forceinline__ double order_val(unsigned long long k) {
 }
 
 // ================================================================ wrappers
-template <class F, class... A>
-__global__ __launch_bounds__(kBlock) void k_one(const Params P, const State S, A... a) {
-    F::run(P, S, xcd_block(), (int64_t)gridDim.x, 0, a...);
+// XCD: logical workgroup = XCD-contiguous remap of the hardware index (the
+// default), or the hardware index itself.  Either way each logical
+// workgroup does the same work, so results do not depend on it.
+template <bool XCD>
+__device__ __forceinline__ int64_t logical_block() {
+    if constexpr (XCD) return xcd_block();
+    else return (int64_t)blockIdx.x;
 }
 
-template <class F, int KIND, class... A>
+template <class F, bool XCD, class... A>
+__global__ __launch_bounds__(kBlock) void k_one(const Params P, const State S, A... a) {
+    F::run(P, S, logical_block<XCD>(), (int64_t)gridDim.x, 0, a...);
+}
+
+template <class F, int KIND, bool XCD, class... A>
 __global__ __launch_bounds__(kBlock) void k_many(const CaseEntry *__restrict__ tab,
                                                  const int32_t *__restrict__ owner,
                                                  const int64_t *__restrict__ first, A... a) {
-    const int64_t b = xcd_block();
+    const int64_t b = logical_block<XCD>();
     const int c = owner[b];
     const CaseEntry &e = tab[c];
     F::run(e.P, e.S, b - first[c], e.nblk[KIND], c, a...);
 }
 
-template <class F, int KIND, class... A>
+template <class F, int KIND, bool XCD = true, class... A>
 void launch(const Target &T, A... a) {
     if (!T.batched) {
         const int64_t nb = kind_blocks(*T.P, KIND);
-        if (nb > 0) k_one<F, A...><<<nb, kBlock, 0, T.s>>>(*T.P, *T.S, a...);
+        if (nb > 0) k_one<F, XCD, A...><<<nb, kBlock, 0, T.s>>>(*T.P, *T.S, a...);
     } else if (T.total[KIND] > 0) {
-        k_many<F, KIND, A...><<<T.total[KIND], kBlock, 0, T.s>>>(T.tab, T.owner[KIND], T.first[KIND], a...);
+        k_many<F, KIND, XCD, A...><<<T.total[KIND], kBlock, 0, T.s>>>(T.tab, T.owner[KIND], T.first[KIND], a...);
     }
 }
 
@@ -844,12 +853,14 @@ struct CopyP32 {
 // once: stopped_at < L can only have been written by an earlier launch, so
 // every wavefront reads the same answer.
 //
-// First batch: slots 1..kSweepFirst loaded without waiting for the row's
-// count (every slot below cap is inside the list storage; slots past the
-// count hold stale words and are discarded by the select), so the row loads,
+// First batch: slots 1..FIRST loaded without waiting for the row's count
+// (every slot below cap is inside the list storage; slots past the count
+// hold stale words and are discarded by the select), so the row loads,
 // these loads and the partial-sum loads form one round trip.  Longer rows
-// continue in batches of kSweepBatch.  The sum still runs in slot order.
-constexpr int kSweepFirst = 24;
+// continue in batches of kSweepBatch.  The sum runs in slot order whatever
+// FIRST is, so FIRST (chosen by the autotuner among kSweepFirsts) and the
+// workgroup mapping change the speed only, never the result.
+constexpr int kSweepFirsts[3] = {16, 24, 32};
 constexpr int kSweepBatch = 8;
 constexpr int kPartialRegs = 8;
 
@@ -961,7 +972,7 @@ __device__ bool stopped_after(const Params &P, const double *partial, int64_t nb
     return stop_sh != 0;
 }
 
-template <typename R>
+template <typename R, int FIRST>
 struct Sweep {
     static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int L) {
         Control *ctl = S.ctl;
@@ -980,14 +991,14 @@ struct Sweep {
         if (i < nf) {
             // one round trip: row values, the first batch of (j, c) words and
             // (above) the partial sums
-            int32_t jj[kSweepFirst];
-            R cc[kSweepFirst];
-            load_batch<R, kSweepFirst>(i, nf, 1, 0, P.cap, true, coef, S.nbr, jj, cc);
+            int32_t jj[FIRST];
+            R cc[FIRST];
+            load_batch<R, FIRST>(i, nf, 1, 0, P.cap, true, coef, S.nbr, jj, cc);
             const double D = S.dii[i], r = S.rhs[i];
             const int32_t f = S.fs[i], c = S.cnt[i];
             pold = pc[i];
-            R s = gather_sum<R, kSweepFirst>(i, 1, c, jj, cc, pc, qc, R(0));
-            for (int k0 = 1 + kSweepFirst; k0 < c; k0 += kSweepBatch) {
+            R s = gather_sum<R, FIRST>(i, 1, c, jj, cc, pc, qc, R(0));
+            for (int k0 = 1 + FIRST; k0 < c; k0 += kSweepBatch) {
                 int32_t jb[kSweepBatch];
                 R cb[kSweepBatch];
                 load_batch<R, kSweepBatch>(i, nf, k0, c, P.cap, false, coef, S.nbr, jb, cb);
@@ -1301,10 +1312,28 @@ void rhs_coef(const Target &T) { SISPH_DISPATCH_KDR(T, (launch<RhsCoef<KER, D, R
 
 void copy_p32(const Target &T) { launch<CopyP32, K_TOT>(T); }
 
+// Sweep variants (numerically identical): first-batch size kSweepFirsts[v % 3],
+// XCD-contiguous workgroup mapping for v < 3, hardware order otherwise.
+template <typename R>
+static void sweep_variant(const Target &T, int L, int v) {
+    switch (v) {
+    case 0: launch<Sweep<R, kSweepFirsts[0]>, K_FLUID, true>(T, L); break;
+    case 2: launch<Sweep<R, kSweepFirsts[2]>, K_FLUID, true>(T, L); break;
+    case 3: launch<Sweep<R, kSweepFirsts[0]>, K_FLUID, false>(T, L); break;
+    case 4: launch<Sweep<R, kSweepFirsts[1]>, K_FLUID, false>(T, L); break;
+    case 5: launch<Sweep<R, kSweepFirsts[2]>, K_FLUID, false>(T, L); break;
+    default: launch<Sweep<R, kSweepFirsts[1]>, K_FLUID, true>(T, L); break;
+    }
+}
+
+void sweep_only(const Target &T, int L) {
+    if (T.precision == SISPH_MIXED) sweep_variant<float>(T, L, T.variant);
+    else sweep_variant<double>(T, L, T.variant);
+}
+
 void ppe_iteration(const Target &T, int L) {
     SISPH_DISPATCH_KDR(T, (launch<WallPressure<KER, D, R>, K_WALL>(T, L, 0)));
-    if (T.precision == SISPH_MIXED) launch<Sweep<float>, K_FLUID>(T, L);
-    else launch<Sweep<double>, K_FLUID>(T, L);
+    sweep_only(T, L);
 }
 
 void settle_pressure(const Target &T) { launch<SettlePressure, K_TOT>(T); }

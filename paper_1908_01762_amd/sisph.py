@@ -18,6 +18,7 @@ from . import cases as _cases
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsisph.so")
 
+SWEEP_VARIANTS = 6
 OK, WARN_MAXITER = 0, 1
 E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_NONFINITE = -1, -2, -3, -4, -5
 
@@ -92,6 +93,12 @@ def lib():
         L.sisph_last_timings.argtypes = [C.c_void_p, _DP, _DP]
         L.sisph_sweep_counters.restype = C.c_int32
         L.sisph_sweep_counters.argtypes = [C.c_void_p, _DP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int32]
+        L.sisph_autotune.restype = C.c_int32
+        L.sisph_autotune.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), _DP]
+        L.sisph_set_variant.restype = C.c_int32
+        L.sisph_set_variant.argtypes = [C.c_void_p, C.c_int32]
+        L.sisph_get_variant.restype = C.c_int32
+        L.sisph_get_variant.argtypes = [C.c_void_p]
         L.sisph_batch_create.restype = C.c_int32
         L.sisph_batch_create.argtypes = [C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
         for f in ("sisph_batch_attach", "sisph_batch_detach"):
@@ -241,16 +248,37 @@ class Context:
         c = self.case
         rows = c.n_fluid if dest == 0 else c.n_wall
         off = np.zeros(rows + 1, dtype=np.int64)
-        cap = max(1, 300 * rows)
-        ids = np.zeros(cap, dtype=np.int32)
-        _check(lib().sisph_debug_neighbors(self.h, stage, dest, off.ctypes.data_as(C.POINTER(C.c_int64)),
-                                            ids.ctypes.data_as(C.POINTER(C.c_int32)), cap), self.h)
+        offp = off.ctypes.data_as(C.POINTER(C.c_int64))
+        # first pass sizes the id buffer (offsets are complete even when the
+        # ids do not fit), second pass fills it
+        code = lib().sisph_debug_neighbors(self.h, stage, dest, offp, None, 0)
+        if code != E_NOMEM or off[-1] == 0:
+            _check(code, self.h)
+        ids = np.zeros(max(int(off[-1]), 1), dtype=np.int32)
+        _check(lib().sisph_debug_neighbors(self.h, stage, dest, offp, ids.ctypes.data_as(C.POINTER(C.c_int32)),
+                                            ids.size), self.h)
         return off, ids[:off[-1]].copy()
 
     def timings(self):
         a, b = C.c_double(), C.c_double()
         _check(lib().sisph_last_timings(self.h, C.byref(a), C.byref(b)), self.h)
         return a.value, b.value
+
+    def autotune(self, reps: int = 20):
+        """Times the sweep variants on the current state (needs one completed
+        step); selects the fastest.  Returns (best, [us per variant])."""
+        best = C.c_int32()
+        us = (C.c_double * SWEEP_VARIANTS)()
+        _check(lib().sisph_autotune(self.h, int(reps), C.byref(best), us), self.h)
+        return best.value, list(us)
+
+    @property
+    def variant(self) -> int:
+        return int(lib().sisph_get_variant(self.h))
+
+    @variant.setter
+    def variant(self, v: int):
+        _check(lib().sisph_set_variant(self.h, int(v)), self.h)
 
     def sweep_counters(self, reset: bool = False):
         ms, n, e = C.c_double(), C.c_int64(), C.c_int64()

@@ -1,0 +1,153 @@
+"""Parity at the benchmark's full sizes, in the configuration bench.py times.
+
+* 160k-particle Taylor-Green (Wendland h = 1.3 dx, Re = 100, tol 1e-4):
+  neighbour sets bit-exact at r^n and r*; one step against the oracle in
+  FP64 (same sweep count, fields to 1e-5 relative L2) and in the mixed mode
+  (oracle run on the GPU's sweep count; FP32-rounding bounds).
+* 2D dam break, dx = 0.005 (80,000 fluid + 7,218 wall particles), mixed.
+* 3D dam break, dx = 0.01 (2,000,000 fluid + 1,343,508 wall particles):
+  the oracle cannot step it in seconds, so sampled rows are compared one by
+  one (neighbour sets bit-exact, summation density from those sets) and the
+  whole step is checked for properties that hold at any size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_01762_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1908_01762_amd import sisph
+    return sisph
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0))
+
+
+def _tg400(precision):
+    return cases.taylor_green(400, kernel="wendland", hdx=1.3, precision=precision, tol=1e-4)
+
+
+def test_tg400_neighbours_bit_exact():
+    sisph = _gpu()
+    case = _tg400("mixed")
+    ctx = sisph.Context(case)
+    ctx.bin()
+    off, ids = ctx.neighbors(0, 0)
+    roff, rids = oracle.neighbors(case)
+    assert np.array_equal(off, roff) and np.array_equal(ids, rids)
+    ctx.predict()
+    xs = ctx.field("xstar")
+    off, ids = ctx.neighbors(1, 0)
+    roff, rids = oracle.neighbors(case, x=xs)
+    assert np.array_equal(off, roff) and np.array_equal(ids, rids)
+    ctx.close()
+
+
+def test_tg400_one_step_fp64():
+    sisph = _gpu()
+    case = _tg400("fp64")
+    ref = oracle.Sim(case)
+    out = ref.step(capture=True)
+    ctx = sisph.Context(case)
+    g = ctx.step(1)[0]
+    s = ctx.read_state()
+    assert g["iters"] == out["iters"]
+    for name, a, b in (("rho", ctx.field("rho"), out["rho"]), ("rhs", ctx.field("rhs"), out["rhs"]),
+                       ("p", s["p"], ref.p), ("u", s["u"], ref.u),
+                       ("displacement", s["x"] - case.x, ref.x - case.x)):
+        e = rel(a, b)
+        say(f"  tg400 fp64 {name:12s} {e:.3e}")
+        assert e < 1e-5, name
+    ctx.close()
+
+
+def test_tg400_one_step_mixed():
+    sisph = _gpu()
+    case = _tg400("mixed")
+    ctx = sisph.Context(case)
+    g = ctx.step(1)[0]
+    ref = oracle.Sim(case, forced_iters=g["iters"])
+    out = ref.step(capture=True)
+    s = ctx.read_state()
+    errs = dict(rho=rel(ctx.field("rho"), out["rho"]), rhs=rel(ctx.field("rhs"), out["rhs"]),
+                p=rel(s["p"], ref.p), u=rel(s["u"], ref.u),
+                displacement=rel(s["x"] - case.x, ref.x - case.x))
+    for k, e in errs.items():
+        say(f"  tg400 mixed {k:12s} {e:.3e}")
+    assert errs["rho"] < 1e-6 and errs["u"] < 1e-4 and errs["displacement"] < 1e-4
+    assert errs["rhs"] < 1e-3 and errs["p"] < 1e-3
+    ctx.close()
+
+
+def test_dam_break_2d_full_one_step_mixed():
+    sisph = _gpu()
+    case = cases.dam_break_2d(dx=0.005, precision="mixed")
+    ctx = sisph.Context(case)
+    ctx.bin()
+    off, ids = ctx.neighbors(0, 0)
+    roff, rids = oracle.neighbors(case)
+    assert np.array_equal(off, roff) and np.array_equal(ids, rids)
+    ctx.predict()
+    g_iters = ctx.ppe_solve()["iters"]
+    ctx.correct()
+    st = ctx.read_state()
+    ref = oracle.Sim(case, forced_iters=g_iters)
+    out = ref.step(capture=True)
+    errs = dict(rho=rel(ctx.field("rho"), out["rho"]), p=rel(st["p"], ref.p), u=rel(st["u"], ref.u))
+    for k, e in errs.items():
+        say(f"  db2d dx=0.005 mixed {k:5s} {e:.3e} ({g_iters} sweeps)")
+    assert errs["rho"] < 1e-6 and errs["p"] < 1e-3 and errs["u"] < 1e-3
+    ctx.close()
+
+
+def test_dam_break_3d_full_sampled():
+    sisph = _gpu()
+    case = cases.dam_break_3d(dx=0.01, precision="mixed")
+    say("3D dam break", case.n_fluid, case.n_wall)
+    ctx = sisph.Context(case)
+    ctx.bin()
+    off, ids = ctx.neighbors(0, 0)
+    rng = np.random.Generator(np.random.PCG64(7))
+    R = oracle.support(case.kernel) * case.h
+    sampled = {}
+    for s0 in rng.integers(0, case.n_fluid - 200, size=5):
+        s0 = int(s0)
+        roff, rids = oracle.neighbors(case, dest=(s0, s0 + 200))
+        for k in range(200):
+            ref = rids[roff[k]:roff[k + 1]]
+            assert np.array_equal(ids[off[s0 + k]:off[s0 + k + 1]], ref), s0 + k
+            sampled[s0 + k] = ref
+    del off, ids
+    ctx.predict()
+    rho = ctx.field("rho")
+    for i in list(sampled)[::10]:
+        nb = sampled[i]
+        r = np.linalg.norm(case.x[i] - case.x[nb], axis=1)
+        assert r.max() < R
+        want = float(np.sum(case.m[nb] * oracle.W(case.kernel, 3, r, case.h)))
+        assert abs(rho[i] - want) < 1e-6 * want, i
+    ctx.ppe_solve()
+    ctx.correct()
+    g = ctx.step(2)
+    s = ctx.read_state()
+    say("  3D steps:", [x["iters"] for x in g])
+    assert all(np.isfinite(s[k]).all() for k in ("x", "u", "p"))
+    assert all(1 <= x["iters"] <= case.max_iter for x in g)
+    # the fluid falls and stays inside the tank
+    z0 = case.x[:case.n_fluid, 2].mean()
+    assert s["x"][:case.n_fluid, 2].mean() < z0
+    assert s["x"][:case.n_fluid, 0].min() > -0.01 and s["x"][:case.n_fluid, 2].min() > -0.01
+    ctx.close()
