@@ -61,6 +61,7 @@ enum { SISPH_ASYMM = 0, SISPH_SYMM = 1 };                /* pressure gradient */
 enum { SISPH_GTVF_OFF = 0, SISPH_GTVF_INTERNAL = 1, SISPH_GTVF_EXTERNAL = 2 };
 enum { SISPH_PREF_FIXED = 0, SISPH_PREF_TWICE_MAX = 1 };
 enum { SISPH_CONV_SUM = 0, SISPH_CONV_MEAN = 1 };
+enum { SISPH_USTAR_SLIP = 0, SISPH_USTAR_NOSLIP = 1 };
 
 /* One case.  Parameters follow the paper's statement of the problem.
  *  precision   SISPH_FP64: every sum in FP64.  SISPH_MIXED: neighbour sums,
@@ -80,6 +81,9 @@ enum { SISPH_CONV_SUM = 0, SISPH_CONV_MEAN = 1 };
  *  eta         the 0.01 of r^2 + eta h^2.
  *  dx          initial particle spacing; sizes the neighbour storage.
  *  nbr_cap     neighbour slots per particle (0: derived from h and dx).
+ *  ustar_wall  wall ghost form for u* in the PPE: SISPH_USTAR_SLIP (the
+ *              Shepard average of u*) or SISPH_USTAR_NOSLIP (2 u_wall minus
+ *              it); either way any part into the solid is removed.
  *  periodic    per axis; the box is [box_lo, box_hi) on periodic axes and
  *              the binning range (particles outside are clamped to the edge
  *              cells) on the others.                                         */
@@ -87,6 +91,7 @@ typedef struct {
     int32_t dim, kernel, precision, pgrad, gtvf, free_surface;
     int32_t p_ref_mode, conv_norm, min_iter, max_iter, gtvf_K, forced_iters;
     int32_t periodic[3], nbr_cap;
+    int32_t ustar_wall, reserved0;
     int64_t n_fluid, n_wall;
     double h, dx, rho0, nu, alpha, c_ref, dt, eta, fs_ratio, omega, tol, p_ref;
     double gravity[3], box_lo[3], box_hi[3];

@@ -23,6 +23,7 @@ PGRAD = {"asymm": 0, "symm": 1}
 GTVF = {"off": 0, "internal": 1, "external": 2}
 PREF = {"fixed": 0, "twice_max": 1}
 CONV = {"sum": 0, "mean": 1}
+USTAR = {"slip": 0, "noslip": 1}
 
 
 def build(force: bool = False) -> str:
@@ -38,7 +39,7 @@ def build(force: bool = False) -> str:
 class Params(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "dim", "kernel", "pgrad", "gtvf", "free_surface", "p_ref_mode",
-        "min_iter", "max_iter", "gtvf_K", "forced_iters", "conv_norm", "nf", "nw")] + \
+        "min_iter", "max_iter", "gtvf_K", "forced_iters", "conv_norm", "ustar_wall", "nf", "nw")] + \
         [(n, C.c_double) for n in (
             "h", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio", "omega", "tol")] + \
         [("g", C.c_double * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
@@ -101,6 +102,7 @@ def params(case, **over) -> Params:
     P.gtvf_K = case.gtvf_K
     P.forced_iters = case.forced_iters
     P.conv_norm = CONV[case.conv_norm]
+    P.ustar_wall = USTAR[case.ustar_wall]
     P.nf = case.n_fluid
     P.nw = case.n_wall
     for k in ("h", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio", "omega", "tol"):

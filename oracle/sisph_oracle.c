@@ -625,10 +625,12 @@ int64_t orc_step(const orc_params *P, double *x, double *u, double *ut, double *
     csr_free(&N);
     csr_free(&Nw);
 
-    /* step 6: neighbours at r*; wall u* in the slip form */
+    /* step 6: neighbours at r*; wall u* in the slip form (default, reading
+     * R12) or the no-slip form (the alternative compared in section 4.3) */
     N = fluid_nbrs(P, xs);
     Nw = wall_nbrs(P, xs);
-    if (nw) wall_velocity_c(P, &Nw, xs, us_all, wall_u, nrm, 1, us_all + nf * dim);
+    if (nw) wall_velocity_c(P, &Nw, xs, us_all, wall_u, nrm, P->ustar_wall == ORC_USTAR_NOSLIP ? 0 : 1,
+                            us_all + nf * dim);
 
     /* step 7: RHS, coefficients, D_ii, Lambda (eq. convergence; |RHS/D| over
      * non-free-surface fluid with D != 0, reading R2) */

@@ -20,10 +20,11 @@ enum { ORC_ASYMM = 0, ORC_SYMM = 1 };
 enum { ORC_GTVF_OFF = 0, ORC_GTVF_INTERNAL = 1, ORC_GTVF_EXTERNAL = 2 };
 enum { ORC_PREF_FIXED = 0, ORC_PREF_TWICE_MAX = 1 };
 enum { ORC_CONV_SUM = 0, ORC_CONV_MEAN = 1 };
+enum { ORC_USTAR_SLIP = 0, ORC_USTAR_NOSLIP = 1 };
 
 typedef struct {
     int64_t dim, kernel, pgrad, gtvf, free_surface, p_ref_mode;
-    int64_t min_iter, max_iter, gtvf_K, forced_iters, conv_norm;
+    int64_t min_iter, max_iter, gtvf_K, forced_iters, conv_norm, ustar_wall;
     int64_t nf, nw;
     double h, rho0, nu, alpha, c_ref, dt, eta, fs_ratio, omega, tol;
     double g[3], lo[3], hi[3];

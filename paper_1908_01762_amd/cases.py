@@ -1,11 +1,11 @@
 """Seeded synthetic particle sets for the SISPH hot path.
 
 This module only lays particles out and fills in the initial fields of the
-paper's test problems (Taylor-Green vortex, section 4.1, eq. tgv; 2D/3D dam
-break, sections 4.5-4.6).  It holds none of the method's arithmetic: no kernel,
-no neighbour search, no SPH sum.  Both the CPU oracle and the HIP path consume
-exactly the arrays built here, so a parity test compares two implementations
-on the same bytes.
+paper's test problems (Taylor-Green vortex, section 4.1, eq. tgv; lid-driven
+cavity, section 4.3; 2D/3D dam break, sections 4.5-4.6).  It holds none of the
+method's arithmetic: no kernel, no neighbour search, no SPH sum.  Both the CPU
+oracle and the HIP path consume exactly the arrays built here, so a parity
+test compares two implementations on the same bytes.
 
 Every array is float64, row-major, fluid rows first and wall rows after them:
 
@@ -14,7 +14,8 @@ Every array is float64, row-major, fluid rows first and wall rows after them:
                                    equal to it)
 * ``p``  [n_fluid + n_wall]        pressure (walls start at 0)
 * ``m``  [n_fluid + n_wall]        mass
-* ``wall_u`` [n_wall][dim]         prescribed wall velocity (zero: static tanks)
+* ``wall_u`` [n_wall][dim]         prescribed wall velocity (zero for static
+                                   walls, (U, 0) for the cavity lid)
 
 Random numbers come from numpy's PCG64 seeded per case; the jitter is uniform
 in [-j*dx, +j*dx] per coordinate, mass and density unchanged.
@@ -33,6 +34,7 @@ GTVF = {"off": 0, "internal": 1, "external": 2}
 PREF = {"fixed": 0, "twice_max": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
 CONV = {"sum": 0, "mean": 1}
+USTAR = {"slip": 0, "noslip": 1}
 SUPPORT = {"quintic": 3.0, "wendland": 2.0}
 
 
@@ -76,6 +78,7 @@ class Case:
     gtvf_K: int = 5
     forced_iters: int = 0
     conv_norm: str = "sum"
+    ustar_wall: str = "slip"
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -206,6 +209,60 @@ def dam_break_2d(dx: float = 0.005, width: float = 1.0, height: float = 2.0,
         x=np.ascontiguousarray(x), u=u, p=p, m=m, n_fluid=nf, n_wall=nw,
         wall_u=np.zeros((nw, 2)), precision=precision, gtvf_K=gtvf_K,
         meta=dict(height=height, width=width, tank=tank, layers=layers, g=g))
+
+
+def lid_driven_cavity(n: int = 50, re: float = 100.0, U: float = 1.0,
+                      layers: int = 3, kernel: str = "quintic",
+                      hdx: float = 1.0, tol: float = 1e-2,
+                      pgrad: str = "symm", precision: str = "fp64",
+                      ustar_wall: str = "slip", gtvf_K: int = 5,
+                      jitter: float = 0.0, seed: int = 0,
+                      dt: Optional[float] = None) -> Case:
+    """Unit-square lid-driven cavity (section 4.3).
+
+    n x n fluid particles on the lattice (i + 1/2) dx of [0, 1]^2 at rest,
+    rho0 = 1, p = 0, nu = U L / Re.  ``layers`` rows of wall particles at
+    (i + 1/2) dx outside the square on all four sides; the bottom and top
+    strips span the corners.  The top strip (the lid) moves with
+    (U, 0); the others are static.  Internal flow: GTVF background pressure
+    2 max p after the first solve.  The fixed step is the minimum of the
+    advective and viscous limits (section 3.2).  ``ustar_wall`` selects the
+    wall ghost form for u* in the PPE (slip by default; the section compares
+    it with the no-slip form, section 3.4).
+    """
+    L = 1.0
+    dx = L / n
+    h = hdx * dx
+    nu = U * L / re
+    xf = _lattice((n, n), dx, (0.0, 0.0))
+    span = n + 2 * layers
+    bottom = _lattice((span, layers), dx, (-layers * dx, -layers * dx))
+    top = _lattice((span, layers), dx, (-layers * dx, L))
+    left = _lattice((layers, n), dx, (-layers * dx, 0.0))
+    right = _lattice((layers, n), dx, (L, 0.0))
+    xw = np.concatenate([bottom, left, right, top], axis=0)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if jitter > 0:
+        xf = xf + rng.uniform(-jitter * dx, jitter * dx, size=xf.shape)
+    nf, nw = xf.shape[0], xw.shape[0]
+    wall_u = np.zeros((nw, 2))
+    wall_u[nw - top.shape[0]:, 0] = U
+    rho0 = 1.0
+    if dt is None:
+        dt = min(0.25 * h / U, 0.25 * h * h / nu)
+    return Case(
+        name=f"ldc{n}", dim=2, kernel=kernel, h=h, dx=dx, rho0=rho0, nu=nu,
+        alpha=0.0, c_ref=10.0 * U, dt=dt, tol=tol, pgrad=pgrad,
+        gtvf="internal", p_ref_mode="twice_max", p_ref=0.0,
+        free_surface=False, gravity=(0.0, 0.0, 0.0),
+        box_lo=(-layers * dx, -layers * dx, 0.0),
+        box_hi=(L + layers * dx, L + layers * dx, 0.0), periodic=(0, 0, 0),
+        x=np.ascontiguousarray(np.concatenate([xf, xw], axis=0)),
+        u=np.zeros((nf, 2)), p=np.zeros(nf + nw),
+        m=np.full(nf + nw, rho0 * dx * dx), n_fluid=nf, n_wall=nw,
+        wall_u=wall_u, precision=precision, gtvf_K=gtvf_K,
+        ustar_wall=ustar_wall,
+        meta=dict(re=re, U=U, layers=layers, lattice=n))
 
 
 def dam_break_3d(dx: float = 0.01, lx: float = 1.0, ly: float = 1.0,

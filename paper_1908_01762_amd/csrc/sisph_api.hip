@@ -60,6 +60,7 @@ static const char *check_desc(const sisph_case_desc *d) {
     if (d->gtvf < SISPH_GTVF_OFF || d->gtvf > SISPH_GTVF_EXTERNAL) return "unknown gtvf mode";
     if (d->p_ref_mode != SISPH_PREF_FIXED && d->p_ref_mode != SISPH_PREF_TWICE_MAX) return "unknown p_ref mode";
     if (d->conv_norm != SISPH_CONV_SUM && d->conv_norm != SISPH_CONV_MEAN) return "unknown conv_norm";
+    if (d->ustar_wall != SISPH_USTAR_SLIP && d->ustar_wall != SISPH_USTAR_NOSLIP) return "unknown ustar_wall";
     if (d->n_fluid <= 0) return "n_fluid must be positive";
     if (d->n_wall < 0) return "n_wall must be >= 0";
     if (d->n_fluid + d->n_wall >= (int64_t)1 << 31) return "particle count exceeds 2^31";
@@ -131,6 +132,7 @@ static Params make_params(const sisph_case_desc *d) {
     P.max_iter = d->max_iter;
     P.forced_iters = d->forced_iters;
     P.gtvf_K = d->gtvf == SISPH_GTVF_OFF ? 0 : d->gtvf_K;
+    P.ustar_noslip = d->ustar_wall == SISPH_USTAR_NOSLIP ? 1 : 0;
     P.cap = neighbour_cap(d);
     P.nf = d->n_fluid;
     P.nw = d->n_wall;
@@ -446,11 +448,11 @@ static void seq_bin(const Target &T) {
 
 static void seq_predict(const Target &T) {
     density(T);
-    wall_velocity(T, POS_X, 0);
+    wall_velocity(T, POS_X);
     predictor(T);
     bin_fluid(T, POS_XS);
     build_neighbors(T, POS_XS);
-    wall_velocity(T, POS_XS, 1);
+    wall_velocity(T, POS_XS);
 }
 
 static void seq_ppe_begin(const Target &T) {

@@ -29,6 +29,7 @@ struct Grid {
 struct Params {
     int32_t dim, kernel, precision, pgrad, gtvf, free_surface;
     int32_t conv_norm, min_iter, max_iter, forced_iters, gtvf_K, cap;
+    int32_t ustar_noslip, pad0;   // wall ghost form for u*: 0 slip, 1 no-slip
     int64_t nf, nw, ntot;
     double h, rho0, nu, alpha, c_ref, dt, eps_h, fs_ratio, omega, tol;
     double R2;      // (support * h)^2, the exact neighbour predicate radius^2
@@ -136,7 +137,9 @@ void bin_walls_once(const Target &T);
 void build_neighbors(const Target &T, int which);
 void wall_normals(const Target &T);
 void density(const Target &T);
-void wall_velocity(const Target &T, int which, int slip);
+// Wall ghost velocity: no-slip form at r^n (POS_X); at r* (POS_XS) the
+// case's form for u* (slip by default).
+void wall_velocity(const Target &T, int which);
 void predictor(const Target &T);
 void rhs_coef(const Target &T);
 void copy_p32(const Target &T);

@@ -649,11 +649,13 @@ struct Density {
 // ---------------------------------------------------------- wall velocity
 // eq. vf: Shepard average of the fluid velocity with a kernel of smoothing
 // length h/2; eq. vg-adami: no-slip ghost 2 u_wall - avg (at r^n, from u),
-// or the slip form avg (at r*, from u*); eq. vg-no-normal: any part into
-// the solid is removed.
+// and at r* (from u*) the slip form avg unless the case asks for the
+// no-slip form there too; eq. vg-no-normal: any part into the solid is
+// removed.
 template <int KER, int D, typename R>
 struct WallVelocity {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which, int slip) {
+    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which) {
+        const int slip = which == POS_XS && !P.ustar_noslip;
         ROW;
         const int64_t w = i;
         if (w >= P.nw) return;
@@ -1302,8 +1304,8 @@ void wall_normals(const Target &T) {
 
 void density(const Target &T) { SISPH_DISPATCH_KDR(T, (launch<Density<KER, D, R>, K_FLUID>(T))); }
 
-void wall_velocity(const Target &T, int which, int slip) {
-    SISPH_DISPATCH_KDR(T, (launch<WallVelocity<KER, D, R>, K_WALL>(T, which, slip)));
+void wall_velocity(const Target &T, int which) {
+    SISPH_DISPATCH_KDR(T, (launch<WallVelocity<KER, D, R>, K_WALL>(T, which)));
 }
 
 void predictor(const Target &T) { SISPH_DISPATCH_KDR(T, (launch<Predictor<KER, D, R>, K_FLUID>(T))); }

@@ -38,7 +38,7 @@ class CaseDesc(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
         "dim", "kernel", "precision", "pgrad", "gtvf", "free_surface",
         "p_ref_mode", "conv_norm", "min_iter", "max_iter", "gtvf_K", "forced_iters")] + \
-        [("periodic", C.c_int32 * 3), ("nbr_cap", C.c_int32),
+        [("periodic", C.c_int32 * 3), ("nbr_cap", C.c_int32), ("ustar_wall", C.c_int32), ("reserved0", C.c_int32),
          ("n_fluid", C.c_int64), ("n_wall", C.c_int64)] + \
         [(n, C.c_double) for n in (
             "h", "dx", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio",
@@ -146,6 +146,7 @@ def describe(case: "_cases.Case") -> CaseDesc:
         d.box_lo[k] = case.box_lo[k]
         d.box_hi[k] = case.box_hi[k]
     d.nbr_cap = int(case.meta.get("nbr_cap", 0))
+    d.ustar_wall = _cases.USTAR[case.ustar_wall]
     d.n_fluid = case.n_fluid
     d.n_wall = case.n_wall
     for k in ("h", "dx", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio", "omega", "tol", "p_ref"):

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_function():
 
 def test_header_struct_layout_matches_binding():
     # sisph_case_desc: 16 int32 + 2 int64 + 12 double + 9 double
-    assert C.sizeof(sisph.CaseDesc) == 16 * 4 + 2 * 8 + 21 * 8
+    assert C.sizeof(sisph.CaseDesc) == 18 * 4 + 2 * 8 + 21 * 8
     assert C.sizeof(sisph.PPEStats) == 4 * 4 + 3 * 8
 
 

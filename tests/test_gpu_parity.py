@@ -45,6 +45,8 @@ def _cases_small():
         "db2d_dx0.05": cases.dam_break_2d(dx=0.05, precision="fp64"),
         "db3d_small": cases.dam_break_3d(dx=0.1, lx=0.5, ly=0.5, lz=0.6, tank_x=1.5, tank_y=0.5, tank_z=1.0,
                                          precision="fp64"),
+        "ldc30_slip": cases.lid_driven_cavity(30),
+        "ldc30_noslip": cases.lid_driven_cavity(30, ustar_wall="noslip"),
     }
 
 
@@ -100,7 +102,7 @@ def test_single_step_fields_fp64(name):
         "dii": (ctx.field("dii"), out["diag"]),
     }
     if case.n_wall:
-        fields["wall_u_slip"] = (ctx.field("wall_ustar"), out["usw"])
+        fields["wall_ustar"] = (ctx.field("wall_ustar"), out["usw"])
         fields["normals"] = (ctx.field("normal"), ref.nrm)
     ctx.correct()
     fields["unew"] = (ctx.field("unew"), out["unew"])
@@ -153,6 +155,28 @@ def test_dam_break_steps_fp64():
     s = ctx.read_state()
     assert rel(s["p"], ref.p) < FP64_TOL
     assert rel(s["u"], ref.u) < FP64_TOL
+    ctx.close()
+
+
+@pytest.mark.parametrize("form", ["slip", "noslip"])
+def test_cavity_steps_fp64(form):
+    """Lid-driven cavity (section 4.3), Re = 100, 30 x 30, quintic h = dx,
+    tol 1e-2, symm, p_ref = 2 max p after the first solve; 20 steps with the
+    slip or the no-slip ghost form for u*."""
+    sisph = _gpu()
+    case = cases.lid_driven_cavity(30, ustar_wall=form)
+    say("case ldc30", form)
+    ref = oracle.Sim(case)
+    ctx = sisph.Context(case)
+    for k in range(20):
+        o = ref.step()
+        g = ctx.step(1)[0]
+        assert g["iters"] == o["iters"], f"step {k}"
+        assert math.isclose(g["p_ref"], o["p_ref"], rel_tol=1e-9), f"step {k}"
+    s = ctx.read_state()
+    assert rel(s["p"], ref.p) < FP64_TOL
+    assert rel(s["u"], ref.u) < FP64_TOL
+    assert rel(s["x"], ref.x) < FP64_TOL
     ctx.close()
 
 

@@ -330,6 +330,43 @@ def test_wall_velocity_rules_by_hand():
         assert np.allclose(oracle.wall_velocity(c, c.x, u, nrm, slip=True)[sel], one * slip, atol=1e-12)
 
 
+def test_cavity_ustar_wall_forms():
+    """Sections 3.4 and 4.3: one cavity step with the slip and the no-slip
+    ghost form for u*.  The fluid u* does not depend on the form, and on every
+    wall particle the two ghost values are the Shepard average a and
+    2 u_wall - a, each with any part into the solid removed (the unit normal
+    points into the fluid).  So along the wall they sum to 2 u_wall; along
+    the normal both are >= 0, and where the slip value a.n is kept the
+    no-slip one is max(2 u_wall.n - a.n, 0)."""
+    base = cases.lid_driven_cavity(n=16)
+    outs = {}
+    for form in ("slip", "noslip"):
+        outs[form] = oracle.Sim(base.replace(ustar_wall=form)).step(capture=True)
+    s, ns = outs["slip"]["usw"], outs["noslip"]["usw"]
+    assert np.array_equal(outs["slip"]["us"], outs["noslip"]["us"])
+    nrm = oracle.wall_normals(base)
+    wu = base.wall_u
+    has_n = np.linalg.norm(nrm, axis=1) > 0.5
+    assert has_n.sum() > 50 and (~has_n).sum() > 10
+    lid = wu[:, 0] > 0
+    assert np.abs(s[lid & has_n, 0]).max() > 1e-6   # the lid drags the fluid
+    tang = np.stack([-nrm[:, 1], nrm[:, 0]], axis=1)
+    both = s + ns
+    t_err = np.einsum("ij,ij->i", both - 2.0 * wu, tang)[has_n]
+    assert np.abs(t_err).max() < 1e-12
+    sn = np.einsum("ij,ij->i", s, nrm)[has_n]
+    nn = np.einsum("ij,ij->i", ns, nrm)[has_n]
+    wn = np.einsum("ij,ij->i", wu, nrm)[has_n]
+    assert sn.min() > -1e-12 and nn.min() > -1e-12
+    kept = sn > 1e-12
+    assert kept.sum() > 10 and (~kept).sum() > 10
+    assert np.abs(nn[kept] - np.maximum(2.0 * wn[kept] - sn[kept], 0.0)).max() < 1e-12
+    assert (nn[~kept] >= np.maximum(2.0 * wn[~kept], 0.0) - 1e-12).all()
+    # no normal, nothing removed: the two forms sum to 2 u_wall outright
+    assert np.abs(both[~has_n] - 2.0 * wu[~has_n]).max() < 1e-12
+    assert not np.array_equal(s, ns)
+
+
 # --------------------------------------------------------------- PPE solver
 def _fs_case(n=12, seed=4):
     """Periodic jittered set where the free-surface test marks a few
