@@ -62,6 +62,7 @@ enum { SISPH_GTVF_OFF = 0, SISPH_GTVF_INTERNAL = 1, SISPH_GTVF_EXTERNAL = 2 };
 enum { SISPH_PREF_FIXED = 0, SISPH_PREF_TWICE_MAX = 1 };
 enum { SISPH_CONV_SUM = 0, SISPH_CONV_MEAN = 1 };
 enum { SISPH_USTAR_SLIP = 0, SISPH_USTAR_NOSLIP = 1 };
+enum { SISPH_DT_FIXED = 0, SISPH_DT_ADAPTIVE = 1 };
 
 /* One case.  Parameters follow the paper's statement of the problem.
  *  precision   SISPH_FP64: every sum in FP64.  SISPH_MIXED: neighbour sums,
@@ -84,6 +85,12 @@ enum { SISPH_USTAR_SLIP = 0, SISPH_USTAR_NOSLIP = 1 };
  *  ustar_wall  wall ghost form for u* in the PPE: SISPH_USTAR_SLIP (the
  *              Shepard average of u*) or SISPH_USTAR_NOSLIP (2 u_wall minus
  *              it); either way any part into the solid is removed.
+ *  dt_mode     SISPH_DT_FIXED: every step takes dt.  SISPH_DT_ADAPTIVE
+ *              (section 3.2, adaptive steps): the first step takes dt; each
+ *              later one min(dt, 0.25 h / max|u^n|, 0.25 sqrt(h / max|f^n|))
+ *              from the previous step's largest fluid speed at its start
+ *              and largest total acceleration (predictor forces, gravity
+ *              and pressure force); dt is the upper bound.
  *  periodic    per axis; the box is [box_lo, box_hi) on periodic axes and
  *              the binning range (particles outside are clamped to the edge
  *              cells) on the others.                                         */
@@ -91,7 +98,7 @@ typedef struct {
     int32_t dim, kernel, precision, pgrad, gtvf, free_surface;
     int32_t p_ref_mode, conv_norm, min_iter, max_iter, gtvf_K, forced_iters;
     int32_t periodic[3], nbr_cap;
-    int32_t ustar_wall, reserved0;
+    int32_t ustar_wall, dt_mode;
     int64_t n_fluid, n_wall;
     double h, dx, rho0, nu, alpha, c_ref, dt, eta, fs_ratio, omega, tol, p_ref;
     double gravity[3], box_lo[3], box_hi[3];
@@ -105,6 +112,7 @@ typedef struct {
     double ratio;        /* eq. convergence at the last sweep               */
     double lambda;       /* max |RHS_i / D_ii| over non-free-surface fluid   */
     double p_ref;        /* GTVF reference pressure in use                  */
+    double dt;           /* this step's time step                          */
 } sisph_ppe_stats;
 
 typedef sisph_ppe_stats sisph_step_stats;

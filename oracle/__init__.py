@@ -24,6 +24,7 @@ GTVF = {"off": 0, "internal": 1, "external": 2}
 PREF = {"fixed": 0, "twice_max": 1}
 CONV = {"sum": 0, "mean": 1}
 USTAR = {"slip": 0, "noslip": 1}
+DT_MODE = {"fixed": 0, "adaptive": 1}
 
 
 def build(force: bool = False) -> str:
@@ -39,9 +40,10 @@ def build(force: bool = False) -> str:
 class Params(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "dim", "kernel", "pgrad", "gtvf", "free_surface", "p_ref_mode",
-        "min_iter", "max_iter", "gtvf_K", "forced_iters", "conv_norm", "ustar_wall", "nf", "nw")] + \
+        "min_iter", "max_iter", "gtvf_K", "forced_iters", "conv_norm", "ustar_wall", "dt_mode",
+        "nf", "nw")] + \
         [(n, C.c_double) for n in (
-            "h", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio", "omega", "tol")] + \
+            "h", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio", "omega", "tol", "dt_max")] + \
         [("g", C.c_double * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
          ("periodic", C.c_int64 * 3)]
 
@@ -54,7 +56,8 @@ class StepOut(C.Structure):
     _fields_ = [(n, _DP) for n in ("rho", "xs", "us", "uw", "usw", "rhs", "diag",
                                    "unew", "fgtvf0")] + \
         [("fs", _I64P), ("iters", C.c_int64), ("converged", C.c_int64),
-         ("ratio", C.c_double), ("lambda_", C.c_double), ("p_ref_used", C.c_double)]
+         ("ratio", C.c_double), ("lambda_", C.c_double), ("p_ref_used", C.c_double),
+         ("umax", C.c_double), ("fmax", C.c_double), ("dt_next", C.c_double)]
 
 
 _lib = None
@@ -103,6 +106,8 @@ def params(case, **over) -> Params:
     P.forced_iters = case.forced_iters
     P.conv_norm = CONV[case.conv_norm]
     P.ustar_wall = USTAR[case.ustar_wall]
+    P.dt_mode = DT_MODE[case.dt_mode]
+    P.dt_max = float(case.dt)
     P.nf = case.n_fluid
     P.nw = case.n_wall
     for k in ("h", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio", "omega", "tol"):
@@ -242,6 +247,7 @@ class Sim:
         self.p_ref = C.c_double(case.p_ref)
         self.p_ref_set = C.c_int64(1 if case.p_ref_mode == "fixed" else 0)
         self.forced_iters = case.forced_iters if forced_iters is None else forced_iters
+        self.dt = float(case.dt)         # the next step's dt
         self.t = 0.0
         self.steps = 0
 
@@ -249,7 +255,7 @@ class Sim:
         c = self.case
         nf, nw, dim = c.n_fluid, c.n_wall, c.dim
         fi = self.forced_iters if forced_iters is None else forced_iters
-        P = params(c, forced_iters=fi)
+        P = params(c, forced_iters=fi, dt=self.dt)
         out = StepOut()
         keep = {}
         if capture:
@@ -264,10 +270,12 @@ class Sim:
         lib().orc_step(C.byref(P), _ptr(self.x), _ptr(self.u), _ptr(self.ut), _ptr(self.p),
                        _ptr(self.m), _ptr(np.ascontiguousarray(self.nrm)), _ptr(self.wall_u),
                        C.byref(self.p_ref), C.byref(self.p_ref_set), C.byref(out))
-        self.t += c.dt
+        self.t += self.dt
         self.steps += 1
         keep.update(iters=int(out.iters), converged=bool(out.converged), ratio=float(out.ratio),
-                    lam=float(out.lambda_), p_ref=float(out.p_ref_used))
+                    lam=float(out.lambda_), p_ref=float(out.p_ref_used), dt=self.dt,
+                    umax=float(out.umax), fmax=float(out.fmax), dt_next=float(out.dt_next))
+        self.dt = float(out.dt_next)
         if capture:
             keep["x0"] = x0
         return keep

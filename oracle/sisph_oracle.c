@@ -693,6 +693,29 @@ int64_t orc_step(const orc_params *P, double *x, double *u, double *ut, double *
         for (int kk = 0; kk < dim; ++kk)
             unew[i * dim + kk] = us_all[i * dim + kk] + dt * fp[i * dim + kk];
 
+    /* the next step's dt (section 3.2, adaptive steps): the largest fluid
+     * speed at the start of this step and the largest total acceleration
+     * of this step (predictor forces with gravity, plus the pressure
+     * force) */
+    double umax2 = 0.0, fmax2 = 0.0;
+    for (int64_t i = 0; i < nf; ++i) {
+        double a = 0.0, b = 0.0;
+        for (int kk = 0; kk < dim; ++kk) {
+            double ui = u[i * dim + kk], fi = f[i * dim + kk] + fp[i * dim + kk];
+            a += ui * ui;
+            b += fi * fi;
+        }
+        if (a > umax2) umax2 = a;
+        if (b > fmax2) fmax2 = b;
+    }
+    double umax = sqrt(umax2), fmax = sqrt(fmax2);
+    double dt_next = dt;
+    if (P->dt_mode == ORC_DT_ADAPTIVE) {
+        dt_next = P->dt_max;
+        if (umax > 0.0 && 0.25 * P->h / umax < dt_next) dt_next = 0.25 * P->h / umax;
+        if (fmax > 0.0 && 0.25 * sqrt(P->h / fmax) < dt_next) dt_next = 0.25 * sqrt(P->h / fmax);
+    }
+
     /* step 10: GTVF sub-steps on the frozen r* neighbour sets
      * (eqs. int:gtvf:pos, int:gtvf:vel:tmp); walls fixed; no wrap inside */
     double *xk = malloc(sizeof(double) * nd);
@@ -748,6 +771,9 @@ int64_t orc_step(const orc_params *P, double *x, double *u, double *ut, double *
         out->lambda = lambda;
         out->converged = ratio < P->tol;
         out->p_ref_used = *p_ref;
+        out->umax = umax;
+        out->fmax = fmax;
+        out->dt_next = dt_next;
     }
     free(coef);
     free(fp);

@@ -21,12 +21,16 @@ enum { ORC_GTVF_OFF = 0, ORC_GTVF_INTERNAL = 1, ORC_GTVF_EXTERNAL = 2 };
 enum { ORC_PREF_FIXED = 0, ORC_PREF_TWICE_MAX = 1 };
 enum { ORC_CONV_SUM = 0, ORC_CONV_MEAN = 1 };
 enum { ORC_USTAR_SLIP = 0, ORC_USTAR_NOSLIP = 1 };
+enum { ORC_DT_FIXED = 0, ORC_DT_ADAPTIVE = 1 };
 
 typedef struct {
     int64_t dim, kernel, pgrad, gtvf, free_surface, p_ref_mode;
     int64_t min_iter, max_iter, gtvf_K, forced_iters, conv_norm, ustar_wall;
+    int64_t dt_mode;  /* ORC_DT_FIXED: every step takes dt; ORC_DT_ADAPTIVE:
+                         dt_next is chosen from this step's maxima */
     int64_t nf, nw;
     double h, rho0, nu, alpha, c_ref, dt, eta, fs_ratio, omega, tol;
+    double dt_max;    /* adaptive mode: upper bound of dt_next             */
     double g[3], lo[3], hi[3];
     int64_t periodic[3];
 } orc_params;
@@ -37,7 +41,7 @@ typedef struct {
     double *xs;       /* [nf][dim]  r* (wrapped into the box)              */
     double *us;       /* [nf][dim]  u*                                     */
     double *uw;       /* [nw][dim]  wall velocity, no-slip form, at r^n    */
-    double *usw;      /* [nw][dim]  wall u*, slip form, at r*              */
+    double *usw;      /* [nw][dim]  wall u* at r* (the case's ghost form)  */
     double *rhs;      /* [nf]       PPE right-hand side                    */
     double *diag;     /* [nf]       D_ii                                   */
     double *unew;     /* [nf][dim]  u^{n+1}                                */
@@ -46,6 +50,9 @@ typedef struct {
     int64_t iters;    /* Jacobi sweeps done                                */
     int64_t converged;
     double ratio, lambda, p_ref_used;
+    double umax;      /* max |u^n| over fluid particles                    */
+    double fmax;      /* max |f^n|, f = predictor forces + pressure force  */
+    double dt_next;   /* the next step's dt (dt itself in fixed mode)      */
 } orc_step_out;
 
 /* Kernel value and radial derivative dW/dr for smoothing length h. */

@@ -35,6 +35,7 @@ PREF = {"fixed": 0, "twice_max": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
 CONV = {"sum": 0, "mean": 1}
 USTAR = {"slip": 0, "noslip": 1}
+DT_MODE = {"fixed": 0, "adaptive": 1}
 SUPPORT = {"quintic": 3.0, "wendland": 2.0}
 
 
@@ -79,6 +80,7 @@ class Case:
     forced_iters: int = 0
     conv_norm: str = "sum"
     ustar_wall: str = "slip"
+    dt_mode: str = "fixed"       # "adaptive": dt is the first step's and the largest step
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property

@@ -61,6 +61,7 @@ static const char *check_desc(const sisph_case_desc *d) {
     if (d->p_ref_mode != SISPH_PREF_FIXED && d->p_ref_mode != SISPH_PREF_TWICE_MAX) return "unknown p_ref mode";
     if (d->conv_norm != SISPH_CONV_SUM && d->conv_norm != SISPH_CONV_MEAN) return "unknown conv_norm";
     if (d->ustar_wall != SISPH_USTAR_SLIP && d->ustar_wall != SISPH_USTAR_NOSLIP) return "unknown ustar_wall";
+    if (d->dt_mode != SISPH_DT_FIXED && d->dt_mode != SISPH_DT_ADAPTIVE) return "unknown dt_mode";
     if (d->n_fluid <= 0) return "n_fluid must be positive";
     if (d->n_wall < 0) return "n_wall must be >= 0";
     if (d->n_fluid + d->n_wall >= (int64_t)1 << 31) return "particle count exceeds 2^31";
@@ -133,6 +134,7 @@ static Params make_params(const sisph_case_desc *d) {
     P.forced_iters = d->forced_iters;
     P.gtvf_K = d->gtvf == SISPH_GTVF_OFF ? 0 : d->gtvf_K;
     P.ustar_noslip = d->ustar_wall == SISPH_USTAR_NOSLIP ? 1 : 0;
+    P.adaptive_dt = d->dt_mode == SISPH_DT_ADAPTIVE ? 1 : 0;
     P.cap = neighbour_cap(d);
     P.nf = d->n_fluid;
     P.nw = d->n_wall;
@@ -233,6 +235,7 @@ static Target single_target(sisph_ctx *ctx) {
     T.kernel = ctx->P.kernel;
     T.precision = ctx->P.precision;
     T.variant = ctx->variant;
+    T.adaptive = ctx->P.adaptive_dt;
     T.s = ctx->stream;
     return T;
 }
@@ -283,6 +286,7 @@ static void fill_stats(const Control &C, const Params &P, sisph_ppe_stats *out) 
     cv.u = C.lambda_bits;
     out->lambda = cv.d;
     out->p_ref = C.p_ref;
+    out->dt = C.dt;
 }
 
 static int32_t status_of(const Control &C, const Params &P, std::string *msg) {
@@ -390,7 +394,7 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
     }
     iota_i32(S.id, nf, s);
     iota_i32(S.wid, nw, s);
-    reset_control(ctx->T, RESET_PPE | RESET_NEIGHBOURS | RESET_PREF);
+    reset_control(ctx->T, RESET_PPE | RESET_NEIGHBOURS | RESET_PREF | RESET_DT);
     if (desc->p_ref_mode == SISPH_PREF_FIXED) {
         Control c0{};
         c0.p_ref = desc->p_ref;
@@ -441,7 +445,7 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
 // ------------------------------------------------------- step sequences
 // The same launch sequences serve one case and a batch (Target).
 static void seq_bin(const Target &T) {
-    reset_control(T, RESET_NEIGHBOURS);
+    reset_control(T, RESET_NEIGHBOURS | RESET_STEP);
     bin_fluid(T, POS_X);
     build_neighbors(T, POS_X);
 }
@@ -469,6 +473,10 @@ static void seq_ppe_end(const Target &T) {
 
 static void seq_correct(const Target &T, int maxK) {
     correct(T);
+    if (T.adaptive) {
+        step_maxima(T);   // before the GTVF sub-steps reuse the acceleration buffer
+        next_dt(T);
+    }
     for (int k = 0; k < maxK; ++k) gtvf_substep(T, k);
     advance(T);
 }
@@ -797,8 +805,9 @@ struct Group {
     int64_t *d_first[K_COUNT] = {};
     Control *d_ctl = nullptr;   // gathered control blocks [members]
     Control *h_ctl = nullptr;   // pinned mirror
-    size_t owner_cap[K_COUNT] = {};
-    size_t case_cap = 0;
+    size_t owner_cap[K_COUNT] = {};   // entries of d_owner[k]
+    size_t first_cap[K_COUNT] = {};   // entries of d_first[k]
+    size_t case_cap = 0;              // entries of d_tab and d_ctl
     bool dirty = true;
     Target T{};
 };
@@ -820,6 +829,7 @@ static void free_group(Group &g) {
         g.d_owner[k] = nullptr;
         g.d_first[k] = nullptr;
         g.owner_cap[k] = 0;
+        g.first_cap[k] = 0;
     }
     if (g.d_ctl) (void)hipFree(g.d_ctl);
     if (g.h_ctl) (void)hipHostFree(g.h_ctl);
@@ -862,6 +872,7 @@ static int32_t rebuild_group(sisph_batch *b, Group &g) {
     T.kernel = g.kernel;
     T.precision = g.precision;
     T.s = b->stream;
+    for (auto *c : g.members) T.adaptive |= c->P.adaptive_dt;
     for (int k = 0; k < K_COUNT; ++k) {
         std::vector<int32_t> owner;
         std::vector<int64_t> first(n);
@@ -872,14 +883,23 @@ static int32_t rebuild_group(sisph_batch *b, Group &g) {
             owner.insert(owner.end(), (size_t)nb, (int32_t)c);
         }
         T.total[k] = (int64_t)owner.size();
-        if (owner.size() > g.owner_cap[k] || !g.d_first[k]) {
+        // the two maps grow independently: the workgroup count can shrink
+        // while the case count grows (large cases leave, small ones join)
+        if (owner.size() > g.owner_cap[k] || !g.d_owner[k]) {
             if (g.d_owner[k]) (void)hipFree(g.d_owner[k]);
-            if (g.d_first[k]) (void)hipFree(g.d_first[k]);
             g.d_owner[k] = nullptr;
+            g.owner_cap[k] = 0;
+            const size_t cap = std::max<size_t>(owner.size(), 1);
+            BCHK(b, hipMalloc((void **)&g.d_owner[k], sizeof(int32_t) * cap));
+            g.owner_cap[k] = cap;
+        }
+        if (n > g.first_cap[k] || !g.d_first[k]) {
+            if (g.d_first[k]) (void)hipFree(g.d_first[k]);
             g.d_first[k] = nullptr;
-            BCHK(b, hipMalloc((void **)&g.d_owner[k], sizeof(int32_t) * std::max<size_t>(owner.size(), 1)));
-            BCHK(b, hipMalloc((void **)&g.d_first[k], sizeof(int64_t) * std::max<size_t>(g.case_cap, 1)));
-            g.owner_cap[k] = owner.size();
+            g.first_cap[k] = 0;
+            const size_t cap = std::max<size_t>(n, 1);
+            BCHK(b, hipMalloc((void **)&g.d_first[k], sizeof(int64_t) * cap));
+            g.first_cap[k] = cap;
         }
         if (!owner.empty())
             BCHK(b, hipMemcpyAsync(g.d_owner[k], owner.data(), sizeof(int32_t) * owner.size(),

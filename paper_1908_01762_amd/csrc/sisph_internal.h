@@ -29,8 +29,11 @@ struct Grid {
 struct Params {
     int32_t dim, kernel, precision, pgrad, gtvf, free_surface;
     int32_t conv_norm, min_iter, max_iter, forced_iters, gtvf_K, cap;
-    int32_t ustar_noslip, pad0;   // wall ghost form for u*: 0 slip, 1 no-slip
+    int32_t ustar_noslip;   // wall ghost form for u*: 0 slip, 1 no-slip
+    int32_t adaptive_dt;    // next dt from this step's maxima
     int64_t nf, nw, ntot;
+    // dt: the fixed step, or the first step and the upper bound when adaptive
+    // (kernels read the current step's dt from Control)
     double h, rho0, nu, alpha, c_ref, dt, eps_h, fs_ratio, omega, tol;
     double R2;      // (support * h)^2, the exact neighbour predicate radius^2
     double g[3];
@@ -51,6 +54,10 @@ struct Control {
     unsigned long long lambda_bits;   // max |RHS/D| (non-negative doubles)
     unsigned long long pmax_key;      // max p, order-preserving key
     double p_ref;
+    double dt;                        // this step's time step
+    double dt_next;                   // the next step's (taken at its start)
+    unsigned long long umax2_bits;    // max |u^n|^2 over fluid (adaptive dt)
+    unsigned long long fmax2_bits;    // max |f^n|^2 over fluid (adaptive dt)
 };
 
 // Per-case device arrays.  Unified particle index: fluid [0, nf) in cell
@@ -63,7 +70,8 @@ struct State {
     double *us[3];     // u* fluid, wall slip u*     [ntot]
     double *un[3];     // u^{n+1}                    [nf]
     double *xk[2][3];  // GTVF sub-step positions    [ntot] x2
-    double *vk[3];     // GTVF sub-step velocity     [nf]
+    double *vk[3];     // GTVF sub-step velocity     [nf]; before the sub-steps,
+                       // the step's total acceleration (adaptive dt)
     double *nrm[3];    // wall unit normals          [nw]
     double *wallu[3];  // prescribed wall velocity   [nw]
     double *p[2];      // pressure iterates; p[0] holds p^n between steps [ntot] x2
@@ -120,11 +128,14 @@ struct Target {
     int32_t ncase;
     int32_t dim, kernel, precision;
     int32_t variant;                 // Jacobi-sweep variant (speed only)
+    int32_t adaptive;                // some case chooses its next dt
     bool batched;
     hipStream_t s;
 };
 
-enum { RESET_PPE = 1, RESET_NEIGHBOURS = 2, RESET_PREF = 4 };
+// RESET_DT: dt = dt_next = the case's dt (at creation); RESET_STEP: start a
+// step (dt = dt_next, maxima cleared).
+enum { RESET_PPE = 1, RESET_NEIGHBOURS = 2, RESET_PREF = 4, RESET_DT = 8, RESET_STEP = 16 };
 enum { POS_X = 0, POS_XS = 1 };
 
 // ---- launch sequences (sisph_kernels.hip) -------------------------------
@@ -152,6 +163,9 @@ void settle_pressure(const Target &T);
 void wall_pressure_final(const Target &T);
 void pressure_max(const Target &T);
 void correct(const Target &T);
+// Adaptive dt: max |u^n|^2 and max |f^n|^2 over the fluid, then dt_next.
+void step_maxima(const Target &T);
+void next_dt(const Target &T);
 void gtvf_substep(const Target &T, int k);
 void advance(const Target &T);
 void gather_control(const Target &T, Control *out);

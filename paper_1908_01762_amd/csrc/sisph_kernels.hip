@@ -260,9 +260,18 @@ void launch(const Target &T, A... a) {
 // ================================================================== bodies
 // ----------------------------------------------------------------- control
 struct ResetControl {
-    static __device__ void run(const Params &, const State &S, int64_t, int64_t, int, int what) {
+    static __device__ void run(const Params &P, const State &S, int64_t, int64_t, int, int what) {
         if (threadIdx.x != 0) return;
         Control *c = S.ctl;
+        if (what & RESET_DT) {
+            c->dt = P.dt;
+            c->dt_next = P.dt;
+        }
+        if (what & RESET_STEP) {
+            c->dt = c->dt_next;
+            c->umax2_bits = 0ull;
+            c->fmax2_bits = 0ull;
+        }
         if (what & RESET_PPE) {
             c->iter = 0;
             c->done = 0;
@@ -751,7 +760,7 @@ struct Predictor {
             }
             for (int a = 0; a < D; ++a) fsr[a] += mj * (ui[a] * inv_rhoi * sgi + uj_over[a] * sgj);
         }
-        const double dt = P.dt;
+        const double dt = S.ctl->dt;
         for (int a = 0; a < D; ++a) {
             const double f = (double)(fv[a] + fa[a] + fsr[a]) + P.g[a];
             double xn;
@@ -761,6 +770,7 @@ struct Predictor {
             }
             S.xs[a][i] = wrap_periodic(xn, P.grid, a);
             S.us[a][i] = u.c[a][i] + dt * f;
+            if (P.adaptive_dt) S.vk[a][i] = f;   // completed by the pressure force
         }
     }
 };
@@ -805,7 +815,7 @@ struct RhsCoef {
                 xi[k] = xs.c[k][i];
                 usi[k] = (R)us.c[k][i];
             }
-            const R rhoi = (R)S.rho[i], eps = (R)P.eps_h, inv_dt = (R)(1.0 / P.dt);
+            const R rhoi = (R)S.rho[i], eps = (R)P.eps_h, inv_dt = (R)(1.0 / S.ctl->dt);
             R s = R(0), Dg = R(0);
             const int c = S.cnt[i];
             for (int k = 1; k < c; ++k) {
@@ -1134,7 +1144,59 @@ struct Correct {
             cf *= dw;
             for (int a = 0; a < D; ++a) f[a] += cf * d[a];
         }
-        for (int a = 0; a < D; ++a) S.un[a][i] = S.us[a][i] + P.dt * (double)f[a];
+        const double dt = S.ctl->dt;
+        for (int a = 0; a < D; ++a) {
+            S.un[a][i] = S.us[a][i] + dt * (double)f[a];
+            if (P.adaptive_dt) S.vk[a][i] += (double)f[a];   // total acceleration of the step
+        }
+    }
+};
+
+// Adaptive time step (section 3.2): the largest fluid speed at the start of
+// the step (u still holds u^n here) and the largest total acceleration
+// (predictor forces, gravity and pressure force, left in vk by the
+// predictor and the correction), as squared magnitudes; non-negative
+// doubles order like their bit patterns, so a wave max and one atomic max
+// per wavefront give an order-independent result.
+template <int D>
+struct StepMaxima {
+    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        if (!P.adaptive_dt) return;
+        ROW;
+        unsigned long long ub = 0ull, fb = 0ull;
+        if (i < P.nf) {
+#pragma clang fp contract(off)
+            double u2 = 0.0, f2 = 0.0;
+            for (int a = 0; a < D; ++a) {
+                const double ua = S.u[a][i], fa = S.vk[a][i];
+                u2 = u2 + ua * ua;
+                f2 = f2 + fa * fa;
+            }
+            ub = (unsigned long long)__double_as_longlong(u2);
+            fb = (unsigned long long)__double_as_longlong(f2);
+        }
+        ub = wave_max_u64(ub);
+        fb = wave_max_u64(fb);
+        if ((threadIdx.x & 63) == 0) {
+            if (ub) max_if_larger(&S.ctl->umax2_bits, ub);
+            if (fb) max_if_larger(&S.ctl->fmax2_bits, fb);
+        }
+    }
+};
+
+// dt^{n+1} = min(dt, 0.25 h / max|u^n|, 0.25 sqrt(h / max|f^n|)), the
+// case's dt being the bound; a zero maximum imposes no limit.
+struct NextDt {
+    static __device__ void run(const Params &P, const State &S, int64_t, int64_t, int) {
+        if (threadIdx.x != 0 || !P.adaptive_dt) return;
+        Control *c = S.ctl;
+        const double u2 = __longlong_as_double((long long)c->umax2_bits);
+        const double f2 = __longlong_as_double((long long)c->fmax2_bits);
+        const double umax = sqrt(u2), fmax = sqrt(f2);
+        double dt = P.dt;
+        if (umax > 0.0 && 0.25 * P.h / umax < dt) dt = 0.25 * P.h / umax;
+        if (fmax > 0.0 && 0.25 * sqrt(P.h / fmax) < dt) dt = 0.25 * sqrt(P.h / fmax);
+        c->dt_next = dt;
     }
 };
 
@@ -1172,7 +1234,7 @@ struct Gtvf {
             const R cf = (R)S.m[j] / (rhoj * rhoj) * dw;
             for (int a = 0; a < D; ++a) s[a] += cf * d[a];
         }
-        const double dtau = P.dt / (double)P.gtvf_K;
+        const double dtau = S.ctl->dt / (double)P.gtvf_K;
         for (int a = 0; a < D; ++a) {
             const double f = -p0 * (double)s[a];
             const double v = k == 0 ? 0.0 : S.vk[a][i];
@@ -1192,9 +1254,10 @@ struct Advance {
         if (i >= P.nf) return;
         const int kfinal = P.gtvf_K - 1;
         double *const *xk = kfinal < 0 ? S.xs : S.xk[kfinal & 1];
+        const double dt = S.ctl->dt;
         for (int a = 0; a < D; ++a) {
-            const double utn = S.un[a][i] + (xk[a][i] - S.xs[a][i]) / P.dt;
-            const double xn = S.x[a][i] + 0.5 * P.dt * (utn + S.ut[a][i]);
+            const double utn = S.un[a][i] + (xk[a][i] - S.xs[a][i]) / dt;
+            const double xn = S.x[a][i] + 0.5 * dt * (utn + S.ut[a][i]);
             S.x[a][i] = wrap_periodic(xn, P.grid, a);
             S.ut[a][i] = utn;
             S.u[a][i] = S.un[a][i];
@@ -1350,6 +1413,10 @@ void pressure_max(const Target &T) {
 }
 
 void correct(const Target &T) { SISPH_DISPATCH_KDR(T, (launch<Correct<KER, D, R>, K_FLUID>(T))); }
+
+void step_maxima(const Target &T) { SISPH_DISPATCH_D(T, (launch<StepMaxima<D>, K_FLUID>(T))); }
+
+void next_dt(const Target &T) { launch<NextDt, K_ONE>(T); }
 
 void gtvf_substep(const Target &T, int k) { SISPH_DISPATCH_KDR(T, (launch<Gtvf<KER, D, R>, K_FLUID>(T, k))); }
 

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function():
 def test_header_struct_layout_matches_binding():
     # sisph_case_desc: 16 int32 + 2 int64 + 12 double + 9 double
     assert C.sizeof(sisph.CaseDesc) == 18 * 4 + 2 * 8 + 21 * 8
-    assert C.sizeof(sisph.PPEStats) == 4 * 4 + 3 * 8
+    assert C.sizeof(sisph.PPEStats) == 4 * 4 + 4 * 8
 
 
 def test_status_strings():
@@ -54,7 +54,7 @@ def test_workspace_bytes_valid_and_monotone():
 
 @pytest.mark.parametrize("field,value", [
     ("dim", 4), ("kernel", 9), ("precision", 7), ("n_fluid", 0), ("h", 0.0), ("dt", -1.0),
-    ("omega", 1.5), ("min_iter", 0), ("max_iter", 1)])
+    ("omega", 1.5), ("min_iter", 0), ("max_iter", 1), ("ustar_wall", 2), ("dt_mode", 3)])
 def test_invalid_descriptor_gives_zero_workspace(field, value):
     c = cases.taylor_green(10).replace(min_iter=2)
     d = sisph.describe(c)

@@ -31,6 +31,7 @@ def _mix():
         cases.taylor_green(30, precision="fp64", seed=4),                 # other group: quintic FP64
         cases.dam_break_3d(dx=0.1, lx=0.4, ly=0.4, lz=0.5, tank_x=1.0, tank_y=0.4, tank_z=0.8,
                            precision="mixed"),                            # other group: 3D
+        cases.dam_break_2d(dx=0.08, precision="mixed").replace(dt_mode="adaptive"),
     ]
 
 
@@ -100,6 +101,42 @@ def test_attach_detach_between_steps():
         st = ctx.read_state()
         assert _same(st, ref[k]), k
     b.close()
+
+
+def test_small_cases_join_after_a_large_one_leaves():
+    """The group then holds more cases than before but fewer workgroups in
+    total; every per-case map must still be sized for the case count (a
+    map sized by the old count corrupted the workgroup-to-case maps)."""
+    sisph = _gpu()
+    big = cases.taylor_green(48, kernel="wendland", hdx=1.3, precision="mixed", seed=11)
+    small = [cases.taylor_green(n, kernel="wendland", hdx=1.3, precision="mixed", seed=12 + n)
+             for n in (12, 14, 16)]
+    steps = {0: 1, 1: 3, 2: 2, 3: 2}
+    allc = [big] + small
+    ref = []
+    for k, c in enumerate(allc):
+        ctx = sisph.Context(c)
+        ctx.step(steps[k])
+        ref.append(ctx.read_state())
+        ctx.close()
+    ctxs = [sisph.Context(c) for c in allc]
+    b = sisph.Batch(8)
+    b.attach(ctxs[0])
+    b.attach(ctxs[1])
+    b.step()
+    b.detach(ctxs[0])
+    b.attach(ctxs[2])
+    b.attach(ctxs[3])
+    b.step()
+    b.step()
+    for k, ctx in enumerate(ctxs):
+        if ctx in b.members:
+            b.detach(ctx)
+        say("case", k, allc[k].name)
+        assert _same(ctx.read_state(), ref[k]), k
+    b.close()
+    for ctx in ctxs:
+        ctx.close()
 
 
 def test_stepping_an_attached_context_directly_is_refused():

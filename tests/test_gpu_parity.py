@@ -180,6 +180,38 @@ def test_cavity_steps_fp64(form):
     ctx.close()
 
 
+@pytest.mark.parametrize("name", ["db2d", "tg", "ldc"])
+def test_adaptive_dt_steps_fp64(name):
+    """Adaptive time steps (section 3.2): each step's dt comes from the
+    previous step's max |u^n| and max |f^n| on the device; the dt series,
+    the sweep counts and the state follow the oracle."""
+    sisph = _gpu()
+    if name == "db2d":       # the force limit acts once the column collapses
+        case = cases.dam_break_2d(dx=0.05, precision="fp64", dt=0.006, tol=1e-2)
+    elif name == "tg":       # the speed limit acts from the second step
+        case = cases.taylor_green(30, jitter=0.05, seed=3, tol=1e-3, dt=0.0125)
+    else:
+        case = cases.lid_driven_cavity(24, dt=0.02)
+    case = case.replace(dt_mode="adaptive")
+    say("case adaptive", name)
+    ref = oracle.Sim(case)
+    ctx = sisph.Context(case)
+    dts = []
+    for k in range(15):
+        o = ref.step()
+        g = ctx.step(1)[0]
+        assert g["iters"] == o["iters"], f"step {k}"
+        assert math.isclose(g["dt"], o["dt"], rel_tol=1e-12), f"step {k}: {g['dt']} vs {o['dt']}"
+        dts.append(g["dt"])
+    say("  dt series", dts[0], min(dts), max(dts))
+    assert len(set(dts)) > 2          # the step really adapts
+    s = ctx.read_state()
+    assert rel(s["p"], ref.p) < FP64_TOL
+    assert rel(s["u"], ref.u) < FP64_TOL
+    assert rel(s["x"], ref.x) < FP64_TOL
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", ["tg50_quintic", "db2d_dx0.05"])
 def test_mixed_precision_single_step(name):
     """Mixed mode against the FP64 oracle with the oracle run on the GPU's

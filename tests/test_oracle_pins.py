@@ -440,6 +440,58 @@ def test_iteration_limits():
     assert out["iters"] == 5 and not out["converged"]
 
 
+@pytest.mark.parametrize("U0,g,which", [(5.0, 0.1, "cfl"), (0.01, 400.0, "force"), (0.01, 0.1, "cap")])
+def test_adaptive_dt_uniform_free_fall(U0, g, which):
+    """Section 3.2, adaptive steps, in closed form: a periodic lattice moving
+    uniformly under gravity has no viscous, stress or pressure force, so
+    max |u^n| = U0 on the first step, max |f| = g, and the next step is
+    min(dt_max, 0.25 h / U0, 0.25 sqrt(h / g)).  On the second step the
+    speed is |(U0, -g dt0)|, from u^n, not from u^{n+1}."""
+    base = cases.periodic_lattice(16, kernel="wendland", hdx=1.3)
+    u = np.zeros_like(base.u)
+    u[:, 0] = U0
+    dt0 = 0.05
+    c = base.replace(u=u, gravity=(0.0, -g, 0.0), dt=dt0, dt_mode="adaptive")
+    h = c.h
+    sim = oracle.Sim(c)
+    o = sim.step()
+    assert o["dt"] == dt0
+    assert math.isclose(o["umax"], U0, rel_tol=1e-13)
+    assert math.isclose(o["fmax"], g, rel_tol=1e-12)
+    terms = {"cap": dt0, "cfl": 0.25 * h / U0, "force": 0.25 * math.sqrt(h / g)}
+    assert min(terms, key=terms.get) == which
+    assert math.isclose(o["dt_next"], terms[which], rel_tol=1e-12)
+    o2 = sim.step()
+    assert o2["dt"] == o["dt_next"]
+    assert math.isclose(o2["umax"], math.hypot(U0, g * dt0), rel_tol=1e-12)
+    assert math.isclose(sim.t, dt0 + o["dt_next"], rel_tol=1e-15)
+    # fixed mode keeps dt whatever the maxima say
+    fixed = oracle.Sim(c.replace(dt_mode="fixed"))
+    assert fixed.step()["dt_next"] == dt0 and fixed.step()["dt"] == dt0
+
+
+@pytest.mark.parametrize("which", ["tg", "db2d"])
+def test_adaptive_dt_force_is_velocity_change(which):
+    """The acceleration behind the force limit is every term of the step
+    (predictor forces with gravity and the pressure force), so it equals
+    (u^{n+1} - u^n) / dt particle by particle; max |u^n| is the start-of-step
+    speed.  A dropped term (pressure or gravity) fails this."""
+    if which == "tg":
+        c = cases.taylor_green(24, jitter=0.1, seed=5)
+    else:
+        c = cases.dam_break_2d(dx=0.05, precision="fp64")
+    c = c.replace(dt_mode="adaptive")
+    sim = oracle.Sim(c)
+    for _ in range(3):
+        u0 = sim.u.copy()
+        o = sim.step()
+        dv = np.linalg.norm((sim.u - u0) / o["dt"], axis=1).max()
+        assert math.isclose(o["fmax"], dv, rel_tol=1e-9)
+        assert math.isclose(o["umax"], np.linalg.norm(u0, axis=1).max(), rel_tol=1e-14, abs_tol=0.0)
+        assert o["dt_next"] <= c.dt
+        assert o["fmax"] > 0
+
+
 def test_projection_reduces_divergence():
     """P12: after the solve the corrected velocity is far less divergent than
     u* (an approximate projection, so not exactly zero).  A smooth divergent
