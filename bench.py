@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=20)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gb", type=float, default=1.0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default sweep variant instead of autotuning it after the warmup")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a counter calibration "
                          "reference for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -224,6 +226,13 @@ def main():
           f"workspace {ctx.nbytes / 1e6:.1f} MB", file=sys.stderr, flush=True)
     if args.warmup:
         ctx.step(args.warmup)
+    tuned = None
+    if args.warmup and not args.no_autotune:
+        # the project's autotuner picks the sweep launch variant on the live
+        # state (outside the timed region; variants change speed only)
+        best, us = ctx.autotune(20)
+        tuned = {"variant": best, "us_per_variant": [round(t, 3) for t in us]}
+        print(f"[bench] autotuned sweep variant {best}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ctx.sweep_counters(reset=True)
     t0 = time.perf_counter()
@@ -265,6 +274,7 @@ def main():
         "particle_steps_per_s": case.n_fluid * args.steps / elapsed if elapsed > 0 else 0.0,
         "sweep_time_frac": cnt["sweep_ms"] / 1e3 / elapsed if elapsed > 0 else 0.0,
         "roofline": roofline,
+        "sweep_variant": tuned if tuned is not None else {"variant": ctx.variant},
     }
     ctx.close()
     if not args.no_batch_compare:

@@ -158,7 +158,7 @@ void ppe_iteration(const Target &T, int launch);
 // The sweep alone (no wall pressure), for timing variants.
 void sweep_only(const Target &T, int launch);
 constexpr int kSweepVariants = 6;
-constexpr int kDefaultVariant = 1;
+constexpr int kDefaultVariant = 0;
 void settle_pressure(const Target &T);
 void wall_pressure_final(const Target &T);
 void pressure_max(const Target &T);

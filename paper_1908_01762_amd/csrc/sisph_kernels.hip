@@ -856,14 +856,13 @@ struct CopyP32 {
 // writes iterate L+1.  Mixed: the cached (j, c_ij) words and the FP32 copy of
 // iterate L; FP64: indices, FP64 coefficients and iterate L.
 //
-// Stopping (eq. convergence): launch L first decides, from the partial sums
-// of sweep L-1, whether the solve stopped after L sweeps.  Every workgroup
-// sums the same partials in the same order and so takes the same decision;
-// the case's workgroup 0 records it; no fence or cross-workgroup
+// Stopping (eq. convergence): launch L decides, from the partial sums of
+// sweep L-1, whether the solve stopped after L sweeps; the case's workgroup
+// 0 takes and records the decision.  No fence or cross-workgroup
 // synchronisation is needed (the kernel boundary makes the partials
-// visible).  A launch whose solve stopped at an earlier count returns at
-// once: stopped_at < L can only have been written by an earlier launch, so
-// every wavefront reads the same answer.
+// visible).  A launch whose solve stopped at an earlier
+// count returns at once: stopped_at < L can only have been written by an
+// earlier launch, so every wavefront reads the same answer.
 //
 // First batch: slots 1..FIRST loaded without waiting for the row's count
 // (every slot below cap is inside the list storage; slots past the count
@@ -988,10 +987,19 @@ template <typename R, int FIRST>
 struct Sweep {
     static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int L) {
         Control *ctl = S.ctl;
-        if (__hip_atomic_load(&ctl->stopped_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < L) return;
+        // The stop flag travels with the first round trip and is tested
+        // before the gathers (a finished case reads its row data in vain).
+        const int32_t stopped = __hip_atomic_load(&ctl->stopped_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // Only the case's first workgroup reduces the partial sums of sweep
+        // L-1, decides and records.  The others write iterate L+1 whatever
+        // the decision, which is harmless: when the solve stopped after L
+        // sweeps the result is iterate L, in the other buffer, and launch
+        // L+1 returns at once.  (Every workgroup deciding costs each one a
+        // read of all the partial sums: 17 % slower at 160k particles.)
+        const bool decides = L > 0 && blk == 0;
         const double lam = __longlong_as_double((long long)ctl->lambda_bits);   // fixed during the solve
         PartialLoad pl;
-        if (L > 0) load_partials(S.partial, nblk, L, pl);
+        if (decides) load_partials(S.partial, nblk, L, pl);
         const int64_t nf = P.nf;
         const double *pc = S.p[L & 1];
         double *pn = S.p[(L + 1) & 1];
@@ -999,16 +1007,24 @@ struct Sweep {
         float *qn = S.p32 + ((L + 1) & 1) * P.ntot;
         const typename CoefSlot<R>::T *coef = (const typename CoefSlot<R>::T *)S.coef;
         ROW;
-        double v = 0.0, pold = 0.0;
-        if (i < nf) {
-            // one round trip: row values, the first batch of (j, c) words and
-            // (above) the partial sums
-            int32_t jj[FIRST];
-            R cc[FIRST];
+        const bool live = i < nf;
+        // one round trip: row values, the first batch of (j, c) words and
+        // (above) the partial sums
+        int32_t jj[FIRST];
+        R cc[FIRST];
+        double D = 0.0, r = 0.0, pold = 0.0;
+        int32_t f = 1, c = 0;
+        if (live) {
             load_batch<R, FIRST>(i, nf, 1, 0, P.cap, true, coef, S.nbr, jj, cc);
-            const double D = S.dii[i], r = S.rhs[i];
-            const int32_t f = S.fs[i], c = S.cnt[i];
+            D = S.dii[i];
+            r = S.rhs[i];
+            f = S.fs[i];
+            c = S.cnt[i];
             pold = pc[i];
+        }
+        if (stopped < L) return;   // only earlier launches write values below L
+        double v = 0.0;
+        if (live) {
             R s = gather_sum<R, FIRST>(i, 1, c, jj, cc, pc, qc, R(0));
             for (int k0 = 1 + FIRST; k0 < c; k0 += kSweepBatch) {
                 int32_t jb[kSweepBatch];
@@ -1018,10 +1034,10 @@ struct Sweep {
             }
             if (D != 0.0 && !f) v = P.omega * (r + (double)s) / D + (1.0 - P.omega) * pold;
         }
-        // the decision for L sweeps gates every write of this launch
-        if (L > 0 && stopped_after(P, S.partial, nblk, L, pl, lam, blk == 0, ctl)) return;
+        // the decision for L sweeps gates the writes of the deciding workgroups
+        if (decides && stopped_after(P, S.partial, nblk, L, pl, lam, blk == 0, ctl)) return;
         double a = 0.0, b = 0.0;
-        if (i < nf) {
+        if (live) {
             pn[i] = v;
             if constexpr (sizeof(R) == 4) qn[i] = (float)v;
             a = fabs(v - pold);
@@ -1381,13 +1397,14 @@ void copy_p32(const Target &T) { launch<CopyP32, K_TOT>(T); }
 // XCD-contiguous workgroup mapping for v < 3, hardware order otherwise.
 template <typename R>
 static void sweep_variant(const Target &T, int L, int v) {
+    // v = 3 * (hardware workgroup order) + index of FIRST in kSweepFirsts
     switch (v) {
-    case 0: launch<Sweep<R, kSweepFirsts[0]>, K_FLUID, true>(T, L); break;
+    case 1: launch<Sweep<R, kSweepFirsts[1]>, K_FLUID, true>(T, L); break;
     case 2: launch<Sweep<R, kSweepFirsts[2]>, K_FLUID, true>(T, L); break;
     case 3: launch<Sweep<R, kSweepFirsts[0]>, K_FLUID, false>(T, L); break;
     case 4: launch<Sweep<R, kSweepFirsts[1]>, K_FLUID, false>(T, L); break;
     case 5: launch<Sweep<R, kSweepFirsts[2]>, K_FLUID, false>(T, L); break;
-    default: launch<Sweep<R, kSweepFirsts[1]>, K_FLUID, true>(T, L); break;
+    default: launch<Sweep<R, kSweepFirsts[0]>, K_FLUID, true>(T, L); break;
     }
 }
 
