@@ -236,6 +236,7 @@ static Target single_target(sisph_ctx *ctx) {
     T.precision = ctx->P.precision;
     T.variant = ctx->variant;
     T.adaptive = ctx->P.adaptive_dt;
+    T.precheck = ctx->P.nf >= kPrecheckRows ? 1 : 0;
     T.s = ctx->stream;
     return T;
 }
@@ -535,7 +536,10 @@ static int32_t ppe_loop(const Target &T, int64_t predicted, int64_t limit, hipEv
         sweep_ms += cms;
         launches += chunk;
         if (all_done || launched >= limit) break;
-        chunk = std::min<int64_t>(std::min<int64_t>(2 * chunk, 64), limit - launched);
+        // the prediction fell short: grow by a quarter of what has been
+        // launched (a launch past the stop is wasted, a poll costs a host
+        // round trip)
+        chunk = std::min<int64_t>(std::min<int64_t>(std::max<int64_t>(2, launched / 4), 64), limit - launched);
         if (chunk < 1) chunk = 1;
     }
     return SISPH_OK;
@@ -873,6 +877,7 @@ static int32_t rebuild_group(sisph_batch *b, Group &g) {
     T.precision = g.precision;
     T.s = b->stream;
     for (auto *c : g.members) T.adaptive |= c->P.adaptive_dt;
+    T.precheck = 1;
     for (int k = 0; k < K_COUNT; ++k) {
         std::vector<int32_t> owner;
         std::vector<int64_t> first(n);

@@ -129,6 +129,10 @@ struct Target {
     int32_t dim, kernel, precision;
     int32_t variant;                 // Jacobi-sweep variant (speed only)
     int32_t adaptive;                // some case chooses its next dt
+    // the sweep tests the stop flag before its other loads: batches (cases
+    // stop at different counts) and large cases (a launch beyond the stop
+    // would read every row), see precheck_for()
+    int32_t precheck;
     bool batched;
     hipStream_t s;
 };
@@ -157,6 +161,8 @@ void copy_p32(const Target &T);
 void ppe_iteration(const Target &T, int launch);
 // The sweep alone (no wall pressure), for timing variants.
 void sweep_only(const Target &T, int launch);
+// Fluid rows from which a single case's sweep tests the stop flag first.
+constexpr int64_t kPrecheckRows = int64_t(1) << 19;
 constexpr int kSweepVariants = 6;
 constexpr int kDefaultVariant = 0;
 void settle_pressure(const Target &T);

@@ -983,13 +983,19 @@ __device__ bool stopped_after(const Params &P, const double *partial, int64_t nb
     return stop_sh != 0;
 }
 
-template <typename R, int FIRST>
+template <typename R, int FIRST, bool PRECHECK>
 struct Sweep {
     static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int L) {
         Control *ctl = S.ctl;
-        // The stop flag travels with the first round trip and is tested
-        // before the gathers (a finished case reads its row data in vain).
+        // PRECHECK: a finished solve is detected before any other load (one
+        // extra round trip per sweep, but a launch beyond the stop costs
+        // almost nothing).  Otherwise the stop flag travels with the first
+        // round trip and is tested before the gathers, and a launch beyond
+        // the stop reads its row data in vain.
         const int32_t stopped = __hip_atomic_load(&ctl->stopped_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if constexpr (PRECHECK) {
+            if (stopped < L) return;
+        }
         // Only the case's first workgroup reduces the partial sums of sweep
         // L-1, decides and records.  The others write iterate L+1 whatever
         // the decision, which is harmless: when the solve stopped after L
@@ -1395,22 +1401,27 @@ void copy_p32(const Target &T) { launch<CopyP32, K_TOT>(T); }
 
 // Sweep variants (numerically identical): first-batch size kSweepFirsts[v % 3],
 // XCD-contiguous workgroup mapping for v < 3, hardware order otherwise.
-template <typename R>
+template <typename R, bool PRE>
 static void sweep_variant(const Target &T, int L, int v) {
     // v = 3 * (hardware workgroup order) + index of FIRST in kSweepFirsts
     switch (v) {
-    case 1: launch<Sweep<R, kSweepFirsts[1]>, K_FLUID, true>(T, L); break;
-    case 2: launch<Sweep<R, kSweepFirsts[2]>, K_FLUID, true>(T, L); break;
-    case 3: launch<Sweep<R, kSweepFirsts[0]>, K_FLUID, false>(T, L); break;
-    case 4: launch<Sweep<R, kSweepFirsts[1]>, K_FLUID, false>(T, L); break;
-    case 5: launch<Sweep<R, kSweepFirsts[2]>, K_FLUID, false>(T, L); break;
-    default: launch<Sweep<R, kSweepFirsts[0]>, K_FLUID, true>(T, L); break;
+    case 1: launch<Sweep<R, kSweepFirsts[1], PRE>, K_FLUID, true>(T, L); break;
+    case 2: launch<Sweep<R, kSweepFirsts[2], PRE>, K_FLUID, true>(T, L); break;
+    case 3: launch<Sweep<R, kSweepFirsts[0], PRE>, K_FLUID, false>(T, L); break;
+    case 4: launch<Sweep<R, kSweepFirsts[1], PRE>, K_FLUID, false>(T, L); break;
+    case 5: launch<Sweep<R, kSweepFirsts[2], PRE>, K_FLUID, false>(T, L); break;
+    default: launch<Sweep<R, kSweepFirsts[0], PRE>, K_FLUID, true>(T, L); break;
     }
 }
 
 void sweep_only(const Target &T, int L) {
-    if (T.precision == SISPH_MIXED) sweep_variant<float>(T, L, T.variant);
-    else sweep_variant<double>(T, L, T.variant);
+    if (T.precision == SISPH_MIXED) {
+        if (T.precheck) sweep_variant<float, true>(T, L, T.variant);
+        else sweep_variant<float, false>(T, L, T.variant);
+    } else {
+        if (T.precheck) sweep_variant<double, true>(T, L, T.variant);
+        else sweep_variant<double, false>(T, L, T.variant);
+    }
 }
 
 void ppe_iteration(const Target &T, int L) {
