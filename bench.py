@@ -243,8 +243,7 @@ def main():
     iters = sum(s["iters"] for s in stats)
     value = case.n_fluid * iters / elapsed if elapsed > 0 else 0.0
     cnt = ctx.sweep_counters()
-    off, _ = ctx.neighbors(1, 0)
-    sb = sweep_bytes(case, int(off[-1]))
+    sb = sweep_bytes(case, ctx.pair_count(1, 0))
     avg_launch_s = cnt["sweep_ms"] / 1e3 / max(cnt["launches"], 1)
     achieved = sb["bytes"] * cnt["effective"] / (cnt["sweep_ms"] / 1e3) / 1e9 if cnt["sweep_ms"] > 0 else 0.0
     traffic = traffic_from_profiles(kernel_sha(), args.workload)

@@ -159,12 +159,16 @@ enum {
     SISPH_FIELD_DII = 4,      /* [n_fluid]                                 */
     SISPH_FIELD_UNEW = 5,     /* [n_fluid][dim]   u^{n+1}                  */
     SISPH_FIELD_WALL_U = 6,   /* [n_wall][dim]    stage-1 ghost velocity   */
-    SISPH_FIELD_WALL_USTAR = 7, /* [n_wall][dim]  stage-2 slip ghost u*    */
+    SISPH_FIELD_WALL_USTAR = 7, /* [n_wall][dim]  stage-2 ghost u*         */
     SISPH_FIELD_FS = 8,       /* [n_fluid]        free-surface flag (0/1)  */
     SISPH_FIELD_NORMAL = 9,   /* [n_wall][dim]    wall unit normals        */
     SISPH_FIELD_PRESSURE = 10 /* [n]              current pressure         */
 };
 int32_t sisph_read_field(sisph_ctx *ctx, int32_t field, double *out);
+
+/* Total number of stored neighbour pairs (self included) of the lists held
+ * for stage / dest (as below); only the per-row counts leave the device. */
+int32_t sisph_pair_count(sisph_ctx *ctx, int32_t stage, int32_t dest, int64_t *pairs);
 
 /* Neighbour sets as CSR in original ids, each row ascending.
  * stage 0: N^n (valid after sisph_bin), stage 1: N* (after sisph_predict);

@@ -86,6 +86,8 @@ def lib():
         L.sisph_write_state.argtypes = [C.c_void_p, _DP, _DP, _DP, _DP]
         L.sisph_read_field.restype = C.c_int32
         L.sisph_read_field.argtypes = [C.c_void_p, C.c_int32, _DP]
+        L.sisph_pair_count.restype = C.c_int32
+        L.sisph_pair_count.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
         L.sisph_debug_neighbors.restype = C.c_int32
         L.sisph_debug_neighbors.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
                                             C.POINTER(C.c_int32), C.c_int64]
@@ -260,6 +262,12 @@ class Context:
         _check(lib().sisph_debug_neighbors(self.h, stage, dest, offp, ids.ctypes.data_as(C.POINTER(C.c_int32)),
                                             ids.size), self.h)
         return off, ids[:off[-1]].copy()
+
+    def pair_count(self, stage: int, dest: int = 0) -> int:
+        """Stored neighbour pairs (self included) of the held lists."""
+        n = C.c_int64()
+        _check(lib().sisph_pair_count(self.h, stage, dest, C.byref(n)), self.h)
+        return n.value
 
     def timings(self):
         a, b = C.c_double(), C.c_double()

@@ -64,6 +64,7 @@ def test_neighbour_sets_bit_exact(name):
     off, ids = ctx.neighbors(0, 0)
     roff, rids = oracle.neighbors(case)
     assert _same_sets(off, ids, roff, rids)
+    assert ctx.pair_count(0, 0) == roff[-1]
     if case.n_wall:
         off, ids = ctx.neighbors(0, 1)
         roff, rids = oracle.neighbors(case, dest=(case.n_fluid, case.n), src=(0, case.n_fluid))
