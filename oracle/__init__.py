@@ -25,6 +25,7 @@ PREF = {"fixed": 0, "twice_max": 1}
 CONV = {"sum": 0, "mean": 1}
 USTAR = {"slip": 0, "noslip": 1}
 DT_MODE = {"fixed": 0, "adaptive": 1}
+SOLVER = {"jacobi": 0, "bicgstab": 1}
 
 
 def build(force: bool = False) -> str:
@@ -41,7 +42,7 @@ class Params(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "dim", "kernel", "pgrad", "gtvf", "free_surface", "p_ref_mode",
         "min_iter", "max_iter", "gtvf_K", "forced_iters", "conv_norm", "ustar_wall", "dt_mode",
-        "nf", "nw")] + \
+        "solver", "nf", "nw")] + \
         [(n, C.c_double) for n in (
             "h", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio", "omega", "tol", "dt_max")] + \
         [("g", C.c_double * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
@@ -107,6 +108,7 @@ def params(case, **over) -> Params:
     P.conv_norm = CONV[case.conv_norm]
     P.ustar_wall = USTAR[case.ustar_wall]
     P.dt_mode = DT_MODE[case.dt_mode]
+    P.solver = SOLVER[case.solver]
     P.dt_max = float(case.dt)
     P.nf = case.n_fluid
     P.nw = case.n_wall
@@ -236,6 +238,8 @@ class Sim:
     """Oracle state of one case, advanced one SISPH step at a time."""
 
     def __init__(self, case, forced_iters: Optional[int] = None):
+        if case.solver == "bicgstab" and not case.free_surface:
+            raise ValueError("BiCGStab needs free-surface rows: without them the PPE fixes p only up to a constant")
         self.case = case
         self.x = case.x.copy()
         self.u = case.u.copy()

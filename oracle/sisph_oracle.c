@@ -411,6 +411,129 @@ static void wall_pressure_c(const orc_params *P, const csr_t *Nw, const double *
     }
 }
 
+/* The linear part of eq. p-shepard (no hydrostatic term, no clamp):
+ * z_w = sum_f z_f W_wf / sum_f W_wf, 0 without fluid neighbours.  Writes
+ * z[nf..nf+nw).  With z = 0 for every fluid particle and hydro set, the
+ * hydrostatic part alone instead. */
+static void wall_extrap_c(const orc_params *P, const csr_t *Nw, const double *x,
+                          const double *rho_all, double *z, int hydro) {
+    int64_t dim = P->dim;
+    double d[3];
+    for (int64_t w = 0; w < P->nw; ++w) {
+        int64_t iw = P->nf + w;
+        double sp = 0.0, sr[3] = {0, 0, 0}, sw = 0.0;
+        for (int64_t e = Nw->off[w]; e < Nw->off[w + 1]; ++e) {
+            int64_t f = Nw->ids[e];
+            pair_vec(P, x + iw * dim, x + f * dim, d);
+            double W = orc_W(P->kernel, dim, sqrt(norm2(dim, d)), P->h);
+            sp += z[f] * W;
+            for (int k = 0; k < dim; ++k) sr[k] += rho_all[f] * d[k] * W;
+            sw += W;
+        }
+        z[iw] = sw > 0.0 ? (hydro ? dot(dim, P->g, sr) : sp) / sw : 0.0;
+    }
+}
+
+/* BiCGStab (van der Vorst 1992) on the PPE scaled by its diagonal: for a
+ * row i with D_ii != 0 that is not on the free surface,
+ *   (M z)_i = z_i - sum_j c_ij z_j / D_ii,   f_i = (RHS_i + sum_w c_iw h_w) / D_ii
+ * where a wall neighbour's value is the linear part of eq. p-shepard applied
+ * to z and h_w its hydrostatic part; every other row is z_i = 0.  Starts from
+ * p^n.  After iteration k the stopping test is eq. convergence with the
+ * Jacobi update replaced by omega times the scaled residual (the update a
+ * Jacobi sweep from x_k would make): omega sum|r_k| / max(Lambda, sum|x_k|)
+ * < tol, or k >= max_iter (forced_iters > 0: exactly that many).  A zero
+ * denominator in a step coefficient stops the iteration after that step.
+ * Only free-surface problems are solved this way: without free-surface
+ * (p = 0) rows every row of M annihilates constants, the system fixes p only
+ * up to one and BiCGStab drifts along it (the caller refuses those).
+ * On return p[0..nf) holds the solution; *iters and *ratio are set. */
+static void bicgstab_c(const orc_params *P, const csr_t *N, const csr_t *Nw, const double *xs,
+                       const double *rho_all, const double *coef, const double *diag,
+                       const double *rhs, const int64_t *fs, double lambda, double *p,
+                       int64_t *iters, double *ratio_out) {
+    int64_t nf = P->nf, n = nf + P->nw;
+    size_t n1 = (size_t)(n > 0 ? n : 1);
+    double *h = calloc(n1, sizeof(double)), *f = calloc(n1, sizeof(double));
+    double *x = calloc(n1, sizeof(double)), *r = calloc(n1, sizeof(double));
+    double *rh = calloc(n1, sizeof(double)), *pv = calloc(n1, sizeof(double));
+    double *v = calloc(n1, sizeof(double)), *sv = calloc(n1, sizeof(double));
+    double *t = calloc(n1, sizeof(double)), *mx = calloc(n1, sizeof(double));
+    char *act = calloc(n1, 1);
+    for (int64_t i = 0; i < nf; ++i) act[i] = diag[i] != 0.0 && !fs[i];
+    if (P->nw) wall_extrap_c(P, Nw, xs, rho_all, h, 1);
+    /* (M z) for the fluid rows; the wall slots of z must hold its extrapolation */
+#define APPLY_M(z, out)                                                        \
+    for (int64_t i = 0; i < nf; ++i) {                                         \
+        if (!act[i]) { (out)[i] = (z)[i]; continue; }                          \
+        double acc = 0.0;                                                      \
+        for (int64_t e = N->off[i]; e < N->off[i + 1]; ++e)                    \
+            acc += coef[e] * (z)[N->ids[e]];                                   \
+        (out)[i] = (z)[i] - acc / diag[i];                                     \
+    }
+    for (int64_t i = 0; i < nf; ++i) {
+        if (!act[i]) continue;
+        double acc = 0.0;
+        for (int64_t e = N->off[i]; e < N->off[i + 1]; ++e)
+            if (N->ids[e] >= nf) acc += coef[e] * h[N->ids[e]];
+        f[i] = (rhs[i] + acc) / diag[i];
+        x[i] = p[i];
+    }
+    if (P->nw) wall_extrap_c(P, Nw, xs, rho_all, x, 0);
+    APPLY_M(x, mx);
+    for (int64_t i = 0; i < nf; ++i) {
+        r[i] = act[i] ? f[i] - mx[i] : 0.0;
+        rh[i] = r[i];
+    }
+    double rho_old = 1.0, alpha = 1.0, om = 1.0, ratio = 0.0;
+    double lam_s = P->conv_norm == ORC_CONV_MEAN ? (double)nf * lambda : lambda;
+    int64_t k = 0;
+    for (;;) {
+        double rho = 0.0;
+        for (int64_t i = 0; i < nf; ++i) rho += rh[i] * r[i];
+        double beta = (rho / rho_old) * (alpha / om);
+        for (int64_t i = 0; i < nf; ++i) pv[i] = r[i] + beta * (pv[i] - om * v[i]);
+        if (P->nw) wall_extrap_c(P, Nw, xs, rho_all, pv, 0);
+        APPLY_M(pv, v);
+        double rv = 0.0;
+        for (int64_t i = 0; i < nf; ++i) rv += rh[i] * v[i];
+        int brk = rv == 0.0;
+        alpha = brk ? 0.0 : rho / rv;
+        for (int64_t i = 0; i < nf; ++i) sv[i] = r[i] - alpha * v[i];
+        if (P->nw) wall_extrap_c(P, Nw, xs, rho_all, sv, 0);
+        APPLY_M(sv, t);
+        double ts = 0.0, tt = 0.0;
+        for (int64_t i = 0; i < nf; ++i) {
+            ts += t[i] * sv[i];
+            tt += t[i] * t[i];
+        }
+        brk = brk || tt == 0.0;
+        om = tt == 0.0 ? 0.0 : ts / tt;
+        double num = 0.0, den = 0.0;
+        for (int64_t i = 0; i < nf; ++i) {
+            x[i] = x[i] + alpha * pv[i] + om * sv[i];
+            r[i] = sv[i] - om * t[i];
+            num += fabs(r[i]);
+            den += fabs(x[i]);
+        }
+        num *= P->omega;
+        double scale = lam_s > den ? lam_s : den;
+        ratio = scale > 0.0 ? num / scale : (num > 0.0 ? INFINITY : 0.0);
+        ++k;
+        rho_old = rho;
+        if (P->forced_iters > 0) {
+            if (k >= P->forced_iters) break;
+        } else if (ratio < P->tol || k >= P->max_iter || brk || !isfinite(num) || !isfinite(den)) {
+            break;
+        }
+    }
+#undef APPLY_M
+    for (int64_t i = 0; i < nf; ++i) p[i] = x[i];
+    *iters = k;
+    *ratio_out = ratio;
+    free(h); free(f); free(x); free(r); free(rh); free(pv); free(v); free(sv); free(t); free(mx); free(act);
+}
+
 /* Pressure acceleration, eq. mom:sph:press:pij (asymm) or
  * eq. mom:sph:press:symm (symm). */
 static void pressure_force_c(const orc_params *P, const csr_t *N, const double *x,
@@ -648,7 +771,12 @@ int64_t orc_step(const orc_params *P, double *x, double *u, double *ut, double *
     memcpy(pk, p, sizeof(double) * (size_t)n);
     int64_t k = 0;
     double ratio = 0.0;
-    for (;;) {
+    if (P->solver == ORC_BICGSTAB && !P->free_surface) {
+        /* refused: see bicgstab_c */
+        k = -1;
+        ratio = NAN;
+    } else if (P->solver == ORC_BICGSTAB) bicgstab_c(P, &N, &Nw, xs, rho_all, coef, diag, rhs, fs, lambda, pk, &k, &ratio);
+    else for (;;) {
         if (nw) wall_pressure_c(P, &Nw, xs, rho_all, pk);
         double num = 0.0, den = 0.0;
         for (int64_t i = 0; i < nf; ++i) {

@@ -22,12 +22,14 @@ enum { ORC_PREF_FIXED = 0, ORC_PREF_TWICE_MAX = 1 };
 enum { ORC_CONV_SUM = 0, ORC_CONV_MEAN = 1 };
 enum { ORC_USTAR_SLIP = 0, ORC_USTAR_NOSLIP = 1 };
 enum { ORC_DT_FIXED = 0, ORC_DT_ADAPTIVE = 1 };
+enum { ORC_JACOBI = 0, ORC_BICGSTAB = 1 };
 
 typedef struct {
     int64_t dim, kernel, pgrad, gtvf, free_surface, p_ref_mode;
     int64_t min_iter, max_iter, gtvf_K, forced_iters, conv_norm, ustar_wall;
     int64_t dt_mode;  /* ORC_DT_FIXED: every step takes dt; ORC_DT_ADAPTIVE:
                          dt_next is chosen from this step's maxima */
+    int64_t solver;   /* ORC_JACOBI (the paper's scheme) or ORC_BICGSTAB */
     int64_t nf, nw;
     double h, rho0, nu, alpha, c_ref, dt, eta, fs_ratio, omega, tol;
     double dt_max;    /* adaptive mode: upper bound of dt_next             */

@@ -36,6 +36,7 @@ PRECISION = {"fp64": 0, "mixed": 1}
 CONV = {"sum": 0, "mean": 1}
 USTAR = {"slip": 0, "noslip": 1}
 DT_MODE = {"fixed": 0, "adaptive": 1}
+SOLVER = {"jacobi": 0, "bicgstab": 1}
 SUPPORT = {"quintic": 3.0, "wendland": 2.0}
 
 
@@ -81,6 +82,7 @@ class Case:
     conv_norm: str = "sum"
     ustar_wall: str = "slip"
     dt_mode: str = "fixed"       # "adaptive": dt is the first step's and the largest step
+    solver: str = "jacobi"       # "bicgstab": the PPE by BiCGStab on the same operator
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property
