@@ -163,6 +163,35 @@ def batched_vs_plain(n_cases: int, steps: int, seed: int) -> dict:
                         "mixed precision, tol 1e-4 (TG) / 1e-3 (dam break)" % seed}
 
 
+def solver_compare(dx: float, steps: int, tols=(1e-2, 1e-3, 1e-4)) -> dict:
+    """Jacobi (the paper's scheme) against BiCGStab on the same cached
+    operator at equal tolerance: 2D dam break (free surface, so the system is
+    non-singular), mixed precision, the same initial state and step count
+    for both.  Operator applications: one per Jacobi sweep, two per BiCGStab
+    iteration plus one for the initial residual."""
+    import torch
+    from paper_1908_01762_amd import cases, sisph
+    out = {"workload": f"2D dam break dx={dx} (mixed), {steps} steps after one warm step", "rows": []}
+    for tol in tols:
+        for solver in ("jacobi", "bicgstab"):
+            case = cases.dam_break_2d(dx=dx, precision="mixed", tol=tol).replace(solver=solver, max_iter=20000)
+            ctx = sisph.Context(case)
+            ctx.step(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = ctx.step(steps)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            its = [s["iters"] for s in st]
+            ops = sum(its) if solver == "jacobi" else sum(2 * k + 1 for k in its)
+            out["rows"].append({"tol": tol, "solver": solver, "fluid_particles": case.n_fluid,
+                                "mean_iters": sum(its) / len(its), "operator_applications": ops,
+                                "ms_per_step": el * 1e3 / steps,
+                                "all_converged": all(s["converged"] for s in st)})
+            ctx.close()
+    return out
+
+
 def serving(n_requests: int, steps: int, rate_hz: float, budget_gb: float, seed: int) -> dict:
     """Continuous batching: Poisson arrivals, admission by workspace bytes."""
     from paper_1908_01762_amd import cases
@@ -192,6 +221,8 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=20)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gb", type=float, default=1.0)
+    ap.add_argument("--no-solver-compare", action="store_true")
+    ap.add_argument("--compare-dx", type=float, default=0.01)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default sweep variant instead of autotuning it after the warmup")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -279,6 +310,9 @@ def main():
     if not args.no_batch_compare:
         print("[bench] batched vs plain", file=sys.stderr, flush=True)
         line["batched_vs_plain"] = batched_vs_plain(args.batch_cases, args.batch_steps, seed=0)
+    if not args.no_solver_compare:
+        print("[bench] Jacobi vs BiCGStab", file=sys.stderr, flush=True)
+        line["solver_compare"] = solver_compare(args.compare_dx, args.batch_steps)
     if not args.no_serving:
         print("[bench] serving", file=sys.stderr, flush=True)
         line["serving"] = serving(args.serve_requests, args.serve_steps, args.serve_rate,

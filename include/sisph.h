@@ -63,6 +63,7 @@ enum { SISPH_PREF_FIXED = 0, SISPH_PREF_TWICE_MAX = 1 };
 enum { SISPH_CONV_SUM = 0, SISPH_CONV_MEAN = 1 };
 enum { SISPH_USTAR_SLIP = 0, SISPH_USTAR_NOSLIP = 1 };
 enum { SISPH_DT_FIXED = 0, SISPH_DT_ADAPTIVE = 1 };
+enum { SISPH_JACOBI = 0, SISPH_BICGSTAB = 1 };
 
 /* One case.  Parameters follow the paper's statement of the problem.
  *  precision   SISPH_FP64: every sum in FP64.  SISPH_MIXED: neighbour sums,
@@ -91,6 +92,16 @@ enum { SISPH_DT_FIXED = 0, SISPH_DT_ADAPTIVE = 1 };
  *              from the previous step's largest fluid speed at its start
  *              and largest total acceleration (predictor forces, gravity
  *              and pressure force); dt is the upper bound.
+ *  solver      SISPH_JACOBI: the paper's damped Jacobi sweeps (eq. p-sor).
+ *              SISPH_BICGSTAB: BiCGStab (the alternative of section 3.1) on
+ *              the same cached coefficients, scaled by D_ii; wall neighbours
+ *              enter through the unclamped Shepard extrapolation (eq.
+ *              p-shepard); stops when omega * sum|scaled residual| /
+ *              max(Lambda, sum|p|) < tol (eq. convergence with the Jacobi
+ *              update of the current iterate).  Free-surface problems only
+ *              (without p = 0 rows the system fixes p only up to a
+ *              constant); such a context cannot join a batch.  iters counts
+ *              BiCGStab iterations (two operator applications each).
  *  periodic    per axis; the box is [box_lo, box_hi) on periodic axes and
  *              the binning range (particles outside are clamped to the edge
  *              cells) on the others.                                         */
@@ -99,6 +110,7 @@ typedef struct {
     int32_t p_ref_mode, conv_norm, min_iter, max_iter, gtvf_K, forced_iters;
     int32_t periodic[3], nbr_cap;
     int32_t ustar_wall, dt_mode;
+    int32_t solver, reserved1;
     int64_t n_fluid, n_wall;
     double h, dx, rho0, nu, alpha, c_ref, dt, eta, fs_ratio, omega, tol, p_ref;
     double gravity[3], box_lo[3], box_hi[3];

@@ -62,6 +62,9 @@ static const char *check_desc(const sisph_case_desc *d) {
     if (d->conv_norm != SISPH_CONV_SUM && d->conv_norm != SISPH_CONV_MEAN) return "unknown conv_norm";
     if (d->ustar_wall != SISPH_USTAR_SLIP && d->ustar_wall != SISPH_USTAR_NOSLIP) return "unknown ustar_wall";
     if (d->dt_mode != SISPH_DT_FIXED && d->dt_mode != SISPH_DT_ADAPTIVE) return "unknown dt_mode";
+    if (d->solver != SISPH_JACOBI && d->solver != SISPH_BICGSTAB) return "unknown solver";
+    if (d->solver == SISPH_BICGSTAB && !d->free_surface)
+        return "BiCGStab needs free-surface rows (otherwise p is fixed only up to a constant)";
     if (d->n_fluid <= 0) return "n_fluid must be positive";
     if (d->n_wall < 0) return "n_wall must be >= 0";
     if (d->n_fluid + d->n_wall >= (int64_t)1 << 31) return "particle count exceeds 2^31";
@@ -135,6 +138,7 @@ static Params make_params(const sisph_case_desc *d) {
     P.gtvf_K = d->gtvf == SISPH_GTVF_OFF ? 0 : d->gtvf_K;
     P.ustar_noslip = d->ustar_wall == SISPH_USTAR_NOSLIP ? 1 : 0;
     P.adaptive_dt = d->dt_mode == SISPH_DT_ADAPTIVE ? 1 : 0;
+    P.solver = d->solver;
     P.cap = neighbour_cap(d);
     P.nf = d->n_fluid;
     P.nw = d->n_wall;
@@ -212,6 +216,12 @@ static void carve(const Params &P, Carver &c, State &S) {
     S.coef = c.take<char>((int64_t)8 * P.cap * nf);
     S.partial = c.take<double>(4 * kind_blocks(P, K_FLUID));
     S.tmp = c.take<double>(16 * nmax);
+    S.bx = S.br = S.brh = S.bp = S.bv = S.bs = S.bt = S.bf = S.bh = S.bpart = nullptr;
+    if (P.solver == SISPH_BICGSTAB) {
+        double **v[9] = {&S.bx, &S.br, &S.brh, &S.bp, &S.bv, &S.bs, &S.bt, &S.bf, &S.bh};
+        for (auto *q : v) *q = c.take<double>(nt);
+        S.bpart = c.take<double>(6 * kind_blocks(P, K_FLUID));
+    }
     S.ctl = c.take<Control>(1);
 }
 
@@ -237,6 +247,7 @@ static Target single_target(sisph_ctx *ctx) {
     T.variant = ctx->variant;
     T.adaptive = ctx->P.adaptive_dt;
     T.precheck = ctx->P.nf >= kPrecheckRows ? 1 : 0;
+    T.solver = ctx->P.solver;
     T.s = ctx->stream;
     return T;
 }
@@ -463,11 +474,13 @@ static void seq_predict(const Target &T) {
 static void seq_ppe_begin(const Target &T) {
     reset_control(T, RESET_PPE);
     rhs_coef(T);
-    if (T.precision == SISPH_MIXED) copy_p32(T);
+    if (T.solver == SISPH_BICGSTAB) bicg_begin(T);
+    else if (T.precision == SISPH_MIXED) copy_p32(T);
 }
 
 static void seq_ppe_end(const Target &T) {
-    settle_pressure(T);
+    if (T.solver == SISPH_BICGSTAB) bicg_settle(T);
+    else settle_pressure(T);
     wall_pressure_final(T);
     pressure_max(T);
 }
@@ -959,6 +972,7 @@ extern "C" int32_t sisph_batch_attach(sisph_batch *b, sisph_ctx *ctx) {
     if (ctx->batch) return fail(ctx, SISPH_E_STATE, "context already attached to a batch");
     if (ctx->state != ST_READY) return fail(ctx, SISPH_E_STATE, "attach between steps only");
     if (ctx->stream != b->stream) return fail(ctx, SISPH_E_INVAL, "context and batch must share a stream");
+    if (ctx->P.solver != SISPH_JACOBI) return fail(ctx, SISPH_E_INVAL, "BiCGStab contexts run alone");
     if ((int32_t)b->cases.size() >= b->max_cases) return fail(ctx, SISPH_E_NOMEM, "batch is full");
     Group *g = nullptr;
     for (auto &x : b->groups)

@@ -31,6 +31,8 @@ struct Params {
     int32_t conv_norm, min_iter, max_iter, forced_iters, gtvf_K, cap;
     int32_t ustar_noslip;   // wall ghost form for u*: 0 slip, 1 no-slip
     int32_t adaptive_dt;    // next dt from this step's maxima
+    int32_t solver;         // SISPH_JACOBI or SISPH_BICGSTAB
+    int32_t pad1;
     int64_t nf, nw, ntot;
     // dt: the fixed step, or the first step and the upper bound when adaptive
     // (kernels read the current step's dt from Control)
@@ -58,6 +60,10 @@ struct Control {
     double dt_next;                   // the next step's (taken at its start)
     unsigned long long umax2_bits;    // max |u^n|^2 over fluid (adaptive dt)
     unsigned long long fmax2_bits;    // max |f^n|^2 over fluid (adaptive dt)
+    // BiCGStab scalars of iterations k (slot k & 1): rho_k = (r^, r_{k-1}),
+    // alpha_k, omega_k; a zero step denominator sets brk
+    double bicg_rho[2], bicg_alpha[2], bicg_omega[2];
+    int32_t bicg_brk, pad2;
 };
 
 // Per-case device arrays.  Unified particle index: fluid [0, nf) in cell
@@ -91,6 +97,10 @@ struct State {
     void *coef;             // cached PPE c_ij: (j, FP32 c) words (mixed) or FP64 [cap][nf]
     double *partial;        // per-workgroup partial sums of two sweeps [2][2][nblk]
     double *tmp;            // reorder scratch [16][max(nf, nw)]
+    // BiCGStab (solver only): x, r, r^, p, v, s, t, scaled RHS f, wall
+    // hydrostatic part h, each [ntot] (wall slots of x, p, s hold their
+    // extrapolation), and six partial-sum rows [6][nblk]
+    double *bx, *br, *brh, *bp, *bv, *bs, *bt, *bf, *bh, *bpart;
     Control *ctl;
 };
 
@@ -133,6 +143,7 @@ struct Target {
     // stop at different counts) and large cases (a launch beyond the stop
     // would read every row), see precheck_for()
     int32_t precheck;
+    int32_t solver;                  // SISPH_JACOBI or SISPH_BICGSTAB (single cases)
     bool batched;
     hipStream_t s;
 };
@@ -158,7 +169,12 @@ void wall_velocity(const Target &T, int which);
 void predictor(const Target &T);
 void rhs_coef(const Target &T);
 void copy_p32(const Target &T);
+// Jacobi: wall pressure and sweep L.  BiCGStab: iteration L+1 (its first
+// kernel decides whether the solve stopped after L iterations).
 void ppe_iteration(const Target &T, int launch);
+// BiCGStab set-up (x = p^n, r = f - M x, r^ = r) and final copy of x into p[0].
+void bicg_begin(const Target &T);
+void bicg_settle(const Target &T);
 // The sweep alone (no wall pressure), for timing variants.
 void sweep_only(const Target &T, int launch);
 // Fluid rows from which a single case's sweep tests the stop flag first.

@@ -282,6 +282,12 @@ struct ResetControl {
             c->den = 0.0;
             c->lambda_bits = 0ull;
             c->pmax_key = 0ull;
+            c->bicg_brk = 0;
+            for (int k = 0; k < 2; ++k) {
+                c->bicg_rho[k] = 1.0;
+                c->bicg_alpha[k] = 1.0;
+                c->bicg_omega[k] = 1.0;
+            }
         }
         if (what & RESET_NEIGHBOURS) {
             c->overflow = 0;
@@ -1287,6 +1293,308 @@ struct Advance {
     }
 };
 
+// -------------------------------------------------------------- BiCGStab
+// The alternative PPE solver of section 3.1 on the cached coefficients:
+// BiCGStab (van der Vorst 1992) on the system scaled by D_ii,
+//   (M z)_i = z_i - sum_j c_ij z_j / D_ii,  f_i = (RHS_i + sum_w c_iw h_w) / D_ii
+// on rows with D_ii != 0 off the free surface (z_i = 0 on the others), a
+// wall neighbour's value being the linear part of eq. p-shepard applied to
+// z and h_w its hydrostatic part (no clamp inside the solve).  Vectors and
+// sums in FP64; the coefficients are the cached ones (FP32 in the mixed
+// mode).  Iteration k runs as seven launches:
+//   Dir (p = r + beta (p - omega v)), wall(p), MatV (v = M p, (r^, v)),
+//   Step (alpha, s = r - alpha v), wall(s), MatT (t = M s, (t, s), (t, t)),
+//   Update (omega, x += alpha p + omega s, r = s - omega t, (r^, r),
+//   sum|r|, sum|x|).
+// Scalars come from per-workgroup partial sums of an earlier launch, which
+// every workgroup adds in the same order (so all agree), or from Control
+// slots written by workgroup 0 of an earlier launch (slot k & 1, never the
+// slot the current launch reads).  Dir of iteration k also takes the
+// stopping decision after k-1 iterations in workgroup 0 (as the Jacobi
+// sweep does); every later kernel of an iteration beyond the stop returns at
+// once, so x keeps the final iterate.  A kernel tests stopped_at only
+// against values that earlier launches write, so all its wavefronts agree.
+
+enum { BP_RHO = 0, BP_ABSR, BP_ABSX, BP_RV, BP_TS, BP_TT, BP_ROWS };
+
+__device__ __forceinline__ bool bicg_active(const State &S, int64_t i) { return S.dii[i] != 0.0 && !S.fs[i]; }
+
+// Sum of one partial-sum row, in a fixed order, returned to every thread.
+__device__ double partial_total(const double *row, int64_t nblk) {
+    __shared__ double sh[kBlock / 64];
+    __shared__ double tot;
+    double a = 0.0;
+    for (int64_t k = threadIdx.x; k < nblk; k += kBlock) a += row[k];
+    a = wave_sum(a);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+        tot = t;
+    }
+    __syncthreads();
+    return tot;
+}
+
+// Workgroup sum of v written to row[blk] (every thread must call).
+__device__ void partial_store(double v, double *row, int64_t blk) {
+    __shared__ double sh[kBlock / 64];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+        row[blk] = t;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool bicg_stopped(const State &S, int it) {
+    return __hip_atomic_load(&S.ctl->stopped_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it;
+}
+
+// (M z)_i for fluid row i (slot 0 is the particle itself, c_ii = 0).
+template <typename R>
+__device__ __forceinline__ double bicg_apply(const Params &P, const State &S, int64_t i, const double *z) {
+    if (!bicg_active(S, i)) return z[i];
+    const int64_t nf = P.nf;
+    const int c = S.cnt[i];
+    double acc = 0.0;
+    for (int k = 1; k < c; ++k) {
+        const int64_t at = (int64_t)k * nf + i;
+        if constexpr (sizeof(R) == 4) {
+            const PairF w = ((const PairF *)S.coef)[at];
+            acc += (double)w.c * z[w.j];
+        } else {
+            acc += ((const double *)S.coef)[at] * z[S.nbr[at]];
+        }
+    }
+    return z[i] - acc / S.dii[i];
+}
+
+struct BicgInitX {
+    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        ROW;
+        if (i < P.nf) S.bx[i] = bicg_active(S, i) ? S.p[0][i] : 0.0;
+    }
+};
+
+// Wall slots of z (0: x, 1: p, 2: s) by the linear part of eq. p-shepard;
+// with hydro, also the hydrostatic part h_w.  it: the iteration (0 at set-up).
+template <int KER, int D, typename R>
+struct BicgWall {
+    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which, int hydro,
+                               int it) {
+        if (it > 0 && bicg_stopped(S, it)) return;
+        ROW;
+        if (i >= P.nw) return;
+        double *z = which == 0 ? S.bx : (which == 1 ? S.bp : S.bs);
+        const int64_t iw = P.nf + i;
+        Kern<KER, D, R> K(P.h);
+        const Pos xs = mkpos(S.xs);
+        double xi[3] = {0, 0, 0};
+        for (int k = 0; k < D; ++k) xi[k] = xs.c[k][iw];
+        double sz = 0.0, sw = 0.0, sr[3] = {0, 0, 0};
+        const int c = S.wcnt[i];
+        for (int k = 0; k < c; ++k) {
+            const int64_t f = S.wnbr[(int64_t)k * P.nw + i];
+            R d[3], r2;
+            pair_diff<D, R>(P.grid, xi, xs, f, d, r2);
+            const double W = (double)K.w(sqrt(r2));
+            sz += z[f] * W;
+            sw += W;
+            if (hydro) {
+                const double rw = S.rho[f] * W;
+                for (int a = 0; a < D; ++a) sr[a] += rw * (double)d[a];
+            }
+        }
+        z[iw] = sw > 0.0 ? sz / sw : 0.0;
+        if (hydro) {
+            double gs = 0.0;
+            for (int a = 0; a < D; ++a) gs += P.g[a] * sr[a];
+            S.bh[iw] = sw > 0.0 ? gs / sw : 0.0;
+        }
+    }
+};
+
+// f, r = f - M x, r^ = r, p = v = 0; partial (r^, r).
+template <typename R>
+struct BicgInitR {
+    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int) {
+        ROW;
+        const int64_t nf = P.nf;
+        double rr = 0.0;
+        if (i < nf) {
+            double f = 0.0, r = 0.0;
+            if (bicg_active(S, i)) {
+                double acc = 0.0;
+                const int c = S.cnt[i];
+                for (int k = 1; k < c; ++k) {
+                    const int64_t at = (int64_t)k * nf + i;
+                    int64_t j;
+                    double cij;
+                    if constexpr (sizeof(R) == 4) {
+                        const PairF w = ((const PairF *)S.coef)[at];
+                        j = w.j;
+                        cij = (double)w.c;
+                    } else {
+                        j = S.nbr[at];
+                        cij = ((const double *)S.coef)[at];
+                    }
+                    if (j >= nf) acc += cij * S.bh[j];
+                }
+                f = (S.rhs[i] + acc) / S.dii[i];
+                r = f - bicg_apply<R>(P, S, i, S.bx);
+            }
+            S.bf[i] = f;
+            S.br[i] = r;
+            S.brh[i] = r;
+            S.bp[i] = 0.0;
+            S.bv[i] = 0.0;
+            rr = r * r;
+        }
+        partial_store(rr, S.bpart + BP_RHO * nblk, blk);
+    }
+};
+
+// Iteration it: workgroup 0 first decides whether the solve stopped after
+// it-1 iterations (eq. convergence on omega * sum|r| and sum|x|); then
+// beta and the new direction p.
+struct BicgDir {
+    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
+        // workgroup 0 of this launch may write stopped_at = it - 1, so only
+        // a stop recorded by an earlier launch (below it - 1) is tested here
+        if (bicg_stopped(S, it - 1)) return;
+        Control *ctl = S.ctl;
+        const double rho = partial_total(S.bpart + BP_RHO * nblk, nblk);
+        if (blk == 0 && it >= 2) {
+            __shared__ int stop_sh;
+            const double num = P.omega * partial_total(S.bpart + BP_ABSR * nblk, nblk);
+            const double den = partial_total(S.bpart + BP_ABSX * nblk, nblk);
+            if (threadIdx.x == 0) {
+                const int k = it - 1;
+                double lam = __longlong_as_double((long long)ctl->lambda_bits);
+                if (P.conv_norm == SISPH_CONV_MEAN) lam *= (double)P.nf;
+                const double scale = lam > den ? lam : den;
+                const double ratio = scale > 0.0 ? num / scale : (num > 0.0 ? INFINITY : 0.0);
+                const bool bad = !isfinite(num) || !isfinite(den);
+                bool stop = P.forced_iters > 0 ? k >= P.forced_iters : (ratio < P.tol || k >= P.max_iter);
+                stop = stop || bad || ctl->bicg_brk;
+                ctl->num = num;
+                ctl->den = den;
+                ctl->ratio = ratio;
+                if (bad) ctl->nonfinite = 1;
+                if (stop) {
+                    ctl->iter = k;
+                    ctl->done = 1;
+                    ctl->stopped_at = k;
+                }
+                stop_sh = stop ? 1 : 0;
+            }
+            __syncthreads();
+            if (stop_sh) return;
+        }
+        const int q = (it - 1) & 1;
+        const double beta = (rho / ctl->bicg_rho[q]) * (ctl->bicg_alpha[q] / ctl->bicg_omega[q]);
+        const double om = ctl->bicg_omega[q];
+        ROW;
+        if (i < P.nf) S.bp[i] = S.br[i] + beta * (S.bp[i] - om * S.bv[i]);
+        if (blk == 0 && threadIdx.x == 0) ctl->bicg_rho[it & 1] = rho;
+    }
+};
+
+// v = M p; partial (r^, v).
+template <typename R>
+struct BicgMatV {
+    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
+        if (bicg_stopped(S, it)) return;
+        ROW;
+        double a = 0.0;
+        if (i < P.nf) {
+            const double v = bicg_apply<R>(P, S, i, S.bp);
+            S.bv[i] = v;
+            a = S.brh[i] * v;
+        }
+        partial_store(a, S.bpart + BP_RV * nblk, blk);
+    }
+};
+
+// alpha = rho / (r^, v); s = r - alpha v.
+struct BicgStep {
+    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
+        if (bicg_stopped(S, it)) return;
+        Control *ctl = S.ctl;
+        const double rv = partial_total(S.bpart + BP_RV * nblk, nblk);
+        const bool brk = rv == 0.0;
+        const double alpha = brk ? 0.0 : ctl->bicg_rho[it & 1] / rv;
+        ROW;
+        if (i < P.nf) S.bs[i] = S.br[i] - alpha * S.bv[i];
+        if (blk == 0 && threadIdx.x == 0) {
+            ctl->bicg_alpha[it & 1] = alpha;
+            if (brk) ctl->bicg_brk = 1;
+        }
+    }
+};
+
+// t = M s; partials (t, s), (t, t).
+template <typename R>
+struct BicgMatT {
+    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
+        if (bicg_stopped(S, it)) return;
+        ROW;
+        double ts = 0.0, tt = 0.0;
+        if (i < P.nf) {
+            const double t = bicg_apply<R>(P, S, i, S.bs);
+            S.bt[i] = t;
+            ts = t * S.bs[i];
+            tt = t * t;
+        }
+        partial_store(ts, S.bpart + BP_TS * nblk, blk);
+        partial_store(tt, S.bpart + BP_TT * nblk, blk);
+    }
+};
+
+// omega = (t, s) / (t, t); x += alpha p + omega s; r = s - omega t;
+// partials (r^, r), sum|r|, sum|x|.
+struct BicgUpdate {
+    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
+        if (bicg_stopped(S, it)) return;
+        Control *ctl = S.ctl;
+        const double ts = partial_total(S.bpart + BP_TS * nblk, nblk);
+        const double tt = partial_total(S.bpart + BP_TT * nblk, nblk);
+        const double om = tt == 0.0 ? 0.0 : ts / tt;
+        const double alpha = ctl->bicg_alpha[it & 1];
+        ROW;
+        double rr = 0.0, ar = 0.0, ax = 0.0;
+        if (i < P.nf) {
+            const double x = S.bx[i] + alpha * S.bp[i] + om * S.bs[i];
+            const double r = S.bs[i] - om * S.bt[i];
+            S.bx[i] = x;
+            S.br[i] = r;
+            rr = S.brh[i] * r;
+            ar = fabs(r);
+            ax = fabs(x);
+        }
+        partial_store(rr, S.bpart + BP_RHO * nblk, blk);
+        partial_store(ar, S.bpart + BP_ABSR * nblk, blk);
+        partial_store(ax, S.bpart + BP_ABSX * nblk, blk);
+        if (blk == 0 && threadIdx.x == 0) {
+            ctl->bicg_omega[it & 1] = om;
+            if (tt == 0.0) ctl->bicg_brk = 1;
+            ctl->iter = it;
+        }
+    }
+};
+
+struct BicgSettle {
+    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        ROW;
+        if (i < P.nf) S.p[0][i] = S.bx[i];
+    }
+};
+
 // --------------------------------------------------------------- utilities
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1425,9 +1733,31 @@ void sweep_only(const Target &T, int L) {
 }
 
 void ppe_iteration(const Target &T, int L) {
+    if (T.solver == SISPH_BICGSTAB) {
+        const int it = L + 1;
+        launch<BicgDir, K_FLUID>(T, it);
+        SISPH_DISPATCH_KDR(T, (launch<BicgWall<KER, D, R>, K_WALL>(T, 1, 0, it)));
+        if (T.precision == SISPH_MIXED) launch<BicgMatV<float>, K_FLUID>(T, it);
+        else launch<BicgMatV<double>, K_FLUID>(T, it);
+        launch<BicgStep, K_FLUID>(T, it);
+        SISPH_DISPATCH_KDR(T, (launch<BicgWall<KER, D, R>, K_WALL>(T, 2, 0, it)));
+        if (T.precision == SISPH_MIXED) launch<BicgMatT<float>, K_FLUID>(T, it);
+        else launch<BicgMatT<double>, K_FLUID>(T, it);
+        launch<BicgUpdate, K_FLUID>(T, it);
+        return;
+    }
     SISPH_DISPATCH_KDR(T, (launch<WallPressure<KER, D, R>, K_WALL>(T, L, 0)));
     sweep_only(T, L);
 }
+
+void bicg_begin(const Target &T) {
+    launch<BicgInitX, K_FLUID>(T);
+    SISPH_DISPATCH_KDR(T, (launch<BicgWall<KER, D, R>, K_WALL>(T, 0, 1, 0)));
+    if (T.precision == SISPH_MIXED) launch<BicgInitR<float>, K_FLUID>(T);
+    else launch<BicgInitR<double>, K_FLUID>(T);
+}
+
+void bicg_settle(const Target &T) { launch<BicgSettle, K_FLUID>(T); }
 
 void settle_pressure(const Target &T) { launch<SettlePressure, K_TOT>(T); }
 

@@ -39,6 +39,7 @@ class CaseDesc(C.Structure):
         "dim", "kernel", "precision", "pgrad", "gtvf", "free_surface",
         "p_ref_mode", "conv_norm", "min_iter", "max_iter", "gtvf_K", "forced_iters")] + \
         [("periodic", C.c_int32 * 3), ("nbr_cap", C.c_int32), ("ustar_wall", C.c_int32), ("dt_mode", C.c_int32),
+         ("solver", C.c_int32), ("reserved1", C.c_int32),
          ("n_fluid", C.c_int64), ("n_wall", C.c_int64)] + \
         [(n, C.c_double) for n in (
             "h", "dx", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio",
@@ -150,6 +151,7 @@ def describe(case: "_cases.Case") -> CaseDesc:
     d.nbr_cap = int(case.meta.get("nbr_cap", 0))
     d.ustar_wall = _cases.USTAR[case.ustar_wall]
     d.dt_mode = _cases.DT_MODE[case.dt_mode]
+    d.solver = _cases.SOLVER[case.solver]
     d.n_fluid = case.n_fluid
     d.n_wall = case.n_wall
     for k in ("h", "dx", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio", "omega", "tol", "p_ref"):

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_function():
 
 def test_header_struct_layout_matches_binding():
     # sisph_case_desc: 16 int32 + 2 int64 + 12 double + 9 double
-    assert C.sizeof(sisph.CaseDesc) == 18 * 4 + 2 * 8 + 21 * 8
+    assert C.sizeof(sisph.CaseDesc) == 20 * 4 + 2 * 8 + 21 * 8
     assert C.sizeof(sisph.PPEStats) == 4 * 4 + 4 * 8
 
 
@@ -54,7 +54,7 @@ def test_workspace_bytes_valid_and_monotone():
 
 @pytest.mark.parametrize("field,value", [
     ("dim", 4), ("kernel", 9), ("precision", 7), ("n_fluid", 0), ("h", 0.0), ("dt", -1.0),
-    ("omega", 1.5), ("min_iter", 0), ("max_iter", 1), ("ustar_wall", 2), ("dt_mode", 3)])
+    ("omega", 1.5), ("min_iter", 0), ("max_iter", 1), ("ustar_wall", 2), ("dt_mode", 3), ("solver", 2)])
 def test_invalid_descriptor_gives_zero_workspace(field, value):
     c = cases.taylor_green(10).replace(min_iter=2)
     d = sisph.describe(c)
@@ -97,3 +97,15 @@ def test_null_context_calls_are_invalid():
         assert getattr(L, f)(None) == sisph.E_INVAL
     assert L.sisph_ppe_solve(None, None) == sisph.E_INVAL
     assert L.sisph_step(None, 1, None) == sisph.E_INVAL
+
+
+def test_bicgstab_needs_a_free_surface():
+    """Without free-surface rows the PPE fixes p only up to a constant:
+    BiCGStab cases are refused there, accepted (with extra vectors) else."""
+    tg = cases.taylor_green(10).replace(solver="bicgstab")
+    assert sisph.lib().sisph_workspace_bytes(C.byref(sisph.describe(tg))) == 0
+    db = cases.dam_break_2d(dx=0.1)
+    jac = sisph.workspace_bytes(db)
+    bic = sisph.workspace_bytes(db.replace(solver="bicgstab"))
+    assert bic > jac + 9 * 8 * db.n
+

@@ -216,6 +216,68 @@ def test_adaptive_dt_steps_fp64(name):
     ctx.close()
 
 
+def _fs_periodic(n=16, seed=4):
+    """Periodic jittered set with a free-surface flag on the sparsest 10 %
+    (Dirichlet rows that make the PPE non-singular)."""
+    c = cases.taylor_green(n, kernel="wendland", hdx=1.3, jitter=0.2, seed=seed)
+    rho = oracle.density(c)
+    thr = np.quantile(rho, 0.1)
+    return c.replace(free_surface=True, fs_ratio=float(thr / c.rho0) + 1e-12, gtvf="off")
+
+
+@pytest.mark.parametrize("name,tol", [("fs_periodic", 1e-10), ("db2d", 1e-6), ("db2d", 1e-3)])
+def test_bicgstab_steps_fp64(name, tol):
+    """BiCGStab on the device (section 3.1's alternative solver): the
+    converged pressure, the iteration count and the state after a few steps
+    follow the oracle.  Both sides run the same recurrences; only summation
+    order differs."""
+    sisph = _gpu()
+    case = _fs_periodic() if name == "fs_periodic" else cases.dam_break_2d(dx=0.05, precision="fp64")
+    case = case.replace(solver="bicgstab", tol=tol, max_iter=2000)
+    say("case bicgstab", name, tol)
+    ref = oracle.Sim(case)
+    ctx = sisph.Context(case)
+    for k in range(4):
+        o = ref.step()
+        g = ctx.step(1)[0]
+        say(f"  step {k}: iters gpu {g['iters']} oracle {o['iters']}, ratio {g['ratio']:.3e} / {o['ratio']:.3e}")
+        assert g["iters"] == o["iters"], f"step {k}"
+        assert g["converged"] and o["converged"]
+    s = ctx.read_state()
+    for key, ours, theirs in (("p", s["p"], ref.p), ("u", s["u"], ref.u), ("x", s["x"], ref.x)):
+        e = rel(ours, theirs)
+        say(f"  {key} rel L2 {e:.3e}")
+        assert e < FP64_TOL, key
+    ctx.close()
+
+
+def test_bicgstab_mixed_single_step():
+    """Mixed precision: FP32 cached coefficients, FP64 vectors and sums."""
+    sisph = _gpu()
+    case = cases.dam_break_2d(dx=0.05, precision="mixed").replace(solver="bicgstab", tol=1e-6, max_iter=2000)
+    ref = oracle.Sim(case.replace(precision="fp64"))
+    o = ref.step()
+    ctx = sisph.Context(case)
+    g = ctx.step(1)[0]
+    s = ctx.read_state()
+    e = rel(s["p"], ref.p)
+    say(f"  mixed bicgstab iters {g['iters']} / {o['iters']}, p rel L2 {e:.3e}, u {rel(s['u'], ref.u):.3e}")
+    assert g["converged"]
+    assert abs(g["iters"] - o["iters"]) <= 3
+    assert e < 1e-3
+    ctx.close()
+
+
+def test_bicgstab_context_cannot_join_a_batch():
+    sisph = _gpu()
+    ctx = sisph.Context(cases.dam_break_2d(dx=0.1, precision="mixed").replace(solver="bicgstab"))
+    b = sisph.Batch(4)
+    with pytest.raises(sisph.SisphError):
+        b.attach(ctx)
+    b.close()
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", ["tg50_quintic", "db2d_dx0.05"])
 def test_mixed_precision_single_step(name):
     """Mixed mode against the FP64 oracle with the oracle run on the GPU's
