@@ -225,12 +225,20 @@ def _fs_periodic(n=16, seed=4):
     return c.replace(free_surface=True, fs_ratio=float(thr / c.rho0) + 1e-12, gtvf="off")
 
 
-@pytest.mark.parametrize("name,tol", [("fs_periodic", 1e-10), ("db2d", 1e-6), ("db2d", 1e-3)])
-def test_bicgstab_steps_fp64(name, tol):
+# (case, tol, exact): with exact, the iteration counts must match and the
+# state agree to FP64_TOL.  At tol 1e-6 the dam break's BiCGStab count is
+# not determined by the arithmetic alone: perturbing p^n by 1e-15 in the
+# oracle itself moves the first solve from 41 to 44-45 iterations and the
+# pressure after four steps by up to 4e-4 (relative L2; u 3e-5, x 1.3e-9).
+# There only convergence and the state within five times that spread are
+# compared.  At 1e-3 and 1e-4 the counts do not move under such
+# perturbations.
+@pytest.mark.parametrize("name,tol,exact", [("fs_periodic", 1e-10, True), ("db2d", 1e-3, True),
+                                            ("db2d", 1e-4, True), ("db2d", 1e-6, False)])
+def test_bicgstab_steps_fp64(name, tol, exact):
     """BiCGStab on the device (section 3.1's alternative solver): the
-    converged pressure, the iteration count and the state after a few steps
-    follow the oracle.  Both sides run the same recurrences; only summation
-    order differs."""
+    iteration count and the state after a few steps follow the oracle.  Both
+    sides run the same recurrences; only summation order differs."""
     sisph = _gpu()
     case = _fs_periodic() if name == "fs_periodic" else cases.dam_break_2d(dx=0.05, precision="fp64")
     case = case.replace(solver="bicgstab", tol=tol, max_iter=2000)
@@ -241,13 +249,15 @@ def test_bicgstab_steps_fp64(name, tol):
         o = ref.step()
         g = ctx.step(1)[0]
         say(f"  step {k}: iters gpu {g['iters']} oracle {o['iters']}, ratio {g['ratio']:.3e} / {o['ratio']:.3e}")
-        assert g["iters"] == o["iters"], f"step {k}"
+        if exact:
+            assert g["iters"] == o["iters"], f"step {k}"
         assert g["converged"] and o["converged"]
     s = ctx.read_state()
+    bounds = {"p": FP64_TOL, "u": FP64_TOL, "x": FP64_TOL} if exact else {"p": 2e-3, "u": 1.5e-4, "x": 1e-8}
     for key, ours, theirs in (("p", s["p"], ref.p), ("u", s["u"], ref.u), ("x", s["x"], ref.x)):
         e = rel(ours, theirs)
         say(f"  {key} rel L2 {e:.3e}")
-        assert e < FP64_TOL, key
+        assert e < bounds[key], key
     ctx.close()
 
 
