@@ -1588,10 +1588,16 @@ struct BicgUpdate {
     }
 };
 
+// x into p[0] and its FP32 copy (the final wall extrapolation of the mixed
+// mode reads the copy).
 struct BicgSettle {
     static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
-        if (i < P.nf) S.p[0][i] = S.bx[i];
+        if (i < P.nf) {
+            const double x = S.bx[i];
+            S.p[0][i] = x;
+            S.p32[i] = (float)x;
+        }
     }
 };
 
