@@ -260,7 +260,7 @@ void launch(const Target &T, A... a) {
 // ================================================================== bodies
 // ----------------------------------------------------------------- control
 struct ResetControl {
-    static __device__ void run(const Params &P, const State &S, int64_t, int64_t, int, int what) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t, int64_t, int, int what) {
         if (threadIdx.x != 0) return;
         Control *c = S.ctl;
         if (what & RESET_DT) {
@@ -301,7 +301,7 @@ struct ResetControl {
 };
 
 struct GatherControl {
-    static __device__ void run(const Params &, const State &S, int64_t, int64_t, int c, Control *out) {
+    static __device__ __forceinline__ void run(const Params &, const State &S, int64_t, int64_t, int c, Control *out) {
         if (threadIdx.x == 0) out[c] = *S.ctl;
     }
 };
@@ -312,7 +312,7 @@ struct GatherControl {
 // original index, or its current slot), which makes the result independent
 // of the atomic ranks.
 struct ZeroCount {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         if (i < P.grid.ncell) S.count[i] = 0u;
     }
@@ -321,7 +321,7 @@ struct ZeroCount {
 template <int D>
 struct BinKeys {
     // walls: rows [nf, nf+nw) at r^n; fluid: rows [0, nf) at r^n or r*
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which, int walls) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which, int walls) {
         ROW;
         const int64_t n = walls ? P.nw : P.nf, base = walls ? P.nf : 0;
         if (i >= n) return;
@@ -336,7 +336,7 @@ struct BinKeys {
 
 // Exclusive scan of one tile of counts per workgroup; writes the tile total.
 struct ScanTiles {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int walls) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int walls) {
         __shared__ uint32_t sh[kBlock];
         uint32_t *out = walls ? S.wstart : S.fstart;
         const int64_t n = P.grid.ncell;
@@ -366,7 +366,7 @@ struct ScanTiles {
 // Exclusive scan of the tile totals by one workgroup; writes the grand
 // total to start[ncell].
 struct ScanSums {
-    static __device__ void run(const Params &P, const State &S, int64_t, int64_t, int, int walls) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t, int64_t, int, int walls) {
         __shared__ uint32_t sh[kBlock];
         __shared__ uint32_t carry;
         uint32_t *out = walls ? S.wstart : S.fstart;
@@ -394,7 +394,7 @@ struct ScanSums {
 };
 
 struct ScanAdd {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int walls) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int walls) {
         ROW;
         uint32_t *out = walls ? S.wstart : S.fstart;
         if (i < P.grid.ncell) out[i] += S.scan_tmp[i / kScanTile];
@@ -402,7 +402,7 @@ struct ScanAdd {
 };
 
 struct Scatter {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int walls) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int walls) {
         ROW;
         const uint32_t *start = walls ? S.wstart : S.fstart;
         if (i < (walls ? P.nw : P.nf)) S.perm[start[S.key[i]] + S.rank[i]] = (int32_t)i;
@@ -411,7 +411,7 @@ struct Scatter {
 
 // sortkey: 0 = slot index, 1 = fluid original index, 2 = wall original index
 struct CellSort {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int walls,
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int walls,
                                int sortkey) {
         ROW;
         if (i >= P.grid.ncell) return;
@@ -439,7 +439,7 @@ struct CellSort {
 // into the new cell order: gather into scratch, then copy back.
 template <int D>
 struct ReorderFluid {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int phase) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int phase) {
         ROW;
         const int64_t n = P.nf;
         if (i >= n) return;
@@ -464,7 +464,7 @@ struct ReorderFluid {
 
 template <int D>
 struct ReorderWalls {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int phase) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int phase) {
         ROW;
         const int64_t n = P.nw, nf = P.nf;
         if (i >= n) return;
@@ -492,7 +492,7 @@ struct ReorderWalls {
 // slots map to particles through perm (the data stay in r^n order).
 template <int D>
 struct BuildFluid {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which) {
         ROW;
         if (i >= P.nf) return;
         const Grid &g = P.grid;
@@ -540,7 +540,7 @@ struct BuildFluid {
 // Wall rows: fluid particles only, no self.
 template <int D>
 struct BuildWall {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which) {
         ROW;
         const int64_t w = i;
         if (w >= P.nw) return;
@@ -587,7 +587,7 @@ struct BuildWall {
 // cancelling and is set to zero).  Once per case, from the wall cells.
 template <int KER, int D>
 struct WallNormals {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int pass) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int pass) {
         ROW;
         const int64_t w = i;
         if (w >= P.nw) return;
@@ -640,7 +640,7 @@ struct WallNormals {
 // rho_i / rho0 < fs_ratio when free_surface is on (section 3).
 template <int KER, int D, typename R>
 struct Density {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         if (i >= P.nf) return;
         Kern<KER, D, R> K(P.h);
@@ -669,7 +669,7 @@ struct Density {
 // removed.
 template <int KER, int D, typename R>
 struct WallVelocity {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which) {
         const int slip = which == POS_XS && !P.ustar_noslip;
         ROW;
         const int64_t w = i;
@@ -711,7 +711,7 @@ struct WallVelocity {
 // u* = u^n + dt f (eq. int:vint).
 template <int KER, int D, typename R>
 struct Predictor {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         if (i >= P.nf) return;
         Kern<KER, D, R> K(P.h);
@@ -807,7 +807,7 @@ struct CoefSlot<double> {
 // atomic per wavefront).
 template <int KER, int D, typename R>
 struct RhsCoef {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         const int64_t nf = P.nf;
         typename CoefSlot<R>::T *coef = (typename CoefSlot<R>::T *)S.coef;
@@ -849,7 +849,7 @@ struct RhsCoef {
 };
 
 struct CopyP32 {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         if (i < P.ntot) S.p32[i] = (float)S.p[0][i];
     }
@@ -872,12 +872,12 @@ struct CopyP32 {
 //
 // First batch: slots 1..FIRST loaded without waiting for the row's count
 // (every slot below cap is inside the list storage; slots past the count
-// hold stale words and are discarded by the select), so the row loads,
-// these loads and the partial-sum loads form one round trip.  Longer rows
+// hold stale words and are discarded by the select), so the row loads and
+// these loads form one round trip.  Longer rows
 // continue in batches of kSweepBatch.  The sum runs in slot order whatever
 // FIRST is, so FIRST (chosen by the autotuner among kSweepFirsts) and the
 // workgroup mapping change the speed only, never the result.
-constexpr int kSweepFirsts[3] = {16, 24, 32};
+constexpr int kSweepFirsts[3] = {16, 20, 24};
 constexpr int kSweepBatch = 8;
 constexpr int kPartialRegs = 8;
 
@@ -932,7 +932,7 @@ __device__ __forceinline__ void load_partials(const double *partial, int64_t nbl
     }
 }
 
-__device__ bool stopped_after(const Params &P, const double *partial, int64_t nblk, int L, const PartialLoad &pl,
+__device__ __forceinline__ bool stopped_after(const Params &P, const double *partial, int64_t nblk, int L, const PartialLoad &pl,
                               double lam, bool first, Control *ctl) {
     __shared__ double sh[2][kBlock / 64];
     __shared__ int stop_sh;
@@ -991,7 +991,7 @@ __device__ bool stopped_after(const Params &P, const double *partial, int64_t nb
 
 template <typename R, int FIRST, bool PRECHECK>
 struct Sweep {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int L) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int L) {
         Control *ctl = S.ctl;
         // PRECHECK: a finished solve is detected before any other load (one
         // extra round trip per sweep, but a launch beyond the stop costs
@@ -1008,10 +1008,14 @@ struct Sweep {
         // sweeps the result is iterate L, in the other buffer, and launch
         // L+1 returns at once.  (Every workgroup deciding costs each one a
         // read of all the partial sums: 17 % slower at 160k particles.)
-        const bool decides = L > 0 && blk == 0;
-        const double lam = __longlong_as_double((long long)ctl->lambda_bits);   // fixed during the solve
-        PartialLoad pl;
-        if (decides) load_partials(S.partial, nblk, L, pl);
+        // (the deciding workgroup reduces before its own row loads, so the
+        // partial sums do not hold registers across the gathers)
+        if (L > 0 && blk == 0) {
+            const double lam = __longlong_as_double((long long)ctl->lambda_bits);   // fixed during the solve
+            PartialLoad pl;
+            load_partials(S.partial, nblk, L, pl);
+            if (stopped_after(P, S.partial, nblk, L, pl, lam, true, ctl)) return;
+        }
         const int64_t nf = P.nf;
         const double *pc = S.p[L & 1];
         double *pn = S.p[(L + 1) & 1];
@@ -1046,8 +1050,6 @@ struct Sweep {
             }
             if (D != 0.0 && !f) v = P.omega * (r + (double)s) / D + (1.0 - P.omega) * pold;
         }
-        // the decision for L sweeps gates the writes of the deciding workgroups
-        if (decides && stopped_after(P, S.partial, nblk, L, pl, lam, blk == 0, ctl)) return;
         double a = 0.0, b = 0.0;
         if (live) {
             pn[i] = v;
@@ -1072,7 +1074,7 @@ struct Sweep {
 // the wall slots of p[0] after the final pressure has been settled there.
 template <int KER, int D, typename R>
 struct WallPressure {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int L, int final) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int L, int final) {
         if (!final && __hip_atomic_load(&S.ctl->stopped_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < L)
             return;
         ROW;
@@ -1113,14 +1115,14 @@ struct WallPressure {
 
 // After the solve: the final iterate into p[0] (it is in p[iters & 1]).
 struct SettlePressure {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         if (i < P.ntot && (S.ctl->iter & 1)) S.p[0][i] = S.p[1][i];
     }
 };
 
 struct PMax {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         unsigned long long k = i < P.nf ? order_key(S.p[0][i]) : 0ull;
         k = wave_max_u64(k);
@@ -1131,7 +1133,7 @@ struct PMax {
 // p_ref for internal flows: twice the largest pressure after the first
 // solve, then held (section 2.1).
 struct PrefFinish {
-    static __device__ void run(const Params &, const State &S, int64_t, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &, const State &S, int64_t, int64_t, int) {
         Control *c = S.ctl;
         if (threadIdx.x == 0 && !c->p_ref_set) {
             c->p_ref = 2.0 * order_val(c->pmax_key);
@@ -1145,7 +1147,7 @@ struct PrefFinish {
 // u^{n+1} = u* + dt f_p (eq. int:vnp1).
 template <int KER, int D, typename R>
 struct Correct {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         if (i >= P.nf) return;
         Kern<KER, D, R> K(P.h);
@@ -1188,7 +1190,7 @@ struct Correct {
 // per wavefront give an order-independent result.
 template <int D>
 struct StepMaxima {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         if (!P.adaptive_dt) return;
         ROW;
         unsigned long long ub = 0ull, fb = 0ull;
@@ -1215,7 +1217,7 @@ struct StepMaxima {
 // dt^{n+1} = min(dt, 0.25 h / max|u^n|, 0.25 sqrt(h / max|f^n|)), the
 // case's dt being the bound; a zero maximum imposes no limit.
 struct NextDt {
-    static __device__ void run(const Params &P, const State &S, int64_t, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t, int64_t, int) {
         if (threadIdx.x != 0 || !P.adaptive_dt) return;
         Control *c = S.ctl;
         const double u2 = __longlong_as_double((long long)c->umax2_bits);
@@ -1235,7 +1237,7 @@ struct NextDt {
 // (eqs. int:gtvf:pos, int:gtvf:vel:tmp), no wrap inside the sub-steps.
 template <int KER, int D, typename R>
 struct Gtvf {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int k) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int k) {
         ROW;
         if (i >= P.nf || k >= P.gtvf_K) return;   // gtvf_K = 0 when GTVF is off
         const bool ext = P.gtvf == SISPH_GTVF_EXTERNAL;
@@ -1277,7 +1279,7 @@ struct Gtvf {
 // r^K is the last sub-step's buffer, or r* itself without GTVF.
 template <int D>
 struct Advance {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         if (i >= P.nf) return;
         const int kfinal = P.gtvf_K - 1;
@@ -1320,7 +1322,7 @@ enum { BP_RHO = 0, BP_ABSR, BP_ABSX, BP_RV, BP_TS, BP_TT, BP_ROWS };
 __device__ __forceinline__ bool bicg_active(const State &S, int64_t i) { return S.dii[i] != 0.0 && !S.fs[i]; }
 
 // Sum of one partial-sum row, in a fixed order, returned to every thread.
-__device__ double partial_total(const double *row, int64_t nblk) {
+__device__ __forceinline__ double partial_total(const double *row, int64_t nblk) {
     __shared__ double sh[kBlock / 64];
     __shared__ double tot;
     double a = 0.0;
@@ -1338,7 +1340,7 @@ __device__ double partial_total(const double *row, int64_t nblk) {
 }
 
 // Workgroup sum of v written to row[blk] (every thread must call).
-__device__ void partial_store(double v, double *row, int64_t blk) {
+__device__ __forceinline__ void partial_store(double v, double *row, int64_t blk) {
     __shared__ double sh[kBlock / 64];
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
@@ -1375,7 +1377,7 @@ __device__ __forceinline__ double bicg_apply(const Params &P, const State &S, in
 }
 
 struct BicgInitX {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         if (i < P.nf) S.bx[i] = bicg_active(S, i) ? S.p[0][i] : 0.0;
     }
@@ -1385,7 +1387,7 @@ struct BicgInitX {
 // with hydro, also the hydrostatic part h_w.  it: the iteration (0 at set-up).
 template <int KER, int D, typename R>
 struct BicgWall {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which, int hydro,
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which, int hydro,
                                int it) {
         if (it > 0 && bicg_stopped(S, it)) return;
         ROW;
@@ -1422,7 +1424,7 @@ struct BicgWall {
 // f, r = f - M x, r^ = r, p = v = 0; partial (r^, r).
 template <typename R>
 struct BicgInitR {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int) {
         ROW;
         const int64_t nf = P.nf;
         double rr = 0.0;
@@ -1463,7 +1465,7 @@ struct BicgInitR {
 // it-1 iterations (eq. convergence on omega * sum|r| and sum|x|); then
 // beta and the new direction p.
 struct BicgDir {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
         // workgroup 0 of this launch may write stopped_at = it - 1, so only
         // a stop recorded by an earlier launch (below it - 1) is tested here
         if (bicg_stopped(S, it - 1)) return;
@@ -1508,7 +1510,7 @@ struct BicgDir {
 // v = M p; partial (r^, v).
 template <typename R>
 struct BicgMatV {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
         if (bicg_stopped(S, it)) return;
         ROW;
         double a = 0.0;
@@ -1523,7 +1525,7 @@ struct BicgMatV {
 
 // alpha = rho / (r^, v); s = r - alpha v.
 struct BicgStep {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
         if (bicg_stopped(S, it)) return;
         Control *ctl = S.ctl;
         const double rv = partial_total(S.bpart + BP_RV * nblk, nblk);
@@ -1541,7 +1543,7 @@ struct BicgStep {
 // t = M s; partials (t, s), (t, t).
 template <typename R>
 struct BicgMatT {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
         if (bicg_stopped(S, it)) return;
         ROW;
         double ts = 0.0, tt = 0.0;
@@ -1559,7 +1561,7 @@ struct BicgMatT {
 // omega = (t, s) / (t, t); x += alpha p + omega s; r = s - omega t;
 // partials (r^, r), sum|r|, sum|x|.
 struct BicgUpdate {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int it) {
         if (bicg_stopped(S, it)) return;
         Control *ctl = S.ctl;
         const double ts = partial_total(S.bpart + BP_TS * nblk, nblk);
@@ -1591,7 +1593,7 @@ struct BicgUpdate {
 // x into p[0] and its FP32 copy (the final wall extrapolation of the mixed
 // mode reads the copy).
 struct BicgSettle {
-    static __device__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         if (i < P.nf) {
             const double x = S.bx[i];
