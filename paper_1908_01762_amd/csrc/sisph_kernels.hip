@@ -1011,6 +1011,8 @@ struct Sweep {
         // (the deciding workgroup reduces before its own row loads, so the
         // partial sums do not hold registers across the gathers)
         if (L > 0 && blk == 0) {
+            // a solve that stopped earlier left stale partial sums: no decision
+            if (stopped < L) return;
             const double lam = __longlong_as_double((long long)ctl->lambda_bits);   // fixed during the solve
             PartialLoad pl;
             load_partials(S.partial, nblk, L, pl);
