@@ -163,6 +163,30 @@ def batched_vs_plain(n_cases: int, steps: int, seed: int) -> dict:
                         "mixed precision, tol 1e-4 (TG) / 1e-3 (dam break)" % seed}
 
 
+def copy_reference(sizes_mib=(32, 1024), reps: int = 20) -> list:
+    """Device-to-device copies (torch, i.e. the runtime's copy kernel) of the
+    given sizes timed with events: the bandwidth a plain streaming kernel
+    reaches, read + write counted."""
+    import torch
+    out = []
+    for mib in sizes_mib:
+        n = mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        out.append({"mib": mib, "us": round(us, 3), "GBps": round(2 * n * 4 / (us * 1e-6) / 1e9, 1)})
+        del src, dst
+    return out
+
+
 def solver_compare(dx: float, steps: int, tols=(1e-2, 1e-3, 1e-4)) -> dict:
     """Jacobi (the paper's scheme) against BiCGStab on the same cached
     operator at equal tolerance: 2D dam break (free surface, so the system is
@@ -310,6 +334,7 @@ def main():
     if not args.no_batch_compare:
         print("[bench] batched vs plain", file=sys.stderr, flush=True)
         line["batched_vs_plain"] = batched_vs_plain(args.batch_cases, args.batch_steps, seed=0)
+    line["copy_reference"] = copy_reference()
     if not args.no_solver_compare:
         print("[bench] Jacobi vs BiCGStab", file=sys.stderr, flush=True)
         line["solver_compare"] = solver_compare(args.compare_dx, args.batch_steps)

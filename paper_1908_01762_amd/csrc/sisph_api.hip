@@ -214,6 +214,8 @@ static void carve(const Params &P, Carver &c, State &S) {
     S.wcnt = c.take<int32_t>(nw);
     // mixed: (index, FP32 c_ij) 8-byte words; FP64: FP64 c_ij (indices from nbr)
     S.coef = c.take<char>((int64_t)8 * P.cap * nf);
+    S.wcoef = c.take<char>((int64_t)8 * P.cap * nw);
+    S.wh = c.take<double>(nw);
     S.partial = c.take<double>(4 * kind_blocks(P, K_FLUID));
     S.tmp = c.take<double>(16 * nmax);
     S.bx = S.br = S.brh = S.bp = S.bv = S.bs = S.bt = S.bf = S.bh = S.bpart = nullptr;
@@ -474,6 +476,7 @@ static void seq_predict(const Target &T) {
 static void seq_ppe_begin(const Target &T) {
     reset_control(T, RESET_PPE);
     rhs_coef(T);
+    wall_coef(T);
     if (T.solver == SISPH_BICGSTAB) bicg_begin(T);
     else if (T.precision == SISPH_MIXED) copy_p32(T);
 }

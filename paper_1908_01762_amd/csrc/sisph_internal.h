@@ -95,6 +95,8 @@ struct State {
     int32_t *nbr, *cnt;     // fluid rows: fluid + wall sources
     int32_t *wnbr, *wcnt;   // wall rows: fluid sources
     void *coef;             // cached PPE c_ij: (j, FP32 c) words (mixed) or FP64 [cap][nf]
+    void *wcoef;            // cached wall weights W_wf / sum W: (f, FP32) words or FP64 [cap][nw]
+    double *wh;             // wall hydrostatic term                 [nw]
     double *partial;        // per-workgroup partial sums of two sweeps [2][2][nblk]
     double *tmp;            // reorder scratch [16][max(nf, nw)]
     // BiCGStab (solver only): x, r, r^, p, v, s, t, scaled RHS f, wall
@@ -168,6 +170,8 @@ void density(const Target &T);
 void wall_velocity(const Target &T, int which);
 void predictor(const Target &T);
 void rhs_coef(const Target &T);
+// Wall extrapolation weights at r* for the solve (walls present).
+void wall_coef(const Target &T);
 void copy_p32(const Target &T);
 // Jacobi: wall pressure and sweep L.  BiCGStab: iteration L+1 (its first
 // kernel decides whether the solve stopped after L iterations).

@@ -1071,10 +1071,60 @@ struct Sweep {
 
 // eq. p-shepard: p_w = [sum_f p_f W_wf + (g - a_w) . sum_f rho_f r_wf W_wf]
 // / sum_f W_wf over fluid neighbours (static wall: a_w = 0); 0 without
-// neighbours; clamped at 0 on free-surface problems.  During the solve it
-// writes the wall slots of iterate L (which sweep L reads); with final set,
-// the wall slots of p[0] after the final pressure has been settled there.
+// neighbours; clamped at 0 on free-surface problems.  Positions and
+// densities are fixed during the solve, so once per step (at r*) WallCoef
+// caches, in list order, the normalised weights a_wf = W_wf / sum W (with
+// the fluid index in the mixed mode, FP32 weight) and the hydrostatic term
+// h_w = g . sum rho_f r_wf W_wf / sum W; each sweep then forms
+// p_w = sum_f a_wf p_f + h_w.
 template <int KER, int D, typename R>
+struct WallCoef {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        ROW;
+        const int64_t w = i;
+        if (w >= P.nw) return;
+        const int64_t iw = P.nf + w, nw = P.nw;
+        Kern<KER, D, R> K(P.h);
+        const Pos xs = mkpos(S.xs);
+        double xi[3] = {0, 0, 0};
+        for (int k = 0; k < D; ++k) xi[k] = xs.c[k][iw];
+        R sr[3] = {0, 0, 0}, sw = R(0);
+        const int c = S.wcnt[w];
+        for (int k = 0; k < c; ++k) {
+            const int64_t f = S.wnbr[(int64_t)k * nw + w];
+            R d[3], r2;
+            pair_diff<D, R>(P.grid, xi, xs, f, d, r2);
+            const R W = K.w(sqrt(r2));
+            const R rw = (R)S.rho[f] * W;
+            for (int a = 0; a < D; ++a) sr[a] += rw * d[a];
+            sw += W;
+        }
+        double h = 0.0;
+        const R inv = sw > R(0) ? R(1) / sw : R(0);
+        if (sw > R(0)) {
+            double gs = 0.0;
+            for (int a = 0; a < D; ++a) gs += P.g[a] * (double)sr[a];
+            h = gs / (double)sw;
+        }
+        S.wh[w] = h;
+        // second pass: the normalised weights (the kernel values again, in
+        // the same order, rather than holding them in registers)
+        for (int k = 0; k < c; ++k) {
+            const int64_t at = (int64_t)k * nw + w;
+            const int64_t f = S.wnbr[at];
+            R d[3], r2;
+            pair_diff<D, R>(P.grid, xi, xs, f, d, r2);
+            const R a = K.w(sqrt(r2)) * inv;
+            if constexpr (sizeof(R) == 4) ((PairF *)S.wcoef)[at] = PairF{(int32_t)f, a};
+            else ((double *)S.wcoef)[at] = a;
+        }
+    }
+};
+
+// During the solve it writes the wall slots of iterate L (which sweep L
+// reads); with final set, the wall slots of p[0] after the final pressure
+// has been settled there.
+template <typename R>
 struct WallPressure {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int L, int final) {
         if (!final && __hip_atomic_load(&S.ctl->stopped_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < L)
@@ -1085,30 +1135,19 @@ struct WallPressure {
         const int par = final ? 0 : (L & 1);
         double *pc = S.p[par];
         float *qc = S.p32 + par * P.ntot;
-        const int64_t iw = P.nf + w;
-        Kern<KER, D, R> K(P.h);
-        const Pos xs = mkpos(S.xs);
-        double xi[3] = {0, 0, 0};
-        for (int k = 0; k < D; ++k) xi[k] = xs.c[k][iw];
-        R sp = R(0), sr[3] = {0, 0, 0}, sw = R(0);
+        const int64_t iw = P.nf + w, nw = P.nw;
         const int c = S.wcnt[w];
+        R sp = R(0);
         for (int k = 0; k < c; ++k) {
-            const int64_t f = S.wnbr[(int64_t)k * P.nw + w];
-            R d[3], r2;
-            pair_diff<D, R>(P.grid, xi, xs, f, d, r2);
-            const R W = K.w(sqrt(r2));
-            const R pf = sizeof(R) == 4 ? (R)qc[f] : (R)pc[f];
-            sp += pf * W;
-            const R rw = (R)S.rho[f] * W;
-            for (int a = 0; a < D; ++a) sr[a] += rw * d[a];
-            sw += W;
+            const int64_t at = (int64_t)k * nw + w;
+            if constexpr (sizeof(R) == 4) {
+                const PairF e = ((const PairF *)S.wcoef)[at];
+                sp += e.c * qc[e.j];
+            } else {
+                sp += ((const double *)S.wcoef)[at] * pc[S.wnbr[at]];
+            }
         }
-        double pw = 0.0;
-        if (sw > R(0)) {
-            double gs = 0.0;
-            for (int a = 0; a < D; ++a) gs += P.g[a] * (double)sr[a];
-            pw = ((double)sp + gs) / (double)sw;
-        }
+        double pw = (double)sp + S.wh[w];
         if (P.free_surface && pw < 0.0) pw = 0.0;
         pc[iw] = pw;
         qc[iw] = (float)pw;
@@ -1385,41 +1424,31 @@ struct BicgInitX {
     }
 };
 
-// Wall slots of z (0: x, 1: p, 2: s) by the linear part of eq. p-shepard;
-// with hydro, also the hydrostatic part h_w.  it: the iteration (0 at set-up).
-template <int KER, int D, typename R>
+// Wall slots of z (0: x, 1: p, 2: s) by the linear part of eq. p-shepard
+// (the cached weights); with hydro, also the hydrostatic part h_w.
+// it: the iteration (0 at set-up).
+template <typename R>
 struct BicgWall {
-    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which, int hydro,
-                               int it) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which,
+                                               int hydro, int it) {
         if (it > 0 && bicg_stopped(S, it)) return;
         ROW;
         if (i >= P.nw) return;
         double *z = which == 0 ? S.bx : (which == 1 ? S.bp : S.bs);
-        const int64_t iw = P.nf + i;
-        Kern<KER, D, R> K(P.h);
-        const Pos xs = mkpos(S.xs);
-        double xi[3] = {0, 0, 0};
-        for (int k = 0; k < D; ++k) xi[k] = xs.c[k][iw];
-        double sz = 0.0, sw = 0.0, sr[3] = {0, 0, 0};
+        const int64_t iw = P.nf + i, nw = P.nw;
         const int c = S.wcnt[i];
+        double sz = 0.0;
         for (int k = 0; k < c; ++k) {
-            const int64_t f = S.wnbr[(int64_t)k * P.nw + i];
-            R d[3], r2;
-            pair_diff<D, R>(P.grid, xi, xs, f, d, r2);
-            const double W = (double)K.w(sqrt(r2));
-            sz += z[f] * W;
-            sw += W;
-            if (hydro) {
-                const double rw = S.rho[f] * W;
-                for (int a = 0; a < D; ++a) sr[a] += rw * (double)d[a];
+            const int64_t at = (int64_t)k * nw + i;
+            if constexpr (sizeof(R) == 4) {
+                const PairF e = ((const PairF *)S.wcoef)[at];
+                sz += (double)e.c * z[e.j];
+            } else {
+                sz += ((const double *)S.wcoef)[at] * z[S.wnbr[at]];
             }
         }
-        z[iw] = sw > 0.0 ? sz / sw : 0.0;
-        if (hydro) {
-            double gs = 0.0;
-            for (int a = 0; a < D; ++a) gs += P.g[a] * sr[a];
-            S.bh[iw] = sw > 0.0 ? gs / sw : 0.0;
-        }
+        z[iw] = sz;
+        if (hydro) S.bh[iw] = S.wh[i];
     }
 };
 
@@ -1746,23 +1775,27 @@ void ppe_iteration(const Target &T, int L) {
     if (T.solver == SISPH_BICGSTAB) {
         const int it = L + 1;
         launch<BicgDir, K_FLUID>(T, it);
-        SISPH_DISPATCH_KDR(T, (launch<BicgWall<KER, D, R>, K_WALL>(T, 1, 0, it)));
+        if (T.precision == SISPH_MIXED) launch<BicgWall<float>, K_WALL>(T, 1, 0, it);
+        else launch<BicgWall<double>, K_WALL>(T, 1, 0, it);
         if (T.precision == SISPH_MIXED) launch<BicgMatV<float>, K_FLUID>(T, it);
         else launch<BicgMatV<double>, K_FLUID>(T, it);
         launch<BicgStep, K_FLUID>(T, it);
-        SISPH_DISPATCH_KDR(T, (launch<BicgWall<KER, D, R>, K_WALL>(T, 2, 0, it)));
+        if (T.precision == SISPH_MIXED) launch<BicgWall<float>, K_WALL>(T, 2, 0, it);
+        else launch<BicgWall<double>, K_WALL>(T, 2, 0, it);
         if (T.precision == SISPH_MIXED) launch<BicgMatT<float>, K_FLUID>(T, it);
         else launch<BicgMatT<double>, K_FLUID>(T, it);
         launch<BicgUpdate, K_FLUID>(T, it);
         return;
     }
-    SISPH_DISPATCH_KDR(T, (launch<WallPressure<KER, D, R>, K_WALL>(T, L, 0)));
+    if (T.precision == SISPH_MIXED) launch<WallPressure<float>, K_WALL>(T, L, 0);
+    else launch<WallPressure<double>, K_WALL>(T, L, 0);
     sweep_only(T, L);
 }
 
 void bicg_begin(const Target &T) {
     launch<BicgInitX, K_FLUID>(T);
-    SISPH_DISPATCH_KDR(T, (launch<BicgWall<KER, D, R>, K_WALL>(T, 0, 1, 0)));
+    if (T.precision == SISPH_MIXED) launch<BicgWall<float>, K_WALL>(T, 0, 1, 0);
+    else launch<BicgWall<double>, K_WALL>(T, 0, 1, 0);
     if (T.precision == SISPH_MIXED) launch<BicgInitR<float>, K_FLUID>(T);
     else launch<BicgInitR<double>, K_FLUID>(T);
 }
@@ -1772,8 +1805,11 @@ void bicg_settle(const Target &T) { launch<BicgSettle, K_FLUID>(T); }
 void settle_pressure(const Target &T) { launch<SettlePressure, K_TOT>(T); }
 
 void wall_pressure_final(const Target &T) {
-    SISPH_DISPATCH_KDR(T, (launch<WallPressure<KER, D, R>, K_WALL>(T, 0, 1)));
+    if (T.precision == SISPH_MIXED) launch<WallPressure<float>, K_WALL>(T, 0, 1);
+    else launch<WallPressure<double>, K_WALL>(T, 0, 1);
 }
+
+void wall_coef(const Target &T) { SISPH_DISPATCH_KDR(T, (launch<WallCoef<KER, D, R>, K_WALL>(T))); }
 
 void pressure_max(const Target &T) {
     launch<PMax, K_FLUID>(T);
