@@ -488,52 +488,153 @@ struct ReorderWalls {
 // -------------------------------------------------------- neighbour lists
 // Fluid rows: self in slot 0, then every fluid and wall particle j != i of
 // the stencil cells with |r_ij|^2 < R^2 (exact FP64 predicate), in stencil
-// order (z, y, x) and, within a cell, in slot order.  At r* the fluid cell
-// slots map to particles through perm (the data stay in r^n order).
+// order (z, y, x) and, within a cell, fluid then walls, each in slot order.
+// At r* the fluid cell slots map to particles through perm (the data stay
+// in r^n order).
+//
+// The workgroup's rows (consecutive in cell order) share most stencil
+// cells, so for each stencil row (a, b) the workgroup first stages, in LDS,
+// the positions and indices of every fluid and wall particle in the cell-id
+// range spanned by its rows' cells of that stencil row (one coalesced pass
+// instead of one gather per row and candidate).  A cell outside the staged
+// range, or a range too large to stage (periodic wrap, clustering), is read
+// from global memory as before; the visiting order, hence the lists, are
+// the same either way.
+constexpr int kStageCap = 1024;
+
+template <int D>
+__device__ __forceinline__ void test_cell_global(const Params &P, const State &S, const Pos &x,
+                                                 const int32_t *items, int64_t i, const double xi[3],
+                                                 int64_t cell, int &c) {
+    const int64_t nf = P.nf;
+    for (int pass = 0; pass < 2; ++pass) {
+        const uint32_t *start = pass == 0 ? S.fstart : S.wstart;
+        const uint32_t t0 = start[cell], t1 = start[cell + 1];
+        for (uint32_t t = t0; t < t1; ++t) {
+            const int64_t j = pass == 0 ? (items ? (int64_t)items[t] : (int64_t)t) : nf + (int64_t)t;
+            if (j == i) continue;
+            double d[3] = {0, 0, 0};
+            for (int k = 0; k < D; ++k) d[k] = min_image(xi[k] - x.c[k][j], P.grid, k);
+            if (exact_r2<D>(d) < P.R2) {
+                if (c < P.cap) S.nbr[(int64_t)c * nf + i] = (int32_t)j;
+                ++c;
+            }
+        }
+    }
+}
+
 template <int D>
 struct BuildFluid {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which) {
+        __shared__ double sx[3][kStageCap];
+        __shared__ int32_t sj[kStageCap];
+        __shared__ long long red_lo[kBlock / 64], red_hi[kBlock / 64];
+        __shared__ long long seg[2];
+        __shared__ uint32_t rng[4];   // fluid [F0, F1), wall [W0, W1) candidate slots
         ROW;
-        if (i >= P.nf) return;
+        const bool live = i < P.nf;
         const Grid &g = P.grid;
         const int64_t nf = P.nf;
         const Pos x = mkpos(which == POS_XS ? S.xs : S.x);
         const int32_t *items = which == POS_XS ? S.perm : nullptr;
         double xi[3] = {0, 0, 0};
         int ci[3] = {0, 0, 0};
-        for (int k = 0; k < D; ++k) {
-            xi[k] = x.c[k][i];
-            ci[k] = cell_coord(xi[k], g, k);
-        }
         Stencil st;
-        make_stencil<D>(g, ci, st);
         int c = 1;
-        const int cap = P.cap;
-        S.nbr[i] = (int32_t)i;
-        for (int a = 0; a < st.n[2]; ++a)
-            for (int b = 0; b < st.n[1]; ++b)
-                for (int e = 0; e < st.n[0]; ++e) {
-                    const int64_t cell = stencil_cell(g, st, a, b, e);
-                    for (int pass = 0; pass < 2; ++pass) {
-                        const uint32_t *start = pass == 0 ? S.fstart : S.wstart;
-                        const uint32_t t0 = start[cell], t1 = start[cell + 1];
-                        for (uint32_t t = t0; t < t1; ++t) {
-                            const int64_t j = pass == 0 ? (items ? (int64_t)items[t] : (int64_t)t) : nf + (int64_t)t;
-                            if (j == i) continue;
-                            double d[3] = {0, 0, 0};
-                            for (int k = 0; k < D; ++k) d[k] = min_image(xi[k] - x.c[k][j], g, k);
-                            if (exact_r2<D>(d) < P.R2) {
-                                if (c < cap) S.nbr[(int64_t)c * nf + i] = (int32_t)j;
-                                ++c;
+        if (live) {
+            for (int k = 0; k < D; ++k) {
+                xi[k] = x.c[k][i];
+                ci[k] = cell_coord(xi[k], g, k);
+            }
+            make_stencil<D>(g, ci, st);
+            S.nbr[i] = (int32_t)i;
+        }
+        const int na = D == 3 ? 3 : 1;
+        for (int a = 0; a < na; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const bool row_ok = live && a < st.n[2] && b < st.n[1];
+                // the cell-id range of this stencil row over the workgroup
+                long long lo = LLONG_MAX, hi = -1;
+                if (row_ok)
+                    for (int e = 0; e < st.n[0]; ++e) {
+                        const long long cc = stencil_cell(g, st, a, b, e);
+                        lo = cc < lo ? cc : lo;
+                        hi = cc > hi ? cc : hi;
+                    }
+                for (int off = 32; off > 0; off >>= 1) {
+                    const long long ol = __shfl_xor(lo, off, 64), oh = __shfl_xor(hi, off, 64);
+                    lo = ol < lo ? ol : lo;
+                    hi = oh > hi ? oh : hi;
+                }
+                if ((threadIdx.x & 63) == 0) {
+                    red_lo[threadIdx.x >> 6] = lo;
+                    red_hi[threadIdx.x >> 6] = hi;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    long long l = LLONG_MAX, h = -1;
+                    for (int w = 0; w < kBlock / 64; ++w) {
+                        l = red_lo[w] < l ? red_lo[w] : l;
+                        h = red_hi[w] > h ? red_hi[w] : h;
+                    }
+                    uint32_t f0 = 0, f1 = 0, w0 = 0, w1 = 0;
+                    if (h >= 0) {
+                        f0 = S.fstart[l];
+                        f1 = S.fstart[h + 1];
+                        w0 = S.wstart[l];
+                        w1 = S.wstart[h + 1];
+                    }
+                    const bool fits = h >= 0 && (int64_t)(f1 - f0) + (int64_t)(w1 - w0) <= kStageCap;
+                    seg[0] = fits ? l : 1;   // empty range when nothing is staged
+                    seg[1] = fits ? h : 0;
+                    rng[0] = f0;
+                    rng[1] = fits ? f1 : f0;
+                    rng[2] = w0;
+                    rng[3] = fits ? w1 : w0;
+                }
+                __syncthreads();
+                const long long s_lo = seg[0], s_hi = seg[1];
+                const uint32_t F0 = rng[0], nF = rng[1] - rng[0], W0 = rng[2], nW = rng[3] - rng[2];
+                for (uint32_t t = threadIdx.x; t < nF + nW; t += kBlock) {
+                    const int64_t j = t < nF ? (items ? (int64_t)items[F0 + t] : (int64_t)(F0 + t))
+                                             : nf + (int64_t)(W0 + (t - nF));
+                    for (int k = 0; k < D; ++k) sx[k][t] = x.c[k][j];
+                    sj[t] = (int32_t)j;
+                }
+                __syncthreads();
+                if (row_ok)
+                    for (int e = 0; e < st.n[0]; ++e) {
+                        const int64_t cell = stencil_cell(g, st, a, b, e);
+                        if (cell < s_lo || cell > s_hi) {
+                            test_cell_global<D>(P, S, x, items, i, xi, cell, c);
+                            continue;
+                        }
+                        // fluid then walls of this cell, from the staged copy
+                        for (int pass = 0; pass < 2; ++pass) {
+                            const uint32_t *start = pass == 0 ? S.fstart : S.wstart;
+                            const uint32_t base = pass == 0 ? F0 : W0;
+                            const uint32_t shift = pass == 0 ? 0u : nF;
+                            const uint32_t t0 = start[cell] - base + shift, t1 = start[cell + 1] - base + shift;
+                            for (uint32_t t = t0; t < t1; ++t) {
+                                const int64_t j = sj[t];
+                                if (j == i) continue;
+                                double d[3] = {0, 0, 0};
+                                for (int k = 0; k < D; ++k) d[k] = min_image(xi[k] - sx[k][t], g, k);
+                                if (exact_r2<D>(d) < P.R2) {
+                                    if (c < P.cap) S.nbr[(int64_t)c * nf + i] = (int32_t)j;
+                                    ++c;
+                                }
                             }
                         }
                     }
-                }
-        if (c > cap) {
+                __syncthreads();   // the next stencil row overwrites the staged copy
+            }
+        if (!live) return;
+        if (c > P.cap) {
             atomicOr(&S.ctl->overflow, 1);
             atomicMax(&S.ctl->maxcnt, c);
         }
-        S.cnt[i] = c < cap ? c : cap;
+        S.cnt[i] = c < P.cap ? c : P.cap;
     }
 };
 
