@@ -195,6 +195,7 @@ static void carve(const Params &P, Carver &c, State &S) {
     S.p32 = c.take<float>(2 * nt);
     S.m = c.take<double>(nt);
     S.rho = c.take<double>(nt);
+    S.mr2 = c.take<double>(nt);
     S.rhs = c.take<double>(nf);
     S.dii = c.take<double>(nf);
     S.fs = c.take<int32_t>(nf);
@@ -466,6 +467,7 @@ static void seq_bin(const Target &T) {
 
 static void seq_predict(const Target &T) {
     density(T);
+    mass_over_rho2(T);
     wall_velocity(T, POS_X);
     predictor(T);
     bin_fluid(T, POS_XS);

@@ -84,6 +84,7 @@ struct State {
     float *p32;        // FP32 copies of the iterates (mixed) [2][ntot]
     double *m;         // mass                       [ntot]
     double *rho;       // density (walls rho0)       [ntot]
+    void *mr2;         // m / rho^2 in the working precision [ntot]
     double *rhs, *dii; //                            [nf]
     int32_t *fs;       // free-surface flag          [nf]
     int32_t *id;       // original index of sorted fluid slot [nf]
@@ -165,6 +166,7 @@ void bin_walls_once(const Target &T);
 void build_neighbors(const Target &T, int which);
 void wall_normals(const Target &T);
 void density(const Target &T);
+void mass_over_rho2(const Target &T);
 // Wall ghost velocity: no-slip form at r^n (POS_X); at r* (POS_XS) the
 // case's form for u* (slip by default).
 void wall_velocity(const Target &T, int which);

@@ -1372,6 +1372,19 @@ struct NextDt {
     }
 };
 
+// m_j / rho_j^2 of every particle in the working precision (the GTVF
+// sub-steps read it per pair instead of m_j and rho_j), formed with the
+// same operations the sub-steps used, so the values are identical.
+template <typename R>
+struct MassOverRho2 {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        ROW;
+        if (i >= P.ntot) return;
+        const R rho = (R)S.rho[i];
+        ((R *)S.mr2)[i] = (R)S.m[i] / (rho * rho);
+    }
+};
+
 // --------------------------------------------------------- GTVF sub-steps
 // f = -p0_i sum_j m_j / rho_j^2 grad_i W(r_ij^{k-1}, h~) on the frozen r*
 // neighbour lists (eq. mom:sph:gtvf), walls fixed;
@@ -1402,8 +1415,7 @@ struct Gtvf {
             R d[3], r2;
             pair_diff<D, R>(P.grid, xi, xsrc, j, d, r2);
             const R dw = K.dwr(sqrt(r2));
-            const R rhoj = (R)S.rho[j];
-            const R cf = (R)S.m[j] / (rhoj * rhoj) * dw;
+            const R cf = ((const R *)S.mr2)[j] * dw;
             for (int a = 0; a < D; ++a) s[a] += cf * d[a];
         }
         const double dtau = S.ctl->dt / (double)P.gtvf_K;
@@ -1922,6 +1934,11 @@ void correct(const Target &T) { SISPH_DISPATCH_KDR(T, (launch<Correct<KER, D, R>
 void step_maxima(const Target &T) { SISPH_DISPATCH_D(T, (launch<StepMaxima<D>, K_FLUID>(T))); }
 
 void next_dt(const Target &T) { launch<NextDt, K_ONE>(T); }
+
+void mass_over_rho2(const Target &T) {
+    if (T.precision == SISPH_MIXED) launch<MassOverRho2<float>, K_TOT>(T);
+    else launch<MassOverRho2<double>, K_TOT>(T);
+}
 
 void gtvf_substep(const Target &T, int k) { SISPH_DISPATCH_KDR(T, (launch<Gtvf<KER, D, R>, K_FLUID>(T, k))); }
 
