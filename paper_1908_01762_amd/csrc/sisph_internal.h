@@ -186,7 +186,7 @@ void sweep_only(const Target &T, int launch);
 // Fluid rows from which a single case's sweep tests the stop flag first.
 constexpr int64_t kPrecheckRows = int64_t(1) << 19;
 constexpr int kSweepVariants = 6;
-constexpr int kDefaultVariant = 0;
+constexpr int kDefaultVariant = 1;
 void settle_pressure(const Target &T);
 void wall_pressure_final(const Target &T);
 void pressure_max(const Target &T);
