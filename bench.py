@@ -92,8 +92,9 @@ def traffic_from_profiles(kernel_src_sha: str, workload: str):
 def kernel_sha() -> str:
     import hashlib
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1908_01762_amd", "csrc", "sisph_kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("sisph_kernels.hip", "sisph_internal.h"):   # kernels and their launch defaults
+        with open(os.path.join(ROOT, "paper_1908_01762_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()
 
 
