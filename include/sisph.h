@@ -125,6 +125,10 @@ typedef struct {
     double lambda;       /* max |RHS_i / D_ii| over non-free-surface fluid   */
     double p_ref;        /* GTVF reference pressure in use                  */
     double dt;           /* this step's time step                          */
+    int32_t index_bytes; /* bytes per neighbour index the sweeps read: 4, or
+                            2 (16-bit offsets: mixed mode, no walls, every
+                            offset of the step within +-32767)            */
+    int32_t reserved;
 } sisph_ppe_stats;
 
 typedef sisph_ppe_stats sisph_step_stats;

@@ -139,6 +139,7 @@ static Params make_params(const sisph_case_desc *d) {
     P.ustar_noslip = d->ustar_wall == SISPH_USTAR_NOSLIP ? 1 : 0;
     P.adaptive_dt = d->dt_mode == SISPH_DT_ADAPTIVE ? 1 : 0;
     P.solver = d->solver;
+    P.compact = d->precision == SISPH_MIXED && d->n_wall == 0 ? 1 : 0;
     P.cap = neighbour_cap(d);
     P.nf = d->n_fluid;
     P.nw = d->n_wall;
@@ -215,6 +216,7 @@ static void carve(const Params &P, Carver &c, State &S) {
     S.wcnt = c.take<int32_t>(nw);
     // mixed: (index, FP32 c_ij) 8-byte words; FP64: FP64 c_ij (indices from nbr)
     S.coef = c.take<char>((int64_t)8 * P.cap * nf);
+    S.coff = P.compact ? c.take<int16_t>((int64_t)P.cap * nf) : nullptr;
     S.wcoef = c.take<char>((int64_t)8 * P.cap * nw);
     S.wh = c.take<double>(nw);
     S.partial = c.take<double>(4 * kind_blocks(P, K_FLUID));
@@ -302,6 +304,8 @@ static void fill_stats(const Control &C, const Params &P, sisph_ppe_stats *out) 
     out->lambda = cv.d;
     out->p_ref = C.p_ref;
     out->dt = C.dt;
+    out->index_bytes = P.compact && !C.wide ? 2 : 4;
+    out->reserved = 0;
 }
 
 static int32_t status_of(const Control &C, const Params &P, std::string *msg) {

@@ -32,7 +32,7 @@ struct Params {
     int32_t ustar_noslip;   // wall ghost form for u*: 0 slip, 1 no-slip
     int32_t adaptive_dt;    // next dt from this step's maxima
     int32_t solver;         // SISPH_JACOBI or SISPH_BICGSTAB
-    int32_t pad1;
+    int32_t compact;        // mixed mode without walls: 16-bit neighbour offsets
     int64_t nf, nw, ntot;
     // dt: the fixed step, or the first step and the upper bound when adaptive
     // (kernels read the current step's dt from Control)
@@ -63,7 +63,8 @@ struct Control {
     // BiCGStab scalars of iterations k (slot k & 1): rho_k = (r^, r_{k-1}),
     // alpha_k, omega_k; a zero step denominator sets brk
     double bicg_rho[2], bicg_alpha[2], bicg_omega[2];
-    int32_t bicg_brk, pad2;
+    int32_t bicg_brk;
+    int32_t wide;                     // a neighbour offset of this step did not fit 16 bits
 };
 
 // Per-case device arrays.  Unified particle index: fluid [0, nf) in cell
@@ -95,7 +96,8 @@ struct State {
     // neighbour lists, slot-major [cap][n]: slot 0 is the particle itself
     int32_t *nbr, *cnt;     // fluid rows: fluid + wall sources
     int32_t *wnbr, *wcnt;   // wall rows: fluid sources
-    void *coef;             // cached PPE c_ij: (j, FP32 c) words (mixed) or FP64 [cap][nf]
+    void *coef;             // cached PPE c_ij in the working precision [cap][nf]
+    int16_t *coff;          // j - i modulo N_f (compact mode) [cap][nf]
     void *wcoef;            // cached wall weights W_wf / sum W: (f, FP32) words or FP64 [cap][nw]
     double *wh;             // wall hydrostatic term                 [nw]
     double *partial;        // per-workgroup partial sums of two sweeps [2][2][nblk]

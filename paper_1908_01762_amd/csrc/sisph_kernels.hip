@@ -283,6 +283,7 @@ struct ResetControl {
             c->lambda_bits = 0ull;
             c->pmax_key = 0ull;
             c->bicg_brk = 0;
+            c->wide = 0;
             for (int k = 0; k < 2; ++k) {
                 c->bicg_rho[k] = 1.0;
                 c->bicg_alpha[k] = 1.0;
@@ -882,28 +883,34 @@ struct Predictor {
     }
 };
 
-// Cached pair of the mixed-precision sweep: neighbour index and FP32 c_ij
-// in one 8-byte word, slot-major [cap][nf] like the neighbour lists.
+// Wall-weight word of the mixed mode: fluid index and FP32 weight in one
+// 8-byte word, slot-major [cap][nw] like the wall lists.
 struct PairF {
     int32_t j;
     float c;
 };
+// The PPE coefficient cache holds c_ij in the working precision, slot-major
+// [cap][nf]; the neighbour index comes from the lists, or, for the mixed
+// mode without walls, from a 16-bit offset j - i (modulo N_f) when every
+// offset of the step fits (rows are in cell order, so neighbours lie within
+// about two cell rows; a periodic wrap is a small offset modulo N_f).
 template <typename R>
-struct CoefSlot;
-template <>
-struct CoefSlot<float> {
-    using T = PairF;
+struct CoefSlot {
+    using T = R;
 };
-template <>
-struct CoefSlot<double> {
-    using T = double;
-};
+
+__device__ __forceinline__ int32_t offset_index(int64_t i, int16_t o, int64_t nf) {
+    int64_t j = i + (int64_t)o;
+    if (j < 0) j += nf;
+    else if (j >= nf) j -= nf;
+    return (int32_t)j;
+}
 
 // ------------------------------------------------- PPE RHS and coefficients
 // eq. sph-ppe / coeff / coeff1 at r*: RHS_i = sum -m_j/(rho_j dt) u*_ij.gradW,
 // c_ij = 4 m_j / (rho_i (rho_i + rho_j)) (r_ij.gradW) / (r^2 + eta h^2),
 // D_ii = sum_j c_ij (r^2 + eta h^2, not "+ eta^2").  c_ij is stored in list
-// order for the sweeps (with its neighbour index in the mixed mode);
+// order for the sweeps (and the 16-bit offsets where they apply);
 // Lambda = max |RHS/D| over non-free-surface rows (wave max, then one
 // atomic per wavefront).
 template <int KER, int D, typename R>
@@ -913,6 +920,7 @@ struct RhsCoef {
         const int64_t nf = P.nf;
         typename CoefSlot<R>::T *coef = (typename CoefSlot<R>::T *)S.coef;
         unsigned long long lam = 0ull;
+        bool wide = false;
         if (i < nf) {
             Kern<KER, D, R> K(P.h);
             const Pos xs = mkpos(S.xs), us = mkpos(S.us);
@@ -935,8 +943,14 @@ struct RhsCoef {
                 for (int a = 0; a < D; ++a) dot += (usi[a] - (R)us.c[a][j]) * d[a];
                 s -= mj / rhoj * inv_dt * dw * dot;
                 const R cij = R(4) * mj / (rhoi * (rhoi + rhoj)) * (dw * r2) / (r2 + eps);
-                if constexpr (sizeof(R) == 4) coef[(int64_t)k * nf + i] = PairF{(int32_t)j, cij};
-                else coef[(int64_t)k * nf + i] = cij;
+                coef[(int64_t)k * nf + i] = cij;
+                if (P.compact) {
+                    int64_t o = j - i;
+                    if (o > nf / 2) o -= nf;
+                    else if (o < -(nf / 2)) o += nf;
+                    if (o >= -32767 && o <= 32767) S.coff[(int64_t)k * nf + i] = (int16_t)o;
+                    else wide = true;
+                }
                 Dg += cij;
             }
             const double rr = (double)s, dd = (double)Dg;
@@ -946,6 +960,7 @@ struct RhsCoef {
         }
         lam = wave_max_u64(lam);   // non-negative doubles order like their bits
         if ((threadIdx.x & 63) == 0 && lam) max_if_larger(&S.ctl->lambda_bits, lam);
+        if (__any(wide) && (threadIdx.x & 63) == 0) atomicOr(&S.ctl->wide, 1);
     }
 };
 
@@ -960,8 +975,8 @@ struct CopyP32 {
 // eq. p-sor with omega: p_i^{k+1} = w (RHS_i + sum_j c_ij p_j^k) / D_ii
 // + (1 - w) p_i^k; p = 0 where D_ii = 0 or on free-surface rows (section 3).
 // Double-buffered (Jacobi): launch L reads iterate L from buffer L & 1 and
-// writes iterate L+1.  Mixed: the cached (j, c_ij) words and the FP32 copy of
-// iterate L; FP64: indices, FP64 coefficients and iterate L.
+// writes iterate L+1.  Mixed: FP32 c_ij, indices (or 16-bit offsets) and
+// the FP32 copy of iterate L; FP64: indices, FP64 coefficients, iterate L.
 //
 // Stopping (eq. convergence): launch L decides, from the partial sums of
 // sweep L-1, whether the solve stopped after L sweeps; the case's workgroup
@@ -982,22 +997,39 @@ constexpr int kSweepFirsts[3] = {16, 20, 24};
 constexpr int kSweepBatch = 8;
 constexpr int kPartialRegs = 8;
 
+// Coefficients and indices of slots k0 .. k0+NB-1 (clamped into the list
+// storage).  With offs, the indices are first read as 16-bit offsets
+// (resolved by resolve_batch once the step's fit flag is known).
 template <typename R, int NB>
 __device__ __forceinline__ void load_batch(int64_t i, int64_t nf, int k0, int c, int cap, bool blind,
                                            const typename CoefSlot<R>::T *coef, const int32_t *nbr,
-                                           int32_t (&jj)[NB], R (&cc)[NB]) {
+                                           const int16_t *offs, int32_t (&jj)[NB], int16_t (&oo)[NB],
+                                           R (&cc)[NB]) {
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
         const int k = k0 + t;
         const int ks = blind ? (k < cap ? k : cap - 1) : (k < c ? k : c - 1);
         const int64_t at = (int64_t)ks * nf + i;
-        if constexpr (sizeof(R) == 4) {
-            const PairF w = coef[at];
-            jj[t] = w.j;
-            cc[t] = w.c;
+        if (offs) oo[t] = offs[at];
+        else jj[t] = nbr[at];
+        cc[t] = coef[at];
+    }
+}
+
+// Indices from the offsets (wide = false) or, when some offset of the step
+// did not fit, from the lists after all.
+template <int NB>
+__device__ __forceinline__ void resolve_batch(int64_t i, int64_t nf, int k0, int c, int cap, bool blind,
+                                              const int32_t *nbr, bool wide, const int16_t (&oo)[NB],
+                                              int32_t (&jj)[NB]) {
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        if (!wide) {
+            jj[t] = offset_index(i, oo[t], nf);
         } else {
-            jj[t] = nbr[at];
-            cc[t] = coef[at];
+            const int k = k0 + t;
+            const int ks = blind ? (k < cap ? k : cap - 1) : (k < c ? k : c - 1);
+            jj[t] = nbr[(int64_t)ks * nf + i];
         }
     }
 }
@@ -1125,16 +1157,18 @@ struct Sweep {
         const float *qc = S.p32 + (L & 1) * P.ntot;
         float *qn = S.p32 + ((L + 1) & 1) * P.ntot;
         const typename CoefSlot<R>::T *coef = (const typename CoefSlot<R>::T *)S.coef;
+        const int16_t *offs = P.compact ? S.coff : nullptr;
+        const int32_t wide_flag = P.compact ? ctl->wide : 0;   // set by this step's coefficients
         ROW;
         const bool live = i < nf;
-        // one round trip: row values, the first batch of (j, c) words and
-        // (above) the partial sums
+        // one round trip: row values, the first batch of (j or offset, c)
         int32_t jj[FIRST];
+        int16_t oo[FIRST];
         R cc[FIRST];
         double D = 0.0, r = 0.0, pold = 0.0;
         int32_t f = 1, c = 0;
         if (live) {
-            load_batch<R, FIRST>(i, nf, 1, 0, P.cap, true, coef, S.nbr, jj, cc);
+            load_batch<R, FIRST>(i, nf, 1, 0, P.cap, true, coef, S.nbr, offs, jj, oo, cc);
             D = S.dii[i];
             r = S.rhs[i];
             f = S.fs[i];
@@ -1144,11 +1178,14 @@ struct Sweep {
         if (stopped < L) return;   // only earlier launches write values below L
         double v = 0.0;
         if (live) {
+            if (offs) resolve_batch<FIRST>(i, nf, 1, 0, P.cap, true, S.nbr, wide_flag != 0, oo, jj);
             R s = gather_sum<R, FIRST>(i, 1, c, jj, cc, pc, qc, R(0));
             for (int k0 = 1 + FIRST; k0 < c; k0 += kSweepBatch) {
                 int32_t jb[kSweepBatch];
+                int16_t ob[kSweepBatch];
                 R cb[kSweepBatch];
-                load_batch<R, kSweepBatch>(i, nf, k0, c, P.cap, false, coef, S.nbr, jb, cb);
+                load_batch<R, kSweepBatch>(i, nf, k0, c, P.cap, false, coef, S.nbr, offs, jb, ob, cb);
+                if (offs) resolve_batch<kSweepBatch>(i, nf, k0, c, P.cap, false, S.nbr, wide_flag != 0, ob, jb);
                 s = gather_sum<R, kSweepBatch>(i, k0, c, jb, cb, pc, qc, s);
             }
             if (D != 0.0 && !f) v = P.omega * (r + (double)s) / D + (1.0 - P.omega) * pold;
@@ -1520,12 +1557,7 @@ __device__ __forceinline__ double bicg_apply(const Params &P, const State &S, in
     double acc = 0.0;
     for (int k = 1; k < c; ++k) {
         const int64_t at = (int64_t)k * nf + i;
-        if constexpr (sizeof(R) == 4) {
-            const PairF w = ((const PairF *)S.coef)[at];
-            acc += (double)w.c * z[w.j];
-        } else {
-            acc += ((const double *)S.coef)[at] * z[S.nbr[at]];
-        }
+        acc += (double)((const R *)S.coef)[at] * z[S.nbr[at]];
     }
     return z[i] - acc / S.dii[i];
 }
@@ -1579,16 +1611,8 @@ struct BicgInitR {
                 const int c = S.cnt[i];
                 for (int k = 1; k < c; ++k) {
                     const int64_t at = (int64_t)k * nf + i;
-                    int64_t j;
-                    double cij;
-                    if constexpr (sizeof(R) == 4) {
-                        const PairF w = ((const PairF *)S.coef)[at];
-                        j = w.j;
-                        cij = (double)w.c;
-                    } else {
-                        j = S.nbr[at];
-                        cij = ((const double *)S.coef)[at];
-                    }
+                    const int64_t j = S.nbr[at];
+                    const double cij = (double)((const R *)S.coef)[at];
                     if (j >= nf) acc += cij * S.bh[j];
                 }
                 f = (S.rhs[i] + acc) / S.dii[i];
