@@ -115,7 +115,7 @@ static Grid make_grid(const sisph_case_desc *d) {
 }
 
 static int32_t neighbour_cap(const sisph_case_desc *d) {
-    if (d->nbr_cap > 0) return d->nbr_cap;
+    if (d->nbr_cap > 0) return (d->nbr_cap + 3) & ~3;   // whole groups of four slots
     const double R = support_of(d->kernel) * d->h / d->dx;
     const double pi = 3.14159265358979323846;
     double n = d->dim == 2 ? pi * R * R : 4.0 / 3.0 * pi * R * R * R;
@@ -216,7 +216,7 @@ static void carve(const Params &P, Carver &c, State &S) {
     S.wcnt = c.take<int32_t>(nw);
     // mixed: (index, FP32 c_ij) 8-byte words; FP64: FP64 c_ij (indices from nbr)
     S.coef = c.take<char>((int64_t)8 * P.cap * nf);
-    S.coff = P.compact ? c.take<int16_t>((int64_t)P.cap * nf) : nullptr;
+    S.cidx = c.take<int32_t>((int64_t)P.cap * nf);
     S.wcoef = c.take<char>((int64_t)8 * P.cap * nw);
     S.wh = c.take<double>(nw);
     S.partial = c.take<double>(4 * kind_blocks(P, K_FLUID));

@@ -96,8 +96,8 @@ struct State {
     // neighbour lists, slot-major [cap][n]: slot 0 is the particle itself
     int32_t *nbr, *cnt;     // fluid rows: fluid + wall sources
     int32_t *wnbr, *wcnt;   // wall rows: fluid sources
-    void *coef;             // cached PPE c_ij in the working precision [cap][nf]
-    int16_t *coff;          // j - i modulo N_f (compact mode) [cap][nf]
+    void *coef;             // cached PPE c_ij, working precision, group-major [cap/4][nf][4]
+    void *cidx;             // their indices (int32) or 16-bit offsets (compact), same layout
     void *wcoef;            // cached wall weights W_wf / sum W: (f, FP32) words or FP64 [cap][nw]
     double *wh;             // wall hydrostatic term                 [nw]
     double *partial;        // per-workgroup partial sums of two sweeps [2][2][nblk]

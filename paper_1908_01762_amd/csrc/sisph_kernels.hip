@@ -889,15 +889,34 @@ struct PairF {
     int32_t j;
     float c;
 };
-// The PPE coefficient cache holds c_ij in the working precision, slot-major
-// [cap][nf]; the neighbour index comes from the lists, or, for the mixed
-// mode without walls, from a 16-bit offset j - i (modulo N_f) when every
-// offset of the step fits (rows are in cell order, so neighbours lie within
-// about two cell rows; a periodic wrap is a small offset modulo N_f).
+// The PPE coefficient cache, group-major: neighbour list slot k >= 1 of row
+// i sits at position p = k - 1, in group g = p / 4, lane q = p % 4, at
+// element (g * N_f + i) * 4 + q, so one 16-byte (FP32) or 32-byte (FP64)
+// load brings four consecutive coefficients of a row and a wavefront's 64
+// rows read one contiguous block.  The indices sit beside them in the same
+// layout: 32-bit, or, for the mixed mode without walls, 16-bit offsets
+// j - i modulo N_f when every offset of the step fits (rows are in cell
+// order, so neighbours lie within about two cell rows; a periodic wrap is a
+// small offset modulo N_f); otherwise the sweep reads the lists.
 template <typename R>
 struct CoefSlot {
     using T = R;
 };
+template <typename R>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using T = float4;
+};
+template <>
+struct Vec4<double> {
+    using T = double4;
+};
+struct __align__(8) Off4 {
+    int16_t o[4];
+};
+
+__device__ __forceinline__ int64_t group_at(int64_t g, int64_t nf, int64_t i) { return g * nf + i; }
 
 __device__ __forceinline__ int32_t offset_index(int64_t i, int16_t o, int64_t nf) {
     int64_t j = i + (int64_t)o;
@@ -943,13 +962,16 @@ struct RhsCoef {
                 for (int a = 0; a < D; ++a) dot += (usi[a] - (R)us.c[a][j]) * d[a];
                 s -= mj / rhoj * inv_dt * dw * dot;
                 const R cij = R(4) * mj / (rhoi * (rhoi + rhoj)) * (dw * r2) / (r2 + eps);
-                coef[(int64_t)k * nf + i] = cij;
+                const int64_t at = group_at((k - 1) >> 2, nf, i) * 4 + ((k - 1) & 3);
+                coef[at] = cij;
                 if (P.compact) {
                     int64_t o = j - i;
                     if (o > nf / 2) o -= nf;
                     else if (o < -(nf / 2)) o += nf;
-                    if (o >= -32767 && o <= 32767) S.coff[(int64_t)k * nf + i] = (int16_t)o;
+                    if (o >= -32767 && o <= 32767) ((int16_t *)S.cidx)[at] = (int16_t)o;
                     else wide = true;
+                } else {
+                    ((int32_t *)S.cidx)[at] = (int32_t)j;
                 }
                 Dg += cij;
             }
@@ -986,68 +1008,81 @@ struct CopyP32 {
 // count returns at once: stopped_at < L can only have been written by an
 // earlier launch, so every wavefront reads the same answer.
 //
-// First batch: slots 1..FIRST loaded without waiting for the row's count
-// (every slot below cap is inside the list storage; slots past the count
-// hold stale words and are discarded by the select), so the row loads and
-// these loads form one round trip.  Longer rows
-// continue in batches of kSweepBatch.  The sum runs in slot order whatever
+// First batch: neighbour positions 0..FIRST-1 (FIRST / 4 groups) loaded
+// without waiting for the row's count (every group below cap / 4 is inside
+// the storage; positions past the count hold stale values and are
+// discarded by the select), so the row loads and these loads form one round
+// trip.  Longer rows continue kSweepBatchGroups groups at a time.  The sum runs in slot order whatever
 // FIRST is, so FIRST (chosen by the autotuner among kSweepFirsts) and the
 // workgroup mapping change the speed only, never the result.
-constexpr int kSweepFirsts[3] = {16, 20, 24};
-constexpr int kSweepBatch = 8;
+constexpr int kSweepFirsts[3] = {16, 20, 24};   // neighbours in the first round trip (multiples of 4)
+constexpr int kSweepBatchGroups = 2;
 constexpr int kPartialRegs = 8;
 
-// Coefficients and indices of slots k0 .. k0+NB-1 (clamped into the list
-// storage).  With offs, the indices are first read as 16-bit offsets
-// (resolved by resolve_batch once the step's fit flag is known).
-template <typename R, int NB>
-__device__ __forceinline__ void load_batch(int64_t i, int64_t nf, int k0, int c, int cap, bool blind,
-                                           const typename CoefSlot<R>::T *coef, const int32_t *nbr,
-                                           const int16_t *offs, int32_t (&jj)[NB], int16_t (&oo)[NB],
-                                           R (&cc)[NB]) {
+// Groups g0 .. g0+NG-1 of a row: coefficients and indices (or offsets),
+// group index clamped into the storage (ngroups = cap / 4).  Positions at
+// or past the row's count hold stale values that gather_groups discards.
+template <typename R, int NG>
+__device__ __forceinline__ void load_groups(int64_t i, int64_t nf, int g0, int gmax, const void *coef,
+                                            const void *cidx, bool offs, typename Vec4<R>::T (&cc)[NG],
+                                            int4 (&jj)[NG], Off4 (&oo)[NG]) {
 #pragma unroll
-    for (int t = 0; t < NB; ++t) {
-        const int k = k0 + t;
-        const int ks = blind ? (k < cap ? k : cap - 1) : (k < c ? k : c - 1);
-        const int64_t at = (int64_t)ks * nf + i;
-        if (offs) oo[t] = offs[at];
-        else jj[t] = nbr[at];
-        cc[t] = coef[at];
+    for (int t = 0; t < NG; ++t) {
+        const int g = g0 + t < gmax ? g0 + t : gmax - 1;
+        const int64_t at = group_at(g, nf, i);
+        cc[t] = ((const typename Vec4<R>::T *)coef)[at];
+        if (offs) oo[t] = ((const Off4 *)cidx)[at];
+        else jj[t] = ((const int4 *)cidx)[at];
     }
 }
 
-// Indices from the offsets (wide = false) or, when some offset of the step
-// did not fit, from the lists after all.
-template <int NB>
-__device__ __forceinline__ void resolve_batch(int64_t i, int64_t nf, int k0, int c, int cap, bool blind,
-                                              const int32_t *nbr, bool wide, const int16_t (&oo)[NB],
-                                              int32_t (&jj)[NB]) {
+// Offsets to indices; when an offset of the step did not fit, the indices
+// of the group's slots come from the lists instead.
+template <int NG>
+__device__ __forceinline__ void resolve_groups(int64_t i, int64_t nf, int g0, int npos, const int32_t *nbr,
+                                               bool wide, const Off4 (&oo)[NG], int4 (&jj)[NG]) {
 #pragma unroll
-    for (int t = 0; t < NB; ++t) {
-        if (!wide) {
-            jj[t] = offset_index(i, oo[t], nf);
-        } else {
-            const int k = k0 + t;
-            const int ks = blind ? (k < cap ? k : cap - 1) : (k < c ? k : c - 1);
-            jj[t] = nbr[(int64_t)ks * nf + i];
+    for (int t = 0; t < NG; ++t) {
+        int32_t j4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int p = (g0 + t) * 4 + q;
+            if (!wide) j4[q] = offset_index(i, oo[t].o[q], nf);
+            else j4[q] = p < npos ? nbr[(int64_t)(p + 1) * nf + i] : (int32_t)i;
         }
+        jj[t] = make_int4(j4[0], j4[1], j4[2], j4[3]);
     }
 }
 
-template <typename R, int NB>
-__device__ __forceinline__ R gather_sum(int64_t i, int k0, int c, const int32_t (&jj)[NB], const R (&cc)[NB],
-                                        const double *pc, const float *qc, R s) {
-    R pv[NB];
-    int32_t js[NB];
+template <typename R>
+__device__ __forceinline__ R vget(const typename Vec4<R>::T &v, int q) {
+    return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ int32_t iget(const int4 &v, int q) {
+    return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
+}
+
+// sum over positions p < npos of the groups, in position (= slot) order
+template <typename R, int NG>
+__device__ __forceinline__ R gather_groups(int64_t i, int g0, int npos, const typename Vec4<R>::T (&cc)[NG],
+                                           const int4 (&jj)[NG], const double *pc, const float *qc, R s) {
+    R pv[NG][4];
 #pragma unroll
-    for (int t = 0; t < NB; ++t) js[t] = (k0 + t < c) ? jj[t] : (int32_t)i;
+    for (int t = 0; t < NG; ++t)
 #pragma unroll
-    for (int t = 0; t < NB; ++t) {
-        if constexpr (sizeof(R) == 4) pv[t] = qc[js[t]];
-        else pv[t] = pc[js[t]];
-    }
+        for (int q = 0; q < 4; ++q) {
+            const int p = (g0 + t) * 4 + q;
+            const int32_t j = p < npos ? iget(jj[t], q) : (int32_t)i;
+            if constexpr (sizeof(R) == 4) pv[t][q] = qc[j];
+            else pv[t][q] = pc[j];
+        }
 #pragma unroll
-    for (int t = 0; t < NB; ++t) s += ((k0 + t < c) ? cc[t] : R(0)) * pv[t];
+    for (int t = 0; t < NG; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int p = (g0 + t) * 4 + q;
+            s += (p < npos ? vget<R>(cc[t], q) : R(0)) * pv[t][q];
+        }
     return s;
 }
 
@@ -1156,19 +1191,21 @@ struct Sweep {
         double *pn = S.p[(L + 1) & 1];
         const float *qc = S.p32 + (L & 1) * P.ntot;
         float *qn = S.p32 + ((L + 1) & 1) * P.ntot;
-        const typename CoefSlot<R>::T *coef = (const typename CoefSlot<R>::T *)S.coef;
-        const int16_t *offs = P.compact ? S.coff : nullptr;
-        const int32_t wide_flag = P.compact ? ctl->wide : 0;   // set by this step's coefficients
+        const bool offs = P.compact != 0;
+        const int32_t wide_flag = offs ? ctl->wide : 0;   // set by this step's coefficients
+        const int gmax = P.cap / 4;
         ROW;
         const bool live = i < nf;
-        // one round trip: row values, the first batch of (j or offset, c)
-        int32_t jj[FIRST];
-        int16_t oo[FIRST];
-        R cc[FIRST];
+        // one round trip: row values and the first FIRST / 4 coefficient and
+        // index groups
+        constexpr int NG = FIRST / 4;
+        typename Vec4<R>::T cc[NG];
+        int4 jj[NG];
+        Off4 oo[NG];
         double D = 0.0, r = 0.0, pold = 0.0;
         int32_t f = 1, c = 0;
         if (live) {
-            load_batch<R, FIRST>(i, nf, 1, 0, P.cap, true, coef, S.nbr, offs, jj, oo, cc);
+            load_groups<R, NG>(i, nf, 0, gmax, S.coef, S.cidx, offs, cc, jj, oo);
             D = S.dii[i];
             r = S.rhs[i];
             f = S.fs[i];
@@ -1178,15 +1215,16 @@ struct Sweep {
         if (stopped < L) return;   // only earlier launches write values below L
         double v = 0.0;
         if (live) {
-            if (offs) resolve_batch<FIRST>(i, nf, 1, 0, P.cap, true, S.nbr, wide_flag != 0, oo, jj);
-            R s = gather_sum<R, FIRST>(i, 1, c, jj, cc, pc, qc, R(0));
-            for (int k0 = 1 + FIRST; k0 < c; k0 += kSweepBatch) {
-                int32_t jb[kSweepBatch];
-                int16_t ob[kSweepBatch];
-                R cb[kSweepBatch];
-                load_batch<R, kSweepBatch>(i, nf, k0, c, P.cap, false, coef, S.nbr, offs, jb, ob, cb);
-                if (offs) resolve_batch<kSweepBatch>(i, nf, k0, c, P.cap, false, S.nbr, wide_flag != 0, ob, jb);
-                s = gather_sum<R, kSweepBatch>(i, k0, c, jb, cb, pc, qc, s);
+            const int npos = c - 1;   // neighbours besides the row itself
+            if (offs) resolve_groups<NG>(i, nf, 0, npos, S.nbr, wide_flag != 0, oo, jj);
+            R s = gather_groups<R, NG>(i, 0, npos, cc, jj, pc, qc, R(0));
+            for (int g0 = NG; 4 * g0 < npos; g0 += kSweepBatchGroups) {
+                typename Vec4<R>::T cb[kSweepBatchGroups];
+                int4 jb[kSweepBatchGroups];
+                Off4 ob[kSweepBatchGroups];
+                load_groups<R, kSweepBatchGroups>(i, nf, g0, gmax, S.coef, S.cidx, offs, cb, jb, ob);
+                if (offs) resolve_groups<kSweepBatchGroups>(i, nf, g0, npos, S.nbr, wide_flag != 0, ob, jb);
+                s = gather_groups<R, kSweepBatchGroups>(i, g0, npos, cb, jb, pc, qc, s);
             }
             if (D != 0.0 && !f) v = P.omega * (r + (double)s) / D + (1.0 - P.omega) * pold;
         }
@@ -1556,8 +1594,8 @@ __device__ __forceinline__ double bicg_apply(const Params &P, const State &S, in
     const int c = S.cnt[i];
     double acc = 0.0;
     for (int k = 1; k < c; ++k) {
-        const int64_t at = (int64_t)k * nf + i;
-        acc += (double)((const R *)S.coef)[at] * z[S.nbr[at]];
+        const int64_t at = group_at((k - 1) >> 2, nf, i) * 4 + ((k - 1) & 3);
+        acc += (double)((const R *)S.coef)[at] * z[S.nbr[(int64_t)k * nf + i]];
     }
     return z[i] - acc / S.dii[i];
 }
@@ -1610,9 +1648,8 @@ struct BicgInitR {
                 double acc = 0.0;
                 const int c = S.cnt[i];
                 for (int k = 1; k < c; ++k) {
-                    const int64_t at = (int64_t)k * nf + i;
-                    const int64_t j = S.nbr[at];
-                    const double cij = (double)((const R *)S.coef)[at];
+                    const int64_t j = S.nbr[(int64_t)k * nf + i];
+                    const double cij = (double)((const R *)S.coef)[group_at((k - 1) >> 2, nf, i) * 4 + ((k - 1) & 3)];
                     if (j >= nf) acc += cij * S.bh[j];
                 }
                 f = (S.rhs[i] + acc) / S.dii[i];
