@@ -48,9 +48,9 @@ def test_workspace_bytes_valid_and_monotone():
     assert small % 256 == 0
     db = sisph.workspace_bytes(cases.dam_break_2d(dx=0.05))
     assert db > 0
-    # the mixed mode without walls adds only the 16-bit offset table
-    mixed = sisph.workspace_bytes(cases.taylor_green(20, precision="mixed"))
-    assert small < mixed <= small + 2 * 400 * 64 + 256
+    # FP64 and mixed cases of the same geometry carve the same storage (the
+    # coefficient cache is sized for FP64, the index table for 32 bits)
+    assert sisph.workspace_bytes(cases.taylor_green(20, precision="mixed")) == small
 
 
 @pytest.mark.parametrize("field,value", [
