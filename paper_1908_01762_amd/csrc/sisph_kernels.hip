@@ -1017,7 +1017,7 @@ struct CopyP32 {
 // workgroup mapping change the speed only, never the result.
 constexpr int kSweepFirsts[3] = {16, 20, 24};   // neighbours in the first round trip (multiples of 4)
 constexpr int kSweepBatchGroups = 2;
-constexpr int kPartialRegs = 8;
+constexpr int kPartialRegs = 4;   // partial sums per thread in the first pass (1024 workgroups)
 
 // Groups g0 .. g0+NG-1 of a row: coefficients and indices (or offsets),
 // group index clamped into the storage (ngroups = cap / 4).  Positions at
@@ -1060,6 +1060,35 @@ __device__ __forceinline__ R vget(const typename Vec4<R>::T &v, int q) {
 }
 __device__ __forceinline__ int32_t iget(const int4 &v, int q) {
     return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
+}
+
+// Gathered iterate values of the groups' positions (the row's own value
+// for positions at or past npos).
+template <typename R, int NG>
+__device__ __forceinline__ void issue_gathers(int64_t i, int g0, int npos, const int4 (&jj)[NG], const double *pc,
+                                              const float *qc, R (&pv)[NG][4]) {
+#pragma unroll
+    for (int t = 0; t < NG; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int p = (g0 + t) * 4 + q;
+            const int32_t j = p < npos ? iget(jj[t], q) : (int32_t)i;
+            if constexpr (sizeof(R) == 4) pv[t][q] = qc[j];
+            else pv[t][q] = pc[j];
+        }
+}
+
+template <typename R, int NG>
+__device__ __forceinline__ R sum_gathers(int g0, int npos, const typename Vec4<R>::T (&cc)[NG],
+                                         const R (&pv)[NG][4], R s) {
+#pragma unroll
+    for (int t = 0; t < NG; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int p = (g0 + t) * 4 + q;
+            s += (p < npos ? vget<R>(cc[t], q) : R(0)) * pv[t][q];
+        }
+    return s;
 }
 
 // sum over positions p < npos of the groups, in position (= slot) order
@@ -1176,16 +1205,12 @@ struct Sweep {
         // sweeps the result is iterate L, in the other buffer, and launch
         // L+1 returns at once.  (Every workgroup deciding costs each one a
         // read of all the partial sums: 17 % slower at 160k particles.)
-        // (the deciding workgroup reduces before its own row loads, so the
-        // partial sums do not hold registers across the gathers)
-        if (L > 0 && blk == 0) {
-            // a solve that stopped earlier left stale partial sums: no decision
-            if (stopped < L) return;
-            const double lam = __longlong_as_double((long long)ctl->lambda_bits);   // fixed during the solve
-            PartialLoad pl;
-            load_partials(S.partial, nblk, L, pl);
-            if (stopped_after(P, S.partial, nblk, L, pl, lam, true, ctl)) return;
-        }
+        // The deciding workgroup issues its partial-sum loads with its row
+        // loads and decides between issuing its gathers and using them, so
+        // the decision costs it no extra round trip.
+        const bool decides = L > 0 && blk == 0;
+        PartialLoad pl;
+        if (decides) load_partials(S.partial, nblk, L, pl);
         const int64_t nf = P.nf;
         const double *pc = S.p[L & 1];
         double *pn = S.p[(L + 1) & 1];
@@ -1214,10 +1239,19 @@ struct Sweep {
         }
         if (stopped < L) return;   // only earlier launches write values below L
         double v = 0.0;
+        const int npos = c - 1;   // neighbours besides the row itself
+        R pv[NG][4];
         if (live) {
-            const int npos = c - 1;   // neighbours besides the row itself
             if (offs) resolve_groups<NG>(i, nf, 0, npos, S.nbr, wide_flag != 0, oo, jj);
-            R s = gather_groups<R, NG>(i, 0, npos, cc, jj, pc, qc, R(0));
+            issue_gathers<R, NG>(i, 0, npos, jj, pc, qc, pv);
+        }
+        // (a solve that stopped earlier returned above: its partials are stale)
+        if (decides) {
+            const double lam = __longlong_as_double((long long)ctl->lambda_bits);   // fixed during the solve
+            if (stopped_after(P, S.partial, nblk, L, pl, lam, true, ctl)) return;
+        }
+        if (live) {
+            R s = sum_gathers<R, NG>(0, npos, cc, pv, R(0));
             for (int g0 = NG; 4 * g0 < npos; g0 += kSweepBatchGroups) {
                 typename Vec4<R>::T cb[kSweepBatchGroups];
                 int4 jb[kSweepBatchGroups];
