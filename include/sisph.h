@@ -205,6 +205,15 @@ int32_t sisph_last_timings(sisph_ctx *ctx, double *ppe_ms, double *step_ms);
 int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_t *launches,
                              int64_t *effective, int32_t reset);
 
+/* Graph replay of the fixed parts of a step (the data-dependent PPE loop
+ * stays a sequence of polled launch chunks with device-side early exit):
+ * with on != 0, sisph_step captures once, then replays, two HIP graphs per
+ * context, the kernels from binning to the PPE set-up and those from the
+ * settle of the pressure to the advance; results are bitwise those of the
+ * launches one by one.  The stage calls (sisph_bin, ...) always launch
+ * directly.  Off by default. */
+int32_t sisph_set_graphs(sisph_ctx *ctx, int32_t on);
+
 int32_t sisph_destroy(sisph_ctx *ctx);
 
 /* ------------------------------------------------------------- autotuning
@@ -245,6 +254,9 @@ int32_t sisph_batch_size(sisph_batch *b);
  * cases (errors of single cases are reported in their entries' nonfinite
  * flag and in the return value). */
 int32_t sisph_batch_step(sisph_batch *b, sisph_step_stats *per_case);
+/* As sisph_set_graphs, per (dimension, kernel, precision) group of the batch;
+ * graphs are captured again after the group's membership changes. */
+int32_t sisph_batch_set_graphs(sisph_batch *b, int32_t on);
 int32_t sisph_batch_destroy(sisph_batch *b);
 
 const char *sisph_status_string(int32_t status);

@@ -34,6 +34,9 @@ struct sisph_ctx {
     bool step_timed;
     sisph_batch *batch;  // non-null while attached
     int32_t variant;     // Jacobi-sweep launch variant
+    bool use_graphs = false;
+    hipStream_t cap_stream = nullptr;                          // capture only
+    hipGraphExec_t g_pre = nullptr, g_post = nullptr;          // fixed step segments
     std::string err;
 };
 
@@ -504,6 +507,43 @@ static void seq_correct(const Target &T, int maxK) {
     advance(T);
 }
 
+// The fixed segments of a step around the data-dependent PPE loop: binning
+// through the PPE set-up, and the settle through the advance.  They are
+// captured once into graphs (kernel launches only: no copies or memsets)
+// on a private stream and replayed on the caller's stream.
+static void seq_pre(const Target &T) {
+    seq_bin(T);
+    seq_predict(T);
+    seq_ppe_begin(T);
+}
+
+static void seq_post(const Target &T, int maxK) {
+    seq_ppe_end(T);
+    seq_correct(T, maxK);
+}
+
+template <class Seq>
+static hipError_t capture_graph(hipStream_t &cs, Target T, Seq seq, hipGraphExec_t *out) {
+    hipError_t e;
+    if (!cs && (e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return e;
+    T.s = cs;
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    seq(T);
+    hipGraph_t g = nullptr;
+    const hipError_t launched = hipGetLastError();
+    e = hipStreamEndCapture(cs, &g);
+    if (launched != hipSuccess) e = launched;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
+static void drop_graphs(hipGraphExec_t &pre, hipGraphExec_t &post) {
+    if (pre) (void)hipGraphExecDestroy(pre);
+    if (post) (void)hipGraphExecDestroy(post);
+    pre = post = nullptr;
+}
+
 // ------------------------------------------------------------ the stages
 static bool attached(sisph_ctx *ctx) { return ctx->batch != nullptr; }
 
@@ -622,9 +662,69 @@ extern "C" int32_t sisph_correct(sisph_ctx *ctx) {
     return SISPH_OK;
 }
 
+// One step with the fixed segments replayed from graphs.
+static int32_t step_graphed(sisph_ctx *ctx, sisph_step_stats *out) {
+    if (attached(ctx)) return fail(ctx, SISPH_E_STATE, "context is attached to a batch");
+    if (ctx->state != ST_READY) return fail(ctx, SISPH_E_STATE, "sisph_step needs a completed step");
+    const Params &P = ctx->P;
+    hipStream_t s = ctx->stream;
+    if (!ctx->g_pre) {
+        hipError_t e = capture_graph(ctx->cap_stream, ctx->T, seq_pre, &ctx->g_pre);
+        const int maxK = P.gtvf_K;
+        if (e == hipSuccess)
+            e = capture_graph(ctx->cap_stream, ctx->T, [maxK](const Target &T) { seq_post(T, maxK); },
+                              &ctx->g_post);
+        if (e != hipSuccess) {
+            drop_graphs(ctx->g_pre, ctx->g_post);
+            return fail(ctx, SISPH_E_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+        }
+    }
+    HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
+    HIPCHK(ctx, hipGraphLaunch(ctx->g_pre, s));
+    HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
+    const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1;
+    const int64_t predicted = P.forced_iters > 0 ? P.forced_iters : std::max(P.min_iter, ctx->last_iters);
+    auto poll = [&](bool &done) -> int32_t {
+        int32_t st = read_ctl(ctx);
+        if (st != SISPH_OK) return st;
+        done = ctx->h_ctl->done != 0;
+        return SISPH_OK;
+    };
+    int32_t st = ppe_loop(ctx->T, predicted, limit, ctx->evc[0], ctx->evc[1], ctx->sweep_ms, ctx->sweep_launches,
+                          poll, ctx->err);
+    if (st != SISPH_OK) return st;
+    HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+    HIPCHK(ctx, hipGraphLaunch(ctx->g_post, s));
+    HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
+    if ((st = read_ctl(ctx)) != SISPH_OK) return st;
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+    ctx->ppe_ms = ms;   // the sweeps (set-up and settle are inside the graphs)
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
+    ctx->step_ms = ms;
+    const Control &C = *ctx->h_ctl;
+    ctx->sweep_effective += C.iter;
+    ctx->last_iters = std::max(C.iter, 1);
+    ctx->nbr_stage = 1;
+    if (out) fill_stats(C, P, out);
+    ctx->state = ST_READY;
+    std::string msg;
+    st = status_of(C, P, &msg);
+    if (st < 0) return fail(ctx, st, msg);
+    return st;
+}
+
 extern "C" int32_t sisph_step(sisph_ctx *ctx, int32_t nsteps, sisph_step_stats *out) {
     if (!ctx || nsteps < 0) return SISPH_E_INVAL;
     int32_t worst = SISPH_OK;
+    if (ctx->use_graphs) {
+        for (int32_t n = 0; n < nsteps; ++n) {
+            const int32_t sp = step_graphed(ctx, out ? out + n : nullptr);
+            if (sp < 0) return sp;
+            if (sp > worst) worst = sp;
+        }
+        return worst;
+    }
     for (int32_t n = 0; n < nsteps; ++n) {
         int32_t st = sisph_bin(ctx);
         if (st < 0) return st;
@@ -852,11 +952,15 @@ struct Group {
     size_t case_cap = 0;              // entries of d_tab and d_ctl
     bool dirty = true;
     Target T{};
+    hipGraphExec_t g_pre = nullptr, g_post = nullptr;   // fixed step segments (graph mode)
+    int g_maxK = -1;
 };
 
 struct sisph_batch {
     int32_t max_cases;
     hipStream_t stream;
+    bool use_graphs = false;
+    hipStream_t cap_stream = nullptr;
     std::vector<sisph_ctx *> cases;   // attach order
     std::vector<Group> groups;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -864,6 +968,7 @@ struct sisph_batch {
 };
 
 static void free_group(Group &g) {
+    drop_graphs(g.g_pre, g.g_post);
     if (g.d_tab) (void)hipFree(g.d_tab);
     for (int k = 0; k < K_COUNT; ++k) {
         if (g.d_owner[k]) (void)hipFree(g.d_owner[k]);
@@ -892,6 +997,7 @@ static void free_group(Group &g) {
 
 // Rebuilds a group's device table and workgroup maps after membership changed.
 static int32_t rebuild_group(sisph_batch *b, Group &g) {
+    drop_graphs(g.g_pre, g.g_post);   // captured against the old tables
     const size_t n = g.members.size();
     if (n > g.case_cap) {
         if (g.d_tab) (void)hipFree(g.d_tab);
@@ -1040,9 +1146,23 @@ static int32_t group_step(sisph_batch *b, Group &g) {
                                                                    : std::max(P.min_iter, c->last_iters));
         maxK = std::max(maxK, P.gtvf_K);
     }
-    seq_bin(T);
-    seq_predict(T);
-    seq_ppe_begin(T);
+    if (b->use_graphs) {
+        if (!g.g_pre || g.g_maxK != maxK) {
+            drop_graphs(g.g_pre, g.g_post);
+            hipError_t e = capture_graph(b->cap_stream, T, seq_pre, &g.g_pre);
+            if (e == hipSuccess)
+                e = capture_graph(b->cap_stream, T, [maxK](const Target &t) { seq_post(t, maxK); }, &g.g_post);
+            if (e != hipSuccess) {
+                drop_graphs(g.g_pre, g.g_post);
+                b->err = std::string("graph capture failed: ") + hipGetErrorString(e);
+                return SISPH_E_DEVICE;
+            }
+            g.g_maxK = maxK;
+        }
+        BCHK(b, hipGraphLaunch(g.g_pre, b->stream));
+    } else {
+        seq_pre(T);
+    }
     auto poll = [&](bool &done) -> int32_t {
         gather_control(T, g.d_ctl);
         BCHK(b, hipMemcpyAsync(g.h_ctl, g.d_ctl, sizeof(Control) * n, hipMemcpyDeviceToHost, b->stream));
@@ -1055,8 +1175,8 @@ static int32_t group_step(sisph_batch *b, Group &g) {
     int64_t launches = 0;
     int32_t st = ppe_loop(T, predicted, limit, b->e0, b->e1, sweep_ms, launches, poll, b->err);
     if (st != SISPH_OK) return st;
-    seq_ppe_end(T);
-    seq_correct(T, maxK);
+    if (b->use_graphs) BCHK(b, hipGraphLaunch(g.g_post, b->stream));
+    else seq_post(T, maxK);
     gather_control(T, g.d_ctl);
     BCHK(b, hipMemcpyAsync(g.h_ctl, g.d_ctl, sizeof(Control) * n, hipMemcpyDeviceToHost, b->stream));
     BCHK(b, hipStreamSynchronize(b->stream));
@@ -1094,11 +1214,18 @@ extern "C" int32_t sisph_batch_step(sisph_batch *b, sisph_step_stats *per_case) 
     return err < 0 ? err : warn;
 }
 
+extern "C" int32_t sisph_batch_set_graphs(sisph_batch *b, int32_t on) {
+    if (!b) return SISPH_E_INVAL;
+    b->use_graphs = on != 0;
+    return SISPH_OK;
+}
+
 extern "C" int32_t sisph_batch_destroy(sisph_batch *b) {
     if (!b) return SISPH_E_INVAL;
     (void)hipStreamSynchronize(b->stream);
     for (auto *c : b->cases) c->batch = nullptr;
     for (auto &g : b->groups) free_group(g);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->e0) (void)hipEventDestroy(b->e0);
     if (b->e1) (void)hipEventDestroy(b->e1);
     delete b;
@@ -1145,10 +1272,18 @@ extern "C" int32_t sisph_set_variant(sisph_ctx *ctx, int32_t variant) {
 
 extern "C" int32_t sisph_get_variant(sisph_ctx *ctx) { return ctx ? ctx->variant : SISPH_E_INVAL; }
 
+extern "C" int32_t sisph_set_graphs(sisph_ctx *ctx, int32_t on) {
+    if (!ctx) return SISPH_E_INVAL;
+    ctx->use_graphs = on != 0;
+    return SISPH_OK;
+}
+
 extern "C" int32_t sisph_destroy(sisph_ctx *ctx) {
     if (!ctx) return SISPH_E_INVAL;
     if (ctx->batch) (void)sisph_batch_detach(ctx->batch, ctx);
     (void)hipStreamSynchronize(ctx->stream);
+    drop_graphs(ctx->g_pre, ctx->g_post);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);

@@ -89,6 +89,10 @@ def lib():
         L.sisph_write_state.argtypes = [C.c_void_p, _DP, _DP, _DP, _DP]
         L.sisph_read_field.restype = C.c_int32
         L.sisph_read_field.argtypes = [C.c_void_p, C.c_int32, _DP]
+        L.sisph_set_graphs.restype = C.c_int32
+        L.sisph_set_graphs.argtypes = [C.c_void_p, C.c_int32]
+        L.sisph_batch_set_graphs.restype = C.c_int32
+        L.sisph_batch_set_graphs.argtypes = [C.c_void_p, C.c_int32]
         L.sisph_pair_count.restype = C.c_int32
         L.sisph_pair_count.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
         L.sisph_debug_neighbors.restype = C.c_int32
@@ -267,6 +271,10 @@ class Context:
                                             ids.size), self.h)
         return off, ids[:off[-1]].copy()
 
+    def use_graphs(self, on: bool = True):
+        """Replay the fixed parts of each step from HIP graphs (sisph_step)."""
+        _check(lib().sisph_set_graphs(self.h, int(bool(on))), self.h)
+
     def pair_count(self, stage: int, dest: int = 0) -> int:
         """Stored neighbour pairs (self included) of the held lists."""
         n = C.c_int64()
@@ -325,6 +333,12 @@ class Batch:
             raise SisphError(code, status_string(code))
         self.h = h
         self.members: List[Context] = []
+
+    def use_graphs(self, on: bool = True):
+        """Replay the fixed parts of each batched step from HIP graphs."""
+        code = lib().sisph_batch_set_graphs(self.h, int(bool(on)))
+        if code != OK:
+            raise SisphError(code, status_string(code))
 
     def attach(self, ctx: Context):
         _check(lib().sisph_batch_attach(self.h, ctx.h), ctx.h)
