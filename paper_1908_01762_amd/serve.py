@@ -47,6 +47,7 @@ class GpuBackend:
         self.sisph = sisph
         self.torch = torch
         self.batch = sisph.Batch(max_slots)
+        self.batch.use_graphs(True)   # fixed step segments replayed from HIP graphs
 
     def workspace_bytes(self, case) -> int:
         return self.sisph.workspace_bytes(case)
