@@ -1372,8 +1372,10 @@ struct SettlePressure {
     }
 };
 
+// max p over the fluid, needed only until p_ref is set (first solve)
 struct PMax {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        if (S.ctl->p_ref_set) return;
         ROW;
         unsigned long long k = i < P.nf ? order_key(S.p[0][i]) : 0ull;
         k = wave_max_u64(k);
