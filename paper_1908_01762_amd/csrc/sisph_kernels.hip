@@ -937,7 +937,6 @@ struct RhsCoef {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         const int64_t nf = P.nf;
-        typename CoefSlot<R>::T *coef = (typename CoefSlot<R>::T *)S.coef;
         unsigned long long lam = 0ull;
         bool wide = false;
         if (i < nf) {
@@ -952,6 +951,11 @@ struct RhsCoef {
             const R rhoi = (R)S.rho[i], eps = (R)P.eps_h, inv_dt = (R)(1.0 / S.ctl->dt);
             R s = R(0), Dg = R(0);
             const int c = S.cnt[i];
+            // one group of four coefficients (and indices or offsets) is
+            // buffered in registers and written with one store each
+            R c4[4] = {R(0), R(0), R(0), R(0)};
+            int32_t j4[4] = {(int32_t)i, (int32_t)i, (int32_t)i, (int32_t)i};
+            int16_t o4[4] = {0, 0, 0, 0};
             for (int k = 1; k < c; ++k) {
                 const int64_t j = S.nbr[(int64_t)k * nf + i];
                 R d[3], r2;
@@ -962,16 +966,43 @@ struct RhsCoef {
                 for (int a = 0; a < D; ++a) dot += (usi[a] - (R)us.c[a][j]) * d[a];
                 s -= mj / rhoj * inv_dt * dw * dot;
                 const R cij = R(4) * mj / (rhoi * (rhoi + rhoj)) * (dw * r2) / (r2 + eps);
-                const int64_t at = group_at((k - 1) >> 2, nf, i) * 4 + ((k - 1) & 3);
-                coef[at] = cij;
+                const int q = (k - 1) & 3;
+                int16_t oq = 0;
                 if (P.compact) {
                     int64_t o = j - i;
                     if (o > nf / 2) o -= nf;
                     else if (o < -(nf / 2)) o += nf;
-                    if (o >= -32767 && o <= 32767) ((int16_t *)S.cidx)[at] = (int16_t)o;
+                    if (o >= -32767 && o <= 32767) oq = (int16_t)o;
                     else wide = true;
-                } else {
-                    ((int32_t *)S.cidx)[at] = (int32_t)j;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (t == q) {
+                        c4[t] = cij;
+                        j4[t] = (int32_t)j;
+                        o4[t] = oq;
+                    }
+                if (q == 3 || k == c - 1) {
+                    const int64_t at = group_at((k - 1) >> 2, nf, i);
+                    typename Vec4<R>::T cv;
+                    cv.x = c4[0];
+                    cv.y = c4[1];
+                    cv.z = c4[2];
+                    cv.w = c4[3];
+                    ((typename Vec4<R>::T *)S.coef)[at] = cv;
+                    if (P.compact) {
+                        Off4 ov;
+                        for (int t = 0; t < 4; ++t) ov.o[t] = o4[t];
+                        ((Off4 *)S.cidx)[at] = ov;
+                    } else {
+                        ((int4 *)S.cidx)[at] = make_int4(j4[0], j4[1], j4[2], j4[3]);
+                    }
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        c4[t] = R(0);
+                        j4[t] = (int32_t)i;
+                        o4[t] = 0;
+                    }
                 }
                 Dg += cij;
             }
