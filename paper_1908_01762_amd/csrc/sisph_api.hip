@@ -200,6 +200,17 @@ static void carve(const Params &P, Carver &c, State &S) {
     S.m = c.take<double>(nt);
     S.rho = c.take<double>(nt);
     S.mr2 = c.take<double>(nt);
+    for (int k = 0; k < 3; ++k) S.u32[k] = S.us32[k] = S.ut32[k] = nullptr;
+    S.m32 = S.rho32 = nullptr;
+    if (P.precision == SISPH_MIXED) {
+        for (int k = 0; k < D; ++k) {
+            S.u32[k] = c.take<float>(nt);
+            S.us32[k] = c.take<float>(nt);
+            S.ut32[k] = c.take<float>(nf);
+        }
+        S.m32 = c.take<float>(nt);
+        S.rho32 = c.take<float>(nt);
+    }
     S.rhs = c.take<double>(nf);
     S.dii = c.take<double>(nf);
     S.fs = c.take<int32_t>(nf);
@@ -476,10 +487,12 @@ static void seq_predict(const Target &T) {
     density(T);
     mass_over_rho2(T);
     wall_velocity(T, POS_X);
+    shadow(T, 0);
     predictor(T);
     bin_fluid(T, POS_XS);
     build_neighbors(T, POS_XS);
     wall_velocity(T, POS_XS);
+    shadow(T, 1);
 }
 
 static void seq_ppe_begin(const Target &T) {

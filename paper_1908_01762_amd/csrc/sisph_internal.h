@@ -86,6 +86,10 @@ struct State {
     double *m;         // mass                       [ntot]
     double *rho;       // density (walls rho0)       [ntot]
     void *mr2;         // m / rho^2 in the working precision [ntot]
+    // FP32 copies for the mixed-mode pair gathers (see Shadow)
+    float *u32[3], *us32[3];   // [ntot]
+    float *ut32[3];            // [nf]
+    float *m32, *rho32;        // [ntot]
     double *rhs, *dii; //                            [nf]
     int32_t *fs;       // free-surface flag          [nf]
     int32_t *id;       // original index of sorted fluid slot [nf]
@@ -169,6 +173,9 @@ void build_neighbors(const Target &T, int which);
 void wall_normals(const Target &T);
 void density(const Target &T);
 void mass_over_rho2(const Target &T);
+// FP32 copies of gathered fields (mixed mode): 0 after the r^n wall
+// velocity, 1 after the r* wall velocity.
+void shadow(const Target &T, int which);
 // Wall ghost velocity: no-slip form at r^n (POS_X); at r* (POS_XS) the
 // case's form for u* (slip by default).
 void wall_velocity(const Target &T, int which);

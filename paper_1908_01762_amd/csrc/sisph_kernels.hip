@@ -841,9 +841,18 @@ struct Predictor {
             R gw[3];
             for (int a = 0; a < 3; ++a) gw[a] = dw * d[a];
             const R F = dw * r2;
-            const R mj = (R)S.m[j], rhoj = (R)S.rho[j];
+            R mj, rhoj, uj[3] = {0, 0, 0};
+            if constexpr (sizeof(R) == 4) {   // the FP32 copies: the same values, half the bytes
+                mj = S.m32[j];
+                rhoj = S.rho32[j];
+                for (int a = 0; a < D; ++a) uj[a] = S.u32[a][j];
+            } else {
+                mj = S.m[j];
+                rhoj = S.rho[j];
+                for (int a = 0; a < D; ++a) uj[a] = u.c[a][j];
+            }
             R uij[3] = {0, 0, 0};
-            for (int a = 0; a < D; ++a) uij[a] = ui[a] - (R)u.c[a][j];
+            for (int a = 0; a < D; ++a) uij[a] = ui[a] - uj[a];
             const R inv_den = R(1) / (r2 + eps);
             const R cv = mj * nu4 / (rhoi + rhoj) * F * inv_den;
             for (int a = 0; a < D; ++a) fv[a] += cv * uij[a];
@@ -861,9 +870,9 @@ struct Predictor {
             if (j < nf) {
                 const R inv_rhoj = R(1) / rhoj;
                 for (int b = 0; b < D; ++b) {
-                    const R ujb = (R)u.c[b][j];
-                    sgj += ((R)ut.c[b][j] - ujb) * gw[b];
-                    uj_over[b] = ujb * inv_rhoj;
+                    const R utjb = sizeof(R) == 4 ? (R)S.ut32[b][j] : (R)ut.c[b][j];
+                    sgj += (utjb - uj[b]) * gw[b];
+                    uj_over[b] = uj[b] * inv_rhoj;
                 }
             }
             for (int a = 0; a < D; ++a) fsr[a] += mj * (ui[a] * inv_rhoi * sgi + uj_over[a] * sgj);
@@ -925,6 +934,28 @@ __device__ __forceinline__ int32_t offset_index(int64_t i, int16_t o, int64_t nf
     return (int32_t)j;
 }
 
+// FP32 copies of the fields the mixed-mode pair loops gather (they convert
+// each gathered value to FP32 anyway): which 0, after the r^n wall
+// velocity: u (with the wall ghost values), u~, m, rho; which 1, after the
+// r* wall velocity: u* (with the wall values).
+template <int D>
+struct Shadow {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which) {
+        ROW;
+        if (i >= P.ntot) return;
+        if (which == 0) {
+            for (int a = 0; a < D; ++a) {
+                S.u32[a][i] = (float)S.u[a][i];
+                if (i < P.nf) S.ut32[a][i] = (float)S.ut[a][i];
+            }
+            S.m32[i] = (float)S.m[i];
+            S.rho32[i] = (float)S.rho[i];
+        } else {
+            for (int a = 0; a < D; ++a) S.us32[a][i] = (float)S.us[a][i];
+        }
+    }
+};
+
 // ------------------------------------------------- PPE RHS and coefficients
 // eq. sph-ppe / coeff / coeff1 at r*: RHS_i = sum -m_j/(rho_j dt) u*_ij.gradW,
 // c_ij = 4 m_j / (rho_i (rho_i + rho_j)) (r_ij.gradW) / (r^2 + eta h^2),
@@ -961,9 +992,18 @@ struct RhsCoef {
                 R d[3], r2;
                 pair_diff<D, R>(P.grid, xi, xs, j, d, r2);
                 const R dw = K.dwr(sqrt(r2));
-                const R mj = (R)S.m[j], rhoj = (R)S.rho[j];
+                R mj, rhoj, usj[3] = {0, 0, 0};
+                if constexpr (sizeof(R) == 4) {
+                    mj = S.m32[j];
+                    rhoj = S.rho32[j];
+                    for (int a = 0; a < D; ++a) usj[a] = S.us32[a][j];
+                } else {
+                    mj = S.m[j];
+                    rhoj = S.rho[j];
+                    for (int a = 0; a < D; ++a) usj[a] = us.c[a][j];
+                }
                 R dot = R(0);
-                for (int a = 0; a < D; ++a) dot += (usi[a] - (R)us.c[a][j]) * d[a];
+                for (int a = 0; a < D; ++a) dot += (usi[a] - usj[a]) * d[a];
                 s -= mj / rhoj * inv_dt * dw * dot;
                 const R cij = R(4) * mj / (rhoi * (rhoi + rhoj)) * (dw * r2) / (r2 + eps);
                 const int q = (k - 1) & 3;
@@ -2062,6 +2102,11 @@ void correct(const Target &T) { SISPH_DISPATCH_KDR(T, (launch<Correct<KER, D, R>
 void step_maxima(const Target &T) { SISPH_DISPATCH_D(T, (launch<StepMaxima<D>, K_FLUID>(T))); }
 
 void next_dt(const Target &T) { launch<NextDt, K_ONE>(T); }
+
+void shadow(const Target &T, int which) {
+    if (T.precision != SISPH_MIXED) return;
+    SISPH_DISPATCH_D(T, (launch<Shadow<D>, K_TOT>(T, which)));
+}
 
 void mass_over_rho2(const Target &T) {
     if (T.precision == SISPH_MIXED) launch<MassOverRho2<float>, K_TOT>(T);
