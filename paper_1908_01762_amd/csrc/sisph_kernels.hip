@@ -1490,7 +1490,7 @@ struct Correct {
             R d[3], r2;
             pair_diff<D, R>(P.grid, xi, xs, j, d, r2);
             const R dw = K.dwr(sqrt(r2));
-            const R mj = (R)S.m[j];
+            const R mj = sizeof(R) == 4 ? (R)S.m32[j] : (R)S.m[j];
             const double rhoj = S.rho[j];
             R cf;
             if (symm) cf = -mj * (pi_r + (R)(p[j] / (rhoj * rhoj)));
