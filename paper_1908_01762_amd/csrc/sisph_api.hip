@@ -267,7 +267,6 @@ static Target single_target(sisph_ctx *ctx) {
     T.adaptive = ctx->P.adaptive_dt;
     T.precheck = ctx->P.nf >= kPrecheckRows ? 1 : 0;
     T.solver = ctx->P.solver;
-    T.window = -1;
     T.s = ctx->stream;
     return T;
 }
@@ -585,21 +584,6 @@ extern "C" int32_t sisph_predict(sisph_ctx *ctx) {
     return SISPH_OK;
 }
 
-// After the coefficients of a step: whether the sweeps can stage a window
-// of the iterate in LDS (single mixed cases without walls whose offsets all
-// fit, small enough not to test the stop flag first, and a solve expected
-// to take enough sweeps to repay the one read of the control block).
-static int32_t choose_window(sisph_ctx *ctx) {
-    ctx->T.window = -1;
-    const Params &P = ctx->P;
-    if (!P.compact || P.nf >= kPrecheckRows || P.forced_iters > 0 || ctx->last_iters < 8) return SISPH_OK;
-    const int32_t st = read_ctl(ctx);
-    if (st != SISPH_OK) return st;
-    const Control &C = *ctx->h_ctl;
-    if (!C.wide && C.wmax >= 0 && (int64_t)kBlock + 2 * (int64_t)C.wmax <= kWindowCap) ctx->T.window = C.wmax;
-    return SISPH_OK;
-}
-
 // Launch L performs sweep L unless its case stopped earlier; the decision
 // for L sweeps is taken at the start of launch L, so each chunk of launches
 // ends one beyond the predicted count.  poll() reads the control state and
@@ -644,8 +628,6 @@ extern "C" int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out) {
     hipStream_t s = ctx->stream;
     HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
     seq_ppe_begin(ctx->T);
-    int32_t wst = choose_window(ctx);
-    if (wst != SISPH_OK) return wst;
     const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1;
     const int64_t predicted = P.forced_iters > 0 ? P.forced_iters : std::max(P.min_iter, ctx->last_iters);
     const int before = 0;
@@ -713,8 +695,6 @@ static int32_t step_graphed(sisph_ctx *ctx, sisph_step_stats *out) {
     HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
     HIPCHK(ctx, hipGraphLaunch(ctx->g_pre, s));
     HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
-    int32_t wst = choose_window(ctx);
-    if (wst != SISPH_OK) return wst;
     const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1;
     const int64_t predicted = P.forced_iters > 0 ? P.forced_iters : std::max(P.min_iter, ctx->last_iters);
     auto poll = [&](bool &done) -> int32_t {
@@ -1055,7 +1035,6 @@ static int32_t rebuild_group(sisph_batch *b, Group &g) {
     T.s = b->stream;
     for (auto *c : g.members) T.adaptive |= c->P.adaptive_dt;
     T.precheck = 1;
-    T.window = -1;
     for (int k = 0; k < K_COUNT; ++k) {
         std::vector<int32_t> owner;
         std::vector<int64_t> first(n);

@@ -65,7 +65,6 @@ struct Control {
     double bicg_rho[2], bicg_alpha[2], bicg_omega[2];
     int32_t bicg_brk;
     int32_t wide;                     // a neighbour offset of this step did not fit 16 bits
-    int32_t wmax;                     // largest |offset| of this step (compact mode)
 };
 
 // Per-case device arrays.  Unified particle index: fluid [0, nf) in cell
@@ -154,10 +153,6 @@ struct Target {
     // would read every row), see precheck_for()
     int32_t precheck;
     int32_t solver;                  // SISPH_JACOBI or SISPH_BICGSTAB (single cases)
-    // >= 0: every neighbour of row i lies within i +- window (modulo N_f), so
-    // the sweep stages that window of the iterate in LDS (single compact
-    // cases, set per solve from the step's largest offset); -1: off
-    int32_t window;
     bool batched;
     hipStream_t s;
 };
@@ -199,8 +194,6 @@ void bicg_settle(const Target &T);
 void sweep_only(const Target &T, int launch);
 // Fluid rows from which a single case's sweep tests the stop flag first.
 constexpr int64_t kPrecheckRows = int64_t(1) << 19;
-// LDS entries of the sweep's iterate window (rows of a workgroup + 2 W).
-constexpr int kWindowCap = 8192;
 constexpr int kSweepVariants = 6;
 constexpr int kDefaultVariant = 1;
 void settle_pressure(const Target &T);

@@ -284,7 +284,6 @@ struct ResetControl {
             c->pmax_key = 0ull;
             c->bicg_brk = 0;
             c->wide = 0;
-            c->wmax = 0;
             for (int k = 0; k < 2; ++k) {
                 c->bicg_rho[k] = 1.0;
                 c->bicg_alpha[k] = 1.0;
@@ -971,7 +970,6 @@ struct RhsCoef {
         const int64_t nf = P.nf;
         unsigned long long lam = 0ull;
         bool wide = false;
-        int32_t omax = 0;
         if (i < nf) {
             Kern<KER, D, R> K(P.h);
             const Pos xs = mkpos(S.xs), us = mkpos(S.us);
@@ -1014,13 +1012,8 @@ struct RhsCoef {
                     int64_t o = j - i;
                     if (o > nf / 2) o -= nf;
                     else if (o < -(nf / 2)) o += nf;
-                    if (o >= -32767 && o <= 32767) {
-                        oq = (int16_t)o;
-                        const int32_t ao = o < 0 ? (int32_t)-o : (int32_t)o;
-                        omax = ao > omax ? ao : omax;
-                    } else {
-                        wide = true;
-                    }
+                    if (o >= -32767 && o <= 32767) oq = (int16_t)o;
+                    else wide = true;
                 }
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
@@ -1061,13 +1054,6 @@ struct RhsCoef {
         lam = wave_max_u64(lam);   // non-negative doubles order like their bits
         if ((threadIdx.x & 63) == 0 && lam) max_if_larger(&S.ctl->lambda_bits, lam);
         if (__any(wide) && (threadIdx.x & 63) == 0) atomicOr(&S.ctl->wide, 1);
-        if (P.compact) {
-            for (int off = 32; off > 0; off >>= 1) {
-                const int32_t o2 = __shfl_xor(omax, off, 64);
-                omax = o2 > omax ? o2 : omax;
-            }
-            if ((threadIdx.x & 63) == 0 && omax > 0) atomicMax(&S.ctl->wmax, omax);
-        }
     }
 };
 
@@ -1160,25 +1146,6 @@ __device__ __forceinline__ void issue_gathers(int64_t i, int g0, int npos, const
             const int32_t j = p < npos ? iget(jj[t], q) : (int32_t)i;
             if constexpr (sizeof(R) == 4) pv[t][q] = qc[j];
             else pv[t][q] = pc[j];
-        }
-}
-
-// The same values from the LDS window (index j - base modulo N_f, clamped
-// into the window).
-template <typename R, int NG>
-__device__ __forceinline__ void window_gathers(int64_t i, int g0, int npos, const int4 (&jj)[NG], int64_t nf,
-                                               int64_t wbase, int wlen, const float *win, R (&pv)[NG][4]) {
-#pragma unroll
-    for (int t = 0; t < NG; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int p = (g0 + t) * 4 + q;
-            const int64_t j = p < npos ? (int64_t)iget(jj[t], q) : i;
-            int64_t k = j - wbase;
-            if (k < 0) k += nf;
-            if (k >= nf) k -= nf;
-            k = k < wlen ? k : wlen - 1;
-            pv[t][q] = (R)win[k];
         }
 }
 
@@ -1290,13 +1257,9 @@ __device__ __forceinline__ bool stopped_after(const Params &P, const double *par
     return stop_sh != 0;
 }
 
-// WIN (mixed mode with 16-bit offsets, window = W >= 0): the iterate values
-// of rows r0 - W .. r1 - 1 + W (modulo N_f) are loaded into LDS with the row
-// loads, and the gathers read LDS: one dependent memory round trip fewer.
-template <typename R, int FIRST, bool PRECHECK, bool WIN>
+template <typename R, int FIRST, bool PRECHECK>
 struct Sweep {
-    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int L,
-                                               int W) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int L) {
         Control *ctl = S.ctl;
         // PRECHECK: a finished solve is detected before any other load (one
         // extra round trip per sweep, but a launch beyond the stop costs
@@ -1329,22 +1292,6 @@ struct Sweep {
         const int gmax = P.cap / 4;
         ROW;
         const bool live = i < nf;
-        __shared__ float win[WIN ? kWindowCap : 1];
-        int64_t wbase = 0;
-        int wlen = 0;
-        if constexpr (WIN) {
-            const int64_t r0 = blk * kBlock;
-            const int64_t rows = nf - r0 < kBlock ? nf - r0 : kBlock;
-            const int64_t want = rows + 2 * (int64_t)W;
-            wlen = (int)(want < nf ? want : nf);
-            wbase = r0 - W;
-            if (wbase < 0) wbase += nf;
-            for (int t = threadIdx.x; t < wlen; t += kBlock) {
-                int64_t j = wbase + t;
-                if (j >= nf) j -= nf;
-                win[t] = qc[j];
-            }
-        }
         // one round trip: row values and the first FIRST / 4 coefficient and
         // index groups
         constexpr int NG = FIRST / 4;
@@ -1362,14 +1309,12 @@ struct Sweep {
             pold = pc[i];
         }
         if (stopped < L) return;   // only earlier launches write values below L
-        if constexpr (WIN) __syncthreads();   // the window is in LDS
         double v = 0.0;
         const int npos = c - 1;   // neighbours besides the row itself
         R pv[NG][4];
         if (live) {
             if (offs) resolve_groups<NG>(i, nf, 0, npos, S.nbr, wide_flag != 0, oo, jj);
-            if constexpr (WIN) window_gathers<R, NG>(i, 0, npos, jj, nf, wbase, wlen, win, pv);
-            else issue_gathers<R, NG>(i, 0, npos, jj, pc, qc, pv);
+            issue_gathers<R, NG>(i, 0, npos, jj, pc, qc, pv);
         }
         // (a solve that stopped earlier returned above: its partials are stale)
         if (decides) {
@@ -1384,13 +1329,7 @@ struct Sweep {
                 Off4 ob[kSweepBatchGroups];
                 load_groups<R, kSweepBatchGroups>(i, nf, g0, gmax, S.coef, S.cidx, offs, cb, jb, ob);
                 if (offs) resolve_groups<kSweepBatchGroups>(i, nf, g0, npos, S.nbr, wide_flag != 0, ob, jb);
-                if constexpr (WIN) {
-                    R pb[kSweepBatchGroups][4];
-                    window_gathers<R, kSweepBatchGroups>(i, g0, npos, jb, nf, wbase, wlen, win, pb);
-                    s = sum_gathers<R, kSweepBatchGroups>(g0, npos, cb, pb, s);
-                } else {
-                    s = gather_groups<R, kSweepBatchGroups>(i, g0, npos, cb, jb, pc, qc, s);
-                }
+                s = gather_groups<R, kSweepBatchGroups>(i, g0, npos, cb, jb, pc, qc, s);
             }
             if (D != 0.0 && !f) v = P.omega * (r + (double)s) / D + (1.0 - P.omega) * pold;
         }
@@ -2090,28 +2029,26 @@ void copy_p32(const Target &T) { launch<CopyP32, K_TOT>(T); }
 
 // Sweep variants (numerically identical): first-batch size kSweepFirsts[v % 3],
 // XCD-contiguous workgroup mapping for v < 3, hardware order otherwise.
-template <typename R, bool PRE, bool WIN>
+template <typename R, bool PRE>
 static void sweep_variant(const Target &T, int L, int v) {
     // v = 3 * (hardware workgroup order) + index of FIRST in kSweepFirsts
-    const int W = T.window;
     switch (v) {
-    case 1: launch<Sweep<R, kSweepFirsts[1], PRE, WIN>, K_FLUID, true>(T, L, W); break;
-    case 2: launch<Sweep<R, kSweepFirsts[2], PRE, WIN>, K_FLUID, true>(T, L, W); break;
-    case 3: launch<Sweep<R, kSweepFirsts[0], PRE, WIN>, K_FLUID, false>(T, L, W); break;
-    case 4: launch<Sweep<R, kSweepFirsts[1], PRE, WIN>, K_FLUID, false>(T, L, W); break;
-    case 5: launch<Sweep<R, kSweepFirsts[2], PRE, WIN>, K_FLUID, false>(T, L, W); break;
-    default: launch<Sweep<R, kSweepFirsts[0], PRE, WIN>, K_FLUID, true>(T, L, W); break;
+    case 1: launch<Sweep<R, kSweepFirsts[1], PRE>, K_FLUID, true>(T, L); break;
+    case 2: launch<Sweep<R, kSweepFirsts[2], PRE>, K_FLUID, true>(T, L); break;
+    case 3: launch<Sweep<R, kSweepFirsts[0], PRE>, K_FLUID, false>(T, L); break;
+    case 4: launch<Sweep<R, kSweepFirsts[1], PRE>, K_FLUID, false>(T, L); break;
+    case 5: launch<Sweep<R, kSweepFirsts[2], PRE>, K_FLUID, false>(T, L); break;
+    default: launch<Sweep<R, kSweepFirsts[0], PRE>, K_FLUID, true>(T, L); break;
     }
 }
 
 void sweep_only(const Target &T, int L) {
     if (T.precision == SISPH_MIXED) {
-        if (T.window >= 0 && !T.batched && !T.precheck) sweep_variant<float, false, true>(T, L, T.variant);
-        else if (T.precheck) sweep_variant<float, true, false>(T, L, T.variant);
-        else sweep_variant<float, false, false>(T, L, T.variant);
+        if (T.precheck) sweep_variant<float, true>(T, L, T.variant);
+        else sweep_variant<float, false>(T, L, T.variant);
     } else {
-        if (T.precheck) sweep_variant<double, true, false>(T, L, T.variant);
-        else sweep_variant<double, false, false>(T, L, T.variant);
+        if (T.precheck) sweep_variant<double, true>(T, L, T.variant);
+        else sweep_variant<double, false>(T, L, T.variant);
     }
 }
 
