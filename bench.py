@@ -56,7 +56,7 @@ def make_case(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def sweep_bytes(case, slots: int, index_bytes: int = 4) -> dict:
+def sweep_bytes(case, slots: int, index_bytes: int = 4, wall_pairs: int = 0) -> dict:
     """Algorithmic HBM bytes of one Jacobi sweep over the whole case.
 
     Per fluid row: neighbour count (4 B), RHS and D_ii (8 + 8), free-surface
@@ -64,15 +64,26 @@ def sweep_bytes(case, slots: int, index_bytes: int = 4) -> dict:
     the new iterate (4) and reads neighbours' FP32 iterate once (4), FP64
     reads it once (8).  Per stored pair (self slot excluded): neighbour index
     (4, or 2 as a 16-bit offset) and cached coefficient (4 mixed, 8 FP64).
-    The wall kernel of the dam-break cases is not counted here.
+    Cases with walls run the wall pressure kernel before every sweep, inside
+    the same timed chunks, so its bytes are added: per wall row the count
+    (4), the hydrostatic term (8) and the new wall pressure (8, and its FP32
+    copy 4 in the mixed mode); per wall pair the cached weight and fluid
+    index (8 mixed, 12 FP64).  The fluid iterate it gathers is counted once,
+    with the sweep's.
     """
-    nf = case.n_fluid
+    nf, nw = case.n_fluid, case.n_wall
     pairs = slots - nf
     mixed = case.precision == "mixed"
     row = 4 + 8 + 8 + 4 + 8 + 8 + (4 + 4 if mixed else 8)
     pair = index_bytes + (4 if mixed else 8)
     total = nf * row + pairs * pair
-    return dict(per_row=row, per_pair=pair, pairs=int(pairs), bytes=int(total))
+    wall_row = 4 + 8 + 8 + (4 if mixed else 0)
+    wall_pair = 8 if mixed else 12
+    if nw:
+        total += nw * wall_row + wall_pairs * wall_pair
+    return dict(per_row=row, per_pair=pair, pairs=int(pairs), bytes=int(total),
+                wall_rows=int(nw), wall_pairs=int(wall_pairs) if nw else 0,
+                per_wall_row=wall_row if nw else 0, per_wall_pair=wall_pair if nw else 0)
 
 
 def traffic_from_profiles(kernel_src_sha: str, workload: str):
@@ -255,8 +266,8 @@ def main():
                          "reference for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(sharding one case over several GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -299,16 +310,21 @@ def main():
     iters = sum(s["iters"] for s in stats)
     value = case.n_fluid * iters / elapsed if elapsed > 0 else 0.0
     cnt = ctx.sweep_counters()
-    sb = sweep_bytes(case, ctx.pair_count(1, 0), index_bytes=stats[-1]["index_bytes"] if stats else 4)
+    sb = sweep_bytes(case, ctx.pair_count(1, 0), index_bytes=stats[-1]["index_bytes"] if stats else 4,
+                     wall_pairs=ctx.pair_count(1, 1) if case.n_wall else 0)
     avg_launch_s = cnt["sweep_ms"] / 1e3 / max(cnt["launches"], 1)
     achieved = sb["bytes"] * cnt["effective"] / (cnt["sweep_ms"] / 1e3) / 1e9 if cnt["sweep_ms"] > 0 else 0.0
     traffic = traffic_from_profiles(kernel_sha(), args.workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "Sweep", "avg_launch_us": round(avg_launch_s * 1e6, 3),
+                "kernel": "Sweep+WallPressure" if case.n_wall else "Sweep",
+                "avg_launch_us": round(avg_launch_s * 1e6, 3),
                 "launches": cnt["launches"], "effective_launches": cnt["effective"],
                 "algorithmic_bytes_per_launch": sb["bytes"], "bytes_per_row": sb["per_row"],
                 "bytes_per_pair": sb["per_pair"], "pairs": sb["pairs"]}
+    if case.n_wall:
+        roofline.update(wall_rows=sb["wall_rows"], wall_pairs=sb["wall_pairs"],
+                        bytes_per_wall_row=sb["per_wall_row"], bytes_per_wall_pair=sb["per_wall_pair"])
     line = {
         "metric": METRIC,
         "value": value,
