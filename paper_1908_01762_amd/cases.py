@@ -317,6 +317,36 @@ def dam_break_3d(dx: float = 0.01, lx: float = 1.0, ly: float = 1.0,
         meta=dict(height=lz, g=g, layers=layers))
 
 
+def cloud_2d(n: int = 40, radius: float = 0.3, seed: int = 7,
+             precision: str = "fp64") -> Case:
+    """Degenerate rows in one case: a free-surface disc of the jittered
+    Taylor-Green lattice (Wendland, h = 1.3 dx) in the periodic unit square,
+    plus two isolated particles (no neighbour but themselves, so D_ii = 0)
+    and an isolated pair, each far from everything else.  The isolated
+    particles start at rest and at U = (0.3, -0.2); the pair with opposite
+    velocities."""
+    c = taylor_green(n, kernel="wendland", hdx=1.3, jitter=0.2, seed=seed, precision=precision)
+    dx = c.dx
+    keep = np.linalg.norm(c.x - 0.5, axis=1) < radius
+    extra_x = np.array([[0.04, 0.04], [0.93, 0.1],
+                        [0.08, 0.88], [0.08 + 0.8 * dx, 0.88 + 0.3 * dx]])
+    extra_u = np.array([[0.0, 0.0], [0.3, -0.2], [0.1, 0.0], [-0.1, 0.05]])
+    x = np.ascontiguousarray(np.vstack([c.x[keep], extra_x]))
+    u = np.ascontiguousarray(np.vstack([c.u[keep], extra_u]))
+    N = x.shape[0]
+    return c.replace(name=f"cloud{n}", x=x, u=u, p=np.zeros(N), m=np.full(N, c.m[0]),
+                     n_fluid=N, free_surface=True,
+                     meta=dict(c.meta, isolated=[N - 4, N - 3], pair=[N - 2, N - 1]))
+
+
+def single_particle(precision: str = "fp64") -> Case:
+    """One particle alone in the periodic unit square (quintic, 10 x 10
+    lattice spacing): every neighbour sum is empty."""
+    c = taylor_green(10, precision=precision)
+    return c.replace(name="single", x=np.array([[0.3, 0.6]]), u=np.array([[0.2, -0.1]]),
+                     p=np.zeros(1), m=c.m[:1].copy(), n_fluid=1)
+
+
 def periodic_lattice(n: int, dim: int = 2, kernel: str = "quintic",
                      hdx: float = 1.0, rho0: float = 1.0) -> Case:
     """Unperturbed periodic lattice at rest (used for symmetry pins)."""

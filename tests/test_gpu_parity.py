@@ -362,6 +362,59 @@ def test_mixed_precision_single_step(name):
     ctx.close()
 
 
+@pytest.mark.parametrize("name", ["cloud", "single"])
+def test_degenerate_rows_fp64(name):
+    """Empty neighbour sums: isolated particles (count 1, D_ii = 0), an
+    isolated pair and a free-surface disc whose 460 rows leave a ragged last
+    workgroup; and a case of one particle.  Neighbour sets bit-exact, three
+    steps against the oracle, zero pressure on the isolated rows."""
+    sisph = _gpu()
+    case = cases.cloud_2d() if name == "cloud" else cases.single_particle()
+    iso = case.meta.get("isolated", [0])
+    say("case", name, case.n_fluid)
+    ctx = sisph.Context(case)
+    ctx.bin()
+    off, ids = ctx.neighbors(0, 0)
+    roff, rids = oracle.neighbors(case)
+    assert _same_sets(off, ids, roff, rids)
+    ctx.close()
+    ref = oracle.Sim(case)
+    ctx = sisph.Context(case)
+    for k in range(3):
+        o = ref.step()
+        g = ctx.step(1)[0]
+        say(f"  step {k}: iters gpu {g['iters']} oracle {o['iters']}")
+        assert g["iters"] == o["iters"]
+        s = ctx.read_state()
+        assert np.all(s["p"][iso] == 0.0)
+        for f in ("x", "u", "ut", "p"):
+            e = rel(s[f], getattr(ref, f))
+            say(f"    {f:3s} rel L2 {e:.3e}")
+            assert e < FP64_TOL, f
+    ctx.close()
+
+
+def test_degenerate_rows_mixed():
+    """The cloud in the mixed mode: zero pressure on the isolated rows and
+    the fields within the FP32 bounds, the oracle run on the GPU's sweep
+    count."""
+    sisph = _gpu()
+    case = cases.cloud_2d(precision="mixed")
+    iso = case.meta["isolated"]
+    ctx = sisph.Context(case)
+    g = ctx.step(1)[0]
+    ref = oracle.Sim(case, forced_iters=g["iters"])
+    ref.step()
+    s = ctx.read_state()
+    assert np.all(s["p"][iso] == 0.0)
+    errs = {f: rel(s[f], getattr(ref, f)) for f in ("p", "u")}
+    errs["displacement"] = rel(s["x"] - case.x, ref.x - case.x)
+    for k, e in errs.items():
+        say(f"  mixed cloud {k:12s} rel L2 {e:.3e}")
+    assert errs["u"] < 1e-4 and errs["displacement"] < 1e-4 and errs["p"] < 1e-3
+    ctx.close()
+
+
 def test_error_paths():
     sisph = _gpu()
     case = cases.taylor_green(16)

@@ -515,6 +515,37 @@ def test_fixed_point_constant_pressure():
     assert np.max(np.abs(s.p - 3.25)) < 1e-12
 
 
+@pytest.mark.parametrize("which", ["cloud", "single"])
+def test_isolated_particles_move_ballistically(which):
+    """Empty neighbour sums (sections 2-3): a particle with no neighbour but
+    itself has D_ii = 0, so its pressure is 0, and no viscous, pressure,
+    stress or shifting force acts on it: after k steps x = x0 + k dt u0
+    (periodic) with u and the transport velocity still u0.  An isolated
+    pair only exchanges equal and opposite forces (both rows sit on the free
+    surface, so p = 0 there): its total momentum stays fixed."""
+    c = cases.cloud_2d() if which == "cloud" else cases.single_particle()
+    iso = c.meta.get("isolated", [0])
+    s = oracle.Sim(c)
+    steps = 3
+    for _ in range(steps):
+        out = s.step(capture=True)
+        assert np.all(out["diag"][iso] == 0.0)
+        assert np.all(s.p[iso] == 0.0)
+    want = (c.x[iso] + steps * c.dt * c.u[iso]) % 1.0
+    assert np.allclose(s.x[iso], want, rtol=0.0, atol=1e-14)
+    assert np.array_equal(s.u[iso], c.u[iso]) and np.array_equal(s.ut[iso], c.u[iso])
+    if which == "cloud":
+        pr = c.meta["pair"]
+        assert np.all(out["fs"][pr] == 1)
+        mom0 = c.u[pr].sum(axis=0)
+        assert np.allclose(s.u[pr].sum(axis=0), mom0, rtol=0.0, atol=1e-14)
+        assert np.allclose(s.ut[pr].sum(axis=0), mom0, rtol=0.0, atol=1e-14)
+        # and the pair did interact
+        assert np.abs(s.u[pr] - c.u[pr]).max() > 1e-3
+    else:
+        assert out["iters"] == c.min_iter
+
+
 def test_iteration_limits():
     """min 2 iterations (section 3.1) and the max_iterations cap."""
     c = cases.taylor_green(16, jitter=0.1)
