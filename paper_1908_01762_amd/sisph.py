@@ -70,6 +70,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_1908_01762_amd/build.py")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded (device memory and streams come from torch), not to a second
+        # copy of it in the same process
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         L.sisph_workspace_bytes.restype = C.c_size_t
         L.sisph_workspace_bytes.argtypes = [C.POINTER(CaseDesc)]
