@@ -157,16 +157,53 @@ struct Kern {
     }
 };
 
-// Pair difference r_i - r_j (FP64, minimum image) converted to R.
+// Pair difference r_i - r_j (FP64, minimum image) converted to R, from the
+// gathered position of j.
 template <int D, typename R>
-__device__ __forceinline__ void pair_diff(const Grid &g, const double xi[3], const Pos &x, int64_t j,
-                                          R d[3], R &r2) {
+__device__ __forceinline__ void pair_diff_v(const Grid &g, const double xi[3], const double xj[3], R d[3],
+                                            R &r2) {
     r2 = R(0);
     for (int k = 0; k < 3; ++k) d[k] = R(0);
     for (int k = 0; k < D; ++k) {
-        double v = min_image(xi[k] - x.c[k][j], g, k);
+        double v = min_image(xi[k] - xj[k], g, k);
         d[k] = (R)v;
         r2 += d[k] * d[k];
+    }
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void pair_diff(const Grid &g, const double xi[3], const Pos &x, int64_t j,
+                                          R d[3], R &r2) {
+    double xj[3] = {0, 0, 0};
+    for (int k = 0; k < D; ++k) xj[k] = x.c[k][j];
+    pair_diff_v<D, R>(g, xi, xj, d, r2);
+}
+
+// Pair loops take the neighbour list kPairBatch slots at a time: the
+// batch's indices, then every field its pair terms read, are loaded before
+// any term is formed, so a wavefront keeps kPairBatch x fields gathers in
+// flight instead of a chain of dependent round trips per pair.  Slots at or
+// past the row's count load the fallback row (a valid index) and add
+// nothing; the terms are added in slot order, as one slot at a time would.
+constexpr int kPairBatch = 4;
+
+// Indices of slots k0 .. k0+kPairBatch-1 of a slot-major list [cap][rows].
+__device__ __forceinline__ void batch_slots(const int32_t *list, int64_t rows, int64_t row, int k0, int c,
+                                            int cap, int64_t fallback, int64_t (&jb)[kPairBatch]) {
+#pragma unroll
+    for (int t = 0; t < kPairBatch; ++t) {
+        const int k = k0 + t < cap ? k0 + t : cap - 1;
+        const int32_t j = list[(int64_t)k * rows + row];
+        jb[t] = k0 + t < c ? (int64_t)j : fallback;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void batch_pos(const Pos &x, const int64_t (&jb)[kPairBatch], double (&xj)[kPairBatch][3]) {
+#pragma unroll
+    for (int t = 0; t < kPairBatch; ++t) {
+        for (int k = 0; k < 3; ++k) xj[t][k] = 0.0;
+        for (int k = 0; k < D; ++k) xj[t][k] = x.c[k][jb[t]];
     }
 }
 
@@ -751,11 +788,20 @@ struct Density {
         for (int k = 0; k < D; ++k) xi[k] = x.c[k][i];
         const int c = S.cnt[i];
         R s = (R)S.m[i] * K.w(R(0));
-        for (int k = 1; k < c; ++k) {
-            const int64_t j = S.nbr[(int64_t)k * P.nf + i];
-            R d[3], r2;
-            pair_diff<D, R>(P.grid, xi, x, j, d, r2);
-            s += (R)S.m[j] * K.w(sqrt(r2));
+        for (int k0 = 1; k0 < c; k0 += kPairBatch) {
+            int64_t jb[kPairBatch];
+            double xj[kPairBatch][3], mb[kPairBatch];
+            batch_slots(S.nbr, P.nf, i, k0, c, P.cap, i, jb);
+            batch_pos<D>(x, jb, xj);
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) mb[t] = S.m[jb[t]];
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) {
+                if (k0 + t >= c) break;
+                R d[3], r2;
+                pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
+                s += (R)mb[t] * K.w(sqrt(r2));
+            }
         }
         const double rh = (double)s;
         S.rho[i] = rh;
@@ -784,13 +830,23 @@ struct WallVelocity {
         for (int k = 0; k < D; ++k) xi[k] = x.c[k][iw];
         R num[3] = {0, 0, 0}, den = R(0);
         const int c = S.wcnt[w];
-        for (int k = 0; k < c; ++k) {
-            const int64_t f = S.wnbr[(int64_t)k * P.nw + w];
-            R d[3], r2;
-            pair_diff<D, R>(P.grid, xi, x, f, d, r2);
-            const R W = K.w(sqrt(r2));
-            for (int a = 0; a < D; ++a) num[a] += (R)uf[a][f] * W;
-            den += W;
+        for (int k0 = 0; k0 < c; k0 += kPairBatch) {
+            int64_t fb[kPairBatch];
+            double xj[kPairBatch][3], ub[kPairBatch][3];
+            batch_slots(S.wnbr, P.nw, w, k0, c, P.cap, iw, fb);
+            batch_pos<D>(x, fb, xj);
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t)
+                for (int a = 0; a < D; ++a) ub[t][a] = uf[a][fb[t]];
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) {
+                if (k0 + t >= c) break;
+                R d[3], r2;
+                pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
+                const R W = K.w(sqrt(r2));
+                for (int a = 0; a < D; ++a) num[a] += (R)ub[t][a] * W;
+                den += W;
+            }
         }
         double v[3] = {0, 0, 0}, vn = 0.0;
         for (int a = 0; a < D; ++a) {
@@ -832,50 +888,71 @@ struct Predictor {
         const R eps = (R)P.eps_h, nu4 = (R)(4.0 * P.nu), avc = (R)(P.alpha * P.h * P.c_ref);
         R fv[3] = {0, 0, 0}, fa[3] = {0, 0, 0}, fsr[3] = {0, 0, 0};
         const int c = S.cnt[i];
-        for (int k = 1; k < c; ++k) {
-            const int64_t j = S.nbr[(int64_t)k * nf + i];
-            R d[3], r2;
-            pair_diff<D, R>(P.grid, xi, x, j, d, r2);
-            const R r = sqrt(r2);
-            const R dw = K.dwr(r);
-            R gw[3];
-            for (int a = 0; a < 3; ++a) gw[a] = dw * d[a];
-            const R F = dw * r2;
-            R mj, rhoj, uj[3] = {0, 0, 0};
-            if constexpr (sizeof(R) == 4) {   // the FP32 copies: the same values, half the bytes
-                mj = S.m32[j];
-                rhoj = S.rho32[j];
-                for (int a = 0; a < D; ++a) uj[a] = S.u32[a][j];
-            } else {
-                mj = S.m[j];
-                rhoj = S.rho[j];
-                for (int a = 0; a < D; ++a) uj[a] = u.c[a][j];
-            }
-            R uij[3] = {0, 0, 0};
-            for (int a = 0; a < D; ++a) uij[a] = ui[a] - uj[a];
-            const R inv_den = R(1) / (r2 + eps);
-            const R cv = mj * nu4 / (rhoi + rhoj) * F * inv_den;
-            for (int a = 0; a < D; ++a) fv[a] += cv * uij[a];
-            R vr = R(0);
-            for (int a = 0; a < D; ++a) vr += uij[a] * d[a];
-            if (vr < R(0)) {
-                const R mu = vr * inv_den;
-                const R Pi = -avc * mu / (R(0.5) * (rhoi + rhoj));
-                for (int a = 0; a < D; ++a) fa[a] -= mj * Pi * gw[a];
-            }
-            // artificial stress: sum_b (A_i/rho_i^2 + A_j/rho_j^2)_ab gw_b
-            R sgi = R(0);
-            for (int b = 0; b < D; ++b) sgi += si[b] * gw[b];
-            R sgj = R(0), uj_over[3] = {0, 0, 0};
-            if (j < nf) {
-                const R inv_rhoj = R(1) / rhoj;
-                for (int b = 0; b < D; ++b) {
-                    const R utjb = sizeof(R) == 4 ? (R)S.ut32[b][j] : (R)ut.c[b][j];
-                    sgj += (utjb - uj[b]) * gw[b];
-                    uj_over[b] = uj[b] * inv_rhoj;
+        for (int k0 = 1; k0 < c; k0 += kPairBatch) {
+            int64_t jb[kPairBatch];
+            double xj[kPairBatch][3];
+            R mb[kPairBatch], rhob[kPairBatch], ub[kPairBatch][3], utb[kPairBatch][3];
+            batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
+            batch_pos<D>(x, jb, xj);
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) {
+                const int64_t j = jb[t], jf = j < nf ? j : i;   // u~ is held for fluid particles only
+                for (int a = 0; a < 3; ++a) ub[t][a] = utb[t][a] = R(0);
+                if constexpr (sizeof(R) == 4) {   // the FP32 copies: the same values, half the bytes
+                    mb[t] = S.m32[j];
+                    rhob[t] = S.rho32[j];
+                    for (int a = 0; a < D; ++a) {
+                        ub[t][a] = S.u32[a][j];
+                        utb[t][a] = S.ut32[a][jf];
+                    }
+                } else {
+                    mb[t] = S.m[j];
+                    rhob[t] = S.rho[j];
+                    for (int a = 0; a < D; ++a) {
+                        ub[t][a] = u.c[a][j];
+                        utb[t][a] = ut.c[a][jf];
+                    }
                 }
             }
-            for (int a = 0; a < D; ++a) fsr[a] += mj * (ui[a] * inv_rhoi * sgi + uj_over[a] * sgj);
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) {
+                if (k0 + t >= c) break;
+                const int64_t j = jb[t];
+                R d[3], r2;
+                pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
+                const R r = sqrt(r2);
+                const R dw = K.dwr(r);
+                R gw[3];
+                for (int a = 0; a < 3; ++a) gw[a] = dw * d[a];
+                const R F = dw * r2;
+                const R mj = mb[t], rhoj = rhob[t];
+                R uj[3] = {0, 0, 0};
+                for (int a = 0; a < D; ++a) uj[a] = ub[t][a];
+                R uij[3] = {0, 0, 0};
+                for (int a = 0; a < D; ++a) uij[a] = ui[a] - uj[a];
+                const R inv_den = R(1) / (r2 + eps);
+                const R cv = mj * nu4 / (rhoi + rhoj) * F * inv_den;
+                for (int a = 0; a < D; ++a) fv[a] += cv * uij[a];
+                R vr = R(0);
+                for (int a = 0; a < D; ++a) vr += uij[a] * d[a];
+                if (vr < R(0)) {
+                    const R mu = vr * inv_den;
+                    const R Pi = -avc * mu / (R(0.5) * (rhoi + rhoj));
+                    for (int a = 0; a < D; ++a) fa[a] -= mj * Pi * gw[a];
+                }
+                // artificial stress: sum_b (A_i/rho_i^2 + A_j/rho_j^2)_ab gw_b
+                R sgi = R(0);
+                for (int b = 0; b < D; ++b) sgi += si[b] * gw[b];
+                R sgj = R(0), uj_over[3] = {0, 0, 0};
+                if (j < nf) {
+                    const R inv_rhoj = R(1) / rhoj;
+                    for (int b = 0; b < D; ++b) {
+                        sgj += (utb[t][b] - uj[b]) * gw[b];
+                        uj_over[b] = uj[b] * inv_rhoj;
+                    }
+                }
+                for (int a = 0; a < D; ++a) fsr[a] += mj * (ui[a] * inv_rhoi * sgi + uj_over[a] * sgj);
+            }
         }
         const double dt = S.ctl->dt;
         for (int a = 0; a < D; ++a) {
@@ -982,69 +1059,71 @@ struct RhsCoef {
             const R rhoi = (R)S.rho[i], eps = (R)P.eps_h, inv_dt = (R)(1.0 / S.ctl->dt);
             R s = R(0), Dg = R(0);
             const int c = S.cnt[i];
-            // one group of four coefficients (and indices or offsets) is
-            // buffered in registers and written with one store each
-            R c4[4] = {R(0), R(0), R(0), R(0)};
-            int32_t j4[4] = {(int32_t)i, (int32_t)i, (int32_t)i, (int32_t)i};
-            int16_t o4[4] = {0, 0, 0, 0};
-            for (int k = 1; k < c; ++k) {
-                const int64_t j = S.nbr[(int64_t)k * nf + i];
-                R d[3], r2;
-                pair_diff<D, R>(P.grid, xi, xs, j, d, r2);
-                const R dw = K.dwr(sqrt(r2));
-                R mj, rhoj, usj[3] = {0, 0, 0};
-                if constexpr (sizeof(R) == 4) {
-                    mj = S.m32[j];
-                    rhoj = S.rho32[j];
-                    for (int a = 0; a < D; ++a) usj[a] = S.us32[a][j];
-                } else {
-                    mj = S.m[j];
-                    rhoj = S.rho[j];
-                    for (int a = 0; a < D; ++a) usj[a] = us.c[a][j];
-                }
-                R dot = R(0);
-                for (int a = 0; a < D; ++a) dot += (usi[a] - usj[a]) * d[a];
-                s -= mj / rhoj * inv_dt * dw * dot;
-                const R cij = R(4) * mj / (rhoi * (rhoi + rhoj)) * (dw * r2) / (r2 + eps);
-                const int q = (k - 1) & 3;
-                int16_t oq = 0;
-                if (P.compact) {
-                    int64_t o = j - i;
-                    if (o > nf / 2) o -= nf;
-                    else if (o < -(nf / 2)) o += nf;
-                    if (o >= -32767 && o <= 32767) oq = (int16_t)o;
-                    else wide = true;
-                }
+            // a batch of kPairBatch = 4 slots is one group of coefficients
+            // (and indices or offsets), written with one store each
+            static_assert(kPairBatch == 4, "one coefficient group per batch");
+            for (int k0 = 1; k0 < c; k0 += kPairBatch) {
+                int64_t jb[kPairBatch];
+                double xj[kPairBatch][3];
+                R mb[kPairBatch], rhob[kPairBatch], usb[kPairBatch][3];
+                batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
+                batch_pos<D>(xs, jb, xj);
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if (t == q) {
-                        c4[t] = cij;
-                        j4[t] = (int32_t)j;
-                        o4[t] = oq;
-                    }
-                if (q == 3 || k == c - 1) {
-                    const int64_t at = group_at((k - 1) >> 2, nf, i);
-                    typename Vec4<R>::T cv;
-                    cv.x = c4[0];
-                    cv.y = c4[1];
-                    cv.z = c4[2];
-                    cv.w = c4[3];
-                    ((typename Vec4<R>::T *)S.coef)[at] = cv;
-                    if (P.compact) {
-                        Off4 ov;
-                        for (int t = 0; t < 4; ++t) ov.o[t] = o4[t];
-                        ((Off4 *)S.cidx)[at] = ov;
+                for (int t = 0; t < kPairBatch; ++t) {
+                    const int64_t j = jb[t];
+                    for (int a = 0; a < 3; ++a) usb[t][a] = R(0);
+                    if constexpr (sizeof(R) == 4) {
+                        mb[t] = S.m32[j];
+                        rhob[t] = S.rho32[j];
+                        for (int a = 0; a < D; ++a) usb[t][a] = S.us32[a][j];
                     } else {
-                        ((int4 *)S.cidx)[at] = make_int4(j4[0], j4[1], j4[2], j4[3]);
-                    }
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        c4[t] = R(0);
-                        j4[t] = (int32_t)i;
-                        o4[t] = 0;
+                        mb[t] = S.m[j];
+                        rhob[t] = S.rho[j];
+                        for (int a = 0; a < D; ++a) usb[t][a] = us.c[a][j];
                     }
                 }
-                Dg += cij;
+                R c4[4] = {R(0), R(0), R(0), R(0)};
+                int32_t j4[4] = {(int32_t)i, (int32_t)i, (int32_t)i, (int32_t)i};
+                int16_t o4[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int t = 0; t < kPairBatch; ++t) {
+                    if (k0 + t >= c) break;
+                    const int64_t j = jb[t];
+                    R d[3], r2;
+                    pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
+                    const R dw = K.dwr(sqrt(r2));
+                    const R mj = mb[t], rhoj = rhob[t];
+                    R dot = R(0);
+                    for (int a = 0; a < D; ++a) dot += (usi[a] - usb[t][a]) * d[a];
+                    s -= mj / rhoj * inv_dt * dw * dot;
+                    const R cij = R(4) * mj / (rhoi * (rhoi + rhoj)) * (dw * r2) / (r2 + eps);
+                    int16_t oq = 0;
+                    if (P.compact) {
+                        int64_t o = j - i;
+                        if (o > nf / 2) o -= nf;
+                        else if (o < -(nf / 2)) o += nf;
+                        if (o >= -32767 && o <= 32767) oq = (int16_t)o;
+                        else wide = true;
+                    }
+                    c4[t] = cij;
+                    j4[t] = (int32_t)j;
+                    o4[t] = oq;
+                    Dg += cij;
+                }
+                const int64_t at = group_at((k0 - 1) >> 2, nf, i);
+                typename Vec4<R>::T cv;
+                cv.x = c4[0];
+                cv.y = c4[1];
+                cv.z = c4[2];
+                cv.w = c4[3];
+                ((typename Vec4<R>::T *)S.coef)[at] = cv;
+                if (P.compact) {
+                    Off4 ov;
+                    for (int t = 0; t < 4; ++t) ov.o[t] = o4[t];
+                    ((Off4 *)S.cidx)[at] = ov;
+                } else {
+                    ((int4 *)S.cidx)[at] = make_int4(j4[0], j4[1], j4[2], j4[3]);
+                }
             }
             const double rr = (double)s, dd = (double)Dg;
             S.rhs[i] = rr;
@@ -1485,18 +1564,32 @@ struct Correct {
         R f[3] = {0, 0, 0};
         const int c = S.cnt[i];
         const bool symm = P.pgrad == SISPH_SYMM;
-        for (int k = 1; k < c; ++k) {
-            const int64_t j = S.nbr[(int64_t)k * nf + i];
-            R d[3], r2;
-            pair_diff<D, R>(P.grid, xi, xs, j, d, r2);
-            const R dw = K.dwr(sqrt(r2));
-            const R mj = sizeof(R) == 4 ? (R)S.m32[j] : (R)S.m[j];
-            const double rhoj = S.rho[j];
-            R cf;
-            if (symm) cf = -mj * (pi_r + (R)(p[j] / (rhoj * rhoj)));
-            else cf = -mj / (rhoi * (R)rhoj) * (R)(p[j] - pi);
-            cf *= dw;
-            for (int a = 0; a < D; ++a) f[a] += cf * d[a];
+        for (int k0 = 1; k0 < c; k0 += kPairBatch) {
+            int64_t jb[kPairBatch];
+            double xj[kPairBatch][3], rhob[kPairBatch], pb[kPairBatch];
+            R mb[kPairBatch];
+            batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
+            batch_pos<D>(xs, jb, xj);
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) {
+                mb[t] = sizeof(R) == 4 ? (R)S.m32[jb[t]] : (R)S.m[jb[t]];
+                rhob[t] = S.rho[jb[t]];
+                pb[t] = p[jb[t]];
+            }
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) {
+                if (k0 + t >= c) break;
+                R d[3], r2;
+                pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
+                const R dw = K.dwr(sqrt(r2));
+                const R mj = mb[t];
+                const double rhoj = rhob[t];
+                R cf;
+                if (symm) cf = -mj * (pi_r + (R)(pb[t] / (rhoj * rhoj)));
+                else cf = -mj / (rhoi * (R)rhoj) * (R)(pb[t] - pi);
+                cf *= dw;
+                for (int a = 0; a < D; ++a) f[a] += cf * d[a];
+            }
         }
         const double dt = S.ctl->dt;
         for (int a = 0; a < D; ++a) {
@@ -1592,13 +1685,23 @@ struct Gtvf {
         }
         R s[3] = {0, 0, 0};
         const int c = S.cnt[i];
-        for (int kk = 1; kk < c; ++kk) {
-            const int64_t j = S.nbr[(int64_t)kk * nf + i];
-            R d[3], r2;
-            pair_diff<D, R>(P.grid, xi, xsrc, j, d, r2);
-            const R dw = K.dwr(sqrt(r2));
-            const R cf = ((const R *)S.mr2)[j] * dw;
-            for (int a = 0; a < D; ++a) s[a] += cf * d[a];
+        for (int k0 = 1; k0 < c; k0 += kPairBatch) {
+            int64_t jb[kPairBatch];
+            double xj[kPairBatch][3];
+            R mr[kPairBatch];
+            batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
+            batch_pos<D>(xsrc, jb, xj);
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) mr[t] = ((const R *)S.mr2)[jb[t]];
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) {
+                if (k0 + t >= c) break;
+                R d[3], r2;
+                pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
+                const R dw = K.dwr(sqrt(r2));
+                const R cf = mr[t] * dw;
+                for (int a = 0; a < D; ++a) s[a] += cf * d[a];
+            }
         }
         const double dtau = S.ctl->dt / (double)P.gtvf_K;
         for (int a = 0; a < D; ++a) {
