@@ -1484,6 +1484,26 @@ struct WallCoef {
 // During the solve it writes the wall slots of iterate L (which sweep L
 // reads); with final set, the wall slots of p[0] after the final pressure
 // has been settled there.
+// Cached wall weights and fluid indices of slots k0 .. k0+kPairBatch-1 of
+// wall row w (slot clamped into the storage).
+template <typename R>
+__device__ __forceinline__ void wall_words(const State &S, int64_t nw, int64_t w, int k0, int cap,
+                                           R (&cb)[kPairBatch], int32_t (&jr)[kPairBatch]) {
+#pragma unroll
+    for (int t = 0; t < kPairBatch; ++t) {
+        const int k = k0 + t < cap ? k0 + t : cap - 1;
+        const int64_t at = (int64_t)k * nw + w;
+        if constexpr (sizeof(R) == 4) {
+            const PairF e = ((const PairF *)S.wcoef)[at];
+            cb[t] = e.c;
+            jr[t] = e.j;
+        } else {
+            cb[t] = ((const double *)S.wcoef)[at];
+            jr[t] = S.wnbr[at];
+        }
+    }
+}
+
 template <typename R>
 struct WallPressure {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int L, int final) {
@@ -1497,15 +1517,34 @@ struct WallPressure {
         float *qc = S.p32 + par * P.ntot;
         const int64_t iw = P.nf + w, nw = P.nw;
         const int c = S.wcnt[w];
+        // kPairBatch slots at a time: weights and indices, then the gathered
+        // iterate values, then the terms in slot order; the first batch's
+        // words are loaded with the count, without waiting for it.
+        // The first batch runs whatever the count (its gathers read the
+        // row's own slot and add nothing when c = 0), and the terms are
+        // selected rather than branched over, so no load waits behind a
+        // branch.  sp + 0 leaves sp unchanged (sp starts at +0 and never
+        // becomes -0), so the sum is the plain slot-order sum.
         R sp = R(0);
-        for (int k = 0; k < c; ++k) {
-            const int64_t at = (int64_t)k * nw + w;
-            if constexpr (sizeof(R) == 4) {
-                const PairF e = ((const PairF *)S.wcoef)[at];
-                sp += e.c * qc[e.j];
-            } else {
-                sp += ((const double *)S.wcoef)[at] * pc[S.wnbr[at]];
+        R cb[kPairBatch];
+        int32_t jr[kPairBatch];
+        wall_words<R>(S, nw, w, 0, P.cap, cb, jr);
+        for (int k0 = 0;;) {
+            R q[kPairBatch];
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) {
+                const int64_t j = k0 + t < c ? (int64_t)jr[t] : iw;   // iw: a valid index, term not added
+                if constexpr (sizeof(R) == 4) q[t] = qc[j];
+                else q[t] = pc[j];
             }
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) {
+                const R acc = fma(cb[t], q[t], sp);
+                sp = k0 + t < c ? acc : sp;
+            }
+            k0 += kPairBatch;
+            if (k0 >= c) break;
+            wall_words<R>(S, nw, w, k0, P.cap, cb, jr);
         }
         double pw = (double)sp + S.wh[w];
         if (P.free_surface && pw < 0.0) pw = 0.0;
