@@ -21,6 +21,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -56,7 +58,7 @@ def make_case(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def sweep_bytes(case, slots: int, index_bytes: int = 4, wall_pairs: int = 0) -> dict:
+def sweep_bytes(case, slots: int, index_bytes: int = 4, wall_pairs: int = 0, wall_rows: int = 0) -> dict:
     """Algorithmic HBM bytes of one Jacobi sweep over the whole case.
 
     Per fluid row: neighbour count (4 B), RHS and D_ii (8 + 8), free-surface
@@ -65,13 +67,14 @@ def sweep_bytes(case, slots: int, index_bytes: int = 4, wall_pairs: int = 0) -> 
     reads it once (8).  Per stored pair (self slot excluded): neighbour index
     (4, or 2 as a 16-bit offset) and cached coefficient (4 mixed, 8 FP64).
     Cases with walls run the wall pressure kernel before every sweep, inside
-    the same timed chunks, so its bytes are added: per wall row the count
-    (4), the hydrostatic term (8) and the new wall pressure (8, and its FP32
-    copy 4 in the mixed mode); per wall pair the cached weight and fluid
+    the same timed chunks, so its bytes are added: per wall row with fluid
+    neighbours (no sweep reads the others, so the kernel skips them) the
+    count (4), the hydrostatic term (8) and the new wall pressure (8, and its
+    FP32 copy 4 in the mixed mode); per wall pair the cached weight and fluid
     index (8 mixed, 12 FP64).  The fluid iterate it gathers is counted once,
     with the sweep's.
     """
-    nf, nw = case.n_fluid, case.n_wall
+    nf, nw = case.n_fluid, wall_rows
     pairs = slots - nf
     mixed = case.precision == "mixed"
     row = 4 + 8 + 8 + 4 + 8 + 8 + (4 + 4 if mixed else 8)
@@ -310,8 +313,9 @@ def main():
     iters = sum(s["iters"] for s in stats)
     value = case.n_fluid * iters / elapsed if elapsed > 0 else 0.0
     cnt = ctx.sweep_counters()
+    wall_rows = int(np.count_nonzero(np.diff(ctx.neighbors(1, 1)[0]))) if case.n_wall else 0
     sb = sweep_bytes(case, ctx.pair_count(1, 0), index_bytes=stats[-1]["index_bytes"] if stats else 4,
-                     wall_pairs=ctx.pair_count(1, 1) if case.n_wall else 0)
+                     wall_pairs=ctx.pair_count(1, 1) if case.n_wall else 0, wall_rows=wall_rows)
     avg_launch_s = cnt["sweep_ms"] / 1e3 / max(cnt["launches"], 1)
     achieved = sb["bytes"] * cnt["effective"] / (cnt["sweep_ms"] / 1e3) / 1e9 if cnt["sweep_ms"] > 0 else 0.0
     traffic = traffic_from_profiles(kernel_sha(), args.workload)

@@ -233,6 +233,8 @@ static void carve(const Params &P, Carver &c, State &S) {
     S.cidx = c.take<int32_t>((int64_t)P.cap * nf);
     S.wcoef = c.take<char>((int64_t)8 * P.cap * nw);
     S.wh = c.take<double>(nw);
+    S.wflag = c.take<int32_t>(kind_blocks(P, K_WALL) + 1);
+    S.wblk = c.take<int32_t>(kind_blocks(P, K_WALL) + 1);
     S.partial = c.take<double>(4 * kind_blocks(P, K_FLUID));
     S.tmp = c.take<double>(16 * nmax);
     S.bx = S.br = S.brh = S.bp = S.bv = S.bs = S.bt = S.bf = S.bh = S.bpart = nullptr;

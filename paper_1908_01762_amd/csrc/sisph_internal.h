@@ -104,6 +104,8 @@ struct State {
     void *cidx;             // their indices (int32) or 16-bit offsets (compact), same layout
     void *wcoef;            // cached wall weights W_wf / sum W: (f, FP32) words or FP64 [cap][nw]
     double *wh;             // wall hydrostatic term                 [nw]
+    int32_t *wflag;         // wall workgroup has a row with fluid neighbours at r*   [nwb]
+    int32_t *wblk;          // [0] = count, then those workgroups in order            [1 + nwb]
     double *partial;        // per-workgroup partial sums of two sweeps [2][2][nblk]
     double *tmp;            // reorder scratch [16][max(nf, nw)]
     // BiCGStab (solver only): x, r, r^, p, v, s, t, scaled RHS f, wall

@@ -1486,6 +1486,44 @@ struct WallCoef {
 // has been settled there.
 // Cached wall weights and fluid indices of slots k0 .. k0+kPairBatch-1 of
 // wall row w (slot clamped into the storage).
+// Wall workgroups the sweeps visit.  A wall row without fluid neighbours
+// at r* is in no fluid row's list either (the neighbour relation is
+// symmetric), so no sweep reads its pressure: the per-sweep wall pass skips
+// workgroups made only of such rows (the final pass after the solve still
+// covers every wall row).  WallFlags marks each wall workgroup; WallBlocks
+// (one workgroup per case) lists the marked ones in order.
+struct WallFlags {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        ROW;
+        const int active = (i < P.nw && S.wcnt[i] > 0) ? 1 : 0;
+        const int any = __syncthreads_or(active);
+        if (threadIdx.x == 0) S.wflag[blk] = any;
+    }
+};
+
+struct WallBlocks {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t, int64_t, int) {
+        __shared__ int32_t sh[kBlock];
+        const int64_t nb = (P.nw + kBlock - 1) / kBlock;
+        const int64_t chunk = (nb + kBlock - 1) / kBlock;
+        const int64_t b0 = threadIdx.x * chunk, b1 = b0 + chunk < nb ? b0 + chunk : nb;
+        int32_t n = 0;
+        for (int64_t b = b0; b < b1; ++b) n += S.wflag[b] != 0;
+        sh[threadIdx.x] = n;
+        __syncthreads();
+        for (int off = 1; off < kBlock; off <<= 1) {   // inclusive scan of the counts
+            const int32_t v = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += v;
+            __syncthreads();
+        }
+        int32_t pos = sh[threadIdx.x] - n;
+        for (int64_t b = b0; b < b1; ++b)
+            if (S.wflag[b] != 0) S.wblk[1 + pos++] = (int32_t)b;
+        if (threadIdx.x == kBlock - 1) S.wblk[0] = sh[kBlock - 1];
+    }
+};
+
 template <typename R>
 __device__ __forceinline__ void wall_words(const State &S, int64_t nw, int64_t w, int k0, int cap,
                                            R (&cb)[kPairBatch], int32_t (&jr)[kPairBatch]) {
@@ -1507,8 +1545,11 @@ __device__ __forceinline__ void wall_words(const State &S, int64_t nw, int64_t w
 template <typename R>
 struct WallPressure {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int L, int final) {
-        if (!final && __hip_atomic_load(&S.ctl->stopped_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < L)
-            return;
+        if (!final) {
+            if (__hip_atomic_load(&S.ctl->stopped_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < L) return;
+            if (blk >= S.wblk[0]) return;   // the listed workgroups take the first launch slots
+            blk = S.wblk[1 + blk];
+        }
         ROW;
         const int64_t w = i;
         if (w >= P.nw) return;
@@ -2210,8 +2251,10 @@ void ppe_iteration(const Target &T, int L) {
         launch<BicgUpdate, K_FLUID>(T, it);
         return;
     }
-    if (T.precision == SISPH_MIXED) launch<WallPressure<float>, K_WALL>(T, L, 0);
-    else launch<WallPressure<double>, K_WALL>(T, L, 0);
+    // hardware workgroup order: the listed workgroups, which take the first
+    // launch slots, then spread over every XCD
+    if (T.precision == SISPH_MIXED) launch<WallPressure<float>, K_WALL, false>(T, L, 0);
+    else launch<WallPressure<double>, K_WALL, false>(T, L, 0);
     sweep_only(T, L);
 }
 
@@ -2232,7 +2275,11 @@ void wall_pressure_final(const Target &T) {
     else launch<WallPressure<double>, K_WALL>(T, 0, 1);
 }
 
-void wall_coef(const Target &T) { SISPH_DISPATCH_KDR(T, (launch<WallCoef<KER, D, R>, K_WALL>(T))); }
+void wall_coef(const Target &T) {
+    SISPH_DISPATCH_KDR(T, (launch<WallCoef<KER, D, R>, K_WALL>(T)));
+    launch<WallFlags, K_WALL>(T);
+    launch<WallBlocks, K_ONE>(T);
+}
 
 void pressure_max(const Target &T) {
     launch<PMax, K_FLUID>(T);
