@@ -21,8 +21,6 @@ import re
 import sys
 import time
 
-import numpy as np
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -313,7 +311,7 @@ def main():
     iters = sum(s["iters"] for s in stats)
     value = case.n_fluid * iters / elapsed if elapsed > 0 else 0.0
     cnt = ctx.sweep_counters()
-    wall_rows = int(np.count_nonzero(np.diff(ctx.neighbors(1, 1)[0]))) if case.n_wall else 0
+    wall_rows = ctx.rows_with_neighbours(1, 1) if case.n_wall else 0
     sb = sweep_bytes(case, ctx.pair_count(1, 0), index_bytes=stats[-1]["index_bytes"] if stats else 4,
                      wall_pairs=ctx.pair_count(1, 1) if case.n_wall else 0, wall_rows=wall_rows)
     avg_launch_s = cnt["sweep_ms"] / 1e3 / max(cnt["launches"], 1)

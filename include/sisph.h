@@ -186,6 +186,12 @@ int32_t sisph_read_field(sisph_ctx *ctx, int32_t field, double *out);
  * for stage / dest (as below); only the per-row counts leave the device. */
 int32_t sisph_pair_count(sisph_ctx *ctx, int32_t stage, int32_t dest, int64_t *pairs);
 
+/* Number of rows of those lists holding at least one particle other than
+ * the row itself (wall rows without fluid neighbours are not read by any
+ * sweep).  Same stage / dest as sisph_pair_count; only per-row counts leave
+ * the device. */
+int32_t sisph_rows_with_neighbours(sisph_ctx *ctx, int32_t stage, int32_t dest, int64_t *rows);
+
 /* Neighbour sets as CSR in original ids, each row ascending.
  * stage 0: N^n (valid after sisph_bin), stage 1: N* (after sisph_predict);
  * dest 0: fluid rows over fluid+wall sources, dest 1: wall rows over fluid

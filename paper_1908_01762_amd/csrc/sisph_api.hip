@@ -892,6 +892,23 @@ extern "C" int32_t sisph_pair_count(sisph_ctx *ctx, int32_t stage, int32_t dest,
     return SISPH_OK;
 }
 
+extern "C" int32_t sisph_rows_with_neighbours(sisph_ctx *ctx, int32_t stage, int32_t dest, int64_t *rows) {
+    if (!ctx || !rows || (dest != 0 && dest != 1)) return SISPH_E_INVAL;
+    if (stage != ctx->nbr_stage) return fail(ctx, SISPH_E_STATE, "requested neighbour stage is not held");
+    int32_t st = read_ctl(ctx);
+    if (st != SISPH_OK) return st;
+    if (ctx->h_ctl->overflow)
+        return fail(ctx, SISPH_E_NOMEM, "neighbour capacity exceeded: " + std::to_string(ctx->h_ctl->maxcnt));
+    std::vector<int32_t> cnt;
+    const int64_t n = dest == 0 ? ctx->P.nf : ctx->P.nw;
+    if ((st = d2h(ctx, cnt, dest == 0 ? ctx->S.cnt : ctx->S.wcnt, n)) != SISPH_OK) return st;
+    const int32_t self = dest == 0 ? 1 : 0;   // fluid lists hold the row itself first
+    int64_t tot = 0;
+    for (int32_t c : cnt) tot += c > self;
+    *rows = tot;
+    return SISPH_OK;
+}
+
 extern "C" int32_t sisph_debug_neighbors(sisph_ctx *ctx, int32_t stage, int32_t dest, int64_t *offsets,
                                          int32_t *ids, int64_t cap) {
     if (!ctx || !offsets || (dest != 0 && dest != 1)) return SISPH_E_INVAL;

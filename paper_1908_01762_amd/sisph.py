@@ -99,6 +99,8 @@ def lib():
         L.sisph_batch_set_graphs.argtypes = [C.c_void_p, C.c_int32]
         L.sisph_pair_count.restype = C.c_int32
         L.sisph_pair_count.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
+        L.sisph_rows_with_neighbours.restype = C.c_int32
+        L.sisph_rows_with_neighbours.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
         L.sisph_debug_neighbors.restype = C.c_int32
         L.sisph_debug_neighbors.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
                                             C.POINTER(C.c_int32), C.c_int64]
@@ -283,6 +285,12 @@ class Context:
         """Stored neighbour pairs (self included) of the held lists."""
         n = C.c_int64()
         _check(lib().sisph_pair_count(self.h, stage, dest, C.byref(n)), self.h)
+        return n.value
+
+    def rows_with_neighbours(self, stage: int, dest: int = 0) -> int:
+        """Rows of the held lists with a particle other than the row itself."""
+        n = C.c_int64()
+        _check(lib().sisph_rows_with_neighbours(self.h, stage, dest, C.byref(n)), self.h)
         return n.value
 
     def timings(self):

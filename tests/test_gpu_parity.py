@@ -65,10 +65,12 @@ def test_neighbour_sets_bit_exact(name):
     roff, rids = oracle.neighbors(case)
     assert _same_sets(off, ids, roff, rids)
     assert ctx.pair_count(0, 0) == roff[-1]
+    assert ctx.rows_with_neighbours(0, 0) == np.count_nonzero(np.diff(roff) > 1)   # sets hold the row itself
     if case.n_wall:
         off, ids = ctx.neighbors(0, 1)
         roff, rids = oracle.neighbors(case, dest=(case.n_fluid, case.n), src=(0, case.n_fluid))
         assert _same_sets(off, ids, roff, rids)
+        assert ctx.rows_with_neighbours(0, 1) == np.count_nonzero(np.diff(roff) > 0)
     # stage 1: r* = r^n + dt u~^n is formed with the same FP64 operations
     ctx.predict()
     out = oracle.Sim(case).step(capture=True)
