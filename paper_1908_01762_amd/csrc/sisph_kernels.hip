@@ -1595,10 +1595,14 @@ struct WallPressure {
 };
 
 // After the solve: the final iterate into p[0] (it is in p[iters & 1]).
+// In the mixed mode the FP32 copy moves too: the final wall pass reads it.
 struct SettlePressure {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
-        if (i < P.ntot && (S.ctl->iter & 1)) S.p[0][i] = S.p[1][i];
+        if (i < P.ntot && (S.ctl->iter & 1)) {
+            S.p[0][i] = S.p[1][i];
+            if (P.precision == SISPH_MIXED) S.p32[i] = S.p32[P.ntot + i];
+        }
     }
 };
 
