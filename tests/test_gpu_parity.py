@@ -384,6 +384,44 @@ def test_mixed_precision_single_step(name):
     ctx.close()
 
 
+def _mixed_steps_cases():
+    return {
+        "tg40_quintic": cases.taylor_green(40, precision="mixed"),
+        "db2d_dx0.05": cases.dam_break_2d(dx=0.05, precision="mixed"),
+        "ldc30_noslip": cases.lid_driven_cavity(30, ustar_wall="noslip", precision="mixed"),
+        "ldc24_adaptive_dt": cases.lid_driven_cavity(24, dt=0.02, precision="mixed").replace(dt_mode="adaptive"),
+        "db2d_bicgstab": cases.dam_break_2d(dx=0.05, precision="mixed").replace(solver="bicgstab"),
+    }
+
+
+@pytest.mark.parametrize("name", list(_mixed_steps_cases().keys()))
+def test_mixed_precision_steps(name):
+    """Five mixed-mode steps against the FP64 oracle, the oracle taking the
+    GPU's iteration count at each step (the stopping test may flip one
+    iteration either way).  FP32 rounding of the pair sums (~1e-7 relative,
+    amplified by the pressure solve) bounds the drift: velocity and
+    displacement to 1e-4, fluid pressure to 1e-3 relative L2, and the
+    adaptive step to 1e-6."""
+    sisph = _gpu()
+    case = _mixed_steps_cases()[name]
+    nf = case.n_fluid
+    say("case mixed steps", name, nf, case.n_wall)
+    ctx = sisph.Context(case)
+    ref = oracle.Sim(case)
+    for k in range(5):
+        g = ctx.step(1)[0]
+        o = ref.step(forced_iters=g["iters"])
+        say(f"  step {k}: iters {g['iters']}, dt gpu {g['dt']:.9e} oracle {o['dt']:.9e}")
+        assert math.isclose(g["dt"], o["dt"], rel_tol=1e-6)
+    s = ctx.read_state()
+    errs = {"u": rel(s["u"][:nf], ref.u[:nf]), "p": rel(s["p"][:nf], ref.p[:nf]),
+            "displacement": rel(s["x"][:nf] - case.x[:nf], ref.x[:nf] - case.x[:nf])}
+    for k, e in errs.items():
+        say(f"  mixed steps {name} {k:12s} rel L2 {e:.3e}")
+    assert errs["u"] < 1e-4 and errs["displacement"] < 1e-4 and errs["p"] < 1e-3
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", ["cloud", "single"])
 def test_degenerate_rows_fp64(name):
     """Empty neighbour sums: isolated particles (count 1, D_ii = 0), an
