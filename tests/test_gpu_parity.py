@@ -45,6 +45,8 @@ def _cases_small():
         "db2d_dx0.05": cases.dam_break_2d(dx=0.05, precision="fp64"),
         "db3d_small": cases.dam_break_3d(dx=0.1, lx=0.5, ly=0.5, lz=0.6, tank_x=1.5, tank_y=0.5, tank_z=1.0,
                                          precision="fp64"),
+        "db3d_quintic": cases.dam_break_3d(dx=0.1, lx=0.5, ly=0.5, lz=0.6, tank_x=1.5, tank_y=0.5, tank_z=1.0,
+                                           kernel="quintic", hdx=1.0, precision="fp64"),
         "ldc30_slip": cases.lid_driven_cavity(30),
         "ldc30_noslip": cases.lid_driven_cavity(30, ustar_wall="noslip"),
     }
@@ -496,16 +498,24 @@ def test_error_paths():
     ctx.close()
 
 
-def test_eisph_single_sweep_matches_oracle():
-    """forced one sweep (EISPH) on both sides."""
+@pytest.mark.parametrize("name", ["tg30_fp64", "db2d_mixed"])
+def test_eisph_single_sweep_matches_oracle(name):
+    """forced one sweep (EISPH) on both sides; with walls in the mixed mode
+    the final iterate sits in the second buffer after every solve."""
     sisph = _gpu()
-    case = cases.taylor_green(30, jitter=0.1, seed=4).replace(forced_iters=1)
+    if name == "tg30_fp64":
+        case, tol_u, tol_p = cases.taylor_green(30, jitter=0.1, seed=4), FP64_TOL, FP64_TOL
+    else:
+        case, tol_u, tol_p = cases.dam_break_2d(dx=0.05, precision="mixed"), 1e-4, 1e-3
+    case = case.replace(forced_iters=1)
     ref = oracle.Sim(case)
     ctx = sisph.Context(case)
     for _ in range(3):
         assert ref.step()["iters"] == 1 and ctx.step(1)[0]["iters"] == 1
     s = ctx.read_state()
-    assert rel(s["p"], ref.p) < FP64_TOL and rel(s["u"], ref.u) < FP64_TOL
+    nf = case.n_fluid
+    say(f"  eisph {name}: p {rel(s['p'], ref.p):.3e} u {rel(s['u'][:nf], ref.u[:nf]):.3e}")
+    assert rel(s["p"], ref.p) < tol_p and rel(s["u"][:nf], ref.u[:nf]) < tol_u
     ctx.close()
 
 
