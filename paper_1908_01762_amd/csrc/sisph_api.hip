@@ -25,6 +25,7 @@ struct sisph_ctx {
     int state;
     int nbr_stage;       // which neighbour lists are held: -1, 0 (r^n), 1 (r*)
     int last_iters;
+    int prev_iters;   // the count before last_iters (0: none yet)
     Control *h_ctl;      // pinned mirror of the control block
     hipEvent_t ev[4];
     hipEvent_t evc[2];   // brackets one chunk of back-to-back sweeps
@@ -372,6 +373,7 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
     ctx->state = ST_READY;
     ctx->nbr_stage = -1;
     ctx->last_iters = desc->min_iter;
+    ctx->prev_iters = 0;
     ctx->ppe_ms = ctx->step_ms = 0.0;
     ctx->sweep_ms = 0.0;
     ctx->sweep_launches = ctx->sweep_effective = 0;
@@ -586,6 +588,26 @@ extern "C" int32_t sisph_predict(sisph_ctx *ctx) {
     return SISPH_OK;
 }
 
+// Sweeps to queue first for a case: the last solve's count moved on by its
+// last change (counts drift slowly from step to step), unless that change
+// was large (leaving the iteration limit, say); at least min_iter.  Only the
+// launch count depends on it, never a result.
+static int64_t predict_iters(const sisph_ctx *ctx) {
+    const Params &P = ctx->P;
+    if (P.forced_iters > 0) return P.forced_iters;
+    int64_t p = ctx->last_iters;
+    if (ctx->prev_iters > 0) {
+        const int64_t trend = (int64_t)ctx->last_iters - ctx->prev_iters;
+        if (8 * std::abs(trend) <= p) p += trend;
+    }
+    return std::max<int64_t>(p, P.min_iter);
+}
+
+static void record_iters(sisph_ctx *ctx, int iters) {
+    ctx->prev_iters = ctx->last_iters;
+    ctx->last_iters = std::max(iters, 1);
+}
+
 // Launch L performs sweep L unless its case stopped earlier; the decision
 // for L sweeps is taken at the start of launch L, so each chunk of launches
 // ends one beyond the predicted count.  poll() reads the control state and
@@ -595,6 +617,7 @@ static int32_t ppe_loop(const Target &T, int64_t predicted, int64_t limit, hipEv
                         double &sweep_ms, int64_t &launches, Poll poll, std::string &err) {
     int64_t chunk = std::min<int64_t>(predicted + 1, limit);
     int64_t launched = 0;
+    int polls = 0;
     for (;;) {
         if (hipEventRecord(e0, T.s) != hipSuccess) return SISPH_E_DEVICE;
         for (int64_t c = 0; c < chunk; ++c) ppe_iteration(T, (int)(launched + c));
@@ -613,10 +636,13 @@ static int32_t ppe_loop(const Target &T, int64_t predicted, int64_t limit, hipEv
         sweep_ms += cms;
         launches += chunk;
         if (all_done || launched >= limit) break;
-        // the prediction fell short: grow by a quarter of what has been
-        // launched (a launch past the stop is wasted, a poll costs a host
+        // the prediction fell short: first by a little, as a rule (a
+        // thirty-second of what has been launched), then grow by a quarter
+        // of it (a launch past the stop is wasted, a poll costs a host
         // round trip)
-        chunk = std::min<int64_t>(std::min<int64_t>(std::max<int64_t>(2, launched / 4), 64), limit - launched);
+        ++polls;
+        const int64_t grow = polls == 1 ? launched / 32 : launched / 4;
+        chunk = std::min<int64_t>(std::min<int64_t>(std::max<int64_t>(2, grow), 64), limit - launched);
         if (chunk < 1) chunk = 1;
     }
     return SISPH_OK;
@@ -631,7 +657,7 @@ extern "C" int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out) {
     HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
     seq_ppe_begin(ctx->T);
     const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1;
-    const int64_t predicted = P.forced_iters > 0 ? P.forced_iters : std::max(P.min_iter, ctx->last_iters);
+    const int64_t predicted = predict_iters(ctx);
     const int before = 0;
     auto poll = [&](bool &done) -> int32_t {
         int32_t st = read_ctl(ctx);
@@ -650,7 +676,7 @@ extern "C" int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out) {
     ctx->ppe_ms = ms;
     const Control &C = *ctx->h_ctl;
     ctx->sweep_effective += C.iter - before;
-    ctx->last_iters = std::max(C.iter, 1);
+    record_iters(ctx, C.iter);
     if (out) fill_stats(C, P, out);
     ctx->state = ST_SOLVED;
     std::string msg;
@@ -698,7 +724,7 @@ static int32_t step_graphed(sisph_ctx *ctx, sisph_step_stats *out) {
     HIPCHK(ctx, hipGraphLaunch(ctx->g_pre, s));
     HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
     const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1;
-    const int64_t predicted = P.forced_iters > 0 ? P.forced_iters : std::max(P.min_iter, ctx->last_iters);
+    const int64_t predicted = predict_iters(ctx);
     auto poll = [&](bool &done) -> int32_t {
         int32_t st = read_ctl(ctx);
         if (st != SISPH_OK) return st;
@@ -719,7 +745,7 @@ static int32_t step_graphed(sisph_ctx *ctx, sisph_step_stats *out) {
     ctx->step_ms = ms;
     const Control &C = *ctx->h_ctl;
     ctx->sweep_effective += C.iter;
-    ctx->last_iters = std::max(C.iter, 1);
+    record_iters(ctx, C.iter);
     ctx->nbr_stage = 1;
     if (out) fill_stats(C, P, out);
     ctx->state = ST_READY;
@@ -1174,8 +1200,7 @@ static int32_t group_step(sisph_batch *b, Group &g) {
     for (auto *c : g.members) {
         const Params &P = c->P;
         limit = std::max<int64_t>(limit, (P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1);
-        predicted = std::max<int64_t>(predicted, P.forced_iters > 0 ? P.forced_iters
-                                                                   : std::max(P.min_iter, c->last_iters));
+        predicted = std::max<int64_t>(predicted, predict_iters(c));
         maxK = std::max(maxK, P.gtvf_K);
     }
     if (b->use_graphs) {
@@ -1216,7 +1241,7 @@ static int32_t group_step(sisph_batch *b, Group &g) {
     for (size_t c = 0; c < n; ++c) {
         sisph_ctx *ctx = g.members[c];
         *ctx->h_ctl = g.h_ctl[c];
-        ctx->last_iters = std::max(g.h_ctl[c].iter, 1);
+        record_iters(ctx, g.h_ctl[c].iter);
         ctx->sweep_effective += g.h_ctl[c].iter;
         ctx->nbr_stage = 1;
     }
