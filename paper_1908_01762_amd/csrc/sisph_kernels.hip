@@ -2280,6 +2280,8 @@ void wall_pressure_final(const Target &T) {
 }
 
 void wall_coef(const Target &T) {
+    const bool walls = T.batched ? T.total[K_WALL] > 0 : kind_blocks(*T.P, K_WALL) > 0;
+    if (!walls) return;
     SISPH_DISPATCH_KDR(T, (launch<WallCoef<KER, D, R>, K_WALL>(T)));
     launch<WallFlags, K_WALL>(T);
     launch<WallBlocks, K_ONE>(T);
