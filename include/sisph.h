@@ -220,6 +220,16 @@ int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_t *launches
  * directly.  Off by default. */
 int32_t sisph_set_graphs(sisph_ctx *ctx, int32_t on);
 
+/* Single Jacobi solves of cases without walls whose fluid workgroups all fit
+ * on the device at once run as one cooperative launch that holds every
+ * sweep (on by default): the rows' coefficients stay in registers, the
+ * workgroups meet at a grid barrier between sweeps and the host waits once
+ * per solve instead of polling between chunks of launches.  Results and
+ * sweep counts are bitwise those of the per-launch sweeps.  on = 0 keeps
+ * the per-launch sweeps (used to compare the two).  A barrier that does not
+ * fill in time ends the solve with SISPH_E_DEVICE. */
+int32_t sisph_set_persistent(sisph_ctx *ctx, int32_t on);
+
 int32_t sisph_destroy(sisph_ctx *ctx);
 
 /* ------------------------------------------------------------- autotuning

@@ -36,6 +36,8 @@ struct sisph_ctx {
     sisph_batch *batch;  // non-null while attached
     int32_t variant;     // Jacobi-sweep launch variant
     bool use_graphs = false;
+    bool use_persistent = true;                                // one-launch solves where they apply
+    int64_t persist_cap[3] = {-1, -1, -1};                     // per first-batch size, -1: not asked yet
     hipStream_t cap_stream = nullptr;                          // capture only
     hipGraphExec_t g_pre = nullptr, g_post = nullptr;          // fixed step segments
     std::string err;
@@ -245,6 +247,7 @@ static void carve(const Params &P, Carver &c, State &S) {
         S.bpart = c.take<double>(6 * kind_blocks(P, K_FLUID));
     }
     S.ctl = c.take<Control>(1);
+    S.sync = c.take<uint32_t>(kSyncWords);
 }
 
 extern "C" size_t sisph_workspace_bytes(const sisph_case_desc *desc) {
@@ -648,6 +651,47 @@ static int32_t ppe_loop(const Target &T, int64_t predicted, int64_t limit, hipEv
     return SISPH_OK;
 }
 
+// A case without walls, solved by Jacobi sweeps, whose fluid workgroups all
+// fit on the device at once, runs its whole solve as one cooperative launch
+// (ppe_persistent); other cases, or a launch the runtime refuses, take the
+// per-launch sweeps.  Both give the same results and sweep counts.
+static bool persistent_ok(sisph_ctx *ctx) {
+    const Params &P = ctx->P;
+    if (!ctx->use_persistent || P.nw > 0 || P.solver != SISPH_JACOBI) return false;
+    const int64_t nb = kind_blocks(P, K_FLUID);
+    int64_t &cap = ctx->persist_cap[ctx->T.variant % 3];
+    if (cap < 0) cap = ppe_persistent_capacity(ctx->T);
+    return nb >= 1 && nb <= cap;
+}
+
+static int32_t ppe_run(sisph_ctx *ctx, int64_t predicted, int64_t limit) {
+    if (persistent_ok(ctx)) {
+        HIPCHK(ctx, hipEventRecord(ctx->evc[0], ctx->stream));
+        const hipError_t e = ppe_persistent(ctx->T, (int)limit);
+        if (e == hipSuccess) {
+            HIPCHK(ctx, hipEventRecord(ctx->evc[1], ctx->stream));
+            int32_t st = read_ctl(ctx);
+            if (st != SISPH_OK) return st;
+            if (ctx->h_ctl->barrier_late) return fail(ctx, SISPH_E_DEVICE, "persistent solve: a grid barrier timed out");
+            float ms = 0.f;
+            HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->evc[0], ctx->evc[1]));
+            ctx->sweep_ms += ms;
+            ctx->sweep_launches += ctx->h_ctl->iter + 1;   // sweeps run, the one after the stop included
+            return SISPH_OK;
+        }
+        (void)hipGetLastError();   // refused (e.g. not all workgroups resident): per-launch sweeps
+        ctx->persist_cap[ctx->T.variant % 3] = 0;
+    }
+    auto poll = [&](bool &done) -> int32_t {
+        int32_t st = read_ctl(ctx);
+        if (st != SISPH_OK) return st;
+        done = ctx->h_ctl->done != 0;
+        return SISPH_OK;
+    };
+    return ppe_loop(ctx->T, predicted, limit, ctx->evc[0], ctx->evc[1], ctx->sweep_ms, ctx->sweep_launches, poll,
+                    ctx->err);
+}
+
 extern "C" int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out) {
     if (!ctx) return SISPH_E_INVAL;
     if (attached(ctx)) return fail(ctx, SISPH_E_STATE, "context is attached to a batch");
@@ -659,14 +703,7 @@ extern "C" int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out) {
     const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1;
     const int64_t predicted = predict_iters(ctx);
     const int before = 0;
-    auto poll = [&](bool &done) -> int32_t {
-        int32_t st = read_ctl(ctx);
-        if (st != SISPH_OK) return st;
-        done = ctx->h_ctl->done != 0;
-        return SISPH_OK;
-    };
-    int32_t st = ppe_loop(ctx->T, predicted, limit, ctx->evc[0], ctx->evc[1], ctx->sweep_ms, ctx->sweep_launches,
-                          poll, ctx->err);
+    int32_t st = ppe_run(ctx, predicted, limit);
     if (st != SISPH_OK) return st;
     seq_ppe_end(ctx->T);
     HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
@@ -725,14 +762,7 @@ static int32_t step_graphed(sisph_ctx *ctx, sisph_step_stats *out) {
     HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
     const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1;
     const int64_t predicted = predict_iters(ctx);
-    auto poll = [&](bool &done) -> int32_t {
-        int32_t st = read_ctl(ctx);
-        if (st != SISPH_OK) return st;
-        done = ctx->h_ctl->done != 0;
-        return SISPH_OK;
-    };
-    int32_t st = ppe_loop(ctx->T, predicted, limit, ctx->evc[0], ctx->evc[1], ctx->sweep_ms, ctx->sweep_launches,
-                          poll, ctx->err);
+    int32_t st = ppe_run(ctx, predicted, limit);
     if (st != SISPH_OK) return st;
     HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
     HIPCHK(ctx, hipGraphLaunch(ctx->g_post, s));
@@ -1332,6 +1362,12 @@ extern "C" int32_t sisph_get_variant(sisph_ctx *ctx) { return ctx ? ctx->variant
 extern "C" int32_t sisph_set_graphs(sisph_ctx *ctx, int32_t on) {
     if (!ctx) return SISPH_E_INVAL;
     ctx->use_graphs = on != 0;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_set_persistent(sisph_ctx *ctx, int32_t on) {
+    if (!ctx) return SISPH_E_INVAL;
+    ctx->use_persistent = on != 0;
     return SISPH_OK;
 }
 

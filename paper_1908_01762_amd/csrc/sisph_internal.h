@@ -51,7 +51,7 @@ struct Control {
     int32_t overflow;      // neighbour capacity exceeded
     int32_t maxcnt;        // largest neighbour count seen (on overflow)
     int32_t p_ref_set;
-    int32_t pad;
+    int32_t barrier_late;  // a grid barrier of the persistent solve timed out
     double ratio, num, den;
     unsigned long long lambda_bits;   // max |RHS/D| (non-negative doubles)
     unsigned long long pmax_key;      // max p, order-preserving key
@@ -113,6 +113,11 @@ struct State {
     // extrapolation), and six partial-sum rows [6][nblk]
     double *bx, *br, *brh, *bp, *bv, *bs, *bt, *bf, *bh, *bpart;
     Control *ctl;
+    // Persistent solve, apart from the Control fields written with ordinary
+    // stores: [0] a barrier timed out; at kSyncBcast + 64 x (x < kSyncCopies,
+    // one 256-byte line each) the word workgroup 0 posts after each sweep;
+    // at kSyncArrive + b the sweeps workgroup b has finished
+    uint32_t *sync;
 };
 
 // Launch-size kinds: how many workgroups one case needs for a kernel.
@@ -199,6 +204,15 @@ constexpr int64_t kPrecheckRows = int64_t(1) << 19;
 constexpr int kSweepVariants = 6;
 constexpr int kDefaultVariant = 1;
 void settle_pressure(const Target &T);
+// The whole Jacobi solve of one wall-less case in one cooperative launch
+// (every workgroup resident); returns the launch's error.  The capacity is
+// the number of fluid workgroups such a launch can hold (0: none).
+hipError_t ppe_persistent(const Target &T, int limit);
+int64_t ppe_persistent_capacity(const Target &T);
+constexpr uint32_t kBarrierSpins = 1u << 18;   // polls before a grid barrier gives up
+constexpr int kSyncCopies = 8;                 // one posted word per XCD
+constexpr int kSyncBcast = 64, kSyncArrive = 64 * (1 + kSyncCopies);
+constexpr int kSyncWords = kSyncArrive + 1024;   // at most 1024 workgroups
 void wall_pressure_final(const Target &T);
 void pressure_max(const Target &T);
 void correct(const Target &T);

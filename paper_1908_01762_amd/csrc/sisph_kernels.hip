@@ -298,6 +298,8 @@ void launch(const Target &T, A... a) {
 // ----------------------------------------------------------------- control
 struct ResetControl {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t, int64_t, int, int what) {
+        if (what & RESET_PPE)   // the persistent solve's barrier words
+            for (int k = threadIdx.x; k < kSyncWords; k += kBlock) S.sync[k] = 0u;
         if (threadIdx.x != 0) return;
         Control *c = S.ctl;
         if (what & RESET_DT) {
@@ -310,6 +312,7 @@ struct ResetControl {
             c->fmax2_bits = 0ull;
         }
         if (what & RESET_PPE) {
+            c->barrier_late = 0;
             c->iter = 0;
             c->done = 0;
             c->stopped_at = INT32_MAX;
@@ -1429,6 +1432,182 @@ struct Sweep {
     }
 };
 
+// ------------------------------------------------- persistent Jacobi solve
+// The whole solve of one case without walls in one cooperative launch (all
+// workgroups resident, one per 256 rows): each workgroup keeps its rows'
+// first FIRST coefficients and neighbour indices, D_ii, RHS, flag, count
+// and own iterate in registers for every sweep.  After sweep L every
+// workgroup posts L+1 in its own arrival word once its stores have
+// completed; workgroup 0 waits for all of them and posts 2 (L+1) + stop in
+// one word per XCD, which the others wait for.  Workgroup 0 takes the
+// per-launch sweep's decision (before sweep L, whether the solve stopped
+// after L sweeps, from sweep L-1's partial sums) while the others run
+// sweep L, so the stop is posted after sweep L, as the per-launch path
+// returns from launch L+1: sums, their order, the decision and the sweep
+// count are bitwise the same.  What other workgroups read during the launch
+// (the gathered iterate, the partial sums, these words) is written and read
+// with device-scope accesses, which are coherent across XCDs without a
+// cache write-back.  A wait that does not end within kBarrierSpins polls
+// sets a flag and every workgroup leaves (the host reports the error).
+template <typename T>
+__device__ __forceinline__ T dev_load(const T *p) {
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void dev_store(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename R, int NG>
+__device__ __forceinline__ void gather_dev(int64_t i, int g0, int npos, const int4 (&jj)[NG], const double *pc,
+                                           const float *qc, R (&pv)[NG][4]) {
+#pragma unroll
+    for (int t = 0; t < NG; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int p = (g0 + t) * 4 + q;
+            const int32_t j = p < npos ? iget(jj[t], q) : (int32_t)i;
+            if constexpr (sizeof(R) == 4) pv[t][q] = dev_load(qc + j);
+            else pv[t][q] = dev_load(pc + j);
+        }
+}
+
+template <typename R, int FIRST>
+__global__ __launch_bounds__(kBlock) void k_ppe_persistent(const Params P, const State S, int limit) {
+    Control *ctl = S.ctl;
+    const int64_t blk = blockIdx.x, nblk = gridDim.x;
+    const int64_t nf = P.nf;
+    const bool offs = P.compact != 0;
+    const int32_t wide_flag = offs ? ctl->wide : 0;
+    const int gmax = P.cap / 4;
+    ROW;
+    const bool live = i < nf;
+    constexpr int NG = FIRST / 4;
+    typename Vec4<R>::T cc[NG];
+    int4 jj[NG];
+    Off4 oo[NG];
+    double D = 0.0, r = 0.0, pold = 0.0;
+    int32_t f = 1, c = 1;
+    if (live) {
+        load_groups<R, NG>(i, nf, 0, gmax, S.coef, S.cidx, offs, cc, jj, oo);
+        D = S.dii[i];
+        r = S.rhs[i];
+        f = S.fs[i];
+        c = S.cnt[i];
+        pold = S.p[0][i];
+        if (offs) resolve_groups<NG>(i, nf, 0, c - 1, S.nbr, wide_flag != 0, oo, jj);
+    }
+    const int npos = c - 1;
+    const double lam = __longlong_as_double((long long)ctl->lambda_bits);   // fixed during the solve
+    uint32_t *const late_flag = S.sync;
+    uint32_t *const arrive = S.sync + kSyncArrive;
+    __shared__ int go;
+    bool stopped = false;   // workgroup 0, once it recorded the stop
+    for (int L = 0; L < limit; ++L) {
+        // workgroup 0 decides whether the solve stopped after L sweeps from
+        // sweep L-1's partial sums (all posted before the last barrier),
+        // while the others already run sweep L; a stop travels with the
+        // word posted after sweep L
+        if (L > 0 && blk == 0 && !stopped) {
+            PartialLoad pl;
+            const double *pa = S.partial + (int64_t)((L - 1) & 1) * 2 * nblk;
+#pragma unroll
+            for (int t = 0; t < kPartialRegs; ++t) {   // nblk <= kPartialRegs * kBlock here
+                const int64_t k = threadIdx.x + (int64_t)t * kBlock;
+                pl.a[t] = k < nblk ? dev_load(pa + k) : 0.0;
+                pl.b[t] = k < nblk ? dev_load(pa + nblk + k) : 0.0;
+            }
+            stopped = stopped_after(P, S.partial, nblk, L, pl, lam, true, ctl);
+        }
+        const double *pc = S.p[L & 1];
+        double *pn = S.p[(L + 1) & 1];
+        const float *qc = S.p32 + (L & 1) * P.ntot;
+        float *qn = S.p32 + ((L + 1) & 1) * P.ntot;
+        double v = 0.0;
+        if (live) {
+            R pv[NG][4];
+            gather_dev<R, NG>(i, 0, npos, jj, pc, qc, pv);
+            R s = sum_gathers<R, NG>(0, npos, cc, pv, R(0));
+            for (int g0 = NG; 4 * g0 < npos; g0 += kSweepBatchGroups) {
+                typename Vec4<R>::T cb[kSweepBatchGroups];
+                int4 jb[kSweepBatchGroups];
+                Off4 ob[kSweepBatchGroups];
+                load_groups<R, kSweepBatchGroups>(i, nf, g0, gmax, S.coef, S.cidx, offs, cb, jb, ob);
+                if (offs) resolve_groups<kSweepBatchGroups>(i, nf, g0, npos, S.nbr, wide_flag != 0, ob, jb);
+                R pb[kSweepBatchGroups][4];
+                gather_dev<R, kSweepBatchGroups>(i, g0, npos, jb, pc, qc, pb);
+                s = sum_gathers<R, kSweepBatchGroups>(g0, npos, cb, pb, s);
+            }
+            if (D != 0.0 && !f) v = P.omega * (r + (double)s) / D + (1.0 - P.omega) * pold;
+        }
+        double a = 0.0, b = 0.0;
+        if (live) {
+            if constexpr (sizeof(R) == 4) {
+                pn[i] = v;
+                dev_store(qn + i, (float)v);
+            } else {
+                dev_store(pn + i, v);
+            }
+            a = fabs(v - pold);
+            b = fabs(v);
+            pold = v;
+        }
+        block_sum2(a, b);
+        if (threadIdx.x == 0) {
+            double *pw = S.partial + (int64_t)(L & 1) * 2 * nblk;
+            dev_store(pw + blk, a);
+            dev_store(pw + nblk + blk, b);
+            if (blk == 0 && !stopped) ctl->iter = L + 1;
+        }
+        __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this sweep's stores completed
+        __syncthreads();
+        if (threadIdx.x == 0) dev_store(arrive + blk, (uint32_t)(L + 1));
+        const uint32_t want = 2u * (uint32_t)(L + 1);
+        if (blk == 0) {
+            bool all = false;
+            for (uint32_t spins = 0;; ++spins) {
+                bool ok = true;
+#pragma unroll
+                for (int t = 0; t < kPartialRegs; ++t) {
+                    const int64_t k = threadIdx.x + (int64_t)t * kBlock;
+                    if (k < nblk && dev_load(arrive + k) < (uint32_t)(L + 1)) ok = false;
+                }
+                const int give_up = threadIdx.x == 0 && (dev_load(late_flag) != 0u || spins >= kBarrierSpins);
+                all = __syncthreads_and(ok);
+                const bool quit = __syncthreads_or(give_up);
+                if (all || quit) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (threadIdx.x == 0) {
+                if (!all) {
+                    dev_store(late_flag, 1u);
+                    ctl->barrier_late = 1;
+                }
+                const bool leave = stopped || !all;
+                const uint32_t word = want + (leave ? 1u : 0u);
+                for (int x = 0; x < kSyncCopies; ++x) dev_store(S.sync + kSyncBcast + 64 * x, word);
+                go = leave ? 0 : 1;
+            }
+        } else if (threadIdx.x == 0) {
+            const uint32_t *w = S.sync + kSyncBcast + 64 * (blk % kSyncCopies);
+            uint32_t word = dev_load(w);
+            for (uint32_t spins = 0; word < want && dev_load(late_flag) == 0u && spins < kBarrierSpins; ++spins) {
+                __builtin_amdgcn_s_sleep(1);
+                word = dev_load(w);
+            }
+            if (word < want) {
+                dev_store(late_flag, 1u);
+                ctl->barrier_late = 1;
+                go = 0;
+            } else {
+                go = (word & 1u) ? 0 : 1;
+            }
+        }
+        __syncthreads();
+        if (!go) break;
+    }
+}
+
 // eq. p-shepard: p_w = [sum_f p_f W_wf + (g - a_w) . sum_f rho_f r_wf W_wf]
 // / sum_f W_wf over fluid neighbours (static wall: a_w = 0); 0 without
 // neighbours; clamped at 0 on free-surface problems.  Positions and
@@ -2237,6 +2416,52 @@ void sweep_only(const Target &T, int L) {
         if (T.precheck) sweep_variant<double, true>(T, L, T.variant);
         else sweep_variant<double, false>(T, L, T.variant);
     }
+}
+
+template <typename R, int FIRST>
+static hipError_t persistent_launch(const Target &T, int limit) {
+    const int64_t nb = kind_blocks(*T.P, K_FLUID);
+    Params P = *T.P;
+    State S = *T.S;
+    void *args[] = {(void *)&P, (void *)&S, (void *)&limit};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_ppe_persistent<R, FIRST>), dim3((unsigned)nb),
+                                      dim3(kBlock), args, 0, T.s);
+}
+
+template <typename R, int FIRST>
+static int64_t persistent_capacity() {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_ppe_persistent<R, FIRST>),
+                                                     kBlock, 0) != hipSuccess)
+        return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const int64_t cap = (int64_t)per_cu * cus;
+    return cap < (int64_t)kPartialRegs * kBlock ? cap : (int64_t)kPartialRegs * kBlock;
+}
+
+#define SISPH_PERSISTENT_FIRST(T, CALL)                                       \
+    do {                                                                      \
+        const int first = kSweepFirsts[(T).variant % 3];                      \
+        if ((T).precision == SISPH_MIXED) {                                   \
+            if (first == 16) { using R = float; constexpr int F = 16; CALL; } \
+            else if (first == 20) { using R = float; constexpr int F = 20; CALL; } \
+            else { using R = float; constexpr int F = 24; CALL; }            \
+        } else {                                                              \
+            if (first == 16) { using R = double; constexpr int F = 16; CALL; } \
+            else if (first == 20) { using R = double; constexpr int F = 20; CALL; } \
+            else { using R = double; constexpr int F = 24; CALL; }           \
+        }                                                                     \
+    } while (0)
+
+hipError_t ppe_persistent(const Target &T, int limit) {
+    SISPH_PERSISTENT_FIRST(T, return (persistent_launch<R, F>(T, limit)));
+    return hipErrorInvalidValue;
+}
+
+int64_t ppe_persistent_capacity(const Target &T) {
+    SISPH_PERSISTENT_FIRST(T, return (persistent_capacity<R, F>()));
+    return 0;
 }
 
 void ppe_iteration(const Target &T, int L) {

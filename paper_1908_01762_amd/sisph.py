@@ -95,6 +95,8 @@ def lib():
         L.sisph_read_field.argtypes = [C.c_void_p, C.c_int32, _DP]
         L.sisph_set_graphs.restype = C.c_int32
         L.sisph_set_graphs.argtypes = [C.c_void_p, C.c_int32]
+        L.sisph_set_persistent.restype = C.c_int32
+        L.sisph_set_persistent.argtypes = [C.c_void_p, C.c_int32]
         L.sisph_batch_set_graphs.restype = C.c_int32
         L.sisph_batch_set_graphs.argtypes = [C.c_void_p, C.c_int32]
         L.sisph_pair_count.restype = C.c_int32
@@ -280,6 +282,10 @@ class Context:
     def use_graphs(self, on: bool = True):
         """Replay the fixed parts of each step from HIP graphs (sisph_step)."""
         _check(lib().sisph_set_graphs(self.h, int(bool(on))), self.h)
+
+    def use_persistent(self, on: bool = True):
+        """One cooperative launch per Jacobi solve where it applies (default)."""
+        _check(lib().sisph_set_persistent(self.h, int(bool(on))), self.h)
 
     def pair_count(self, stage: int, dest: int = 0) -> int:
         """Stored neighbour pairs (self included) of the held lists."""

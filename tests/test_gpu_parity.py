@@ -284,35 +284,13 @@ def test_bicgstab_mixed_single_step():
     ctx.close()
 
 
-def _long_strip(nx=16384, ny=8, seed=9):
-    """Periodic strip nx x ny particles (Wendland h = 1.3 dx, cells of about
-    2.7 dx): one row of cells holds ~44k particles, so neighbours in the next
-    cell row are more than 32767 rows away and the 16-bit offsets cannot be
-    used."""
-    base = cases.taylor_green(16, kernel="wendland", hdx=1.3, precision="mixed")
-    dx = 1.0 / 1024
-    ii, jj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
-    x = np.stack([(ii.ravel() + 0.5) * dx, (jj.ravel() + 0.5) * dx], axis=1)
-    rng = np.random.default_rng(seed)
-    x = x + rng.uniform(-0.05 * dx, 0.05 * dx, size=x.shape)
-    Lx, Ly = nx * dx, ny * dx
-    x[:, 0] = np.mod(x[:, 0], Lx)
-    x[:, 1] = np.mod(x[:, 1], Ly)
-    u = 0.1 * np.stack([np.sin(2 * np.pi * x[:, 1] / Ly), np.sin(2 * np.pi * x[:, 0] / Lx)], axis=1)
-    n = x.shape[0]
-    h = 1.3 * dx
-    return base.replace(name="strip", x=x, u=u, p=np.zeros(n), m=np.full(n, dx * dx), n_fluid=n,
-                        h=h, dx=dx, box_lo=(0.0, 0.0, 0.0), box_hi=(Lx, Ly, 0.0), nu=1e-3,
-                        dt=0.25 * h / 0.1, tol=1e-4, p_ref_mode="twice_max")
-
-
 def test_index_offsets_compact_and_wide():
     """Mixed cases without walls read 16-bit neighbour offsets when every
     offset of the step fits (Taylor-Green), and the full indices otherwise
     (a long periodic strip); both agree with the FP64 path."""
     sisph = _gpu()
     for case, expect in ((cases.taylor_green(60, kernel="wendland", hdx=1.3, precision="mixed", seed=2), 2),
-                         (_long_strip(), 4)):
+                         (cases.long_strip(), 4)):
         a = sisph.Context(case)
         b = sisph.Context(case.replace(precision="fp64"))
         sa = a.step(2)
