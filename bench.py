@@ -292,8 +292,7 @@ def main():
     ctx = sisph.Context(case, device="cuda:0")
     print(f"[bench] workload {args.workload}: {case.n_fluid} fluid + {case.n_wall} wall particles, "
           f"workspace {ctx.nbytes / 1e6:.1f} MB", file=sys.stderr, flush=True)
-    if args.warmup:
-        ctx.step(args.warmup)
+    warm = ctx.step(args.warmup) if args.warmup else []
     tuned = None
     if args.warmup and not args.no_autotune:
         # the project's autotuner picks the sweep launch variant on the live
@@ -308,22 +307,43 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    # per-step sweep counts of this process's solves, warmup first (the
+    # profile summaries turn per-launch counters into per-sweep figures)
+    print(f"[bench] solve sweep counts: {[s['iters'] for s in warm] + [s['iters'] for s in stats]}",
+          file=sys.stderr, flush=True)
     iters = sum(s["iters"] for s in stats)
     value = case.n_fluid * iters / elapsed if elapsed > 0 else 0.0
     cnt = ctx.sweep_counters()
     wall_rows = ctx.rows_with_neighbours(1, 1) if case.n_wall else 0
     sb = sweep_bytes(case, ctx.pair_count(1, 0), index_bytes=stats[-1]["index_bytes"] if stats else 4,
                      wall_pairs=ctx.pair_count(1, 1) if case.n_wall else 0, wall_rows=wall_rows)
-    avg_launch_s = cnt["sweep_ms"] / 1e3 / max(cnt["launches"], 1)
+    # Per-launch mode: one launch per sweep (with the wall pass before it in
+    # cases with walls).  Persistent mode: one launch per solve holding all
+    # its sweeps; the algorithmic bytes of a launch are then those of its
+    # sweeps.  Either way achieved = algorithmic bytes of the sweeps that
+    # advanced the solves / the HIP-event time of the launches.
+    pinfo = ctx.persistent_info()
+    persistent = pinfo["solves"] > 0
+    launches = pinfo["solves"] if persistent else cnt["launches"]
+    avg_launch_s = cnt["sweep_ms"] / 1e3 / max(launches, 1)
     achieved = sb["bytes"] * cnt["effective"] / (cnt["sweep_ms"] / 1e3) / 1e9 if cnt["sweep_ms"] > 0 else 0.0
     traffic = traffic_from_profiles(kernel_sha(), args.workload)
+    if persistent:
+        kernel = "k_ppe_persistent (one launch per solve)"
+    else:
+        kernel = "Sweep+WallPressure" if case.n_wall else "Sweep"
+    sweeps_per_launch = cnt["launches"] / max(launches, 1)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "Sweep+WallPressure" if case.n_wall else "Sweep",
-                "avg_launch_us": round(avg_launch_s * 1e6, 3),
-                "launches": cnt["launches"], "effective_launches": cnt["effective"],
-                "algorithmic_bytes_per_launch": sb["bytes"], "bytes_per_row": sb["per_row"],
-                "bytes_per_pair": sb["per_pair"], "pairs": sb["pairs"]}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(traffic * sweeps_per_launch) if traffic is not None else None,
+                "traffic_per_sweep": round(traffic) if traffic is not None else None,
+                "kernel": kernel, "mode": "persistent" if persistent else "per-sweep launches",
+                "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches": launches,
+                "sweeps": cnt["launches"], "effective_sweeps": cnt["effective"],
+                "avg_sweep_us": round(cnt["sweep_ms"] * 1e3 / max(cnt["launches"], 1), 3),
+                "algorithmic_bytes_per_sweep": sb["bytes"],
+                "algorithmic_bytes_per_launch": int(round(sb["bytes"] * cnt["effective"] / max(launches, 1))),
+                "bytes_per_row": sb["per_row"], "bytes_per_pair": sb["per_pair"], "pairs": sb["pairs"]}
     if case.n_wall:
         roofline.update(wall_rows=sb["wall_rows"], wall_pairs=sb["wall_pairs"],
                         bytes_per_wall_row=sb["per_wall_row"], bytes_per_wall_pair=sb["per_wall_pair"])

@@ -205,11 +205,16 @@ int32_t sisph_last_timings(sisph_ctx *ctx, double *ppe_ms, double *step_ms);
 
 /* Accumulated since the last reset: HIP-event time of the Jacobi sweep
  * chunks (each chunk = sweeps queued back to back, with the wall-pressure
- * kernel of each sweep when the case has walls), the number of sweep
- * launches, and the number of launches that did a sweep (the rest found
- * the solve already finished).  reset != 0 clears after reading. */
+ * kernel of each sweep when the case has walls; for a persistent solve, its
+ * one launch), the number of sweeps run (per-launch: one per launch), and
+ * the number of those that advanced the solve (the rest found it already
+ * finished).  reset != 0 clears after reading. */
 int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_t *launches,
                              int64_t *effective, int32_t reset);
+
+/* Persistent solves (see sisph_set_persistent) since the last counter reset
+ * (kernel launches, one per solve), and whether the last solve was one. */
+int32_t sisph_persistent_info(sisph_ctx *ctx, int64_t *solves, int32_t *last);
 
 /* Graph replay of the fixed parts of a step (the data-dependent PPE loop
  * stays a sequence of polled launch chunks with device-side early exit):

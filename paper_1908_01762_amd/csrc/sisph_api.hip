@@ -38,6 +38,8 @@ struct sisph_ctx {
     bool use_graphs = false;
     bool use_persistent = true;                                // one-launch solves where they apply
     int64_t persist_cap[3] = {-1, -1, -1};                     // per first-batch size, -1: not asked yet
+    int64_t persist_solves = 0;                                // since the counter reset
+    bool persist_last = false;
     hipStream_t cap_stream = nullptr;                          // capture only
     hipGraphExec_t g_pre = nullptr, g_post = nullptr;          // fixed step segments
     std::string err;
@@ -665,6 +667,7 @@ static bool persistent_ok(sisph_ctx *ctx) {
 }
 
 static int32_t ppe_run(sisph_ctx *ctx, int64_t predicted, int64_t limit) {
+    ctx->persist_last = false;
     if (persistent_ok(ctx)) {
         HIPCHK(ctx, hipEventRecord(ctx->evc[0], ctx->stream));
         const hipError_t e = ppe_persistent(ctx->T, (int)limit);
@@ -677,6 +680,8 @@ static int32_t ppe_run(sisph_ctx *ctx, int64_t predicted, int64_t limit) {
             HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->evc[0], ctx->evc[1]));
             ctx->sweep_ms += ms;
             ctx->sweep_launches += ctx->h_ctl->iter + 1;   // sweeps run, the one after the stop included
+            ctx->persist_solves += 1;
+            ctx->persist_last = true;
             return SISPH_OK;
         }
         (void)hipGetLastError();   // refused (e.g. not all workgroups resident): per-launch sweeps
@@ -1020,7 +1025,15 @@ extern "C" int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_
     if (reset) {
         ctx->sweep_ms = 0.0;
         ctx->sweep_launches = ctx->sweep_effective = 0;
+        ctx->persist_solves = 0;
     }
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_persistent_info(sisph_ctx *ctx, int64_t *solves, int32_t *last) {
+    if (!ctx) return SISPH_E_INVAL;
+    if (solves) *solves = ctx->persist_solves;
+    if (last) *last = ctx->persist_last ? 1 : 0;
     return SISPH_OK;
 }
 
