@@ -231,8 +231,12 @@ int32_t sisph_set_graphs(sisph_ctx *ctx, int32_t on);
  * workgroups meet at a grid barrier between sweeps and the host waits once
  * per solve instead of polling between chunks of launches.  Results and
  * sweep counts are bitwise those of the per-launch sweeps.  on = 0 keeps
- * the per-launch sweeps (used to compare the two).  A barrier that does not
- * fill in time ends the solve with SISPH_E_DEVICE. */
+ * the per-launch sweeps (used to compare the two).  The launch needs the
+ * device's compute units to itself: a persistent solve of another context
+ * running at the same time on the same device can keep a workgroup from
+ * starting, and a barrier that does not fill in time ends the solve with
+ * SISPH_E_DEVICE (the pressure iterate is then not valid).  Contexts solved
+ * concurrently on one device should turn it off. */
 int32_t sisph_set_persistent(sisph_ctx *ctx, int32_t on);
 
 int32_t sisph_destroy(sisph_ctx *ctx);
