@@ -8,8 +8,10 @@ throughput: fluid particles x Jacobi sweeps done in the timed steps, divided
 by the wall-clock of those steps (bracketed by device synchronisation).
 
 The JSON line also carries the roofline of the dominant kernel (the Jacobi
-sweep), timed live with HIP events on the library's stream, and the CPU
-oracle's rate on a bounded sample of the same case.
+sweep: one launch per sweep, or, for a wall-less case that fits on the
+device, one persistent launch per solve holding all its sweeps), timed live
+with HIP events on the library's stream, and the CPU oracle's rate on a
+bounded sample of the same case.
 """
 from __future__ import annotations
 
