@@ -82,29 +82,45 @@ __device__ __forceinline__ int cell_coord(double x, const Grid &g, int k) {
 
 // Stencil cells per axis: c-1, c, c+1, wrapped on periodic axes, skipped
 // outside the grid otherwise, each cell at most once.
+// The 3^D cell stencil of a cell: per dimension the cells at offsets -1, 0,
+// +1 (wrapped on periodic axes), in that order, in fixed slots; a slot is
+// off when it falls outside a non-periodic grid or repeats an earlier slot
+// (a periodic axis of fewer than three cells).  Dimensions beyond D hold
+// cell 0 in slot 0 only.  Loops over the slots unroll, so the struct stays
+// in registers.
 struct Stencil {
     int v[3][3];
-    int n[3];
+    bool ok[3][3];
 };
 
 template <int D>
 __device__ __forceinline__ void make_stencil(const Grid &g, const int ci[3], Stencil &st) {
-    for (int k = 0; k < 3; ++k) {
-        st.n[k] = 1;
-        st.v[k][0] = 0;
-    }
-    for (int k = 0; k < D; ++k) {
-        int n = 0;
-        for (int o = -1; o <= 1; ++o) {
-            int c = ci[k] + o;
-            if (g.per[k]) c = (c + g.nc[k]) % g.nc[k];
-            else if (c < 0 || c >= g.nc[k]) continue;
-            bool dup = false;
-            for (int t = 0; t < n; ++t) dup |= (st.v[k][t] == c);
-            if (!dup) st.v[k][n++] = c;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            st.v[k][s] = 0;
+            st.ok[k][s] = s == 0;
         }
-        st.n[k] = n;
-    }
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            int c = ci[k] + s - 1;
+            bool ok = true;
+            if (g.per[k]) c = (c + g.nc[k]) % g.nc[k];
+            else ok = c >= 0 && c < g.nc[k];
+#pragma unroll
+            for (int t = 0; t < s; ++t) ok = ok && !(st.ok[k][t] && st.v[k][t] == c);
+            st.v[k][s] = c;
+            st.ok[k][s] = ok;
+        }
+}
+
+// arr[idx] for idx < 3 by selects (no dynamically indexed local array)
+template <typename T>
+__device__ __forceinline__ T pick3(const T (&arr)[3], int idx) {
+    return idx == 0 ? arr[0] : (idx == 1 ? arr[1] : arr[2]);
 }
 
 __device__ __forceinline__ int64_t stencil_cell(const Grid &g, const Stencil &st, int a, int b, int e) {
@@ -590,15 +606,19 @@ struct BuildFluid {
             make_stencil<D>(g, ci, st);
             S.nbr[i] = (int32_t)i;
         }
-        const int na = D == 3 ? 3 : 1;
+        constexpr int na = D == 3 ? 3 : 1;
         for (int a = 0; a < na; ++a)
             for (int b = 0; b < 3; ++b) {
-                const bool row_ok = live && a < st.n[2] && b < st.n[1];
+                // this stencil row's cells: (va, vb, v[0][e]) for the slots e on
+                const bool row_ok = live && pick3(st.ok[2], a) && pick3(st.ok[1], b);
+                const int64_t row_base = ((int64_t)pick3(st.v[2], a) * g.nc[1] + pick3(st.v[1], b)) * g.nc[0];
                 // the cell-id range of this stencil row over the workgroup
                 long long lo = LLONG_MAX, hi = -1;
                 if (row_ok)
-                    for (int e = 0; e < st.n[0]; ++e) {
-                        const long long cc = stencil_cell(g, st, a, b, e);
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) {
+                        if (!st.ok[0][e]) continue;
+                        const long long cc = row_base + st.v[0][e];
                         lo = cc < lo ? cc : lo;
                         hi = cc > hi ? cc : hi;
                     }
@@ -644,8 +664,10 @@ struct BuildFluid {
                 }
                 __syncthreads();
                 if (row_ok)
-                    for (int e = 0; e < st.n[0]; ++e) {
-                        const int64_t cell = stencil_cell(g, st, a, b, e);
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) {
+                        if (!st.ok[0][e]) continue;
+                        const int64_t cell = row_base + st.v[0][e];
                         if (cell < s_lo || cell > s_hi) {
                             test_cell_global<D>(P, S, x, items, i, xi, cell, c);
                             continue;
@@ -700,9 +722,13 @@ struct BuildWall {
         make_stencil<D>(g, ci, st);
         int c = 0;
         const int cap = P.cap;
-        for (int a = 0; a < st.n[2]; ++a)
-            for (int b = 0; b < st.n[1]; ++b)
-                for (int e = 0; e < st.n[0]; ++e) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    if (!(st.ok[2][a] && st.ok[1][b] && st.ok[0][e])) continue;
                     const int64_t cell = stencil_cell(g, st, a, b, e);
                     for (uint32_t t = S.fstart[cell]; t < S.fstart[cell + 1]; ++t) {
                         const int64_t j = items ? (int64_t)items[t] : (int64_t)t;
@@ -747,9 +773,13 @@ struct WallNormals {
         Stencil st;
         make_stencil<D>(g, ci, st);
         double a[3] = {0, 0, 0};
-        for (int aa = 0; aa < st.n[2]; ++aa)
-            for (int b = 0; b < st.n[1]; ++b)
-                for (int e = 0; e < st.n[0]; ++e) {
+#pragma unroll
+        for (int aa = 0; aa < 3; ++aa)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    if (!(st.ok[2][aa] && st.ok[1][b] && st.ok[0][e])) continue;
                     const int64_t cell = stencil_cell(g, st, aa, b, e);
                     for (uint32_t t = S.wstart[cell]; t < S.wstart[cell + 1]; ++t) {
                         const int64_t j = nf + t;
