@@ -33,6 +33,7 @@ struct sisph_ctx {
     double sweep_ms;
     int64_t sweep_launches, sweep_effective;
     bool step_timed;
+    bool step_pending = false;   // the last step's end event is recorded, its time not yet read
     sisph_batch *batch;  // non-null while attached
     int32_t variant;     // Jacobi-sweep launch variant
     bool use_graphs = false;
@@ -735,12 +736,7 @@ extern "C" int32_t sisph_correct(sisph_ctx *ctx) {
     seq_correct(ctx->T, ctx->P.gtvf_K);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
-    if (ctx->step_timed) {
-        HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
-        float ms = 0.f;
-        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
-        ctx->step_ms = ms;
-    }
+    ctx->step_pending = ctx->step_timed;   // read when asked: the host does not wait for the step here
     ctx->state = ST_READY;
     return SISPH_OK;
 }
@@ -778,6 +774,7 @@ static int32_t step_graphed(sisph_ctx *ctx, sisph_step_stats *out) {
     ctx->ppe_ms = ms;   // the sweeps (set-up and settle are inside the graphs)
     HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
     ctx->step_ms = ms;
+    ctx->step_pending = false;
     const Control &C = *ctx->h_ctl;
     ctx->sweep_effective += C.iter;
     record_iters(ctx, C.iter);
@@ -1011,6 +1008,13 @@ extern "C" int32_t sisph_debug_neighbors(sisph_ctx *ctx, int32_t stage, int32_t 
 
 extern "C" int32_t sisph_last_timings(sisph_ctx *ctx, double *ppe_ms, double *step_ms) {
     if (!ctx) return SISPH_E_INVAL;
+    if (ctx->step_pending) {
+        HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
+        float ms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
+        ctx->step_ms = ms;
+        ctx->step_pending = false;
+    }
     if (ppe_ms) *ppe_ms = ctx->ppe_ms;
     if (step_ms) *step_ms = ctx->step_ms;
     return SISPH_OK;
