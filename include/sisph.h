@@ -234,10 +234,16 @@ int32_t sisph_set_graphs(sisph_ctx *ctx, int32_t on);
  * the per-launch sweeps (used to compare the two).  The launch needs the
  * device's compute units to itself: a persistent solve of another context
  * running at the same time on the same device can keep a workgroup from
- * starting, and a barrier that does not fill in time ends the solve with
- * SISPH_E_DEVICE (the pressure iterate is then not valid).  Contexts solved
- * concurrently on one device should turn it off. */
+ * starting.  Every wait in the launch is bounded; when a barrier does not
+ * fill in time the solve is redone from its starting iterate with
+ * per-launch sweeps (same results), and the context keeps those from then
+ * on.  Contexts solved concurrently on one device should turn the mode off
+ * (each timeout costs a fraction of a second). */
 int32_t sisph_set_persistent(sisph_ctx *ctx, int32_t on);
+
+/* Test hook: the number of polls after which a wait of the persistent
+ * solve gives up (0: at once, which exercises the fallback above). */
+int32_t sisph_debug_barrier_spins(sisph_ctx *ctx, uint32_t spins);
 
 int32_t sisph_destroy(sisph_ctx *ctx);
 

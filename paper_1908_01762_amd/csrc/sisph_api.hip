@@ -134,6 +134,7 @@ static int32_t neighbour_cap(const sisph_case_desc *d) {
 
 static Params make_params(const sisph_case_desc *d) {
     Params P{};
+    P.barrier_spins = kBarrierSpins;
     P.dim = d->dim;
     P.kernel = d->kernel;
     P.precision = d->precision;
@@ -670,13 +671,26 @@ static bool persistent_ok(sisph_ctx *ctx) {
 static int32_t ppe_run(sisph_ctx *ctx, int64_t predicted, int64_t limit) {
     ctx->persist_last = false;
     if (persistent_ok(ctx)) {
+        // the starting iterate, kept in the binning scratch (unused during the
+        // solve) in case the launch has to be redone with per-launch sweeps
+        const size_t pbytes = sizeof(double) * (size_t)ctx->P.ntot;
+        HIPCHK(ctx, hipMemcpyAsync(ctx->S.tmp, ctx->S.p[0], pbytes, hipMemcpyDeviceToDevice, ctx->stream));
         HIPCHK(ctx, hipEventRecord(ctx->evc[0], ctx->stream));
         const hipError_t e = ppe_persistent(ctx->T, (int)limit);
         if (e == hipSuccess) {
             HIPCHK(ctx, hipEventRecord(ctx->evc[1], ctx->stream));
             int32_t st = read_ctl(ctx);
             if (st != SISPH_OK) return st;
-            if (ctx->h_ctl->barrier_late) return fail(ctx, SISPH_E_DEVICE, "persistent solve: a grid barrier timed out");
+            if (ctx->h_ctl->barrier_late) {
+                // a workgroup never reached a barrier (the device was shared,
+                // say): restore the starting iterate, set the solve up again
+                // and run it with per-launch sweeps; this context keeps them
+                for (auto &cap : ctx->persist_cap) cap = 0;
+                HIPCHK(ctx, hipMemcpyAsync(ctx->S.p[0], ctx->S.tmp, pbytes, hipMemcpyDeviceToDevice, ctx->stream));
+                seq_ppe_begin(ctx->T);
+                HIPCHK(ctx, hipGetLastError());
+                return ppe_run(ctx, predicted, limit);
+            }
             float ms = 0.f;
             HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->evc[0], ctx->evc[1]));
             ctx->sweep_ms += ms;
@@ -1031,6 +1045,12 @@ extern "C" int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_
         ctx->sweep_launches = ctx->sweep_effective = 0;
         ctx->persist_solves = 0;
     }
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_debug_barrier_spins(sisph_ctx *ctx, uint32_t spins) {
+    if (!ctx) return SISPH_E_INVAL;
+    ctx->P.barrier_spins = spins;
     return SISPH_OK;
 }
 

@@ -33,6 +33,8 @@ struct Params {
     int32_t adaptive_dt;    // next dt from this step's maxima
     int32_t solver;         // SISPH_JACOBI or SISPH_BICGSTAB
     int32_t compact;        // mixed mode without walls: 16-bit neighbour offsets
+    uint32_t barrier_spins; // polls before a wait of the persistent solve gives up
+    int32_t pad0;
     int64_t nf, nw, ntot;
     // dt: the fixed step, or the first step and the upper bound when adaptive
     // (kernels read the current step's dt from Control)

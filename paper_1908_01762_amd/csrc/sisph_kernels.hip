@@ -1477,7 +1477,7 @@ struct Sweep {
 // count are bitwise the same.  What other workgroups read during the launch
 // (the gathered iterate, the partial sums, these words) is written and read
 // with device-scope accesses, which are coherent across XCDs without a
-// cache write-back.  A wait that does not end within kBarrierSpins polls
+// cache write-back.  A wait that does not end within P.barrier_spins polls
 // sets a flag and every workgroup leaves (the host reports the error).
 template <typename T>
 __device__ __forceinline__ T dev_load(const T *p) {
@@ -1602,7 +1602,7 @@ __global__ __launch_bounds__(kBlock) void k_ppe_persistent(const Params P, const
                     const int64_t k = threadIdx.x + (int64_t)t * kBlock;
                     if (k < nblk && dev_load(arrive + k) < (uint32_t)(L + 1)) ok = false;
                 }
-                const int give_up = threadIdx.x == 0 && (dev_load(late_flag) != 0u || spins >= kBarrierSpins);
+                const int give_up = threadIdx.x == 0 && (dev_load(late_flag) != 0u || spins >= P.barrier_spins);
                 all = __syncthreads_and(ok);
                 const bool quit = __syncthreads_or(give_up);
                 if (all || quit) break;
@@ -1621,7 +1621,7 @@ __global__ __launch_bounds__(kBlock) void k_ppe_persistent(const Params P, const
         } else if (threadIdx.x == 0) {
             const uint32_t *w = S.sync + kSyncBcast + 64 * (blk % kSyncCopies);
             uint32_t word = dev_load(w);
-            for (uint32_t spins = 0; word < want && dev_load(late_flag) == 0u && spins < kBarrierSpins; ++spins) {
+            for (uint32_t spins = 0; word < want && dev_load(late_flag) == 0u && spins < P.barrier_spins; ++spins) {
                 __builtin_amdgcn_s_sleep(1);
                 word = dev_load(w);
             }

@@ -97,6 +97,8 @@ def lib():
         L.sisph_set_graphs.argtypes = [C.c_void_p, C.c_int32]
         L.sisph_set_persistent.restype = C.c_int32
         L.sisph_set_persistent.argtypes = [C.c_void_p, C.c_int32]
+        L.sisph_debug_barrier_spins.restype = C.c_int32
+        L.sisph_debug_barrier_spins.argtypes = [C.c_void_p, C.c_uint32]
         L.sisph_persistent_info.restype = C.c_int32
         L.sisph_persistent_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         L.sisph_batch_set_graphs.restype = C.c_int32
@@ -326,6 +328,10 @@ class Context:
         ms, n, e = C.c_double(), C.c_int64(), C.c_int64()
         _check(lib().sisph_sweep_counters(self.h, C.byref(ms), C.byref(n), C.byref(e), int(reset)), self.h)
         return dict(sweep_ms=ms.value, launches=n.value, effective=e.value)
+
+    def debug_barrier_spins(self, spins: int):
+        """Test hook: polls before a persistent-solve wait gives up."""
+        _check(lib().sisph_debug_barrier_spins(self.h, int(spins)), self.h)
 
     def persistent_info(self):
         """Persistent solves since the counter reset, and whether the last

@@ -94,3 +94,24 @@ def test_persistent_nonfinite_is_reported():
             ctx.step(1)
         assert e.value.code == sisph.E_NONFINITE
         ctx.close()
+
+
+def test_barrier_timeout_falls_back_to_per_launch_sweeps():
+    """A barrier that gives up (forced from the host: the waits give up at
+    once) makes the library redo the solve from its starting iterate with
+    per-launch sweeps: the same results, and the context keeps them."""
+    sisph = _gpu()
+    case = cases.taylor_green(40, kernel="wendland", hdx=1.3, precision="mixed")
+    ctx = sisph.Context(case)
+    ctx.debug_barrier_spins(0)
+    ctx.sweep_counters(reset=True)
+    st = ctx.step(3)
+    a = ctx.read_state()
+    info = ctx.persistent_info()
+    ctx.close()
+    b, ib, _ = _run(sisph, case, False, 3)
+    say("  fallback iters", [x["iters"] for x in st], ib, info)
+    assert [x["iters"] for x in st] == ib
+    assert info["solves"] == 0 and not info["last"]
+    for k in ("x", "u", "ut", "p", "rho"):
+        assert np.array_equal(a[k], b[k]), k
