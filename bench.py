@@ -129,7 +129,26 @@ def cpu_baseline(case, budget_s: float) -> dict:
     return {"value": case.n_fluid * iters / dt, "unit": "particle-iters/s", "cores": 1, "kind": "oracle",
             "sample": f"first {steps} step(s) of the same case ({iters} Jacobi sweeps, {case.n_fluid} fluid "
                       f"particles), {dt:.1f} s on one host core; serial FP64 C oracle",
-            "particle_steps_per_s": case.n_fluid * steps / dt}
+            "particle_steps_per_s": case.n_fluid * steps / dt, "host": host_info()}
+
+
+def host_info() -> dict:
+    """The host the oracle ran on: logical CPUs, those this process may use,
+    and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
 
 
 def batched_vs_plain(n_cases: int, steps: int, seed: int) -> dict:
