@@ -34,6 +34,7 @@ struct sisph_ctx {
     int64_t sweep_launches, sweep_effective;
     bool step_timed;
     bool step_pending = false;   // the last step's end event is recorded, its time not yet read
+    bool ppe_pending = false;    // the same for the last solve (ev[1] .. ev[2])
     sisph_batch *batch;  // non-null while attached
     int32_t variant;     // Jacobi-sweep launch variant
     bool use_graphs = false;
@@ -304,6 +305,18 @@ static int32_t upload_vec(sisph_ctx *ctx, double *const dst[3], int64_t at, cons
 static int32_t read_ctl(sisph_ctx *ctx) {
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_ctl, ctx->S.ctl, sizeof(Control), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SISPH_OK;
+}
+
+// The last solve's time, when the host did not wait for its end; done
+// before its events are recorded again.
+static int32_t settle_ppe_time(sisph_ctx *ctx) {
+    if (!ctx->ppe_pending) return SISPH_OK;
+    HIPCHK(ctx, hipEventSynchronize(ctx->ev[2]));
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+    ctx->ppe_ms = ms;
+    ctx->ppe_pending = false;
     return SISPH_OK;
 }
 
@@ -718,19 +731,31 @@ extern "C" int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out) {
     if (ctx->state != ST_PREDICTED) return fail(ctx, SISPH_E_STATE, "sisph_ppe_solve needs sisph_predict first");
     const Params &P = ctx->P;
     hipStream_t s = ctx->stream;
+    int32_t st = settle_ppe_time(ctx);
+    if (st != SISPH_OK) return st;
     HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
     seq_ppe_begin(ctx->T);
     const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1;
     const int64_t predicted = predict_iters(ctx);
     const int before = 0;
-    int32_t st = ppe_run(ctx, predicted, limit);
+    st = ppe_run(ctx, predicted, limit);
     if (st != SISPH_OK) return st;
+    // A persistent solve's control block, read at its end, already holds all
+    // that the stats report once p_ref is set: the settle then only moves the
+    // final iterate into buffer 0 (no walls, the maximum-pressure pass does
+    // nothing), so the host does not wait for it and goes on queueing.
+    const bool no_wait = ctx->persist_last && ctx->h_ctl->p_ref_set;
     seq_ppe_end(ctx->T);
     HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
-    if ((st = read_ctl(ctx)) != SISPH_OK) return st;
-    float ms = 0.f;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
-    ctx->ppe_ms = ms;
+    if (no_wait) {
+        HIPCHK(ctx, hipGetLastError());
+        ctx->ppe_pending = true;
+    } else {
+        if ((st = read_ctl(ctx)) != SISPH_OK) return st;
+        float ms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+        ctx->ppe_ms = ms;
+    }
     const Control &C = *ctx->h_ctl;
     ctx->sweep_effective += C.iter - before;
     record_iters(ctx, C.iter);
@@ -772,6 +797,8 @@ static int32_t step_graphed(sisph_ctx *ctx, sisph_step_stats *out) {
             return fail(ctx, SISPH_E_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
         }
     }
+    const int32_t pst = settle_ppe_time(ctx);
+    if (pst != SISPH_OK) return pst;
     HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
     HIPCHK(ctx, hipGraphLaunch(ctx->g_pre, s));
     HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
@@ -1022,6 +1049,8 @@ extern "C" int32_t sisph_debug_neighbors(sisph_ctx *ctx, int32_t stage, int32_t 
 
 extern "C" int32_t sisph_last_timings(sisph_ctx *ctx, double *ppe_ms, double *step_ms) {
     if (!ctx) return SISPH_E_INVAL;
+    const int32_t st = settle_ppe_time(ctx);
+    if (st != SISPH_OK) return st;
     if (ctx->step_pending) {
         HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
         float ms = 0.f;

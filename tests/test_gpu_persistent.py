@@ -53,7 +53,7 @@ def _run(sisph, case, persistent, steps):
     s = ctx.read_state()
     c = ctx.sweep_counters()
     ctx.close()
-    return s, [x["iters"] for x in st], c
+    return s, st, c
 
 
 @pytest.mark.parametrize("name", list(_cases().keys()))
@@ -61,10 +61,13 @@ def test_persistent_equals_per_launch(name):
     sisph = _gpu()
     case = _cases()[name]
     say("case", name, case.n_fluid, case.precision)
-    a, ia, ca = _run(sisph, case, True, 4)
-    b, ib, cb = _run(sisph, case, False, 4)
+    a, sa, ca = _run(sisph, case, True, 4)
+    b, sb, cb = _run(sisph, case, False, 4)
+    ia, ib = [x["iters"] for x in sa], [x["iters"] for x in sb]
     say("  iters", ia, "counters persistent", ca, "per-launch", cb)
     assert ia == ib
+    # every reported field (the persistent path reads them before the settle)
+    assert sa == sb
     assert ca["effective"] == cb["effective"]
     for k in ("x", "u", "ut", "p", "rho"):
         assert np.array_equal(a[k], b[k]), k
@@ -109,9 +112,33 @@ def test_barrier_timeout_falls_back_to_per_launch_sweeps():
     a = ctx.read_state()
     info = ctx.persistent_info()
     ctx.close()
-    b, ib, _ = _run(sisph, case, False, 3)
-    say("  fallback iters", [x["iters"] for x in st], ib, info)
-    assert [x["iters"] for x in st] == ib
+    b, sb, _ = _run(sisph, case, False, 3)
+    say("  fallback iters", [x["iters"] for x in st], [x["iters"] for x in sb], info)
+    assert st == sb
     assert info["solves"] == 0 and not info["last"]
     for k in ("x", "u", "ut", "p", "rho"):
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_timings_when_the_host_does_not_wait_for_the_settle():
+    """After a persistent solve (p_ref set) the host queues the settle and
+    the next stages without waiting; the solve and step times are read
+    from their events later, through step() and through the staged calls."""
+    sisph = _gpu()
+    case = cases.taylor_green(60, kernel="wendland", hdx=1.3, precision="mixed")
+    ctx = sisph.Context(case)
+    st = ctx.step(3)
+    assert ctx.persistent_info()["last"]
+    ppe, step = ctx.timings()
+    say("  step():", st[-1]["iters"], "sweeps, ppe", ppe, "ms, step", step, "ms")
+    assert 0.0 < ppe <= step
+    ctx.bin()
+    ctx.predict()
+    ctx.ppe_solve()
+    ctx.correct()
+    ppe2, step2 = ctx.timings()
+    say("  staged:", "ppe", ppe2, "ms, step", step2, "ms")
+    assert 0.0 < ppe2 <= step2
+    assert ctx.timings() == (ppe2, step2)
+    ctx.close()
+
