@@ -31,6 +31,12 @@
  * memory owned by the caller (for instance a torch uint8 tensor); the
  * library sub-allocates it and never frees it.  A context is not
  * thread-safe; distinct contexts on distinct streams are independent.
+ * Work is queued on the context's stream and a call may return before its
+ * last kernels finish (sisph_correct; the settle of the final iterate at
+ * the end of sisph_ppe_solve once its reference pressure is set, for a
+ * case solved in one persistent launch); calls that return host data wait
+ * for the stream, so the workspace is consistent only after such a call or
+ * a synchronisation of the stream.
  * Every function returns a status code and never throws.
  */
 #ifndef SISPH_H
