@@ -283,6 +283,9 @@ def main():
     ap.add_argument("--compare-dx", type=float, default=0.01)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default sweep variant instead of autotuning it after the warmup")
+    ap.add_argument("--launch", choices=("eager", "graphs"), default="eager",
+                    help="launch the fixed parts of each step one kernel at a time, or replay them "
+                         "from HIP graphs")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a counter calibration "
                          "reference for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -311,6 +314,8 @@ def main():
         del src, dst
     case = make_case(args.workload)
     ctx = sisph.Context(case, device="cuda:0")
+    if args.launch == "graphs":
+        ctx.use_graphs(True)
     print(f"[bench] workload {args.workload}: {case.n_fluid} fluid + {case.n_wall} wall particles, "
           f"workspace {ctx.nbytes / 1e6:.1f} MB", file=sys.stderr, flush=True)
     warm = ctx.step(args.warmup) if args.warmup else []
@@ -383,7 +388,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "fluid_particles": case.n_fluid, "wall_particles": case.n_wall,
-                   "parallelism": "single GPU"},
+                   "launch": args.launch, "parallelism": "single GPU"},
         "mean_ppe_iters": iters / max(len(stats), 1),
         "particle_steps_per_s": case.n_fluid * args.steps / elapsed if elapsed > 0 else 0.0,
         "sweep_time_frac": cnt["sweep_ms"] / 1e3 / elapsed if elapsed > 0 else 0.0,

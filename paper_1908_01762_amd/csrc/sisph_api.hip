@@ -308,6 +308,21 @@ static int32_t read_ctl(sisph_ctx *ctx) {
     return SISPH_OK;
 }
 
+// The last step's time if its end has passed, else the previous value
+// stays; done, without waiting, before the step's start event is recorded
+// again.  A not-ready query is no error and is not left behind as one.
+static void settle_step_time_if_done(sisph_ctx *ctx) {
+    if (!ctx->step_pending) return;
+    const hipError_t q = hipEventQuery(ctx->ev[3]);
+    if (q == hipSuccess) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]) == hipSuccess) ctx->step_ms = ms;
+    } else if (q == hipErrorNotReady) {
+        (void)hipGetLastError();
+    }
+    ctx->step_pending = false;
+}
+
 // The last solve's time, when the host did not wait for its end; done
 // before its events are recorded again.
 static int32_t settle_ppe_time(sisph_ctx *ctx) {
@@ -588,6 +603,7 @@ extern "C" int32_t sisph_bin(sisph_ctx *ctx) {
     if (!ctx) return SISPH_E_INVAL;
     if (attached(ctx)) return fail(ctx, SISPH_E_STATE, "context is attached to a batch");
     if (ctx->state != ST_READY) return fail(ctx, SISPH_E_STATE, "sisph_bin needs a completed step");
+    settle_step_time_if_done(ctx);
     HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
     seq_bin(ctx->T);
     HIPCHK(ctx, hipGetLastError());
@@ -799,6 +815,7 @@ static int32_t step_graphed(sisph_ctx *ctx, sisph_step_stats *out) {
     }
     const int32_t pst = settle_ppe_time(ctx);
     if (pst != SISPH_OK) return pst;
+    settle_step_time_if_done(ctx);
     HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
     HIPCHK(ctx, hipGraphLaunch(ctx->g_pre, s));
     HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
@@ -806,16 +823,24 @@ static int32_t step_graphed(sisph_ctx *ctx, sisph_step_stats *out) {
     const int64_t predicted = predict_iters(ctx);
     int32_t st = ppe_run(ctx, predicted, limit);
     if (st != SISPH_OK) return st;
+    // as in sisph_ppe_solve: after a persistent solve with p_ref set, the
+    // control block read at the solve's end is final for the stats
+    const bool no_wait = ctx->persist_last && ctx->h_ctl->p_ref_set;
     HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
     HIPCHK(ctx, hipGraphLaunch(ctx->g_post, s));
     HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
-    if ((st = read_ctl(ctx)) != SISPH_OK) return st;
-    float ms = 0.f;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
-    ctx->ppe_ms = ms;   // the sweeps (set-up and settle are inside the graphs)
-    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
-    ctx->step_ms = ms;
-    ctx->step_pending = false;
+    if (no_wait) {
+        ctx->ppe_pending = true;   // the sweeps (set-up and settle are inside the graphs)
+        ctx->step_pending = true;
+    } else {
+        if ((st = read_ctl(ctx)) != SISPH_OK) return st;
+        float ms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+        ctx->ppe_ms = ms;   // the sweeps (set-up and settle are inside the graphs)
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
+        ctx->step_ms = ms;
+        ctx->step_pending = false;
+    }
     const Control &C = *ctx->h_ctl;
     ctx->sweep_effective += C.iter;
     record_iters(ctx, C.iter);
