@@ -350,6 +350,9 @@ def main():
     # advanced the solves / the HIP-event time of the launches.
     pinfo = ctx.persistent_info()
     persistent = pinfo["solves"] > 0
+    fallbacks = ctx.persistent_fallbacks()
+    print(f"[bench] persistent solves in the timed steps: {pinfo['solves']} of {len(stats)}; "
+          f"fallbacks to per-launch sweeps since creation: {fallbacks}", file=sys.stderr, flush=True)
     launches = pinfo["solves"] if persistent else cnt["launches"]
     avg_launch_s = cnt["sweep_ms"] / 1e3 / max(launches, 1)
     achieved = sb["bytes"] * cnt["effective"] / (cnt["sweep_ms"] / 1e3) / 1e9 if cnt["sweep_ms"] > 0 else 0.0
@@ -364,6 +367,7 @@ def main():
                 "traffic": round(traffic * sweeps_per_launch) if traffic is not None else None,
                 "traffic_per_sweep": round(traffic) if traffic is not None else None,
                 "kernel": kernel, "mode": "persistent" if persistent else "per-sweep launches",
+                "persistent_fallbacks": fallbacks,
                 "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches": launches,
                 "sweeps": cnt["launches"], "effective_sweeps": cnt["effective"],
                 "avg_sweep_us": round(cnt["sweep_ms"] * 1e3 / max(cnt["launches"], 1), 3),

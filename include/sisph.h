@@ -222,6 +222,14 @@ int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_t *launches
  * (kernel launches, one per solve), and whether the last solve was one. */
 int32_t sisph_persistent_info(sisph_ctx *ctx, int64_t *solves, int32_t *last);
 
+/* Since creation, how often a solve meant for one persistent launch ran as
+ * per-launch sweeps instead: the runtime refused the cooperative launch
+ * (it is tried again on later solves; after eight refusals that first-batch
+ * size is given up), or a workgroup waited
+ * longer than the spin limit at a grid barrier (the solve was redone from
+ * its starting iterate; the context keeps per-launch sweeps). */
+int32_t sisph_persistent_fallbacks(sisph_ctx *ctx, int64_t *refused, int64_t *timed_out);
+
 /* Graph replay of the fixed parts of a step (the data-dependent PPE loop
  * stays a sequence of polled launch chunks with device-side early exit):
  * with on != 0, sisph_step captures once, then replays, two HIP graphs per

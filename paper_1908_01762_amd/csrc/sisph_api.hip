@@ -41,6 +41,8 @@ struct sisph_ctx {
     bool use_persistent = true;                                // one-launch solves where they apply
     int64_t persist_cap[3] = {-1, -1, -1};                     // per first-batch size, -1: not asked yet
     int64_t persist_solves = 0;                                // since the counter reset
+    int64_t persist_refused = 0, persist_timeouts = 0;         // fallbacks to per-launch sweeps
+    int32_t persist_refusals[3] = {0, 0, 0};                   // per first-batch size, until it is given up
     bool persist_last = false;
     hipStream_t cap_stream = nullptr;                          // capture only
     hipGraphExec_t g_pre = nullptr, g_post = nullptr;          // fixed step segments
@@ -688,6 +690,8 @@ static int32_t ppe_loop(const Target &T, int64_t predicted, int64_t limit, hipEv
 // fit on the device at once, runs its whole solve as one cooperative launch
 // (ppe_persistent); other cases, or a launch the runtime refuses, take the
 // per-launch sweeps.  Both give the same results and sweep counts.
+constexpr int32_t kPersistRetries = 8;   // refused cooperative launches per first-batch size before giving up
+
 static bool persistent_ok(sisph_ctx *ctx) {
     const Params &P = ctx->P;
     if (!ctx->use_persistent || P.nw > 0 || P.solver != SISPH_JACOBI) return false;
@@ -711,6 +715,7 @@ static int32_t ppe_run(sisph_ctx *ctx, int64_t predicted, int64_t limit) {
             int32_t st = read_ctl(ctx);
             if (st != SISPH_OK) return st;
             if (ctx->h_ctl->barrier_late) {
+                ctx->persist_timeouts += 1;
                 // a workgroup never reached a barrier (the device was shared,
                 // say): restore the starting iterate, set the solve up again
                 // and run it with per-launch sweeps; this context keeps them
@@ -728,8 +733,12 @@ static int32_t ppe_run(sisph_ctx *ctx, int64_t predicted, int64_t limit) {
             ctx->persist_last = true;
             return SISPH_OK;
         }
-        (void)hipGetLastError();   // refused (e.g. not all workgroups resident): per-launch sweeps
-        ctx->persist_cap[ctx->T.variant % 3] = 0;
+        // refused (not all workgroups resident, say, or the device busy with
+        // another process): this solve takes per-launch sweeps; the launch is
+        // tried again on later solves, up to kPersistRetries refusals
+        (void)hipGetLastError();
+        ctx->persist_refused += 1;
+        if (++ctx->persist_refusals[ctx->T.variant % 3] >= kPersistRetries) ctx->persist_cap[ctx->T.variant % 3] = 0;
     }
     auto poll = [&](bool &done) -> int32_t {
         int32_t st = read_ctl(ctx);
@@ -1105,6 +1114,13 @@ extern "C" int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_
 extern "C" int32_t sisph_debug_barrier_spins(sisph_ctx *ctx, uint32_t spins) {
     if (!ctx) return SISPH_E_INVAL;
     ctx->P.barrier_spins = spins;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_persistent_fallbacks(sisph_ctx *ctx, int64_t *refused, int64_t *timed_out) {
+    if (!ctx) return SISPH_E_INVAL;
+    if (refused) *refused = ctx->persist_refused;
+    if (timed_out) *timed_out = ctx->persist_timeouts;
     return SISPH_OK;
 }
 

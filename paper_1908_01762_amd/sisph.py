@@ -101,6 +101,8 @@ def lib():
         L.sisph_debug_barrier_spins.argtypes = [C.c_void_p, C.c_uint32]
         L.sisph_persistent_info.restype = C.c_int32
         L.sisph_persistent_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+        L.sisph_persistent_fallbacks.restype = C.c_int32
+        L.sisph_persistent_fallbacks.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.sisph_batch_set_graphs.restype = C.c_int32
         L.sisph_batch_set_graphs.argtypes = [C.c_void_p, C.c_int32]
         L.sisph_pair_count.restype = C.c_int32
@@ -339,6 +341,13 @@ class Context:
         n, last = C.c_int64(), C.c_int32()
         _check(lib().sisph_persistent_info(self.h, C.byref(n), C.byref(last)), self.h)
         return dict(solves=n.value, last=bool(last.value))
+
+    def persistent_fallbacks(self):
+        """Solves meant for one persistent launch that ran per-launch sweeps
+        instead: cooperative launch refused, or a grid barrier timed out."""
+        r, t = C.c_int64(), C.c_int64()
+        _check(lib().sisph_persistent_fallbacks(self.h, C.byref(r), C.byref(t)), self.h)
+        return dict(refused=r.value, timed_out=t.value)
 
     def close(self):
         if getattr(self, "h", None):
