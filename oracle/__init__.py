@@ -26,6 +26,7 @@ CONV = {"sum": 0, "mean": 1}
 USTAR = {"slip": 0, "noslip": 1}
 DT_MODE = {"fixed": 0, "adaptive": 1}
 SOLVER = {"jacobi": 0, "bicgstab": 1}
+NULL_SPACE = {"none": 0, "project": 1}
 
 
 def build(force: bool = False) -> str:
@@ -42,7 +43,7 @@ class Params(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "dim", "kernel", "pgrad", "gtvf", "free_surface", "p_ref_mode",
         "min_iter", "max_iter", "gtvf_K", "forced_iters", "conv_norm", "ustar_wall", "dt_mode",
-        "solver", "nf", "nw")] + \
+        "solver", "null_space", "nf", "nw")] + \
         [(n, C.c_double) for n in (
             "h", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio", "omega", "tol", "dt_max")] + \
         [("g", C.c_double * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
@@ -58,6 +59,7 @@ class StepOut(C.Structure):
                                    "unew", "fgtvf0")] + \
         [("fs", _I64P), ("iters", C.c_int64), ("converged", C.c_int64),
          ("ratio", C.c_double), ("lambda_", C.c_double), ("p_ref_used", C.c_double),
+         ("beta", C.c_double),
          ("umax", C.c_double), ("fmax", C.c_double), ("dt_next", C.c_double)]
 
 
@@ -109,6 +111,7 @@ def params(case, **over) -> Params:
     P.ustar_wall = USTAR[case.ustar_wall]
     P.dt_mode = DT_MODE[case.dt_mode]
     P.solver = SOLVER[case.solver]
+    P.null_space = NULL_SPACE[case.null_space]
     P.dt_max = float(case.dt)
     P.nf = case.n_fluid
     P.nw = case.n_wall
@@ -271,13 +274,15 @@ class Sim:
             keep["fs"] = np.zeros(nf, dtype=np.int64)
             out.fs = _ptr(keep["fs"])
         x0 = self.x.copy()
-        lib().orc_step(C.byref(P), _ptr(self.x), _ptr(self.u), _ptr(self.ut), _ptr(self.p),
+        rc = lib().orc_step(C.byref(P), _ptr(self.x), _ptr(self.u), _ptr(self.ut), _ptr(self.p),
                        _ptr(self.m), _ptr(np.ascontiguousarray(self.nrm)), _ptr(self.wall_u),
                        C.byref(self.p_ref), C.byref(self.p_ref_set), C.byref(out))
+        if rc != 0:
+            raise ValueError("null_space='project' needs a case without walls or free surface")
         self.t += self.dt
         self.steps += 1
         keep.update(iters=int(out.iters), converged=bool(out.converged), ratio=float(out.ratio),
-                    lam=float(out.lambda_), p_ref=float(out.p_ref_used), dt=self.dt,
+                    lam=float(out.lambda_), p_ref=float(out.p_ref_used), beta=float(out.beta), dt=self.dt,
                     umax=float(out.umax), fmax=float(out.fmax), dt_next=float(out.dt_next))
         self.dt = float(out.dt_next)
         if capture:

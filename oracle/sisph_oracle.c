@@ -385,6 +385,34 @@ static void rhs_coef_c(const orc_params *P, const csr_t *N, const double *x,
     }
 }
 
+/* Fully periodic problems without walls or a free surface (the Taylor-Green
+ * vortex): every row of eq. sph-ppe sums c_ij (p_j - p_i), so a constant
+ * pressure solves the homogeneous system and the operator A = D - C is
+ * singular.  Because m_i rho_i c_ij is symmetric in i and j, y_i = m_i rho_i
+ * is a left null vector (y^T A = 0): the system has a solution only when
+ * y . RHS = 0.  The discrete RHS does not satisfy this exactly (its pair
+ * terms are not antisymmetric on a disordered set), and then each Jacobi
+ * sweep of eq. p-sor shifts the iterate by the same constant w beta, with
+ * beta = (y . RHS) / (y . D); the shift never settles, and the stopping test
+ * of eq. convergence sees it as a change of the pressure.  Reading R24
+ * removes that component once per solve, RHS_i <- RHS_i - beta D_ii; every
+ * iterate then equals the unprojected one minus k w beta after k sweeps
+ * (eq. p-sor maps p + c to its image + c), so only the constant, to which
+ * the asymm pressure force is blind, changes.  Returns beta. */
+static double project_rhs_c(const orc_params *P, const double *m, const double *rho_all,
+                            double *rhs, const double *diag) {
+    double num = 0.0, den = 0.0;
+    for (int64_t i = 0; i < P->nf; ++i) {
+        double y = m[i] * rho_all[i];
+        num += y * rhs[i];
+        den += y * diag[i];
+    }
+    double beta = den != 0.0 ? num / den : 0.0;
+    for (int64_t i = 0; i < P->nf; ++i)
+        if (diag[i] != 0.0) rhs[i] -= beta * diag[i];
+    return beta;
+}
+
 /* Solid-wall pressure, eq. p-shepard: Shepard average of the fluid pressure
  * plus the hydrostatic term (g - a_w) . sum rho_f r_wf W_wf, static wall so
  * a_w = 0; zero when no fluid neighbour; clamped at 0 on free-surface
@@ -710,6 +738,9 @@ int64_t orc_step(const orc_params *P, double *x, double *u, double *ut, double *
                  double *p_ref, int64_t *p_ref_set, orc_step_out *out) {
     int64_t nf = P->nf, nw = P->nw, n = nf + nw, dim = P->dim;
     double dt = P->dt;
+    /* R24 holds only where constants are the null space: no walls (their
+     * hydrostatic term) and no free-surface rows (p = 0 there) */
+    if (P->null_space == ORC_NULL_PROJECT && (nw > 0 || P->free_surface)) return -1;
     size_t nd = (size_t)(n * dim > 0 ? n * dim : 1), n1 = (size_t)(n > 0 ? n : 1);
     double *rho_all = malloc(sizeof(double) * n1);
     double *u_all = calloc(nd, sizeof(double));
@@ -759,6 +790,8 @@ int64_t orc_step(const orc_params *P, double *x, double *u, double *ut, double *
      * non-free-surface fluid with D != 0, reading R2) */
     double *coef = malloc(sizeof(double) * (size_t)(N.off[nf] > 0 ? N.off[nf] : 1));
     rhs_coef_c(P, &N, xs, m, rho_all, us_all, rhs, coef, diag);
+    double beta = 0.0;
+    if (P->null_space == ORC_NULL_PROJECT) beta = project_rhs_c(P, m, rho_all, rhs, diag);
     double lambda = 0.0;
     for (int64_t i = 0; i < nf; ++i)
         if (diag[i] != 0.0 && !fs[i]) {
@@ -897,6 +930,7 @@ int64_t orc_step(const orc_params *P, double *x, double *u, double *ut, double *
         out->iters = k;
         out->ratio = ratio;
         out->lambda = lambda;
+        out->beta = beta;
         out->converged = ratio < P->tol;
         out->p_ref_used = *p_ref;
         out->umax = umax;

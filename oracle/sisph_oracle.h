@@ -23,6 +23,7 @@ enum { ORC_CONV_SUM = 0, ORC_CONV_MEAN = 1 };
 enum { ORC_USTAR_SLIP = 0, ORC_USTAR_NOSLIP = 1 };
 enum { ORC_DT_FIXED = 0, ORC_DT_ADAPTIVE = 1 };
 enum { ORC_JACOBI = 0, ORC_BICGSTAB = 1 };
+enum { ORC_NULL_NONE = 0, ORC_NULL_PROJECT = 1 };
 
 typedef struct {
     int64_t dim, kernel, pgrad, gtvf, free_surface, p_ref_mode;
@@ -30,6 +31,10 @@ typedef struct {
     int64_t dt_mode;  /* ORC_DT_FIXED: every step takes dt; ORC_DT_ADAPTIVE:
                          dt_next is chosen from this step's maxima */
     int64_t solver;   /* ORC_JACOBI (the paper's scheme) or ORC_BICGSTAB */
+    int64_t null_space; /* ORC_NULL_PROJECT: on a fully periodic case (no
+                           walls, no free surface) remove from the RHS its
+                           component along the operator's left null vector
+                           before the solve; ORC_NULL_NONE: as printed */
     int64_t nf, nw;
     double h, rho0, nu, alpha, c_ref, dt, eta, fs_ratio, omega, tol;
     double dt_max;    /* adaptive mode: upper bound of dt_next             */
@@ -52,6 +57,8 @@ typedef struct {
     int64_t iters;    /* Jacobi sweeps done                                */
     int64_t converged;
     double ratio, lambda, p_ref_used;
+    double beta;      /* the constant removed per unit D_ii from the RHS
+                         (ORC_NULL_PROJECT), else 0                        */
     double umax;      /* max |u^n| over fluid particles                    */
     double fmax;      /* max |f^n|, f = predictor forces + pressure force  */
     double dt_next;   /* the next step's dt (dt itself in fixed mode)      */

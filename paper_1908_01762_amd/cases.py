@@ -37,6 +37,7 @@ CONV = {"sum": 0, "mean": 1}
 USTAR = {"slip": 0, "noslip": 1}
 DT_MODE = {"fixed": 0, "adaptive": 1}
 SOLVER = {"jacobi": 0, "bicgstab": 1}
+NULL_SPACE = {"none": 0, "project": 1}
 SUPPORT = {"quintic": 3.0, "wendland": 2.0}
 
 
@@ -83,6 +84,9 @@ class Case:
     ustar_wall: str = "slip"
     dt_mode: str = "fixed"       # "adaptive": dt is the first step's and the largest step
     solver: str = "jacobi"       # "bicgstab": the PPE by BiCGStab on the same operator
+    # "project": fully periodic cases (no walls, no free surface) remove the
+    # RHS component the singular operator cannot match; "none": as printed
+    null_space: str = "none"
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -119,14 +123,17 @@ def taylor_green(n: int = 50, kernel: str = "quintic", hdx: float = 1.0,
                  seed: int = 0, tol: float = 1e-4, pgrad: str = "asymm",
                  precision: str = "fp64", gtvf_K: int = 5,
                  p_ref_mode: str = "twice_max", p_ref: float = 0.0,
-                 dt: Optional[float] = None) -> Case:
+                 dt: Optional[float] = None, null_space: str = "project") -> Case:
     """Periodic unit-square Taylor-Green vortex (eq. tgv at t = 0).
 
     Lattice x = (i + 1/2) dx, uniform jitter of +-jitter*dx per coordinate,
     velocity and pressure taken exactly at the jittered positions, rho0 = 1,
     m = rho0 dx^2, nu = U L / Re with L = 1.  The fixed time step is the
     minimum of the advective and viscous limits (section 3.2), there is no
-    body force here.
+    body force here.  The PPE of this wall-less, fully periodic problem is
+    singular (constants solve it); ``null_space="project"`` (the default)
+    removes the RHS component it cannot match, ``"none"`` iterates as
+    printed.
     """
     L = 1.0
     dx = L / n
@@ -155,7 +162,7 @@ def taylor_green(n: int = 50, kernel: str = "quintic", hdx: float = 1.0,
         box_lo=(0.0, 0.0, 0.0), box_hi=(L, L, 0.0), periodic=(1, 1, 0),
         x=np.ascontiguousarray(x), u=np.ascontiguousarray(u),
         p=np.ascontiguousarray(p), m=m, n_fluid=n * n, n_wall=0,
-        wall_u=None, precision=precision, gtvf_K=gtvf_K,
+        wall_u=None, precision=precision, gtvf_K=gtvf_K, null_space=null_space,
         meta=dict(re=re, U=U, seed=seed, jitter=jitter, lattice=n))
 
 
@@ -335,7 +342,7 @@ def cloud_2d(n: int = 40, radius: float = 0.3, seed: int = 7,
     u = np.ascontiguousarray(np.vstack([c.u[keep], extra_u]))
     N = x.shape[0]
     return c.replace(name=f"cloud{n}", x=x, u=u, p=np.zeros(N), m=np.full(N, c.m[0]),
-                     n_fluid=N, free_surface=True,
+                     n_fluid=N, free_surface=True, null_space="none",
                      meta=dict(c.meta, isolated=[N - 4, N - 3], pair=[N - 2, N - 1]))
 
 

@@ -374,7 +374,7 @@ def _fs_case(n=12, seed=4):
     c = cases.taylor_green(n, kernel="wendland", hdx=1.3, jitter=0.2, seed=seed)
     rho = oracle.density(c)
     thr = np.quantile(rho, 0.1)
-    return c.replace(free_surface=True, fs_ratio=float(thr / c.rho0) + 1e-12, gtvf="off")
+    return c.replace(free_surface=True, fs_ratio=float(thr / c.rho0) + 1e-12, gtvf="off", null_space="none")
 
 
 def test_jacobi_converges_to_dense_solve():
