@@ -70,6 +70,7 @@ enum { SISPH_CONV_SUM = 0, SISPH_CONV_MEAN = 1 };
 enum { SISPH_USTAR_SLIP = 0, SISPH_USTAR_NOSLIP = 1 };
 enum { SISPH_DT_FIXED = 0, SISPH_DT_ADAPTIVE = 1 };
 enum { SISPH_JACOBI = 0, SISPH_BICGSTAB = 1 };
+enum { SISPH_NULL_NONE = 0, SISPH_NULL_PROJECT = 1 };
 
 /* One case.  Parameters follow the paper's statement of the problem.
  *  precision   SISPH_FP64: every sum in FP64.  SISPH_MIXED: neighbour sums,
@@ -108,6 +109,18 @@ enum { SISPH_JACOBI = 0, SISPH_BICGSTAB = 1 };
  *              (without p = 0 rows the system fixes p only up to a
  *              constant); such a context cannot join a batch.  iters counts
  *              BiCGStab iterations (two operator applications each).
+ *  null_space  SISPH_NULL_NONE: the iteration as printed.  SISPH_NULL_PROJECT
+ *              (fully periodic cases only: no wall particles, no free
+ *              surface, Jacobi): there a constant pressure solves the
+ *              homogeneous PPE (every row of eq. sph-ppe sums c_ij (p_j -
+ *              p_i)), y_i = m_i rho_i is a left null vector of the operator,
+ *              and a right-hand side with y . RHS != 0 makes every sweep of
+ *              eq. p-sor shift the iterate by the same constant, which the
+ *              test of eq. convergence never sees settle.  Before the sweeps
+ *              RHS_i becomes RHS_i - beta D_ii with beta = (y . RHS) /
+ *              (y . D), and Lambda is taken from it; iterate k then equals
+ *              the unprojected one minus k omega beta, the same field up to
+ *              a constant.  Other cases are refused (SISPH_E_INVAL).
  *  periodic    per axis; the box is [box_lo, box_hi) on periodic axes and
  *              the binning range (particles outside are clamped to the edge
  *              cells) on the others.                                         */
@@ -116,7 +129,7 @@ typedef struct {
     int32_t p_ref_mode, conv_norm, min_iter, max_iter, gtvf_K, forced_iters;
     int32_t periodic[3], nbr_cap;
     int32_t ustar_wall, dt_mode;
-    int32_t solver, reserved1;
+    int32_t solver, null_space;
     int64_t n_fluid, n_wall;
     double h, dx, rho0, nu, alpha, c_ref, dt, eta, fs_ratio, omega, tol, p_ref;
     double gravity[3], box_lo[3], box_hi[3];
@@ -135,6 +148,8 @@ typedef struct {
                             2 (16-bit offsets: mixed mode, no walls, every
                             offset of the step within +-32767)            */
     int32_t reserved;
+    double beta;         /* SISPH_NULL_PROJECT: the constant removed per unit
+                            D_ii from the RHS (else 0)                      */
 } sisph_ppe_stats;
 
 typedef sisph_ppe_stats sisph_step_stats;

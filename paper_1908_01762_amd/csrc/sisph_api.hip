@@ -77,6 +77,9 @@ static const char *check_desc(const sisph_case_desc *d) {
     if (d->solver != SISPH_JACOBI && d->solver != SISPH_BICGSTAB) return "unknown solver";
     if (d->solver == SISPH_BICGSTAB && !d->free_surface)
         return "BiCGStab needs free-surface rows (otherwise p is fixed only up to a constant)";
+    if (d->null_space != SISPH_NULL_NONE && d->null_space != SISPH_NULL_PROJECT) return "unknown null_space";
+    if (d->null_space == SISPH_NULL_PROJECT && (d->n_wall != 0 || d->free_surface || d->solver != SISPH_JACOBI))
+        return "null_space PROJECT needs a fully periodic Jacobi case (no walls, no free surface)";
     if (d->n_fluid <= 0) return "n_fluid must be positive";
     if (d->n_wall < 0) return "n_wall must be >= 0";
     if (d->n_fluid + d->n_wall >= (int64_t)1 << 31) return "particle count exceeds 2^31";
@@ -152,6 +155,7 @@ static Params make_params(const sisph_case_desc *d) {
     P.ustar_noslip = d->ustar_wall == SISPH_USTAR_NOSLIP ? 1 : 0;
     P.adaptive_dt = d->dt_mode == SISPH_DT_ADAPTIVE ? 1 : 0;
     P.solver = d->solver;
+    P.null_space = d->null_space;
     P.compact = d->precision == SISPH_MIXED && d->n_wall == 0 ? 1 : 0;
     P.cap = neighbour_cap(d);
     P.nf = d->n_fluid;
@@ -210,14 +214,8 @@ static void carve(const Params &P, Carver &c, State &S) {
     S.m = c.take<double>(nt);
     S.rho = c.take<double>(nt);
     S.mr2 = c.take<double>(nt);
-    for (int k = 0; k < 3; ++k) S.u32[k] = S.us32[k] = S.ut32[k] = nullptr;
     S.m32 = S.rho32 = nullptr;
     if (P.precision == SISPH_MIXED) {
-        for (int k = 0; k < D; ++k) {
-            S.u32[k] = c.take<float>(nt);
-            S.us32[k] = c.take<float>(nt);
-            S.ut32[k] = c.take<float>(nf);
-        }
         S.m32 = c.take<float>(nt);
         S.rho32 = c.take<float>(nt);
     }
@@ -280,6 +278,7 @@ static Target single_target(sisph_ctx *ctx) {
     T.adaptive = ctx->P.adaptive_dt;
     T.precheck = ctx->P.nf >= kPrecheckRows ? 1 : 0;
     T.solver = ctx->P.solver;
+    T.null_space = ctx->P.null_space;
     T.s = ctx->stream;
     return T;
 }
@@ -360,6 +359,7 @@ static void fill_stats(const Control &C, const Params &P, sisph_ppe_stats *out) 
     out->dt = C.dt;
     out->index_bytes = P.compact && !C.wide ? 2 : 4;
     out->reserved = 0;
+    out->beta = P.null_space == SISPH_NULL_PROJECT ? C.beta : 0.0;
 }
 
 static int32_t status_of(const Control &C, const Params &P, std::string *msg) {
@@ -528,17 +528,17 @@ static void seq_predict(const Target &T) {
     density(T);
     mass_over_rho2(T);
     wall_velocity(T, POS_X);
-    shadow(T, 0);
+    shadow(T);
     predictor(T);
     bin_fluid(T, POS_XS);
     build_neighbors(T, POS_XS);
     wall_velocity(T, POS_XS);
-    shadow(T, 1);
 }
 
 static void seq_ppe_begin(const Target &T) {
     reset_control(T, RESET_PPE);
     rhs_coef(T);
+    if (T.null_space) project_rhs(T);
     wall_coef(T);
     if (T.solver == SISPH_BICGSTAB) bicg_begin(T);
     else if (T.precision == SISPH_MIXED) copy_p32(T);
@@ -1215,7 +1215,10 @@ static int32_t rebuild_group(sisph_batch *b, Group &g) {
     T.kernel = g.kernel;
     T.precision = g.precision;
     T.s = b->stream;
-    for (auto *c : g.members) T.adaptive |= c->P.adaptive_dt;
+    for (auto *c : g.members) {
+        T.adaptive |= c->P.adaptive_dt;
+        T.null_space |= c->P.null_space;
+    }
     T.precheck = 1;
     for (int k = 0; k < K_COUNT; ++k) {
         std::vector<int32_t> owner;

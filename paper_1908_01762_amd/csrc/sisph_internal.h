@@ -34,7 +34,7 @@ struct Params {
     int32_t solver;         // SISPH_JACOBI or SISPH_BICGSTAB
     int32_t compact;        // mixed mode without walls: 16-bit neighbour offsets
     uint32_t barrier_spins; // polls before a wait of the persistent solve gives up
-    int32_t pad0;
+    int32_t null_space;     // SISPH_NULL_PROJECT: RHS made compatible before the sweeps
     int64_t nf, nw, ntot;
     // dt: the fixed step, or the first step and the upper bound when adaptive
     // (kernels read the current step's dt from Control)
@@ -67,6 +67,8 @@ struct Control {
     double bicg_rho[2], bicg_alpha[2], bicg_omega[2];
     int32_t bicg_brk;
     int32_t wide;                     // a neighbour offset of this step did not fit 16 bits
+    int32_t pad1;
+    double beta;                      // SISPH_NULL_PROJECT: (y . RHS) / (y . D), y = m rho
 };
 
 // Per-case device arrays.  Unified particle index: fluid [0, nf) in cell
@@ -89,8 +91,6 @@ struct State {
     double *rho;       // density (walls rho0)       [ntot]
     void *mr2;         // m / rho^2 in the working precision [ntot]
     // FP32 copies for the mixed-mode pair gathers (see Shadow)
-    float *u32[3], *us32[3];   // [ntot]
-    float *ut32[3];            // [nf]
     float *m32, *rho32;        // [ntot]
     double *rhs, *dii; //                            [nf]
     int32_t *fs;       // free-surface flag          [nf]
@@ -125,7 +125,7 @@ struct State {
 // Launch-size kinds: how many workgroups one case needs for a kernel.
 enum Kind { K_FLUID = 0, K_WALL, K_TOT, K_CELL, K_TILE, K_ONE, K_COUNT };
 
-inline int64_t kind_blocks(const Params &P, int kind) {
+__host__ __device__ inline int64_t kind_blocks(const Params &P, int kind) {
     switch (kind) {
     case K_FLUID: return (P.nf + kBlock - 1) / kBlock;
     case K_WALL: return (P.nw + kBlock - 1) / kBlock;
@@ -162,6 +162,7 @@ struct Target {
     // would read every row), see precheck_for()
     int32_t precheck;
     int32_t solver;                  // SISPH_JACOBI or SISPH_BICGSTAB (single cases)
+    int32_t null_space;              // some case projects its RHS (SISPH_NULL_PROJECT)
     bool batched;
     hipStream_t s;
 };
@@ -182,14 +183,16 @@ void build_neighbors(const Target &T, int which);
 void wall_normals(const Target &T);
 void density(const Target &T);
 void mass_over_rho2(const Target &T);
-// FP32 copies of gathered fields (mixed mode): 0 after the r^n wall
-// velocity, 1 after the r* wall velocity.
-void shadow(const Target &T, int which);
+// FP32 copies of mass and density (mixed mode), after the density.
+void shadow(const Target &T);
 // Wall ghost velocity: no-slip form at r^n (POS_X); at r* (POS_XS) the
 // case's form for u* (slip by default).
 void wall_velocity(const Target &T, int which);
 void predictor(const Target &T);
 void rhs_coef(const Target &T);
+// SISPH_NULL_PROJECT cases: beta from the per-workgroup sums rhs_coef left,
+// then RHS_i -= beta D_ii and Lambda from the result.
+void project_rhs(const Target &T);
 // Wall extrapolation weights at r* for the solve (walls present).
 void wall_coef(const Target &T);
 void copy_p32(const Target &T);

@@ -908,12 +908,13 @@ struct Predictor {
         Kern<KER, D, R> K(P.h);
         const int64_t nf = P.nf;
         const Pos x = mkpos(S.x), u = mkpos(S.u), ut = mkpos(S.ut);
-        double xi[3] = {0, 0, 0};
+        double xi[3] = {0, 0, 0}, ui_d[3] = {0, 0, 0};
         R ui[3] = {0, 0, 0}, si[3] = {0, 0, 0};
         const R rhoi = (R)S.rho[i];
         for (int k = 0; k < D; ++k) {
             xi[k] = x.c[k][i];
-            ui[k] = (R)u.c[k][i];
+            ui_d[k] = u.c[k][i];
+            ui[k] = (R)ui_d[k];
             si[k] = (R)(ut.c[k][i] - u.c[k][i]);   // u~ - u
         }
         // A_i / rho_i^2 = (u_i / rho_i) (x) (u~_i - u_i)
@@ -923,28 +924,27 @@ struct Predictor {
         const int c = S.cnt[i];
         for (int k0 = 1; k0 < c; k0 += kPairBatch) {
             int64_t jb[kPairBatch];
-            double xj[kPairBatch][3];
-            R mb[kPairBatch], rhob[kPairBatch], ub[kPairBatch][3], utb[kPairBatch][3];
+            double xj[kPairBatch][3], ub[kPairBatch][3], utb[kPairBatch][3];
+            R mb[kPairBatch], rhob[kPairBatch];
             batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
             batch_pos<D>(x, jb, xj);
 #pragma unroll
             for (int t = 0; t < kPairBatch; ++t) {
                 const int64_t j = jb[t], jf = j < nf ? j : i;   // u~ is held for fluid particles only
-                for (int a = 0; a < 3; ++a) ub[t][a] = utb[t][a] = R(0);
+                for (int a = 0; a < 3; ++a) ub[t][a] = utb[t][a] = 0.0;
+                // velocities in FP64 in every mode: their pair differences
+                // are small against the velocities and are formed before
+                // any rounding to the working precision
+                for (int a = 0; a < D; ++a) {
+                    ub[t][a] = u.c[a][j];
+                    utb[t][a] = ut.c[a][jf];
+                }
                 if constexpr (sizeof(R) == 4) {   // the FP32 copies: the same values, half the bytes
                     mb[t] = S.m32[j];
                     rhob[t] = S.rho32[j];
-                    for (int a = 0; a < D; ++a) {
-                        ub[t][a] = S.u32[a][j];
-                        utb[t][a] = S.ut32[a][jf];
-                    }
                 } else {
                     mb[t] = S.m[j];
                     rhob[t] = S.rho[j];
-                    for (int a = 0; a < D; ++a) {
-                        ub[t][a] = u.c[a][j];
-                        utb[t][a] = ut.c[a][jf];
-                    }
                 }
             }
 #pragma unroll
@@ -960,9 +960,9 @@ struct Predictor {
                 const R F = dw * r2;
                 const R mj = mb[t], rhoj = rhob[t];
                 R uj[3] = {0, 0, 0};
-                for (int a = 0; a < D; ++a) uj[a] = ub[t][a];
+                for (int a = 0; a < D; ++a) uj[a] = (R)ub[t][a];
                 R uij[3] = {0, 0, 0};
-                for (int a = 0; a < D; ++a) uij[a] = ui[a] - uj[a];
+                for (int a = 0; a < D; ++a) uij[a] = (R)(ui_d[a] - ub[t][a]);
                 const R inv_den = R(1) / (r2 + eps);
                 const R cv = mj * nu4 / (rhoi + rhoj) * F * inv_den;
                 for (int a = 0; a < D; ++a) fv[a] += cv * uij[a];
@@ -980,7 +980,7 @@ struct Predictor {
                 if (j < nf) {
                     const R inv_rhoj = R(1) / rhoj;
                     for (int b = 0; b < D; ++b) {
-                        sgj += (utb[t][b] - uj[b]) * gw[b];
+                        sgj += (R)(utb[t][b] - ub[t][b]) * gw[b];
                         uj_over[b] = uj[b] * inv_rhoj;
                     }
                 }
@@ -1044,25 +1044,16 @@ __device__ __forceinline__ int32_t offset_index(int64_t i, int16_t o, int64_t nf
     return (int32_t)j;
 }
 
-// FP32 copies of the fields the mixed-mode pair loops gather (they convert
-// each gathered value to FP32 anyway): which 0, after the r^n wall
-// velocity: u (with the wall ghost values), u~, m, rho; which 1, after the
-// r* wall velocity: u* (with the wall values).
-template <int D>
+// FP32 copies of the mass and density the mixed-mode pair loops gather
+// (they convert each gathered value to FP32 anyway), after the density.
+// Velocities are gathered in FP64: the loops form their pair differences
+// first.
 struct Shadow {
-    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         if (i >= P.ntot) return;
-        if (which == 0) {
-            for (int a = 0; a < D; ++a) {
-                S.u32[a][i] = (float)S.u[a][i];
-                if (i < P.nf) S.ut32[a][i] = (float)S.ut[a][i];
-            }
-            S.m32[i] = (float)S.m[i];
-            S.rho32[i] = (float)S.rho[i];
-        } else {
-            for (int a = 0; a < D; ++a) S.us32[a][i] = (float)S.us[a][i];
-        }
+        S.m32[i] = (float)S.m[i];
+        S.rho32[i] = (float)S.rho[i];
     }
 };
 
@@ -1075,19 +1066,19 @@ struct Shadow {
 // atomic per wavefront).
 template <int KER, int D, typename R>
 struct RhsCoef {
-    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int) {
         ROW;
         const int64_t nf = P.nf;
         unsigned long long lam = 0ull;
+        double ya = 0.0, yd = 0.0;
         bool wide = false;
         if (i < nf) {
             Kern<KER, D, R> K(P.h);
             const Pos xs = mkpos(S.xs), us = mkpos(S.us);
-            double xi[3] = {0, 0, 0};
-            R usi[3] = {0, 0, 0};
+            double xi[3] = {0, 0, 0}, usi[3] = {0, 0, 0};
             for (int k = 0; k < D; ++k) {
                 xi[k] = xs.c[k][i];
-                usi[k] = (R)us.c[k][i];
+                usi[k] = us.c[k][i];
             }
             const R rhoi = (R)S.rho[i], eps = (R)P.eps_h, inv_dt = (R)(1.0 / S.ctl->dt);
             R s = R(0), Dg = R(0);
@@ -1097,22 +1088,24 @@ struct RhsCoef {
             static_assert(kPairBatch == 4, "one coefficient group per batch");
             for (int k0 = 1; k0 < c; k0 += kPairBatch) {
                 int64_t jb[kPairBatch];
-                double xj[kPairBatch][3];
-                R mb[kPairBatch], rhob[kPairBatch], usb[kPairBatch][3];
+                double xj[kPairBatch][3], usb[kPairBatch][3];
+                R mb[kPairBatch], rhob[kPairBatch];
                 batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
                 batch_pos<D>(xs, jb, xj);
 #pragma unroll
                 for (int t = 0; t < kPairBatch; ++t) {
                     const int64_t j = jb[t];
-                    for (int a = 0; a < 3; ++a) usb[t][a] = R(0);
+                    for (int a = 0; a < 3; ++a) usb[t][a] = 0.0;
+                    // u* in FP64: u*_ij is formed before rounding (the RHS
+                    // is the divergence of a nearly solenoidal field, a sum
+                    // of terms that mostly cancel)
+                    for (int a = 0; a < D; ++a) usb[t][a] = us.c[a][j];
                     if constexpr (sizeof(R) == 4) {
                         mb[t] = S.m32[j];
                         rhob[t] = S.rho32[j];
-                        for (int a = 0; a < D; ++a) usb[t][a] = S.us32[a][j];
                     } else {
                         mb[t] = S.m[j];
                         rhob[t] = S.rho[j];
-                        for (int a = 0; a < D; ++a) usb[t][a] = us.c[a][j];
                     }
                 }
                 R c4[4] = {R(0), R(0), R(0), R(0)};
@@ -1127,7 +1120,7 @@ struct RhsCoef {
                     const R dw = K.dwr(sqrt(r2));
                     const R mj = mb[t], rhoj = rhob[t];
                     R dot = R(0);
-                    for (int a = 0; a < D; ++a) dot += (usi[a] - usb[t][a]) * d[a];
+                    for (int a = 0; a < D; ++a) dot += (R)(usi[a] - usb[t][a]) * d[a];
                     s -= mj / rhoj * inv_dt * dw * dot;
                     const R cij = R(4) * mj / (rhoi * (rhoi + rhoj)) * (dw * r2) / (r2 + eps);
                     int16_t oq = 0;
@@ -1162,10 +1155,67 @@ struct RhsCoef {
             S.rhs[i] = rr;
             S.dii[i] = dd;
             if (dd != 0.0 && !S.fs[i]) lam = (unsigned long long)__double_as_longlong(fabs(rr / dd));
+            if (P.null_space) {
+                const double y = S.m[i] * S.rho[i];
+                ya = y * rr;
+                yd = y * dd;
+            }
+        }
+        if (__any(wide) && (threadIdx.x & 63) == 0) atomicOr(&S.ctl->wide, 1);
+        if (P.null_space) {
+            // y . RHS and y . D of this workgroup's rows (fixed order), for
+            // ProjectFinish; Lambda waits for the projected RHS (ProjectRhs)
+            block_sum2(ya, yd);
+            if (threadIdx.x == 0) {
+                double *pa = S.partial + 2 * nblk;   // the slots of odd sweeps, free until sweep 1
+                pa[blk] = ya;
+                pa[nblk + blk] = yd;
+            }
+            return;
         }
         lam = wave_max_u64(lam);   // non-negative doubles order like their bits
         if ((threadIdx.x & 63) == 0 && lam) max_if_larger(&S.ctl->lambda_bits, lam);
-        if (__any(wide) && (threadIdx.x & 63) == 0) atomicOr(&S.ctl->wide, 1);
+    }
+};
+
+// Fully periodic cases (SISPH_NULL_PROJECT): constants solve the homogeneous
+// PPE and y_i = m_i rho_i is a left null vector of the operator (m_i rho_i
+// c_ij is symmetric), so the system is consistent only if y . RHS = 0.  The
+// component of the RHS that breaks this is removed once per solve:
+// beta = (y . RHS) / (y . D), RHS_i -= beta D_ii; the sweeps of eq. p-sor
+// then differ from the unprojected ones by the constant k omega beta only.
+// One workgroup per case sums the per-workgroup sums of RhsCoef in a fixed
+// order.
+struct ProjectFinish {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t, int64_t, int) {
+        if (!P.null_space) return;
+        const int64_t nb = kind_blocks(P, K_FLUID);
+        const double *pa = S.partial + 2 * nb;
+        double a = 0.0, b = 0.0;
+        for (int64_t k = threadIdx.x; k < nb; k += kBlock) {
+            a += pa[k];
+            b += pa[nb + k];
+        }
+        block_sum2(a, b);
+        if (threadIdx.x == 0) S.ctl->beta = b != 0.0 ? a / b : 0.0;
+    }
+};
+
+struct ProjectRhs {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        if (!P.null_space) return;
+        ROW;
+        unsigned long long lam = 0ull;
+        if (i < P.nf) {
+            const double dd = S.dii[i];
+            if (dd != 0.0) {
+                const double rr = S.rhs[i] - S.ctl->beta * dd;
+                S.rhs[i] = rr;
+                if (!S.fs[i]) lam = (unsigned long long)__double_as_longlong(fabs(rr / dd));
+            }
+        }
+        lam = wave_max_u64(lam);
+        if ((threadIdx.x & 63) == 0 && lam) max_if_larger(&S.ctl->lambda_bits, lam);
     }
 };
 
@@ -2421,6 +2471,11 @@ void predictor(const Target &T) { SISPH_DISPATCH_KDR(T, (launch<Predictor<KER, D
 
 void rhs_coef(const Target &T) { SISPH_DISPATCH_KDR(T, (launch<RhsCoef<KER, D, R>, K_FLUID>(T))); }
 
+void project_rhs(const Target &T) {
+    launch<ProjectFinish, K_ONE>(T);
+    launch<ProjectRhs, K_FLUID>(T);
+}
+
 void copy_p32(const Target &T) { launch<CopyP32, K_TOT>(T); }
 
 // Sweep variants (numerically identical): first-batch size kSweepFirsts[v % 3],
@@ -2553,9 +2608,9 @@ void step_maxima(const Target &T) { SISPH_DISPATCH_D(T, (launch<StepMaxima<D>, K
 
 void next_dt(const Target &T) { launch<NextDt, K_ONE>(T); }
 
-void shadow(const Target &T, int which) {
+void shadow(const Target &T) {
     if (T.precision != SISPH_MIXED) return;
-    SISPH_DISPATCH_D(T, (launch<Shadow<D>, K_TOT>(T, which)));
+    launch<Shadow, K_TOT>(T);
 }
 
 void mass_over_rho2(const Target &T) {

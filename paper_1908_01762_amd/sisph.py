@@ -39,7 +39,7 @@ class CaseDesc(C.Structure):
         "dim", "kernel", "precision", "pgrad", "gtvf", "free_surface",
         "p_ref_mode", "conv_norm", "min_iter", "max_iter", "gtvf_K", "forced_iters")] + \
         [("periodic", C.c_int32 * 3), ("nbr_cap", C.c_int32), ("ustar_wall", C.c_int32), ("dt_mode", C.c_int32),
-         ("solver", C.c_int32), ("reserved1", C.c_int32),
+         ("solver", C.c_int32), ("null_space", C.c_int32),
          ("n_fluid", C.c_int64), ("n_wall", C.c_int64)] + \
         [(n, C.c_double) for n in (
             "h", "dx", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio",
@@ -51,13 +51,13 @@ class PPEStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("nonfinite", C.c_int32),
                 ("status", C.c_int32), ("ratio", C.c_double), ("lambda_", C.c_double),
                 ("p_ref", C.c_double), ("dt", C.c_double), ("index_bytes", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("beta", C.c_double)]
 
     def as_dict(self) -> dict:
         return dict(iters=self.iters, converged=bool(self.converged), nonfinite=bool(self.nonfinite),
                     case_status=self.status,
                     ratio=self.ratio, lam=self.lambda_, p_ref=self.p_ref, dt=self.dt,
-                    index_bytes=self.index_bytes)
+                    index_bytes=self.index_bytes, beta=self.beta)
 
 
 _lib = None
@@ -172,6 +172,7 @@ def describe(case: "_cases.Case") -> CaseDesc:
     d.ustar_wall = _cases.USTAR[case.ustar_wall]
     d.dt_mode = _cases.DT_MODE[case.dt_mode]
     d.solver = _cases.SOLVER[case.solver]
+    d.null_space = _cases.NULL_SPACE[case.null_space]
     d.n_fluid = case.n_fluid
     d.n_wall = case.n_wall
     for k in ("h", "dx", "rho0", "nu", "alpha", "c_ref", "dt", "eta", "fs_ratio", "omega", "tol", "p_ref"):

@@ -29,10 +29,27 @@ def test_library_exports_every_declared_function():
     assert not missing, missing
 
 
+def _c_layout(struct: str, fields) -> list:
+    """sizeof and offsetof of the header's struct, from a C compiler."""
+    import subprocess
+    import tempfile
+    inc = os.path.join(ROOT, "include")
+    body = "".join(f'printf("%zu\\n", offsetof({struct}, {f}));' for f in fields)
+    src = ("#include <stdio.h>\n#include <stddef.h>\n#include \"sisph.h\"\n"
+           f'int main(void) {{ printf("%zu\\n", sizeof({struct})); {body} return 0; }}\n')
+    with tempfile.TemporaryDirectory() as d:
+        with open(os.path.join(d, "l.c"), "w") as f:
+            f.write(src)
+        exe = os.path.join(d, "l")
+        subprocess.check_call(["gcc", "-I", inc, "-o", exe, os.path.join(d, "l.c")])
+        return [int(v) for v in subprocess.check_output([exe]).split()]
+
+
 def test_header_struct_layout_matches_binding():
-    # sisph_case_desc: 16 int32 + 2 int64 + 12 double + 9 double
-    assert C.sizeof(sisph.CaseDesc) == 20 * 4 + 2 * 8 + 21 * 8
-    assert C.sizeof(sisph.PPEStats) == 4 * 4 + 4 * 8 + 2 * 4
+    for struct, cls in (("sisph_case_desc", sisph.CaseDesc), ("sisph_ppe_stats", sisph.PPEStats)):
+        names = [f[0] for f in cls._fields_]
+        want = [C.sizeof(cls)] + [getattr(cls, n).offset for n in names]
+        assert _c_layout(struct, [n if n != "lambda_" else "lambda" for n in names]) == want, struct
 
 
 def test_status_strings():
@@ -48,10 +65,10 @@ def test_workspace_bytes_valid_and_monotone():
     assert small % 256 == 0
     db = sisph.workspace_bytes(cases.dam_break_2d(dx=0.05))
     assert db > 0
-    # the mixed mode adds only the FP32 copies of gathered fields (u, u*,
-    # u~, m, rho: 8 arrays in 2D), the caches being sized for FP64
+    # the mixed mode adds only the FP32 copies of gathered fields (m and
+    # rho), the caches being sized for FP64
     mixed = sisph.workspace_bytes(cases.taylor_green(20, precision="mixed"))
-    assert small + 8 * 4 * 400 <= mixed <= small + 8 * (4 * 400 + 256)
+    assert small + 2 * 4 * 400 <= mixed <= small + 2 * (4 * 400 + 256)
 
 
 @pytest.mark.parametrize("field,value", [

@@ -87,8 +87,12 @@ def test_tg400_one_step_mixed():
                 displacement=rel(s["x"] - case.x, ref.x - case.x))
     for k, e in errs.items():
         say(f"  tg400 mixed {k:12s} {e:.3e}")
-    assert errs["rho"] < 1e-6 and errs["u"] < 1e-4 and errs["displacement"] < 1e-4
-    assert errs["rhs"] < 1e-3 and errs["p"] < 1e-3
+    # measured rho 1.3e-7, RHS 1.9e-5, p 8.0e-8, u 2.1e-9, displacement
+    # 4.5e-9.  The RHS is the divergence of a nearly solenoidal u*: its pair
+    # terms sum to about 1/244 of their magnitudes here, so FP32 products
+    # (u*_ij and r_ij formed in FP64 first) leave 6e-8 x ~250 of it
+    assert errs["rho"] < 4e-7 and errs["u"] < 1e-8 and errs["displacement"] < 2e-8
+    assert errs["rhs"] < 5e-5 and errs["p"] < 3e-7
     ctx.close()
 
 
@@ -109,7 +113,8 @@ def test_dam_break_2d_full_one_step_mixed():
     errs = dict(rho=rel(ctx.field("rho"), out["rho"]), p=rel(st["p"], ref.p), u=rel(st["u"], ref.u))
     for k, e in errs.items():
         say(f"  db2d dx=0.005 mixed {k:5s} {e:.3e} ({g_iters} sweeps)")
-    assert errs["rho"] < 1e-6 and errs["p"] < 1e-3 and errs["u"] < 1e-3
+    # measured rho 5.4e-8, p 1.2e-7, u 2.2e-6
+    assert errs["rho"] < 2e-7 and errs["p"] < 4e-7 and errs["u"] < 7e-6
     ctx.close()
 
 

@@ -226,7 +226,7 @@ def _fs_periodic(n=16, seed=4):
     c = cases.taylor_green(n, kernel="wendland", hdx=1.3, jitter=0.2, seed=seed)
     rho = oracle.density(c)
     thr = np.quantile(rho, 0.1)
-    return c.replace(free_surface=True, fs_ratio=float(thr / c.rho0) + 1e-12, gtvf="off")
+    return c.replace(free_surface=True, fs_ratio=float(thr / c.rho0) + 1e-12, gtvf="off", null_space="none")
 
 
 # (case, tol, exact): with exact, the iteration counts must match and the
@@ -276,10 +276,13 @@ def test_bicgstab_mixed_single_step():
     g = ctx.step(1)[0]
     s = ctx.read_state()
     e = rel(s["p"], ref.p)
-    say(f"  mixed bicgstab iters {g['iters']} / {o['iters']}, p rel L2 {e:.3e}, u {rel(s['u'], ref.u):.3e}")
+    eu = rel(s["u"], ref.u)
+    say(f"  mixed bicgstab iters {g['iters']} / {o['iters']}, p rel L2 {e:.3e}, u {eu:.3e}")
     assert g["converged"]
     assert abs(g["iters"] - o["iters"]) <= 3
-    assert e < 1e-3
+    # measured 4.0e-5 / 2.9e-5: BiCGStab's inner products amplify the FP32
+    # rounding of the operator applications more than damped Jacobi does
+    assert e < 1.2e-4 and eu < 1e-4
     assert np.all(np.isfinite(s["p"])) and np.all(np.isfinite(s["u"]))
     ctx.close()
 
@@ -358,9 +361,14 @@ def test_mixed_precision_single_step(name):
         errs["p_wall"] = rel(s["p"][nf:][~graze], ref.p[nf:][~graze])
     for k, e in errs.items():
         say(f"  mixed {name} {k:12s} rel L2 {e:.3e}")
-    assert errs["rho"] < 1e-6 and errs["dii"] < 1e-5
-    assert errs["u"] < 1e-4 and errs["displacement"] < 1e-4
-    assert errs["rhs"] < 1e-3 and errs["p"] < 1e-3 and errs.get("p_wall", 0.0) < 1e-3
+    # measured maxima over these cases: rho 2.2e-7, D 2.6e-7, RHS 2.2e-6
+    # (its terms cancel), p 1.8e-5, u 1.9e-5 (2D dam break: 280 sweeps, each
+    # rounding its FP32 neighbour sum; the damped Jacobi map is
+    # non-expansive, so the per-sweep rounding of ~1e-7 adds up over the
+    # sweeps), wall p 1.5e-5
+    assert errs["rho"] < 7e-7 and errs["dii"] < 8e-7
+    assert errs["u"] < 6e-5 and errs["displacement"] < 6e-5
+    assert errs["rhs"] < 7e-6 and errs["p"] < 6e-5 and errs.get("p_wall", 0.0) < 5e-5
     ctx.close()
 
 
@@ -379,9 +387,10 @@ def test_mixed_precision_steps(name):
     """Five mixed-mode steps against the FP64 oracle, the oracle taking the
     GPU's iteration count at each step (the stopping test may flip one
     iteration either way).  FP32 rounding of the pair sums (~1e-7 relative,
-    amplified by the pressure solve) bounds the drift: velocity and
-    displacement to 1e-4, fluid pressure to 1e-3 relative L2, and the
-    adaptive step to 1e-6."""
+    accumulated over the sweeps) bounds the drift: velocity and displacement
+    to 1e-5, fluid pressure to 2e-5 relative L2 (measured at most 3.2e-6 and
+    6.8e-6), BiCGStab 1e-4 (measured 2.9e-5 / 3.4e-5), and the adaptive step
+    to 1e-6."""
     sisph = _gpu()
     case = _mixed_steps_cases()[name]
     nf = case.n_fluid
@@ -398,7 +407,8 @@ def test_mixed_precision_steps(name):
             "displacement": rel(s["x"][:nf] - case.x[:nf], ref.x[:nf] - case.x[:nf])}
     for k, e in errs.items():
         say(f"  mixed steps {name} {k:12s} rel L2 {e:.3e}")
-    assert errs["u"] < 1e-4 and errs["displacement"] < 1e-4 and errs["p"] < 1e-3
+    b = 1e-4 if case.solver == "bicgstab" else 1e-5
+    assert errs["u"] < b and errs["displacement"] < b and errs["p"] < 2 * b
     ctx.close()
 
 
@@ -451,7 +461,8 @@ def test_degenerate_rows_mixed():
     errs["displacement"] = rel(s["x"] - case.x, ref.x - case.x)
     for k, e in errs.items():
         say(f"  mixed cloud {k:12s} rel L2 {e:.3e}")
-    assert errs["u"] < 1e-4 and errs["displacement"] < 1e-4 and errs["p"] < 1e-3
+    # measured 2.5e-8, 1.3e-8, 8.6e-7
+    assert errs["u"] < 1e-7 and errs["displacement"] < 5e-8 and errs["p"] < 3e-6
     ctx.close()
 
 
@@ -513,3 +524,37 @@ def test_save_restore_bitwise():
         assert np.array_equal(sa[k], sb[k]), k
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_null_space_projection(precision):
+    """Reading R24 on the GPU (fully periodic Taylor-Green, the RHS component
+    along the left null vector y = m rho removed once per solve): beta of
+    every step against the oracle's, the same sweep counts in FP64 (mixed:
+    the oracle on the GPU's counts), the fields to the parity bounds, and no
+    drift of the mean pressure."""
+    sisph = _gpu()
+    case = cases.taylor_green(40, kernel="wendland", hdx=1.3, jitter=0.2, seed=3, precision=precision)
+    assert case.null_space == "project"
+    ctx = sisph.Context(case)
+    ref = oracle.Sim(case)
+    for k in range(5):
+        g = ctx.step(1)[0]
+        o = ref.step(forced_iters=None if precision == "fp64" else g["iters"])
+        say(f"  step {k}: iters gpu {g['iters']} oracle {o['iters']}, beta gpu {g['beta']:.6e} oracle {o['beta']:.6e}")
+        if precision == "fp64":
+            assert g["iters"] == o["iters"]
+            assert math.isclose(g["beta"], o["beta"], rel_tol=1e-8)
+        else:
+            assert math.isclose(g["beta"], o["beta"], rel_tol=2e-2)
+        assert g["iters"] < case.max_iter
+    s = ctx.read_state()
+    nf = case.n_fluid
+    errs = {"p": rel(s["p"][:nf], ref.p[:nf]), "u": rel(s["u"], ref.u),
+            "displacement": rel(s["x"] - case.x, ref.x - case.x)}
+    for name, e in errs.items():
+        say(f"  projected {precision} {name:12s} rel L2 {e:.3e}")
+    bound = FP64_TOL if precision == "fp64" else 1e-4
+    assert all(e < bound for e in errs.values())
+    assert abs(s["p"][:nf].mean()) < 0.05 * np.abs(s["p"][:nf]).mean()
+    ctx.close()

@@ -30,7 +30,7 @@ def say(*a):
 
 def _fs_periodic():
     c = cases.taylor_green(16, kernel="wendland", hdx=1.3, jitter=0.2, seed=4)
-    return c.replace(free_surface=True, fs_ratio=0.97, gtvf="off")
+    return c.replace(free_surface=True, fs_ratio=0.97, gtvf="off", null_space="none")
 
 
 def _cases():
