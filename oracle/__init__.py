@@ -16,7 +16,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sisph_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_HDR = os.path.join(_HERE, "sisph_oracle.h")
+_LIB = os.path.join(_HERE, "liboracle.so")          # serial
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")  # OpenMP, bitwise equal to the serial build
 
 KERNEL = {"quintic": 0, "wendland": 1}
 PGRAD = {"asymm": 0, "symm": 1}
@@ -29,14 +31,19 @@ SOLVER = {"jacobi": 0, "bicgstab": 1}
 NULL_SPACE = {"none": 0, "project": 1}
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (no contraction, so FP64 ops are exact as written)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+def build(force: bool = False, parallel: bool = False) -> str:
+    """Compile the oracle with gcc (no contraction, so FP64 ops are exact as
+    written): the serial build, or the OpenMP one (per-row loops in
+    parallel, sums over rows serial: bitwise the same results)."""
+    lib_path = _LIB_OMP if parallel else _LIB
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_HDR))
+    if force or not os.path.exists(lib_path) or os.path.getmtime(lib_path) < newest:
+        tmp = lib_path + ".tmp"
+        omp = ["-fopenmp"] if parallel else ["-Wno-unknown-pragmas"]
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC",
-                               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+                               "-shared", "-Wall"] + omp + ["-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, lib_path)
+    return lib_path
 
 
 class Params(C.Structure):
@@ -63,23 +70,35 @@ class StepOut(C.Structure):
          ("umax", C.c_double), ("fmax", C.c_double), ("dt_next", C.c_double)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        _lib = C.CDLL(build())
-        _lib.orc_W.restype = C.c_double
-        _lib.orc_W.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_double]
-        _lib.orc_dWdr.restype = C.c_double
-        _lib.orc_dWdr.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_double]
-        _lib.orc_support.restype = C.c_double
-        _lib.orc_support.argtypes = [C.c_int64]
+def lib(parallel: bool = False):
+    """The serial oracle library, or the OpenMP build."""
+    if parallel not in _libs:
+        L = C.CDLL(build(parallel=parallel))
+        L.orc_W.restype = C.c_double
+        L.orc_W.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_double]
+        L.orc_dWdr.restype = C.c_double
+        L.orc_dWdr.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_double]
+        L.orc_support.restype = C.c_double
+        L.orc_support.argtypes = [C.c_int64]
         for f in ("orc_neighbors_brute", "orc_neighbors_cells"):
-            getattr(_lib, f).restype = C.c_int64
-        _lib.orc_step.restype = C.c_int64
-    return _lib
+            getattr(L, f).restype = C.c_int64
+        L.orc_step.restype = C.c_int64
+        L.orc_threads.restype = C.c_int64
+        _libs[parallel] = L
+    return _libs[parallel]
+
+
+def threads(parallel: bool = True) -> int:
+    """Threads the per-row loops of that build use."""
+    return int(lib(parallel).orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the OpenMP build's per-row loops."""
+    lib(True).orc_set_threads(C.c_int64(int(n)))
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -240,10 +259,11 @@ def wall_velocity(case, x, u_fluid, nrm, slip: bool, wall_u=None) -> np.ndarray:
 class Sim:
     """Oracle state of one case, advanced one SISPH step at a time."""
 
-    def __init__(self, case, forced_iters: Optional[int] = None):
+    def __init__(self, case, forced_iters: Optional[int] = None, parallel: bool = False):
         if case.solver == "bicgstab" and not case.free_surface:
             raise ValueError("BiCGStab needs free-surface rows: without them the PPE fixes p only up to a constant")
         self.case = case
+        self.parallel = parallel
         self.x = case.x.copy()
         self.u = case.u.copy()
         self.ut = case.u.copy()          # transport velocity starts equal to u
@@ -274,7 +294,7 @@ class Sim:
             keep["fs"] = np.zeros(nf, dtype=np.int64)
             out.fs = _ptr(keep["fs"])
         x0 = self.x.copy()
-        rc = lib().orc_step(C.byref(P), _ptr(self.x), _ptr(self.u), _ptr(self.ut), _ptr(self.p),
+        rc = lib(self.parallel).orc_step(C.byref(P), _ptr(self.x), _ptr(self.u), _ptr(self.ut), _ptr(self.p),
                        _ptr(self.m), _ptr(np.ascontiguousarray(self.nrm)), _ptr(self.wall_u),
                        C.byref(self.p_ref), C.byref(self.p_ref_set), C.byref(out))
         if rc != 0:

@@ -13,6 +13,9 @@
  * is stated beside the code (readings R1..R19 are listed with the design
  * notes).
  */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include "sisph_oracle.h"
 
 #include <math.h>
@@ -28,6 +31,26 @@
  *   bracket is positive; s = 7/(478 pi h^2) in 2D, 1/(120 pi h^3) in 3D.
  * Wendland C2: W = s (1 - q/2)^4 (2q + 1) for q < 2; s = 7/(4 pi h^2) in 2D,
  *   21/(16 pi h^3) in 3D.  q = r/h.                                          */
+/* Threads the per-row loops use: the OpenMP build parallelises every loop
+ * whose rows are independent (each row's neighbour sum stays serial, in
+ * ascending neighbour order) and keeps every sum over rows serial, so its
+ * results are bitwise those of the serial build. */
+int64_t orc_threads(void) {
+#ifdef _OPENMP
+    return (int64_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int64_t n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads((int)n);
+#else
+    (void)n;
+#endif
+}
+
 double orc_support(int64_t kernel) { return kernel == ORC_QUINTIC ? 3.0 : 2.0; }
 
 static double sigma(int64_t kernel, int64_t dim, double h) {
@@ -178,48 +201,55 @@ static csr_t build_cells(const orc_params *P, const double *x,
     for (int64_t j = s0; j < s1; ++j) items[fill[cellof[j - s0]]++] = (int32_t)j;
     free(fill);
 
-    int64_t nd = d1 - d0, cap = 64 * (nd > 0 ? nd : 1), cnt = 0;
+    int64_t nd = d1 - d0;
     csr_t out;
     out.off = malloc(sizeof(int64_t) * (size_t)(nd + 1));
-    out.ids = malloc(sizeof(int32_t) * (size_t)cap);
+    out.ids = NULL;
     out.off[0] = 0;
-    double d[3];
-    for (int64_t i = d0; i < d1; ++i) {
-        int64_t ci[3] = {0, 0, 0};
-        for (int k = 0; k < dim; ++k) ci[k] = cell_coord(x[i * dim + k], P->lo[k], edge[k], nc[k]);
-        /* candidate cell coordinates per axis, deduplicated */
-        int64_t cand[3][3], ncand[3] = {1, 1, 1};
-        for (int k = 0; k < 3; ++k) cand[k][0] = 0;
-        for (int k = 0; k < dim; ++k) {
-            ncand[k] = 0;
-            for (int o = -1; o <= 1; ++o) {
-                int64_t c = ci[k] + o;
-                if (P->periodic[k]) c = (c % nc[k] + nc[k]) % nc[k];
-                else if (c < 0 || c >= nc[k]) continue;
-                int dup = 0;
-                for (int t = 0; t < ncand[k]; ++t) dup |= (cand[k][t] == c);
-                if (!dup) cand[k][ncand[k]++] = c;
-            }
+    /* two passes over the destination rows, each row independent of the
+     * others: count the accepted candidates, then, after a prefix sum,
+     * write them and sort each row ascending */
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            for (int64_t i = 0; i < nd; ++i) out.off[i + 1] += out.off[i];
+            out.ids = malloc(sizeof(int32_t) * (size_t)(out.off[nd] > 0 ? out.off[nd] : 1));
         }
-        int64_t row0 = cnt;
-        for (int a = 0; a < ncand[2]; ++a)
-            for (int b = 0; b < ncand[1]; ++b)
-                for (int e = 0; e < ncand[0]; ++e) {
-                    int64_t cell = (cand[2][a] * nc[1] + cand[1][b]) * nc[0] + cand[0][e];
-                    for (int64_t t = start[cell]; t < start[cell + 1]; ++t) {
-                        int32_t j = items[t];
-                        pair_vec(P, x + i * dim, x + (int64_t)j * dim, d);
-                        if (norm2(dim, d) < R2) {
-                            if (cnt == cap) {
-                                cap *= 2;
-                                out.ids = realloc(out.ids, sizeof(int32_t) * (size_t)cap);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = d0; i < d1; ++i) {
+            double d[3];
+            int64_t ci[3] = {0, 0, 0};
+            for (int k = 0; k < dim; ++k) ci[k] = cell_coord(x[i * dim + k], P->lo[k], edge[k], nc[k]);
+            /* candidate cell coordinates per axis, deduplicated */
+            int64_t cand[3][3], ncand[3] = {1, 1, 1};
+            for (int k = 0; k < 3; ++k) cand[k][0] = 0;
+            for (int k = 0; k < dim; ++k) {
+                ncand[k] = 0;
+                for (int o = -1; o <= 1; ++o) {
+                    int64_t c = ci[k] + o;
+                    if (P->periodic[k]) c = (c % nc[k] + nc[k]) % nc[k];
+                    else if (c < 0 || c >= nc[k]) continue;
+                    int dup = 0;
+                    for (int t = 0; t < ncand[k]; ++t) dup |= (cand[k][t] == c);
+                    if (!dup) cand[k][ncand[k]++] = c;
+                }
+            }
+            int64_t cnt = 0, row0 = pass == 1 ? out.off[i - d0] : 0;
+            for (int a = 0; a < ncand[2]; ++a)
+                for (int b = 0; b < ncand[1]; ++b)
+                    for (int e = 0; e < ncand[0]; ++e) {
+                        int64_t cell = (cand[2][a] * nc[1] + cand[1][b]) * nc[0] + cand[0][e];
+                        for (int64_t t = start[cell]; t < start[cell + 1]; ++t) {
+                            int32_t j = items[t];
+                            pair_vec(P, x + i * dim, x + (int64_t)j * dim, d);
+                            if (norm2(dim, d) < R2) {
+                                if (pass == 1) out.ids[row0 + cnt] = j;
+                                ++cnt;
                             }
-                            out.ids[cnt++] = j;
                         }
                     }
-                }
-        qsort(out.ids + row0, (size_t)(cnt - row0), sizeof(int32_t), cmp_i32);
-        out.off[i - d0 + 1] = cnt;
+            if (pass == 0) out.off[i - d0 + 1] = cnt;
+            else qsort(out.ids + row0, (size_t)cnt, sizeof(int32_t), cmp_i32);
+        }
     }
     free(start);
     free(cellof);
@@ -251,6 +281,7 @@ static void density_c(const orc_params *P, const csr_t *N, const double *x,
                       const double *m, double *rho) {
     int64_t dim = P->dim;
     double d[3];
+#pragma omp parallel for schedule(static) private(d)
     for (int64_t i = 0; i < P->nf; ++i) {
         double s = 0.0;
         for (int64_t e = N->off[i]; e < N->off[i + 1]; ++e) {
@@ -272,6 +303,7 @@ static void wall_velocity_c(const orc_params *P, const csr_t *Nw, const double *
                             const double *nrm, int64_t slip, double *uw) {
     int64_t dim = P->dim;
     double d[3];
+#pragma omp parallel for schedule(static) private(d)
     for (int64_t w = 0; w < P->nw; ++w) {
         int64_t iw = P->nf + w;
         double num[3] = {0, 0, 0}, den = 0.0;
@@ -311,6 +343,7 @@ static void forces_c(const orc_params *P, const csr_t *N, const double *x,
                      const double *rho_all, double *f) {
     int64_t dim = P->dim;
     double epsh = P->eta * P->h * P->h, d[3], g[3];
+#pragma omp parallel for schedule(static) private(d, g)
     for (int64_t i = 0; i < P->nf; ++i) {
         double fv[3] = {0, 0, 0}, fa[3] = {0, 0, 0}, fs[3] = {0, 0, 0};
         double Ai[3][3];
@@ -366,6 +399,7 @@ static void rhs_coef_c(const orc_params *P, const csr_t *N, const double *x,
                        double *rhs, double *coef, double *diag) {
     int64_t dim = P->dim;
     double epsh = P->eta * P->h * P->h, d[3], g[3];
+#pragma omp parallel for schedule(static) private(d, g)
     for (int64_t i = 0; i < P->nf; ++i) {
         double s = 0.0, D = 0.0;
         for (int64_t e = N->off[i]; e < N->off[i + 1]; ++e) {
@@ -421,6 +455,7 @@ static void wall_pressure_c(const orc_params *P, const csr_t *Nw, const double *
                             const double *rho_all, double *p_all) {
     int64_t dim = P->dim;
     double d[3];
+#pragma omp parallel for schedule(static) private(d)
     for (int64_t w = 0; w < P->nw; ++w) {
         int64_t iw = P->nf + w;
         double sp = 0.0, sr[3] = {0, 0, 0}, sw = 0.0;
@@ -447,6 +482,7 @@ static void wall_extrap_c(const orc_params *P, const csr_t *Nw, const double *x,
                           const double *rho_all, double *z, int hydro) {
     int64_t dim = P->dim;
     double d[3];
+#pragma omp parallel for schedule(static) private(d)
     for (int64_t w = 0; w < P->nw; ++w) {
         int64_t iw = P->nf + w;
         double sp = 0.0, sr[3] = {0, 0, 0}, sw = 0.0;
@@ -492,6 +528,7 @@ static void bicgstab_c(const orc_params *P, const csr_t *N, const csr_t *Nw, con
     if (P->nw) wall_extrap_c(P, Nw, xs, rho_all, h, 1);
     /* (M z) for the fluid rows; the wall slots of z must hold its extrapolation */
 #define APPLY_M(z, out)                                                        \
+    _Pragma("omp parallel for schedule(static)")                               \
     for (int64_t i = 0; i < nf; ++i) {                                         \
         if (!act[i]) { (out)[i] = (z)[i]; continue; }                          \
         double acc = 0.0;                                                      \
@@ -569,6 +606,7 @@ static void pressure_force_c(const orc_params *P, const csr_t *N, const double *
                              double *f) {
     int64_t dim = P->dim;
     double d[3], g[3];
+#pragma omp parallel for schedule(static) private(d, g)
     for (int64_t i = 0; i < P->nf; ++i) {
         double a[3] = {0, 0, 0};
         for (int64_t e = N->off[i]; e < N->off[i + 1]; ++e) {
@@ -594,6 +632,7 @@ static void gtvf_force_c(const orc_params *P, const csr_t *N, const double *x,
                          double ht, double *f) {
     int64_t dim = P->dim;
     double d[3], g[3];
+#pragma omp parallel for schedule(static) private(d, g)
     for (int64_t i = 0; i < P->nf; ++i) {
         double a[3] = {0, 0, 0};
         for (int64_t e = N->off[i]; e < N->off[i + 1]; ++e) {
@@ -698,6 +737,7 @@ void orc_wall_normals(const orc_params *P, const double *x, const double *m, dou
     csr_t N = build_cells(P, x, nf, nf + nw, nf, nf + nw);
     double *ns = calloc((size_t)(nw * dim), sizeof(double));
     double d[3], g[3];
+#pragma omp parallel for schedule(static) private(d, g)
     for (int64_t w = 0; w < nw; ++w) {
         int64_t iw = nf + w;
         double a[3] = {0, 0, 0};
@@ -710,6 +750,7 @@ void orc_wall_normals(const orc_params *P, const double *x, const double *m, dou
         double mag = sqrt(dot(dim, a, a));
         for (int k = 0; k < dim; ++k) ns[w * dim + k] = mag < 1.0 / (4.0 * P->h) ? 0.0 : a[k] / mag;
     }
+#pragma omp parallel for schedule(static) private(d)
     for (int64_t w = 0; w < nw; ++w) {
         int64_t iw = nf + w;
         double a[3] = {0, 0, 0};
@@ -811,7 +852,7 @@ int64_t orc_step(const orc_params *P, double *x, double *u, double *ut, double *
     } else if (P->solver == ORC_BICGSTAB) bicgstab_c(P, &N, &Nw, xs, rho_all, coef, diag, rhs, fs, lambda, pk, &k, &ratio);
     else for (;;) {
         if (nw) wall_pressure_c(P, &Nw, xs, rho_all, pk);
-        double num = 0.0, den = 0.0;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < nf; ++i) {
             double v = 0.0;
             if (diag[i] != 0.0 && !fs[i]) {
@@ -820,8 +861,12 @@ int64_t orc_step(const orc_params *P, double *x, double *u, double *ut, double *
                 v = P->omega * (rhs[i] + s) / diag[i] + (1.0 - P->omega) * pk[i];
             }
             pn[i] = v;
-            num += fabs(v - pk[i]);
-            den += fabs(v);
+        }
+        /* the two sums in row order, whatever the thread count */
+        double num = 0.0, den = 0.0;
+        for (int64_t i = 0; i < nf; ++i) {
+            num += fabs(pn[i] - pk[i]);
+            den += fabs(pn[i]);
         }
         /* printed form: max(Lambda, sum|p|); the "mean" reading scales Lambda
          * by the fluid count so both terms measure a per-particle pressure */

@@ -69,6 +69,11 @@ double orc_W(int64_t kernel, int64_t dim, double r, double h);
 double orc_dWdr(int64_t kernel, int64_t dim, double r, double h);
 double orc_support(int64_t kernel);
 
+/* Threads of the per-row loops (1 in the serial build), and a setter
+ * (ignored by the serial build). */
+int64_t orc_threads(void);
+void orc_set_threads(int64_t n);
+
 /* Neighbour sets {j in [s0,s1) : |r_ij|^2 < R^2} for dest i in [d0,d1).
  * Brute force O(N^2) and cell-list variants; both return CSR with ids in
  * ascending order.  Return value = number of entries written, or -1 if cap

@@ -650,6 +650,29 @@ def test_determinism():
     assert np.array_equal(a.x, b.x) and np.array_equal(a.p, b.p) and np.array_equal(a.u, b.u)
 
 
+@pytest.mark.parametrize("name", ["tg", "db2d", "db3d", "ldc", "db2d_bicgstab", "cloud"])
+def test_openmp_build_is_bitwise_serial(name):
+    """P17: the OpenMP build (per-row loops in parallel, every sum over rows
+    serial) gives bitwise the serial build's results, on more than one
+    thread."""
+    c = {"tg": lambda: cases.taylor_green(40, kernel="wendland", hdx=1.3, jitter=0.2, seed=2),
+         "db2d": lambda: cases.dam_break_2d(dx=0.05, jitter=0.05),
+         "db3d": lambda: cases.dam_break_3d(dx=0.1, lx=0.5, ly=0.5, lz=0.6, tank_x=1.5, tank_y=0.5, tank_z=1.0),
+         "ldc": lambda: cases.lid_driven_cavity(20),
+         "db2d_bicgstab": lambda: cases.dam_break_2d(dx=0.1).replace(solver="bicgstab", tol=1e-4),
+         "cloud": lambda: cases.cloud_2d()}[name]()
+    before = oracle.threads(parallel=True)
+    oracle.set_threads(4)
+    assert oracle.threads(parallel=True) == 4
+    a, b = oracle.Sim(c), oracle.Sim(c, parallel=True)
+    for _ in range(3):
+        oa, ob = a.step(), b.step()
+        assert oa["iters"] == ob["iters"] and oa["ratio"] == ob["ratio"]
+    oracle.set_threads(before)
+    for f in ("x", "u", "ut", "p"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+
+
 # ------------------------------------------------------ whole-run behaviour
 def test_taylor_green_decay_band():
     """P11: |u|max(t)/|u|max(0) follows exp(b t), b = -8 pi^2 / Re (eq. tgv;
