@@ -3,15 +3,25 @@
 
 A step is one full SISPH time step (binning, predictor, PPE solve,
 correction, GTVF, advance) through the C ABI on a seeded synthetic case whose
-particles are already resident in HBM.  The headline value is whole-job PPE
-throughput: fluid particles x Jacobi sweeps done in the timed steps, divided
-by the wall-clock of those steps (bracketed by device synchronisation).
+particles are already resident in HBM.  The headline workload is the 3D dam
+break (2,000,000 fluid + 1,343,508 wall particles), the largest
+configuration; its value is whole-job PPE throughput: fluid particles x
+Jacobi sweeps done in the timed steps, divided by the wall-clock of those
+steps (bracketed by device synchronisation).
 
-The JSON line also carries the roofline of the dominant kernel (the Jacobi
-sweep: one launch per sweep, or, for a wall-less case that fits on the
-device, one persistent launch per solve holding all its sweeps), timed live
-with HIP events on the library's stream, and the CPU oracle's rate on a
-bounded sample of the same case.
+The JSON line also carries the roofline of the dominant kernel, the Jacobi
+sweep (one launch per sweep, or, for a wall-less case that fits on the
+device, one persistent launch per solve holding all its sweeps): every
+sweep launch is bracketed by its own HIP events on the library's stream
+(the wall pressure pass before it left out), and the achieved rate counts
+the cached-coefficient method's algorithmic bytes per fluid particle and
+sweep (4 B per coefficient over the lattice neighbour count, a neighbour
+bitmask over the stencil candidates, 40 B of per-particle data: 420 B in
+3D, 128 B in 2D, mixed precision).  The implementation's own stored bytes
+and the counter-measured traffic are reported beside it.  A secondary block
+measures the 160,000-particle Taylor-Green case, and the CPU oracle (its
+OpenMP build, all usable cores) is timed on a bounded sample of the
+headline case.
 """
 from __future__ import annotations
 
@@ -56,6 +66,16 @@ def make_case(name: str):
     if name == "db3d_dx0.01_mixed":
         return cases.dam_break_3d(dx=0.01, precision="mixed", tol=1e-3)
     raise SystemExit(f"unknown workload {name}")
+
+
+# Algorithmic bytes of one cached-coefficient Jacobi sweep per fluid
+# particle: coefficients (4 B mixed, 8 B FP64) over the neighbours of an
+# unperturbed lattice without self (2D Wendland h = 1.3 dx: 20, 3D: 80), a
+# neighbour bitmask over the stencil candidates (2D 61 bits ~ 8 B, 3D 475 bits
+# ~ 60 B), and 40 B of per-particle data (RHS, D_ii, own and new iterate,
+# flag, count).
+UNIT_BYTES = {(2, "mixed"): 4 * 20 + 8 + 40, (3, "mixed"): 4 * 80 + 60 + 40,
+              (2, "fp64"): 8 * 20 + 8 + 40, (3, "fp64"): 8 * 80 + 60 + 40}
 
 
 def sweep_bytes(case, slots: int, index_bytes: int = 4, wall_pairs: int = 0, wall_rows: int = 0) -> dict:
@@ -113,10 +133,16 @@ def kernel_sha() -> str:
 
 
 def cpu_baseline(case, budget_s: float) -> dict:
-    """The FP64 oracle (serial C) on the first steps of the same case, for
-    about budget_s seconds of CPU work (at least one step)."""
+    """The FP64 oracle (its OpenMP build, bitwise equal to the serial one)
+    on the first steps of the same case, on every usable host core, for
+    about budget_s seconds (at least one step).  The rate counts whole
+    steps: the oracle's Jacobi sweeps are only part of them."""
     import oracle
-    sim = oracle.Sim(case)
+    info = host_info()
+    usable = info.get("usable_cpus") or os.cpu_count() or 1
+    oracle.set_threads(usable)
+    threads = oracle.threads(parallel=True)
+    sim = oracle.Sim(case, parallel=True)
     t0 = time.perf_counter()
     iters = steps = 0
     while True:
@@ -126,10 +152,10 @@ def cpu_baseline(case, budget_s: float) -> dict:
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": case.n_fluid * iters / dt, "unit": "particle-iters/s", "cores": 1, "kind": "oracle",
+    return {"value": case.n_fluid * iters / dt, "unit": "particle-iters/s", "cores": threads, "kind": "oracle",
             "sample": f"first {steps} step(s) of the same case ({iters} Jacobi sweeps, {case.n_fluid} fluid "
-                      f"particles), {dt:.1f} s on one host core; serial FP64 C oracle",
-            "particle_steps_per_s": case.n_fluid * steps / dt, "host": host_info()}
+                      f"particles), {dt:.1f} s on {threads} host threads; FP64 C oracle, OpenMP build",
+            "particle_steps_per_s": case.n_fluid * steps / dt, "host": info}
 
 
 def host_info() -> dict:
@@ -263,12 +289,116 @@ def serving(n_requests: int, steps: int, rate_hz: float, budget_gb: float, seed:
     return rep
 
 
+def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool) -> dict:
+    """Steps one case: warmup steps, the autotuner, then `steps` timed steps
+    with every sweep kernel launch timed by its own HIP events."""
+    import torch
+    from paper_1908_01762_amd import sisph
+    case = make_case(workload)
+    ctx = sisph.Context(case, device="cuda:0")
+    if launch == "graphs":
+        ctx.use_graphs(True)
+    print(f"[bench] workload {workload}: {case.n_fluid} fluid + {case.n_wall} wall particles, "
+          f"workspace {ctx.nbytes / 1e6:.1f} MB", file=sys.stderr, flush=True)
+    warm = ctx.step(warmup) if warmup else []
+    tuned = None
+    if warmup and autotune:
+        # the project's autotuner picks the sweep launch variant on the live
+        # state (outside the timed region; variants change speed only)
+        best, us = ctx.autotune(20)
+        tuned = {"variant": best, "us_per_variant": [round(t, 3) for t in us]}
+        print(f"[bench] autotuned sweep variant {best}", file=sys.stderr, flush=True)
+    ctx.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    ctx.sweep_counters(reset=True)
+    t0 = time.perf_counter()
+    stats = ctx.step(steps) if steps > 0 else []
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] {workload}: timed {steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    # per-step sweep counts of this process's solves, warmup first (the
+    # profile summaries turn per-launch counters into per-sweep figures)
+    counts = [s["iters"] for s in warm] + [s["iters"] for s in stats]
+    print(f"[bench] solve sweep counts: {counts}", file=sys.stderr, flush=True)
+    iters = sum(s["iters"] for s in stats)
+    value = case.n_fluid * iters / elapsed if elapsed > 0 else 0.0
+    cnt = ctx.sweep_counters()
+    kt = ctx.kernel_timing()
+    pinfo = ctx.persistent_info()
+    fallbacks = ctx.persistent_fallbacks()   # since the reset: the timed steps only
+    wall_rows = ctx.rows_with_neighbours(1, 1) if case.n_wall else 0
+    sb = sweep_bytes(case, ctx.pair_count(1, 0), index_bytes=stats[-1]["index_bytes"] if stats else 4,
+                     wall_pairs=ctx.pair_count(1, 1) if case.n_wall else 0, wall_rows=wall_rows)
+    unit = UNIT_BYTES[(case.dim, case.precision)]
+    # the dominant kernel: the sweep, one launch per sweep, or one persistent
+    # launch per solve holding its sweeps; both are timed by their own events
+    n_persistent = kt["persistent"]
+    n_perlaunch = kt["launches"] - n_persistent
+    if n_persistent and n_perlaunch:
+        mode = "mixed"
+    elif n_persistent:
+        mode = "persistent"
+    else:
+        mode = "per-sweep launches"
+    kernel_s = kt["ms"] / 1e3
+    launches = kt["launches"]
+    eff = cnt["effective"]
+    alg_per_sweep = unit * case.n_fluid
+    achieved = alg_per_sweep * eff / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    layout_rate = sb["bytes"] * eff / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    traffic = traffic_from_profiles(kernel_sha(), workload)
+    kernel = {"persistent": "k_ppe_persistent (one launch per solve)", "per-sweep launches": "Sweep",
+              "mixed": "k_ppe_persistent + Sweep"}[mode]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(traffic * eff / max(launches, 1)) if traffic is not None else None,
+                "kernel": kernel, "mode": mode,
+                "algorithmic_bytes_per_particle_iter": unit,
+                "algorithmic_bytes_per_sweep": alg_per_sweep,
+                "algorithmic_bytes_per_launch": int(round(alg_per_sweep * eff / max(launches, 1))),
+                "avg_launch_us": round(kernel_s * 1e6 / max(launches, 1), 3), "launches": launches,
+                "persistent_launches": n_persistent, "per_sweep_launches": n_perlaunch,
+                "effective_sweeps": eff,
+                "avg_us_per_effective_sweep": round(kernel_s * 1e6 / max(eff, 1), 3),
+                "persistent_fallbacks": fallbacks,
+                "layout": {"bytes_per_sweep": sb["bytes"], "bytes_per_row": sb["per_row"],
+                           "bytes_per_pair": sb["per_pair"], "pairs": sb["pairs"],
+                           "achieved_GBps": round(layout_rate, 1),
+                           "traffic_per_sweep": round(traffic) if traffic is not None else None}}
+    if case.n_wall:
+        # the wall pressure pass runs before every sweep, outside the timed
+        # sweep kernel: its share of the chunk time and its own bytes
+        roofline["wall_pass"] = {"rows": sb["wall_rows"], "pairs": sb["wall_pairs"],
+                                 "bytes_per_row": sb["per_wall_row"], "bytes_per_pair": sb["per_wall_pair"],
+                                 "us_per_sweep": round((cnt["sweep_ms"] - kt["ms"]) * 1e3 / max(cnt["launches"], 1),
+                                                       3)}
+    out = {
+        "value": value,
+        "ms_per_step": elapsed * 1e3 / max(steps, 1),
+        "dtype": "f32+f64" if case.precision == "mixed" else "f64",
+        "config": {"workload": workload, "description": WORKLOADS[workload],
+                   "fluid_particles": case.n_fluid, "wall_particles": case.n_wall,
+                   "launch": launch, "parallelism": "single GPU"},
+        "mean_ppe_iters": iters / max(len(stats), 1),
+        "solves_at_max_iter": sum(1 for s in stats if s["iters"] >= case.max_iter),
+        "particle_steps_per_s": case.n_fluid * steps / elapsed if elapsed > 0 else 0.0,
+        "sweep_time_frac": cnt["sweep_ms"] / 1e3 / elapsed if elapsed > 0 else 0.0,
+        "roofline": roofline,
+        "sweep_variant": tuned if tuned is not None else {"variant": ctx.variant},
+    }
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=195)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="tg400_wendland_mixed", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="db3d_dx0.01_mixed", choices=sorted(WORKLOADS))
+    ap.add_argument("--secondary", default="tg400_wendland_mixed", choices=sorted(WORKLOADS) + ["none"],
+                    help="a second workload measured the same way and reported under 'secondary'")
+    ap.add_argument("--secondary-steps", type=int, default=195)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch-compare", action="store_true")
@@ -312,94 +442,27 @@ def main():
         print(f"[bench] copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written",
               file=sys.stderr, flush=True)
         del src, dst
-    case = make_case(args.workload)
-    ctx = sisph.Context(case, device="cuda:0")
-    if args.launch == "graphs":
-        ctx.use_graphs(True)
-    print(f"[bench] workload {args.workload}: {case.n_fluid} fluid + {case.n_wall} wall particles, "
-          f"workspace {ctx.nbytes / 1e6:.1f} MB", file=sys.stderr, flush=True)
-    warm = ctx.step(args.warmup) if args.warmup else []
-    tuned = None
-    if args.warmup and not args.no_autotune:
-        # the project's autotuner picks the sweep launch variant on the live
-        # state (outside the timed region; variants change speed only)
-        best, us = ctx.autotune(20)
-        tuned = {"variant": best, "us_per_variant": [round(t, 3) for t in us]}
-        print(f"[bench] autotuned sweep variant {best}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    ctx.sweep_counters(reset=True)
-    t0 = time.perf_counter()
-    stats = ctx.step(args.steps) if args.steps > 0 else []
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
-    # per-step sweep counts of this process's solves, warmup first (the
-    # profile summaries turn per-launch counters into per-sweep figures)
-    print(f"[bench] solve sweep counts: {[s['iters'] for s in warm] + [s['iters'] for s in stats]}",
-          file=sys.stderr, flush=True)
-    iters = sum(s["iters"] for s in stats)
-    value = case.n_fluid * iters / elapsed if elapsed > 0 else 0.0
-    cnt = ctx.sweep_counters()
-    wall_rows = ctx.rows_with_neighbours(1, 1) if case.n_wall else 0
-    sb = sweep_bytes(case, ctx.pair_count(1, 0), index_bytes=stats[-1]["index_bytes"] if stats else 4,
-                     wall_pairs=ctx.pair_count(1, 1) if case.n_wall else 0, wall_rows=wall_rows)
-    # Per-launch mode: one launch per sweep (with the wall pass before it in
-    # cases with walls).  Persistent mode: one launch per solve holding all
-    # its sweeps; the algorithmic bytes of a launch are then those of its
-    # sweeps.  Either way achieved = algorithmic bytes of the sweeps that
-    # advanced the solves / the HIP-event time of the launches.
-    pinfo = ctx.persistent_info()
-    persistent = pinfo["solves"] > 0
-    fallbacks = ctx.persistent_fallbacks()
-    print(f"[bench] persistent solves in the timed steps: {pinfo['solves']} of {len(stats)}; "
-          f"fallbacks to per-launch sweeps since creation: {fallbacks}", file=sys.stderr, flush=True)
-    launches = pinfo["solves"] if persistent else cnt["launches"]
-    avg_launch_s = cnt["sweep_ms"] / 1e3 / max(launches, 1)
-    achieved = sb["bytes"] * cnt["effective"] / (cnt["sweep_ms"] / 1e3) / 1e9 if cnt["sweep_ms"] > 0 else 0.0
-    traffic = traffic_from_profiles(kernel_sha(), args.workload)
-    if persistent:
-        kernel = "k_ppe_persistent (one launch per solve)"
-    else:
-        kernel = "Sweep+WallPressure" if case.n_wall else "Sweep"
-    sweeps_per_launch = cnt["launches"] / max(launches, 1)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": round(traffic * sweeps_per_launch) if traffic is not None else None,
-                "traffic_per_sweep": round(traffic) if traffic is not None else None,
-                "kernel": kernel, "mode": "persistent" if persistent else "per-sweep launches",
-                "persistent_fallbacks": fallbacks,
-                "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches": launches,
-                "sweeps": cnt["launches"], "effective_sweeps": cnt["effective"],
-                "avg_sweep_us": round(cnt["sweep_ms"] * 1e3 / max(cnt["launches"], 1), 3),
-                "algorithmic_bytes_per_sweep": sb["bytes"],
-                "algorithmic_bytes_per_launch": int(round(sb["bytes"] * cnt["effective"] / max(launches, 1))),
-                "bytes_per_row": sb["per_row"], "bytes_per_pair": sb["per_pair"], "pairs": sb["pairs"]}
-    if case.n_wall:
-        roofline.update(wall_rows=sb["wall_rows"], wall_pairs=sb["wall_pairs"],
-                        bytes_per_wall_row=sb["per_wall_row"], bytes_per_wall_pair=sb["per_wall_pair"])
+    primary = measure(args.workload, args.steps, args.warmup, args.launch, not args.no_autotune)
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": primary.pop("value"),
         "unit": "particle-iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / max(args.steps, 1),
+        "ms_per_step": primary.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if case.precision == "mixed" else "f64",
+        "dtype": primary.pop("dtype"),
         "data": "synthetic",
-        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
-                   "fluid_particles": case.n_fluid, "wall_particles": case.n_wall,
-                   "launch": args.launch, "parallelism": "single GPU"},
-        "mean_ppe_iters": iters / max(len(stats), 1),
-        "particle_steps_per_s": case.n_fluid * args.steps / elapsed if elapsed > 0 else 0.0,
-        "sweep_time_frac": cnt["sweep_ms"] / 1e3 / elapsed if elapsed > 0 else 0.0,
-        "roofline": roofline,
-        "sweep_variant": tuned if tuned is not None else {"variant": ctx.variant},
+        "config": primary.pop("config"),
     }
-    ctx.close()
+    line.update(primary)
+    if args.secondary != "none" and args.secondary != args.workload:
+        print(f"[bench] secondary workload {args.secondary}", file=sys.stderr, flush=True)
+        line["secondary"] = measure(args.secondary, args.secondary_steps, args.warmup, args.launch,
+                                    not args.no_autotune)
     if not args.no_batch_compare:
         print("[bench] batched vs plain", file=sys.stderr, flush=True)
         line["batched_vs_plain"] = batched_vs_plain(args.batch_cases, args.batch_steps, seed=0)

@@ -233,12 +233,24 @@ int32_t sisph_last_timings(sisph_ctx *ctx, double *ppe_ms, double *step_ms);
 int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_t *launches,
                              int64_t *effective, int32_t reset);
 
+/* Timing of the Jacobi sweep kernel alone.  With on != 0 every sweep
+ * launch of a single context is bracketed by its own pair of HIP events on
+ * the context's stream (the wall pressure pass before it is left out; a
+ * persistent solve's one launch is timed whole), from a pool of
+ * 2 (max_iter + 1) events created here; on = 0 frees the pool.  Off by
+ * default.  sisph_kernel_timing returns, accumulated since the last reset of
+ * sisph_sweep_counters, the summed kernel time in milliseconds, the number
+ * of timed launches (launches past a solve's stop included) and how many of
+ * them were persistent solves.  Any pointer may be NULL. */
+int32_t sisph_set_kernel_timing(sisph_ctx *ctx, int32_t on);
+int32_t sisph_kernel_timing(sisph_ctx *ctx, double *ms, int64_t *launches, int64_t *persistent);
+
 /* Persistent solves (see sisph_set_persistent) since the last counter reset
  * (kernel launches, one per solve), and whether the last solve was one. */
 int32_t sisph_persistent_info(sisph_ctx *ctx, int64_t *solves, int32_t *last);
 
-/* Since creation, how often a solve meant for one persistent launch ran as
- * per-launch sweeps instead: the runtime refused the cooperative launch
+/* Since the last reset of sisph_sweep_counters, how often a solve meant
+ * for one persistent launch ran as per-launch sweeps instead: the runtime refused the cooperative launch
  * (it is tried again on later solves; after eight refusals that first-batch
  * size is given up), or a workgroup waited
  * longer than the spin limit at a grid barrier (the solve was redone from

@@ -44,12 +44,18 @@ struct sisph_ctx {
     int64_t persist_refused = 0, persist_timeouts = 0;         // fallbacks to per-launch sweeps
     int32_t persist_refusals[3] = {0, 0, 0};                   // per first-batch size, until it is given up
     bool persist_last = false;
+    // sweep-kernel timing (sisph_set_kernel_timing): one event pair per
+    // sweep launch of a chunk, the wall pass left out
+    std::vector<hipEvent_t> kev;
+    double kt_ms = 0.0;
+    int64_t kt_launches = 0, kt_persistent = 0;
     hipStream_t cap_stream = nullptr;                          // capture only
     hipGraphExec_t g_pre = nullptr, g_post = nullptr;          // fixed step segments
     std::string err;
 };
 
 static thread_local std::string g_create_err;
+
 
 #define HIPCHK(ctx, expr)                                                               \
     do {                                                                                \
@@ -59,6 +65,18 @@ static thread_local std::string g_create_err;
             return SISPH_E_DEVICE;                                                      \
         }                                                                               \
     } while (0)
+
+// Event helpers that accept a missing event (recording skipped, time zero).
+static hipError_t ev_record(hipEvent_t e, hipStream_t s) { return e ? hipEventRecord(e, s) : hipSuccess; }
+static hipError_t ev_elapsed(float *ms, hipEvent_t a, hipEvent_t b) {
+    if (!a || !b) {
+        *ms = 0.f;
+        return hipSuccess;
+    }
+    return hipEventElapsedTime(ms, a, b);
+}
+static hipError_t ev_query(hipEvent_t e) { return e ? hipEventQuery(e) : hipSuccess; }
+static hipError_t ev_sync(hipEvent_t e) { return e ? hipEventSynchronize(e) : hipSuccess; }
 
 // ----------------------------------------------------------- descriptor
 static double support_of(int kernel) { return kernel == SISPH_QUINTIC ? 3.0 : 2.0; }
@@ -290,16 +308,16 @@ static int32_t h2d(sisph_ctx *ctx, double *dst, const double *src, int64_t n) {
     return SISPH_OK;
 }
 
-// Host row-major [n][dim] -> device SoA component arrays (offset `at`).
+// Host row-major [n][dim] -> device SoA component arrays (offset `at`),
+// through the reorder scratch (16 x max(n_fluid, n_wall) doubles, free
+// between steps) and a transpose kernel: no host staging buffer.
 static int32_t upload_vec(sisph_ctx *ctx, double *const dst[3], int64_t at, const double *src, int64_t n) {
     const int D = ctx->P.dim;
-    std::vector<double> col((size_t)n);
-    for (int k = 0; k < D; ++k) {
-        for (int64_t i = 0; i < n; ++i) col[(size_t)i] = src[i * D + k];
-        HIPCHK(ctx, hipMemcpyAsync(dst[k] + at, col.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice,
-                                   ctx->stream));
-        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->S.tmp, src, sizeof(double) * (size_t)(n * D), hipMemcpyHostToDevice,
+                               ctx->stream));
+    aos_to_soa(ctx->S.tmp, dst, at, D, n, ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return SISPH_OK;
 }
 
@@ -314,10 +332,10 @@ static int32_t read_ctl(sisph_ctx *ctx) {
 // again.  A not-ready query is no error and is not left behind as one.
 static void settle_step_time_if_done(sisph_ctx *ctx) {
     if (!ctx->step_pending) return;
-    const hipError_t q = hipEventQuery(ctx->ev[3]);
+    const hipError_t q = ev_query(ctx->ev[3]);
     if (q == hipSuccess) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]) == hipSuccess) ctx->step_ms = ms;
+        if (ev_elapsed(&ms, ctx->ev[0], ctx->ev[3]) == hipSuccess) ctx->step_ms = ms;
     } else if (q == hipErrorNotReady) {
         (void)hipGetLastError();
     }
@@ -328,9 +346,9 @@ static void settle_step_time_if_done(sisph_ctx *ctx) {
 // before its events are recorded again.
 static int32_t settle_ppe_time(sisph_ctx *ctx) {
     if (!ctx->ppe_pending) return SISPH_OK;
-    HIPCHK(ctx, hipEventSynchronize(ctx->ev[2]));
+    HIPCHK(ctx, ev_sync(ctx->ev[2]));
     float ms = 0.f;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+    HIPCHK(ctx, ev_elapsed(&ms, ctx->ev[1], ctx->ev[2]));
     ctx->ppe_ms = ms;
     ctx->ppe_pending = false;
     return SISPH_OK;
@@ -377,33 +395,84 @@ static int32_t status_of(const Control &C, const Params &P, std::string *msg) {
 }
 
 // ---------------------------------------------------------------- create
-extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, size_t ws_bytes, const double *x,
-                                const double *u, const double *p, const double *m, const double *wall_u,
-                                void *hip_stream, sisph_ctx **out) {
-    if (!out) return SISPH_E_INVAL;
-    *out = nullptr;
-    if (const char *why = check_desc(desc)) {
-        g_create_err = why;
-        return SISPH_E_INVAL;
+// Sets a context up for a case whose workspace is carved already: uploads
+// the state (through the workspace, no host buffers), clears the control
+// block, bins the walls once and computes their normals.  On an error the
+// message is in ctx->err.
+static int32_t init_state(sisph_ctx *ctx, const sisph_case_desc *desc, const double *x, const double *u,
+                          const double *p, const double *m, const double *wall_u) {
+    auto fail_create = [](int32_t code) { return code; };
+    const Params &P = ctx->P;
+    State &S = ctx->S;
+    const int64_t nf = P.nf, nw = P.nw, nt = P.ntot, D = P.dim;
+    hipStream_t s = ctx->stream;
+    int32_t st;
+    // state in caller order; fluid ids are 0..nf-1, wall ids 0..nw-1
+    if ((st = upload_vec(ctx, S.x, 0, x, nt)) != SISPH_OK) return fail_create(st);
+    if ((st = upload_vec(ctx, S.u, 0, u, nf)) != SISPH_OK) return fail_create(st);
+    if ((st = upload_vec(ctx, S.ut, 0, u, nf)) != SISPH_OK) return fail_create(st);
+    if ((st = h2d(ctx, S.p[0], p, nt)) != SISPH_OK) return fail_create(st);
+    if ((st = h2d(ctx, S.m, m, nt)) != SISPH_OK) return fail_create(st);
+    if (nw > 0) {
+        if (wall_u) {
+            if ((st = upload_vec(ctx, S.wallu, 0, wall_u, nw)) != SISPH_OK) return fail_create(st);
+        } else {
+            for (int k = 0; k < D; ++k) fill_f64(S.wallu[k], 0.0, nw, s);
+        }
     }
-    if (!x || !u || !p || !m || !d_workspace) {
-        g_create_err = "null array argument";
-        return SISPH_E_INVAL;
+    iota_i32(S.id, nf, s);
+    iota_i32(S.wid, nw, s);
+    reset_control(ctx->T, RESET_PPE | RESET_NEIGHBOURS | RESET_PREF | RESET_DT);
+    if (desc->p_ref_mode == SISPH_PREF_FIXED) {
+        Control c0{};
+        c0.p_ref = desc->p_ref;
+        c0.p_ref_set = 1;
+        if (hipMemcpyAsync(&S.ctl->p_ref, &c0.p_ref, sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(&S.ctl->p_ref_set, &c0.p_ref_set, sizeof(int32_t), hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            ctx->err = "control upload failed";
+            return fail_create(SISPH_E_DEVICE);
+        }
     }
-    if (((uintptr_t)d_workspace & 255) != 0) {
-        g_create_err = "workspace must be 256-byte aligned";
-        return SISPH_E_INVAL;
+    // walls: one stable sort into cell order (they never move)
+    fill_u32(S.wstart, 0u, P.grid.ncell + 1, s);
+    if (nw > 0) {
+        bin_walls_once(ctx->T);
+        fill_f64(S.rho + nf, P.rho0, nw, s);
+        fill_f64(S.p[0] + nf, 0.0, nw, s);
+        fill_f64(S.p[1] + nf, 0.0, nw, s);
+        for (int k = 0; k < D; ++k) {
+            if (hipMemcpyAsync(S.xs[k] + nf, S.x[k] + nf, sizeof(double) * nw, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess ||
+                hipMemcpyAsync(S.xk[0][k] + nf, S.x[k] + nf, sizeof(double) * nw, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess ||
+                hipMemcpyAsync(S.xk[1][k] + nf, S.x[k] + nf, sizeof(double) * nw, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess) {
+                ctx->err = "wall copy failed";
+                return fail_create(SISPH_E_DEVICE);
+            }
+            fill_f64(S.u[k] + nf, 0.0, nw, s);
+            fill_f64(S.us[k] + nf, 0.0, nw, s);
+        }
+        wall_normals(ctx->T);
     }
-    size_t need = sisph_workspace_bytes(desc);
-    if (need == 0) {
-        g_create_err = "binning grid too large";
-        return SISPH_E_INVAL;
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        ctx->err = "device error during create";
+        return fail_create(SISPH_E_DEVICE);
     }
-    if (ws_bytes < need) {
-        g_create_err = "workspace too small: need " + std::to_string(need) + " bytes";
-        return SISPH_E_NOMEM;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg, "kernel launch failed: %s", hipGetErrorString(e));
+        ctx->err.assign(msg);
+        return fail_create(SISPH_E_DEVICE);
     }
-    sisph_ctx *ctx = new sisph_ctx();
+    return SISPH_OK;
+}
+
+// The host fields of a fresh context (everything but the workspace).
+static void reset_ctx(sisph_ctx *ctx, const sisph_case_desc *desc, void *hip_stream) {
     ctx->desc = *desc;
     ctx->P = make_params(desc);
     ctx->stream = (hipStream_t)hip_stream;
@@ -415,8 +484,62 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
     ctx->sweep_ms = 0.0;
     ctx->sweep_launches = ctx->sweep_effective = 0;
     ctx->step_timed = false;
+    ctx->step_pending = ctx->ppe_pending = false;
     ctx->batch = nullptr;
     ctx->variant = kDefaultVariant;
+    ctx->use_graphs = false;
+    ctx->use_persistent = true;
+    for (auto &c : ctx->persist_cap) c = -1;
+    ctx->persist_solves = ctx->persist_refused = ctx->persist_timeouts = 0;
+    for (auto &r : ctx->persist_refusals) r = 0;
+    ctx->persist_last = false;
+    ctx->kt_ms = 0.0;
+    ctx->kt_launches = ctx->kt_persistent = 0;
+    ctx->err.clear();
+}
+
+// Descriptor, arrays and workspace size; the message of a refusal in *why.
+static int32_t check_create(const sisph_case_desc *desc, const double *x, const double *u, const double *p,
+                            const double *m, size_t *need, const char **why) {
+    if ((*why = check_desc(desc))) return SISPH_E_INVAL;
+    if (!x || !u || !p || !m) {
+        *why = "null array argument";
+        return SISPH_E_INVAL;
+    }
+    *need = sisph_workspace_bytes(desc);
+    if (*need == 0) {
+        *why = "binning grid too large";
+        return SISPH_E_INVAL;
+    }
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, size_t ws_bytes, const double *x,
+                                const double *u, const double *p, const double *m, const double *wall_u,
+                                void *hip_stream, sisph_ctx **out) {
+    if (!out) return SISPH_E_INVAL;
+    *out = nullptr;
+    size_t need = 0;
+    const char *why = nullptr;
+    int32_t st = check_create(desc, x, u, p, m, &need, &why);
+    if (st != SISPH_OK) {
+        g_create_err = why;
+        return st;
+    }
+    if (!d_workspace) {
+        g_create_err = "null workspace";
+        return SISPH_E_INVAL;
+    }
+    if (((uintptr_t)d_workspace & 255) != 0) {
+        g_create_err = "workspace must be 256-byte aligned";
+        return SISPH_E_INVAL;
+    }
+    if (ws_bytes < need) {
+        g_create_err = "workspace too small: need " + std::to_string(need) + " bytes";
+        return SISPH_E_NOMEM;
+    }
+    sisph_ctx *ctx = new sisph_ctx();
+    reset_ctx(ctx, desc, hip_stream);
     ctx->h_ctl = nullptr;
     for (auto &e : ctx->ev) e = nullptr;
     for (auto &e : ctx->evc) e = nullptr;
@@ -448,70 +571,7 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
             ctx->err = "hipEventCreate failed";
             return bail(SISPH_E_DEVICE);
         }
-    const Params &P = ctx->P;
-    State &S = ctx->S;
-    const int64_t nf = P.nf, nw = P.nw, nt = P.ntot, D = P.dim;
-    hipStream_t s = ctx->stream;
-    int32_t st;
-    // state in caller order; fluid ids are 0..nf-1, wall ids 0..nw-1
-    if ((st = upload_vec(ctx, S.x, 0, x, nt)) != SISPH_OK) return bail(st);
-    if ((st = upload_vec(ctx, S.u, 0, u, nf)) != SISPH_OK) return bail(st);
-    if ((st = upload_vec(ctx, S.ut, 0, u, nf)) != SISPH_OK) return bail(st);
-    if ((st = h2d(ctx, S.p[0], p, nt)) != SISPH_OK) return bail(st);
-    if ((st = h2d(ctx, S.m, m, nt)) != SISPH_OK) return bail(st);
-    if (nw > 0) {
-        if (wall_u) {
-            if ((st = upload_vec(ctx, S.wallu, 0, wall_u, nw)) != SISPH_OK) return bail(st);
-        } else {
-            for (int k = 0; k < D; ++k) fill_f64(S.wallu[k], 0.0, nw, s);
-        }
-    }
-    iota_i32(S.id, nf, s);
-    iota_i32(S.wid, nw, s);
-    reset_control(ctx->T, RESET_PPE | RESET_NEIGHBOURS | RESET_PREF | RESET_DT);
-    if (desc->p_ref_mode == SISPH_PREF_FIXED) {
-        Control c0{};
-        c0.p_ref = desc->p_ref;
-        c0.p_ref_set = 1;
-        if (hipMemcpyAsync(&S.ctl->p_ref, &c0.p_ref, sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipMemcpyAsync(&S.ctl->p_ref_set, &c0.p_ref_set, sizeof(int32_t), hipMemcpyHostToDevice, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            ctx->err = "control upload failed";
-            return bail(SISPH_E_DEVICE);
-        }
-    }
-    // walls: one stable sort into cell order (they never move)
-    fill_u32(S.wstart, 0u, P.grid.ncell + 1, s);
-    if (nw > 0) {
-        bin_walls_once(ctx->T);
-        fill_f64(S.rho + nf, P.rho0, nw, s);
-        fill_f64(S.p[0] + nf, 0.0, nw, s);
-        fill_f64(S.p[1] + nf, 0.0, nw, s);
-        for (int k = 0; k < D; ++k) {
-            if (hipMemcpyAsync(S.xs[k] + nf, S.x[k] + nf, sizeof(double) * nw, hipMemcpyDeviceToDevice, s) !=
-                    hipSuccess ||
-                hipMemcpyAsync(S.xk[0][k] + nf, S.x[k] + nf, sizeof(double) * nw, hipMemcpyDeviceToDevice, s) !=
-                    hipSuccess ||
-                hipMemcpyAsync(S.xk[1][k] + nf, S.x[k] + nf, sizeof(double) * nw, hipMemcpyDeviceToDevice, s) !=
-                    hipSuccess) {
-                ctx->err = "wall copy failed";
-                return bail(SISPH_E_DEVICE);
-            }
-            fill_f64(S.u[k] + nf, 0.0, nw, s);
-            fill_f64(S.us[k] + nf, 0.0, nw, s);
-        }
-        wall_normals(ctx->T);
-    }
-    if (hipStreamSynchronize(s) != hipSuccess) {
-        ctx->err = "device error during create";
-        return bail(SISPH_E_DEVICE);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        ctx->err = std::string("kernel launch failed: ") + hipGetErrorString(e);
-        return bail(SISPH_E_DEVICE);
-    }
+    if ((st = init_state(ctx, desc, x, u, p, m, wall_u)) != SISPH_OK) return bail(st);
     *out = ctx;
     return SISPH_OK;
 }
@@ -606,7 +666,7 @@ extern "C" int32_t sisph_bin(sisph_ctx *ctx) {
     if (attached(ctx)) return fail(ctx, SISPH_E_STATE, "context is attached to a batch");
     if (ctx->state != ST_READY) return fail(ctx, SISPH_E_STATE, "sisph_bin needs a completed step");
     settle_step_time_if_done(ctx);
-    HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    HIPCHK(ctx, ev_record(ctx->ev[0], ctx->stream));
     seq_bin(ctx->T);
     HIPCHK(ctx, hipGetLastError());
     ctx->state = ST_BINNED;
@@ -650,16 +710,38 @@ static void record_iters(sisph_ctx *ctx, int iters) {
 // for L sweeps is taken at the start of launch L, so each chunk of launches
 // ends one beyond the predicted count.  poll() reads the control state and
 // reports whether every case has stopped.
+// Optional timing of the sweep kernel alone: each sweep launch of a chunk
+// (up to the pool's size) between its own pair of events, read after the
+// chunk's poll.
+struct KTimer {
+    hipEvent_t *ev;      // 2 per launch
+    int64_t cap;         // launches the pool covers
+    double *ms;
+    int64_t *launches;
+};
+
 template <class Poll>
 static int32_t ppe_loop(const Target &T, int64_t predicted, int64_t limit, hipEvent_t e0, hipEvent_t e1,
-                        double &sweep_ms, int64_t &launches, Poll poll, std::string &err) {
+                        double &sweep_ms, int64_t &launches, Poll poll, std::string &err,
+                        const KTimer *kt = nullptr) {
     int64_t chunk = std::min<int64_t>(predicted + 1, limit);
     int64_t launched = 0;
     int polls = 0;
     for (;;) {
-        if (hipEventRecord(e0, T.s) != hipSuccess) return SISPH_E_DEVICE;
-        for (int64_t c = 0; c < chunk; ++c) ppe_iteration(T, (int)(launched + c));
-        if (hipEventRecord(e1, T.s) != hipSuccess) return SISPH_E_DEVICE;
+        if (ev_record(e0, T.s) != hipSuccess) return SISPH_E_DEVICE;
+        int64_t timed = 0;
+        for (int64_t c = 0; c < chunk; ++c) {
+            if (kt && timed < kt->cap && T.solver == SISPH_JACOBI) {
+                wall_pressure_iteration(T, (int)(launched + c));
+                if (hipEventRecord(kt->ev[2 * timed], T.s) != hipSuccess) return SISPH_E_DEVICE;
+                sweep_only(T, (int)(launched + c));
+                if (hipEventRecord(kt->ev[2 * timed + 1], T.s) != hipSuccess) return SISPH_E_DEVICE;
+                ++timed;
+            } else {
+                ppe_iteration(T, (int)(launched + c));
+            }
+        }
+        if (ev_record(e1, T.s) != hipSuccess) return SISPH_E_DEVICE;
         launched += chunk;
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
@@ -670,9 +752,15 @@ static int32_t ppe_loop(const Target &T, int64_t predicted, int64_t limit, hipEv
         int32_t st = poll(all_done);
         if (st != SISPH_OK) return st;
         float cms = 0.f;
-        if (hipEventElapsedTime(&cms, e0, e1) != hipSuccess) return SISPH_E_DEVICE;
+        if (ev_elapsed(&cms, e0, e1) != hipSuccess) return SISPH_E_DEVICE;
         sweep_ms += cms;
         launches += chunk;
+        for (int64_t c = 0; c < timed; ++c) {
+            float kms = 0.f;
+            if (hipEventElapsedTime(&kms, kt->ev[2 * c], kt->ev[2 * c + 1]) != hipSuccess) return SISPH_E_DEVICE;
+            *kt->ms += kms;
+            *kt->launches += 1;
+        }
         if (all_done || launched >= limit) break;
         // the prediction fell short: first by a little, as a rule (a
         // thirty-second of what has been launched), then grow by a quarter
@@ -708,10 +796,10 @@ static int32_t ppe_run(sisph_ctx *ctx, int64_t predicted, int64_t limit) {
         // solve) in case the launch has to be redone with per-launch sweeps
         const size_t pbytes = sizeof(double) * (size_t)ctx->P.ntot;
         HIPCHK(ctx, hipMemcpyAsync(ctx->S.tmp, ctx->S.p[0], pbytes, hipMemcpyDeviceToDevice, ctx->stream));
-        HIPCHK(ctx, hipEventRecord(ctx->evc[0], ctx->stream));
+        HIPCHK(ctx, ev_record(ctx->evc[0], ctx->stream));
         const hipError_t e = ppe_persistent(ctx->T, (int)limit);
         if (e == hipSuccess) {
-            HIPCHK(ctx, hipEventRecord(ctx->evc[1], ctx->stream));
+            HIPCHK(ctx, ev_record(ctx->evc[1], ctx->stream));
             int32_t st = read_ctl(ctx);
             if (st != SISPH_OK) return st;
             if (ctx->h_ctl->barrier_late) {
@@ -726,9 +814,14 @@ static int32_t ppe_run(sisph_ctx *ctx, int64_t predicted, int64_t limit) {
                 return ppe_run(ctx, predicted, limit);
             }
             float ms = 0.f;
-            HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->evc[0], ctx->evc[1]));
+            HIPCHK(ctx, ev_elapsed(&ms, ctx->evc[0], ctx->evc[1]));
             ctx->sweep_ms += ms;
             ctx->sweep_launches += ctx->h_ctl->iter + 1;   // sweeps run, the one after the stop included
+            if (!ctx->kev.empty()) {   // the persistent launch is the sweep kernel
+                ctx->kt_ms += ms;
+                ctx->kt_launches += 1;
+                ctx->kt_persistent += 1;
+            }
             ctx->persist_solves += 1;
             ctx->persist_last = true;
             return SISPH_OK;
@@ -746,8 +839,9 @@ static int32_t ppe_run(sisph_ctx *ctx, int64_t predicted, int64_t limit) {
         done = ctx->h_ctl->done != 0;
         return SISPH_OK;
     };
+    KTimer kt{ctx->kev.data(), (int64_t)ctx->kev.size() / 2, &ctx->kt_ms, &ctx->kt_launches};
     return ppe_loop(ctx->T, predicted, limit, ctx->evc[0], ctx->evc[1], ctx->sweep_ms, ctx->sweep_launches, poll,
-                    ctx->err);
+                    ctx->err, ctx->kev.empty() ? nullptr : &kt);
 }
 
 extern "C" int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out) {
@@ -758,7 +852,7 @@ extern "C" int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out) {
     hipStream_t s = ctx->stream;
     int32_t st = settle_ppe_time(ctx);
     if (st != SISPH_OK) return st;
-    HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
+    HIPCHK(ctx, ev_record(ctx->ev[1], s));
     seq_ppe_begin(ctx->T);
     const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1;
     const int64_t predicted = predict_iters(ctx);
@@ -771,14 +865,14 @@ extern "C" int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out) {
     // nothing), so the host does not wait for it and goes on queueing.
     const bool no_wait = ctx->persist_last && ctx->h_ctl->p_ref_set;
     seq_ppe_end(ctx->T);
-    HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+    HIPCHK(ctx, ev_record(ctx->ev[2], s));
     if (no_wait) {
         HIPCHK(ctx, hipGetLastError());
         ctx->ppe_pending = true;
     } else {
         if ((st = read_ctl(ctx)) != SISPH_OK) return st;
         float ms = 0.f;
-        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+        HIPCHK(ctx, ev_elapsed(&ms, ctx->ev[1], ctx->ev[2]));
         ctx->ppe_ms = ms;
     }
     const Control &C = *ctx->h_ctl;
@@ -799,7 +893,7 @@ extern "C" int32_t sisph_correct(sisph_ctx *ctx) {
     hipStream_t s = ctx->stream;
     seq_correct(ctx->T, ctx->P.gtvf_K);
     HIPCHK(ctx, hipGetLastError());
-    HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
+    HIPCHK(ctx, ev_record(ctx->ev[3], s));
     ctx->step_pending = ctx->step_timed;   // read when asked: the host does not wait for the step here
     ctx->state = ST_READY;
     return SISPH_OK;
@@ -825,9 +919,9 @@ static int32_t step_graphed(sisph_ctx *ctx, sisph_step_stats *out) {
     const int32_t pst = settle_ppe_time(ctx);
     if (pst != SISPH_OK) return pst;
     settle_step_time_if_done(ctx);
-    HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
+    HIPCHK(ctx, ev_record(ctx->ev[0], s));
     HIPCHK(ctx, hipGraphLaunch(ctx->g_pre, s));
-    HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
+    HIPCHK(ctx, ev_record(ctx->ev[1], s));
     const int64_t limit = (int64_t)(P.forced_iters > 0 ? P.forced_iters : P.max_iter) + 1;
     const int64_t predicted = predict_iters(ctx);
     int32_t st = ppe_run(ctx, predicted, limit);
@@ -835,18 +929,18 @@ static int32_t step_graphed(sisph_ctx *ctx, sisph_step_stats *out) {
     // as in sisph_ppe_solve: after a persistent solve with p_ref set, the
     // control block read at the solve's end is final for the stats
     const bool no_wait = ctx->persist_last && ctx->h_ctl->p_ref_set;
-    HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+    HIPCHK(ctx, ev_record(ctx->ev[2], s));
     HIPCHK(ctx, hipGraphLaunch(ctx->g_post, s));
-    HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
+    HIPCHK(ctx, ev_record(ctx->ev[3], s));
     if (no_wait) {
         ctx->ppe_pending = true;   // the sweeps (set-up and settle are inside the graphs)
         ctx->step_pending = true;
     } else {
         if ((st = read_ctl(ctx)) != SISPH_OK) return st;
         float ms = 0.f;
-        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+        HIPCHK(ctx, ev_elapsed(&ms, ctx->ev[1], ctx->ev[2]));
         ctx->ppe_ms = ms;   // the sweeps (set-up and settle are inside the graphs)
-        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
+        HIPCHK(ctx, ev_elapsed(&ms, ctx->ev[0], ctx->ev[3]));
         ctx->step_ms = ms;
         ctx->step_pending = false;
     }
@@ -1086,9 +1180,9 @@ extern "C" int32_t sisph_last_timings(sisph_ctx *ctx, double *ppe_ms, double *st
     const int32_t st = settle_ppe_time(ctx);
     if (st != SISPH_OK) return st;
     if (ctx->step_pending) {
-        HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
+        HIPCHK(ctx, ev_sync(ctx->ev[3]));
         float ms = 0.f;
-        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
+        HIPCHK(ctx, ev_elapsed(&ms, ctx->ev[0], ctx->ev[3]));
         ctx->step_ms = ms;
         ctx->step_pending = false;
     }
@@ -1107,7 +1201,40 @@ extern "C" int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_
         ctx->sweep_ms = 0.0;
         ctx->sweep_launches = ctx->sweep_effective = 0;
         ctx->persist_solves = 0;
+        ctx->persist_refused = ctx->persist_timeouts = 0;
+        ctx->kt_ms = 0.0;
+        ctx->kt_launches = ctx->kt_persistent = 0;
     }
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_set_kernel_timing(sisph_ctx *ctx, int32_t on) {
+    if (!ctx) return SISPH_E_INVAL;
+    if (!on) {
+        for (auto &e : ctx->kev) (void)hipEventDestroy(e);
+        ctx->kev.clear();
+        return SISPH_OK;
+    }
+    if (!ctx->kev.empty()) return SISPH_OK;
+    // one pair per launch a chunk can hold: max_iter + 1 (or forced_iters + 1)
+    const int64_t n = 2 * ((int64_t)(ctx->P.forced_iters > 0 ? ctx->P.forced_iters : ctx->P.max_iter) + 1);
+    ctx->kev.assign((size_t)n, nullptr);
+    for (auto &e : ctx->kev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &f : ctx->kev)
+                if (f) (void)hipEventDestroy(f);
+            ctx->kev.clear();
+            return fail(ctx, SISPH_E_DEVICE, "hipEventCreate failed");
+        }
+    }
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_kernel_timing(sisph_ctx *ctx, double *ms, int64_t *launches, int64_t *persistent) {
+    if (!ctx) return SISPH_E_INVAL;
+    if (ms) *ms = ctx->kt_ms;
+    if (launches) *launches = ctx->kt_launches;
+    if (persistent) *persistent = ctx->kt_persistent;
     return SISPH_OK;
 }
 
@@ -1443,13 +1570,13 @@ extern "C" int32_t sisph_autotune(sisph_ctx *ctx, int32_t reps, int32_t *best, d
     for (int v = 0; v < kSweepVariants; ++v) {
         T.variant = v;
         sweep_only(T, 0);   // warm-up
-        HIPCHK(ctx, hipEventRecord(ctx->evc[0], ctx->stream));
+        HIPCHK(ctx, ev_record(ctx->evc[0], ctx->stream));
         for (int r = 0; r < reps; ++r) sweep_only(T, 0);
-        HIPCHK(ctx, hipEventRecord(ctx->evc[1], ctx->stream));
-        HIPCHK(ctx, hipEventSynchronize(ctx->evc[1]));
+        HIPCHK(ctx, ev_record(ctx->evc[1], ctx->stream));
+        HIPCHK(ctx, ev_sync(ctx->evc[1]));
         HIPCHK(ctx, hipGetLastError());
         float ms = 0.f;
-        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->evc[0], ctx->evc[1]));
+        HIPCHK(ctx, ev_elapsed(&ms, ctx->evc[0], ctx->evc[1]));
         t_us[v] = ms * 1e3 / reps;
         if (us) us[v] = t_us[v];
         if (v == 0 || t_us[v] < t_us[win]) win = v;
@@ -1485,12 +1612,15 @@ extern "C" int32_t sisph_destroy(sisph_ctx *ctx) {
     if (!ctx) return SISPH_E_INVAL;
     if (ctx->batch) (void)sisph_batch_detach(ctx->batch, ctx);
     (void)hipStreamSynchronize(ctx->stream);
+
     drop_graphs(ctx->g_pre, ctx->g_post);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->evc)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : ctx->kev)
         if (e) (void)hipEventDestroy(e);
     delete ctx;
     return SISPH_OK;

@@ -202,8 +202,10 @@ void ppe_iteration(const Target &T, int launch);
 // BiCGStab set-up (x = p^n, r = f - M x, r^ = r) and final copy of x into p[0].
 void bicg_begin(const Target &T);
 void bicg_settle(const Target &T);
-// The sweep alone (no wall pressure), for timing variants.
+// The sweep alone (no wall pressure), for timing variants; the wall
+// pressure pass of Jacobi sweep L alone.
 void sweep_only(const Target &T, int launch);
+void wall_pressure_iteration(const Target &T, int launch);
 // Fluid rows from which a single case's sweep tests the stop flag first.
 constexpr int64_t kPrecheckRows = int64_t(1) << 19;
 constexpr int kSweepVariants = 6;
@@ -231,5 +233,7 @@ void gather_control(const Target &T, Control *out);
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void fill_f64(double *p, double v, int64_t n, hipStream_t s);
 void iota_i32(int32_t *p, int64_t n, hipStream_t s);
+// Row-major [n][dim] device array -> the SoA component arrays dst[k] + at.
+void aos_to_soa(const double *src, double *const dst[3], int64_t at, int dim, int64_t n, hipStream_t s);
 
 }  // namespace sisph

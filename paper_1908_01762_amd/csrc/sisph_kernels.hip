@@ -2421,6 +2421,21 @@ void iota_i32(int32_t *p, int64_t n, hipStream_t s) {
     if (n > 0) k_iota<<<nblocks(n), kBlock, 0, s>>>(p, n);
 }
 
+__global__ __launch_bounds__(kBlock) void k_aos_to_soa(const double *__restrict__ src, double *d0, double *d1,
+                                                       double *d2, int dim, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    d0[i] = src[i * dim];
+    if (dim > 1) d1[i] = src[i * dim + 1];
+    if (dim > 2) d2[i] = src[i * dim + 2];
+}
+
+void aos_to_soa(const double *src, double *const dst[3], int64_t at, int dim, int64_t n, hipStream_t s) {
+    if (n > 0)
+        k_aos_to_soa<<<nblocks(n), kBlock, 0, s>>>(src, dst[0] + at, dim > 1 ? dst[1] + at : nullptr,
+                                                    dim > 2 ? dst[2] + at : nullptr, dim, n);
+}
+
 void reset_control(const Target &T, int what) { launch<ResetControl, K_ONE>(T, what); }
 
 void gather_control(const Target &T, Control *out) { launch<GatherControl, K_ONE>(T, out); }
@@ -2565,11 +2580,15 @@ void ppe_iteration(const Target &T, int L) {
         launch<BicgUpdate, K_FLUID>(T, it);
         return;
     }
+    wall_pressure_iteration(T, L);
+    sweep_only(T, L);
+}
+
+void wall_pressure_iteration(const Target &T, int L) {
     // hardware workgroup order: the listed workgroups, which take the first
     // launch slots, then spread over every XCD
     if (T.precision == SISPH_MIXED) launch<WallPressure<float>, K_WALL, false>(T, L, 0);
     else launch<WallPressure<double>, K_WALL, false>(T, L, 0);
-    sweep_only(T, L);
 }
 
 void bicg_begin(const Target &T) {

@@ -101,6 +101,10 @@ def lib():
         L.sisph_debug_barrier_spins.argtypes = [C.c_void_p, C.c_uint32]
         L.sisph_persistent_info.restype = C.c_int32
         L.sisph_persistent_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+        L.sisph_set_kernel_timing.restype = C.c_int32
+        L.sisph_set_kernel_timing.argtypes = [C.c_void_p, C.c_int32]
+        L.sisph_kernel_timing.restype = C.c_int32
+        L.sisph_kernel_timing.argtypes = [C.c_void_p, _DP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.sisph_persistent_fallbacks.restype = C.c_int32
         L.sisph_persistent_fallbacks.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.sisph_batch_set_graphs.restype = C.c_int32
@@ -332,6 +336,18 @@ class Context:
         _check(lib().sisph_sweep_counters(self.h, C.byref(ms), C.byref(n), C.byref(e), int(reset)), self.h)
         return dict(sweep_ms=ms.value, launches=n.value, effective=e.value)
 
+    def set_kernel_timing(self, on: bool = True):
+        """Bracket every sweep launch with its own HIP events (wall pass
+        left out)."""
+        _check(lib().sisph_set_kernel_timing(self.h, int(bool(on))), self.h)
+
+    def kernel_timing(self):
+        """Sweep-kernel time (ms), timed launches and persistent ones among
+        them, since the last sweep_counters reset."""
+        ms, n, p = C.c_double(), C.c_int64(), C.c_int64()
+        _check(lib().sisph_kernel_timing(self.h, C.byref(ms), C.byref(n), C.byref(p)), self.h)
+        return dict(ms=ms.value, launches=n.value, persistent=p.value)
+
     def debug_barrier_spins(self, spins: int):
         """Test hook: polls before a persistent-solve wait gives up."""
         _check(lib().sisph_debug_barrier_spins(self.h, int(spins)), self.h)
@@ -345,7 +361,8 @@ class Context:
 
     def persistent_fallbacks(self):
         """Solves meant for one persistent launch that ran per-launch sweeps
-        instead: cooperative launch refused, or a grid barrier timed out."""
+        instead (cooperative launch refused, or a grid barrier timed out),
+        since the last sweep_counters reset."""
         r, t = C.c_int64(), C.c_int64()
         _check(lib().sisph_persistent_fallbacks(self.h, C.byref(r), C.byref(t)), self.h)
         return dict(refused=r.value, timed_out=t.value)

@@ -16,34 +16,50 @@ def test_bench_line_fields():
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    cmd = [sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--steps", "3", "--warmup", "2",
-           "--no-batch-compare", "--no-serving", "--no-solver-compare", "--cpu-budget", "0.1"]
+    cmd = [sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--steps", "2", "--warmup", "1",
+           "--secondary-steps", "3", "--no-batch-compare", "--no-serving", "--no-solver-compare",
+           "--cpu-budget", "0.1"]
     print("running", " ".join(cmd[1:]), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True, timeout=240)
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=400)
     print(r.stderr[-3000:], flush=True)
     assert r.returncode == 0, r.stderr[-3000:]
     lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
     assert len(lines) == 1, r.stdout[-2000:]
     d = json.loads(lines[0])
     for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
-              "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+              "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline", "secondary"):
         assert k in d, k
-    assert d["n_gpus"] == 1 and d["steps"] == 3 and d["warmup"] == 2
+    assert d["n_gpus"] == 1 and d["steps"] == 2 and d["warmup"] == 1
     assert d["value"] > 0 and d["ms_per_step"] > 0 and d["higher_is_better"] is True
     assert d["unit"] == "particle-iters/s" and d["data"] == "synthetic" and d["dtype"] == "f32+f64"
-    assert d["config"]["workload"] == "tg400_wendland_mixed" and d["config"]["launch"] == "eager"
+    assert d["config"]["workload"] == "db3d_dx0.01_mixed" and d["config"]["launch"] == "eager"
+    assert d["config"]["fluid_particles"] == 2000000 and d["config"]["wall_particles"] == 1343508
     rf = d["roofline"]
-    print("roofline", {k: v for k, v in rf.items() if k != "kernel"}, flush=True)
+    print("roofline", rf, flush=True)
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
     assert rf["achieved"] > 0 and abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-3
-    assert rf["sweeps"] >= rf["effective_sweeps"] > 0
-    # one launch per solve, or (the cooperative launch refused, e.g. while
-    # another process holds the device) one per sweep, with the fallback counted
-    if rf["mode"] == "persistent":
-        assert rf["launches"] == 3
+    # achieved = 420 B per fluid particle and effective sweep / sweep-kernel time
+    assert rf["algorithmic_bytes_per_particle_iter"] == 420
+    assert rf["algorithmic_bytes_per_sweep"] == 420 * 2000000
+    per_launch = rf["algorithmic_bytes_per_launch"] / (rf["avg_launch_us"] * 1e-6) / 1e9
+    assert abs(per_launch - rf["achieved"]) < 0.01 * rf["achieved"]
+    # walls: per-sweep launches, each timed on its own, the wall pass apart
+    assert rf["mode"] == "per-sweep launches" and rf["persistent_launches"] == 0
+    assert rf["launches"] == rf["per_sweep_launches"] >= rf["effective_sweeps"] > 0
+    assert rf["wall_pass"]["rows"] > 0 and rf["wall_pass"]["us_per_sweep"] > 0
+    assert rf["layout"]["bytes_per_sweep"] > 0
+    sec = d["secondary"]
+    assert sec["config"]["workload"] == "tg400_wendland_mixed"
+    sr = sec["roofline"]
+    assert sr["algorithmic_bytes_per_particle_iter"] == 128
+    assert sr["launches"] == sr["persistent_launches"] + sr["per_sweep_launches"]
+    # one persistent launch per solve unless the runtime refused one (for
+    # instance while another process holds the device), which is counted
+    if sr["per_sweep_launches"]:
+        assert sr["persistent_fallbacks"]["refused"] + sr["persistent_fallbacks"]["timed_out"] > 0
     else:
-        assert rf["launches"] == rf["sweeps"]
-        assert rf["persistent_fallbacks"]["refused"] + rf["persistent_fallbacks"]["timed_out"] > 0
+        assert sr["mode"] == "persistent" and sr["persistent_launches"] == 3
+    assert sec["solves_at_max_iter"] == 0
     cb = d["cpu_baseline"]
-    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["value"] > 0 and cb["unit"] == d["unit"]
+    assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["unit"] == d["unit"]
     assert cb["host"]["nproc"] >= 1

@@ -3,13 +3,20 @@
 * 160k-particle Taylor-Green (Wendland h = 1.3 dx, Re = 100, tol 1e-4):
   neighbour sets bit-exact at r^n and r*; one step against the oracle in
   FP64 (same sweep count, fields to 1e-5 relative L2) and in the mixed mode
-  (oracle run on the GPU's sweep count; FP32-rounding bounds).
+  (oracle run on the GPU's sweep count; FP32-rounding bounds); the whole
+  200-step run's |u|max(t) decay against the oracle's series
+  (tests/golden/tg400_decay_series.json, written from the oracle alone).
 * 2D dam break, dx = 0.005 (80,000 fluid + 7,218 wall particles), mixed.
+* 3D dam break, dx = 0.015 (597,037 fluid rows, above 2^19, 2,333 fluid
+  workgroups): one step against the live oracle, FP64 and mixed.
 * 3D dam break, dx = 0.01 (2,000,000 fluid + 1,343,508 wall particles):
   the oracle cannot step it in seconds, so sampled rows are compared one by
   one (neighbour sets bit-exact, summation density from those sets) and the
   whole step is checked for properties that hold at any size.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -156,3 +163,74 @@ def test_dam_break_3d_full_sampled():
     assert s["x"][:case.n_fluid, 2].mean() < z0
     assert s["x"][:case.n_fluid, 0].min() > -0.01 and s["x"][:case.n_fluid, 2].min() > -0.01
     ctx.close()
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "tg400_decay_series.json")
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_tg400_decay_series(precision):
+    """The 160k-particle Taylor-Green case for its 200 steps: |u|max(t) /
+    |u|max(0) within 1e-4 of the FP64 oracle's series at every step (FP64:
+    the same sweep counts and 1e-9), and no solve at the iteration limit."""
+    sisph = _gpu()
+    gold = json.load(open(GOLDEN))
+    assert gold["case"]["null_space"] == "project" and gold["case"]["steps"] == 200
+    case = _tg400(precision)
+    assert case.dt == gold["case"]["dt"]
+    u0 = float(np.linalg.norm(case.u, axis=1).max())
+    ctx = sisph.Context(case)
+    worst, iters = 0.0, []
+    for k in range(gold["case"]["steps"]):
+        st = ctx.step(1)[0]
+        iters.append(st["iters"])
+        ratio = float(np.linalg.norm(ctx.read_state()["u"], axis=1).max()) / u0
+        worst = max(worst, abs(ratio - gold["umax_ratio"][k]))
+    ctx.close()
+    say(f"  tg400 {precision}: worst |u|max ratio difference {worst:.3e} over 200 steps; "
+        f"sweeps {sum(iters)} (oracle {sum(gold['iters'])}), max {max(iters)}")
+    assert max(iters) < case.max_iter
+    if precision == "fp64":
+        assert iters == gold["iters"]
+        assert worst < 1e-9
+    else:
+        assert worst < 1e-4
+
+
+def test_dam_break_3d_above_2p19_rows_one_step():
+    """The 3D dam break at dx = 0.015: 597,037 fluid rows, so the single-case
+    sweep tests the stop flag before its loads (from 2^19 rows) and the stop
+    reduction reads 2,333 partial sums, more than its registers hold.  One
+    step against the live oracle (OpenMP build): FP64 with the same sweep
+    count and every field to 1e-9; mixed with the oracle on the GPU's count."""
+    sisph = _gpu()
+    base = cases.dam_break_3d(dx=0.015, precision="fp64", tol=1e-3)
+    assert base.n_fluid > (1 << 19) and (base.n_fluid + 255) // 256 > 1024
+    say("3D dam break dx=0.015:", base.n_fluid, "fluid", base.n_wall, "wall")
+    ref = oracle.Sim(base, parallel=True)
+    out = ref.step(capture=True)
+    results = {}
+    for precision in ("fp64", "mixed"):
+        ctx = sisph.Context(base.replace(precision=precision))
+        g = ctx.step(1)[0]
+        s = ctx.read_state()
+        results[precision] = (g, s, ctx.field("rho"), ctx.field("rhs"))
+        ctx.close()
+    g, s, rho, rhs = results["fp64"]
+    say(f"  sweeps gpu {g['iters']} oracle {out['iters']}")
+    assert g["iters"] == out["iters"]
+    nf = base.n_fluid
+    for name, a, b in (("rho", rho, out["rho"]), ("rhs", rhs, out["rhs"]), ("p", s["p"], ref.p),
+                       ("u", s["u"], ref.u), ("displacement", s["x"][:nf] - base.x[:nf], ref.x[:nf] - base.x[:nf])):
+        e = rel(a, b)
+        say(f"  fp64 {name:12s} {e:.3e}")
+        assert e < 1e-9, name
+    g, s, rho, rhs = results["mixed"]
+    if g["iters"] != out["iters"]:
+        ref = oracle.Sim(base, parallel=True, forced_iters=g["iters"])
+        out = ref.step(capture=True)
+    errs = dict(rho=rel(rho, out["rho"]), p=rel(s["p"][:nf], ref.p[:nf]), u=rel(s["u"], ref.u),
+                displacement=rel(s["x"][:nf] - base.x[:nf], ref.x[:nf] - base.x[:nf]))
+    for k, e in errs.items():
+        say(f"  mixed {k:12s} {e:.3e} ({g['iters']} sweeps)")
+    assert errs["rho"] < 7e-7 and errs["p"] < 6e-5 and errs["u"] < 6e-5 and errs["displacement"] < 6e-5

@@ -52,8 +52,20 @@ def _run(sisph, case, persistent, steps):
     st = ctx.step(steps)
     s = ctx.read_state()
     c = ctx.sweep_counters()
+    c.update(ctx.persistent_info(), **ctx.persistent_fallbacks())
     ctx.close()
     return s, st, c
+
+
+def _require_persistent(c, steps):
+    """The comparison means something only if the persistent path ran: every
+    solve was one persistent launch, or the test is skipped naming the
+    refusals (the runtime refuses cooperative launches while another process
+    holds the device)."""
+    if c["solves"] != steps:
+        if c["refused"] or c["timed_out"]:
+            pytest.skip(f"persistent launch refused {c['refused']}x / timed out {c['timed_out']}x")
+        raise AssertionError(f"only {c['solves']} of {steps} solves were persistent")
 
 
 @pytest.mark.parametrize("name", list(_cases().keys()))
@@ -62,7 +74,9 @@ def test_persistent_equals_per_launch(name):
     case = _cases()[name]
     say("case", name, case.n_fluid, case.precision)
     a, sa, ca = _run(sisph, case, True, 4)
+    _require_persistent(ca, 4)
     b, sb, cb = _run(sisph, case, False, 4)
+    assert cb["solves"] == 0
     ia, ib = [x["iters"] for x in sa], [x["iters"] for x in sb]
     say("  iters", ia, "counters persistent", ca, "per-launch", cb)
     assert ia == ib
@@ -79,6 +93,7 @@ def test_persistent_wide_indices():
     sisph = _gpu()
     case = cases.long_strip()
     a, ia, ca = _run(sisph, case, True, 2)
+    _require_persistent(ca, 2)
     b, ib, cb = _run(sisph, case, False, 2)
     say("  strip iters", ia, ib, ca, cb)
     assert ia == ib
