@@ -170,6 +170,29 @@ int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, size_t ws_b
                      const double *x, const double *u, const double *p, const double *m,
                      const double *wall_u, void *hip_stream, sisph_ctx **out);
 
+/* For callers that cannot allocate (code running under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): sisph_create with
+ * the workspace taken from a library-owned device array of
+ * SISPH_STATIC_WORKSPACE_BYTES per device (a static device variable, held
+ * by every device the library runs on until the process ends) instead of
+ * the caller's, on the current device.  It calls no hipMalloc, hipHostMalloc,
+ * hipFree or hipEventCreate and allocates no host memory: the context and
+ * its control-block mirror live in a static slot per device, and the
+ * context has no timing events (its timings read zero; sisph_set_graphs,
+ * sisph_set_kernel_timing and sisph_autotune refuse it with
+ * SISPH_E_STATE).  Arguments as for sisph_create; hip_stream must belong
+ * to the current device.  Errors: SISPH_E_NOMEM if the case needs more than
+ * SISPH_STATIC_WORKSPACE_BYTES (sisph_workspace_bytes), SISPH_E_STATE while
+ * a context created here on the same device is alive (one per device;
+ * sisph_destroy releases it), SISPH_E_INVAL for a bad descriptor;
+ * sisph_last_error(NULL) gives the message.  Every call on a device reuses
+ * the same array, which keeps the previous case's contents; create sets up
+ * every value a step reads.  Work of two threads on one device's static
+ * context is not synchronised: such calls race. */
+#define SISPH_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int32_t sisph_create_static(const sisph_case_desc *desc, const double *x, const double *u, const double *p,
+                            const double *m, const double *wall_u, void *hip_stream, sisph_ctx **out);
+
 int32_t sisph_bin(sisph_ctx *ctx);
 int32_t sisph_predict(sisph_ctx *ctx);
 int32_t sisph_ppe_solve(sisph_ctx *ctx, sisph_ppe_stats *out /* nullable */);

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -49,13 +51,16 @@ struct sisph_ctx {
     std::vector<hipEvent_t> kev;
     double kt_ms = 0.0;
     int64_t kt_launches = 0, kt_persistent = 0;
+    bool is_static = false;                                    // lives in a device's static slot
     hipStream_t cap_stream = nullptr;                          // capture only
     hipGraphExec_t g_pre = nullptr, g_post = nullptr;          // fixed step segments
     std::string err;
 };
 
 static thread_local std::string g_create_err;
-
+// sisph_create_static's last refusal (written without allocating)
+static thread_local char g_static_err[256];
+static thread_local bool g_static_err_set = false;
 
 #define HIPCHK(ctx, expr)                                                               \
     do {                                                                                \
@@ -66,7 +71,8 @@ static thread_local std::string g_create_err;
         }                                                                               \
     } while (0)
 
-// Event helpers that accept a missing event (recording skipped, time zero).
+// A context created in the static workspace has no events (creating them
+// is an allocation): recording is skipped and its timings read zero.
 static hipError_t ev_record(hipEvent_t e, hipStream_t s) { return e ? hipEventRecord(e, s) : hipSuccess; }
 static hipError_t ev_elapsed(float *ms, hipEvent_t a, hipEvent_t b) {
     if (!a || !b) {
@@ -519,6 +525,7 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
                                 void *hip_stream, sisph_ctx **out) {
     if (!out) return SISPH_E_INVAL;
     *out = nullptr;
+    g_static_err_set = false;
     size_t need = 0;
     const char *why = nullptr;
     int32_t st = check_create(desc, x, u, p, m, &need, &why);
@@ -574,6 +581,92 @@ extern "C" int32_t sisph_create(const sisph_case_desc *desc, void *d_workspace, 
     if ((st = init_state(ctx, desc, x, u, p, m, wall_u)) != SISPH_OK) return bail(st);
     *out = ctx;
     return SISPH_OK;
+}
+
+// ----------------------------------------------- the static workspace
+// For callers that cannot allocate: one workspace per device in a
+// file-scope device array.  In host code `scratch` names a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, once per
+// device with that device current, and only that address is used.  Each
+// device also has one static host slot (the context and its control-block
+// mirror in pageable memory), so a context created here allocates nothing:
+// no device or pinned memory, no events (its timings read zero), no host
+// heap.  A device holds one such context at a time.
+static __device__ __align__(256) unsigned char scratch[SISPH_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+struct StaticSlot {
+    void *ptr = nullptr;              // device address of scratch on this device
+    std::atomic<int> in_use{0};
+    sisph_ctx ctx;
+    Control ctl;                      // host mirror of the control block
+    StaticSlot() { ctx.err.reserve(512); }   // messages are written without allocating
+};
+StaticSlot g_static[kMaxDevices];
+std::mutex g_static_mu;               // guards the one-time address lookups
+
+int32_t static_refuse(int32_t code, const char *msg) {
+    std::snprintf(g_static_err, sizeof g_static_err, "%s", msg);
+    g_static_err_set = true;
+    return code;
+}
+}  // namespace
+
+extern "C" int32_t sisph_create_static(const sisph_case_desc *desc, const double *x, const double *u,
+                                       const double *p, const double *m, const double *wall_u, void *hip_stream,
+                                       sisph_ctx **out) {
+    if (!out) return SISPH_E_INVAL;
+    *out = nullptr;
+    size_t need = 0;
+    const char *why = nullptr;
+    int32_t st = check_create(desc, x, u, p, m, &need, &why);
+    if (st != SISPH_OK) return static_refuse(st, why);
+    if (need > (size_t)SISPH_STATIC_WORKSPACE_BYTES) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "case needs %zu workspace bytes, above the static workspace's %zu", need,
+                      (size_t)SISPH_STATIC_WORKSPACE_BYTES);
+        return static_refuse(SISPH_E_NOMEM, msg);
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return static_refuse(SISPH_E_DEVICE, "no current device");
+    StaticSlot &slot = g_static[dev];
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (!slot.ptr) {
+            void *ptr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr) return static_refuse(SISPH_E_DEVICE, "hipGetSymbolAddress(scratch) failed");
+            slot.ptr = ptr;
+        }
+    }
+    int expect = 0;
+    if (!slot.in_use.compare_exchange_strong(expect, 1))
+        return static_refuse(SISPH_E_STATE, "the static workspace of this device holds a live context");
+    sisph_ctx *ctx = &slot.ctx;
+    reset_ctx(ctx, desc, hip_stream);
+    ctx->is_static = true;
+    ctx->h_ctl = &slot.ctl;
+    for (auto &e : ctx->ev) e = nullptr;
+    for (auto &e : ctx->evc) e = nullptr;
+    Carver c{(char *)slot.ptr};
+    carve(ctx->P, c, ctx->S);
+    ctx->T = single_target(ctx);
+    if ((st = init_state(ctx, desc, x, u, p, m, wall_u)) != SISPH_OK) {
+        static_refuse(st, ctx->err.c_str());
+        slot.in_use.store(0);
+        return st;
+    }
+    g_static_err_set = false;
+    *out = ctx;
+    return SISPH_OK;
+}
+
+// Releases a context of the static workspace (called by sisph_destroy).
+static void release_static(sisph_ctx *ctx) {
+    for (auto &slot : g_static)
+        if (&slot.ctx == ctx) slot.in_use.store(0);
 }
 
 // ------------------------------------------------------- step sequences
@@ -1215,6 +1308,7 @@ extern "C" int32_t sisph_set_kernel_timing(sisph_ctx *ctx, int32_t on) {
         ctx->kev.clear();
         return SISPH_OK;
     }
+    if (ctx->is_static) return fail(ctx, SISPH_E_STATE, "a context in the static workspace creates no events");
     if (!ctx->kev.empty()) return SISPH_OK;
     // one pair per launch a chunk can hold: max_iter + 1 (or forced_iters + 1)
     const int64_t n = 2 * ((int64_t)(ctx->P.forced_iters > 0 ? ctx->P.forced_iters : ctx->P.max_iter) + 1);
@@ -1562,6 +1656,7 @@ extern "C" int32_t sisph_autotune(sisph_ctx *ctx, int32_t reps, int32_t *best, d
     if (attached(ctx)) return fail(ctx, SISPH_E_STATE, "context is attached to a batch");
     if (ctx->state != ST_READY || ctx->nbr_stage != 1)
         return fail(ctx, SISPH_E_STATE, "sisph_autotune needs one completed step");
+    if (ctx->is_static) return fail(ctx, SISPH_E_STATE, "a context in the static workspace has no timing events");
     // launch 0 of a sweep reads the current pressure (iterate 0) and writes
     // only iterate 1, the FP32 copy and the partial sums: scratch between steps
     Target T = ctx->T;
@@ -1598,6 +1693,7 @@ extern "C" int32_t sisph_get_variant(sisph_ctx *ctx) { return ctx ? ctx->variant
 
 extern "C" int32_t sisph_set_graphs(sisph_ctx *ctx, int32_t on) {
     if (!ctx) return SISPH_E_INVAL;
+    if (on && ctx->is_static) return fail(ctx, SISPH_E_STATE, "a context in the static workspace captures no graphs");
     ctx->use_graphs = on != 0;
     return SISPH_OK;
 }
@@ -1612,7 +1708,11 @@ extern "C" int32_t sisph_destroy(sisph_ctx *ctx) {
     if (!ctx) return SISPH_E_INVAL;
     if (ctx->batch) (void)sisph_batch_detach(ctx->batch, ctx);
     (void)hipStreamSynchronize(ctx->stream);
-
+    if (ctx->is_static) {   // nothing of its own to free
+        ctx->is_static = false;
+        release_static(ctx);
+        return SISPH_OK;
+    }
     drop_graphs(ctx->g_pre, ctx->g_post);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
@@ -1640,5 +1740,6 @@ extern "C" const char *sisph_status_string(int32_t status) {
 }
 
 extern "C" const char *sisph_last_error(sisph_ctx *ctx) {
-    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+    if (ctx) return ctx->err.c_str();
+    return g_static_err_set ? g_static_err : g_create_err.c_str();
 }

@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsisph.so")
 
 SWEEP_VARIANTS = 6
+STATIC_WORKSPACE_BYTES = 64 << 20
 OK, WARN_MAXITER = 0, 1
 E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_NONFINITE = -1, -2, -3, -4, -5
 
@@ -77,6 +78,9 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.sisph_workspace_bytes.restype = C.c_size_t
         L.sisph_workspace_bytes.argtypes = [C.POINTER(CaseDesc)]
+        L.sisph_create_static.restype = C.c_int32
+        L.sisph_create_static.argtypes = [C.POINTER(CaseDesc), _DP, _DP, _DP, _DP, _DP, C.c_void_p,
+                                          C.POINTER(C.c_void_p)]
         L.sisph_create.restype = C.c_int32
         L.sisph_create.argtypes = [C.POINTER(CaseDesc), C.c_void_p, C.c_size_t, _DP, _DP, _DP, _DP, _DP,
                                    C.c_void_p, C.POINTER(C.c_void_p)]
@@ -202,7 +206,10 @@ def _check(code: int, ctx=None, allow_warn: bool = True) -> int:
 class Context:
     """One SISPH case resident on the GPU."""
 
-    def __init__(self, case, device: str = "cuda", stream=None):
+    def __init__(self, case, device: str = "cuda", stream=None, static: bool = False):
+        """static=True: the case lives in the library's static device
+        workspace (sisph_create_static, one context per device, nothing
+        allocated); otherwise in a torch uint8 tensor this object owns."""
         import torch
         self.case = case
         self.desc = describe(case)
@@ -210,18 +217,27 @@ class Context:
         nbytes = int(L.sisph_workspace_bytes(C.byref(self.desc)))
         if nbytes == 0:
             raise SisphError(E_INVAL, "invalid case descriptor")
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-        base = self.workspace.data_ptr()
-        aligned = (base + 255) & ~255
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        dev = torch.device(device)
         h = C.c_void_p()
         x = np.ascontiguousarray(case.x, dtype=np.float64)
         u = np.ascontiguousarray(case.u, dtype=np.float64)
         p = np.ascontiguousarray(case.p, dtype=np.float64)
         m = np.ascontiguousarray(case.m, dtype=np.float64)
         wu = None if case.wall_u is None or case.n_wall == 0 else np.ascontiguousarray(case.wall_u, dtype=np.float64)
-        code = L.sisph_create(C.byref(self.desc), C.c_void_p(aligned), C.c_size_t(nbytes), _p(x), _p(u), _p(p),
-                              _p(m), _p(wu), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if static:
+            if dev.index is not None:   # the static workspace is the current device's
+                torch.cuda.set_device(dev)
+            self.workspace = None
+            self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+            code = L.sisph_create_static(C.byref(self.desc), _p(x), _p(u), _p(p), _p(m), _p(wu),
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        else:
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) & ~255
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+            code = L.sisph_create(C.byref(self.desc), C.c_void_p(aligned), C.c_size_t(nbytes), _p(x), _p(u),
+                                  _p(p), _p(m), _p(wu), C.c_void_p(self.stream.cuda_stream), C.byref(h))
         _check(code, None)
         self.h = h
         self.nbytes = nbytes
