@@ -62,7 +62,7 @@ enum {
 
 /* ----------------------------------------------------------- enumerations */
 enum { SISPH_QUINTIC = 0, SISPH_WENDLAND_C2 = 1 };      /* support 3h / 2h  */
-enum { SISPH_FP64 = 0, SISPH_MIXED = 1 };                /* see precision    */
+enum { SISPH_FP64 = 0, SISPH_MIXED = 1, SISPH_FP32 = 2 }; /* see precision   */
 enum { SISPH_ASYMM = 0, SISPH_SYMM = 1 };                /* pressure gradient */
 enum { SISPH_GTVF_OFF = 0, SISPH_GTVF_INTERNAL = 1, SISPH_GTVF_EXTERNAL = 2 };
 enum { SISPH_PREF_FIXED = 0, SISPH_PREF_TWICE_MAX = 1 };
@@ -77,6 +77,14 @@ enum { SISPH_NULL_NONE = 0, SISPH_NULL_PROJECT = 1 };
  *              kernel values and the cached PPE coefficients in FP32 (pair
  *              differences formed in FP64 first); PPE residual, convergence
  *              test, per-particle results and positions in FP64.
+ *              SISPH_FP32: plain single precision, the form the paper's own
+ *              GPU runs use: as MIXED for the neighbour sums, and every
+ *              per-particle result (density, accelerations, u*, r*, RHS,
+ *              D_ii, the Jacobi update, the wall pressure, u^{n+1}, the GTVF
+ *              sub-steps, the transport velocity, the positions) rounded to
+ *              FP32 as it is formed, the PPE residual sums and the stopping
+ *              test in FP32 too (arrays keep their FP64 storage, holding
+ *              FP32 values).  Jacobi only.
  *  pgrad       "asymm" (eq. mom:sph:press:pij) or "symm" (eq. ...:symm).
  *  gtvf        OFF; INTERNAL: h~ = h, p0 = p_ref; EXTERNAL: h~ = h/2,
  *              p0 = min(10 |p_i|, p_ref) (section 2.1).
@@ -352,6 +360,16 @@ int32_t sisph_batch_step(sisph_batch *b, sisph_step_stats *per_case);
 /* As sisph_set_graphs, per (dimension, kernel, precision) group of the batch;
  * graphs are captured again after the group's membership changes. */
 int32_t sisph_batch_set_graphs(sisph_batch *b, int32_t on);
+/* Jacobi solves of the wall-less cases of a (dimension, kernel, precision)
+ * group in one cooperative launch (on by default) when all their fluid
+ * workgroups fit on the device at once: each case keeps its own stopping
+ * decision and results bitwise those of per-launch sweeps; the group's
+ * cases with walls then take per-launch sweeps.  A refused launch or a grid
+ * barrier that does not fill in time falls back to per-launch sweeps for
+ * that step.  sisph_batch_persistent_info counts, since the batch's
+ * creation, such launches and the fallbacks. */
+int32_t sisph_batch_set_persistent(sisph_batch *b, int32_t on);
+int32_t sisph_batch_persistent_info(sisph_batch *b, int64_t *launches, int64_t *fallbacks);
 int32_t sisph_batch_destroy(sisph_batch *b);
 
 const char *sisph_status_string(int32_t status);

@@ -32,7 +32,7 @@ KERNELS = {"quintic": 0, "wendland": 1}
 PGRAD = {"asymm": 0, "symm": 1}
 GTVF = {"off": 0, "internal": 1, "external": 2}
 PREF = {"fixed": 0, "twice_max": 1}
-PRECISION = {"fp64": 0, "mixed": 1}
+PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2}
 CONV = {"sum": 0, "mean": 1}
 USTAR = {"slip": 0, "noslip": 1}
 DT_MODE = {"fixed": 0, "adaptive": 1}

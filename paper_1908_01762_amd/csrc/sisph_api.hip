@@ -91,7 +91,9 @@ static const char *check_desc(const sisph_case_desc *d) {
     if (!d) return "null descriptor";
     if (d->dim != 2 && d->dim != 3) return "dim must be 2 or 3";
     if (d->kernel != SISPH_QUINTIC && d->kernel != SISPH_WENDLAND_C2) return "unknown kernel";
-    if (d->precision != SISPH_FP64 && d->precision != SISPH_MIXED) return "unknown precision";
+    if (d->precision != SISPH_FP64 && d->precision != SISPH_MIXED && d->precision != SISPH_FP32)
+        return "unknown precision";
+    if (d->precision == SISPH_FP32 && d->solver != SISPH_JACOBI) return "the FP32 mode solves by Jacobi sweeps only";
     if (d->pgrad != SISPH_ASYMM && d->pgrad != SISPH_SYMM) return "unknown pressure-gradient form";
     if (d->gtvf < SISPH_GTVF_OFF || d->gtvf > SISPH_GTVF_EXTERNAL) return "unknown gtvf mode";
     if (d->p_ref_mode != SISPH_PREF_FIXED && d->p_ref_mode != SISPH_PREF_TWICE_MAX) return "unknown p_ref mode";
@@ -180,7 +182,8 @@ static Params make_params(const sisph_case_desc *d) {
     P.adaptive_dt = d->dt_mode == SISPH_DT_ADAPTIVE ? 1 : 0;
     P.solver = d->solver;
     P.null_space = d->null_space;
-    P.compact = d->precision == SISPH_MIXED && d->n_wall == 0 ? 1 : 0;
+    P.compact = f32_sums(d->precision) && d->n_wall == 0 ? 1 : 0;
+    P.packed = d->n_wall > 0 && !d->periodic[0] && d->solver == SISPH_JACOBI ? 1 : 0;
     P.cap = neighbour_cap(d);
     P.nf = d->n_fluid;
     P.nw = d->n_wall;
@@ -239,7 +242,7 @@ static void carve(const Params &P, Carver &c, State &S) {
     S.rho = c.take<double>(nt);
     S.mr2 = c.take<double>(nt);
     S.m32 = S.rho32 = nullptr;
-    if (P.precision == SISPH_MIXED) {
+    if (f32_sums(P.precision)) {
         S.m32 = c.take<float>(nt);
         S.rho32 = c.take<float>(nt);
     }
@@ -263,6 +266,12 @@ static void carve(const Params &P, Carver &c, State &S) {
     // mixed: (index, FP32 c_ij) 8-byte words; FP64: FP64 c_ij (indices from nbr)
     S.coef = c.take<char>((int64_t)8 * P.cap * nf);
     S.cidx = c.take<int32_t>((int64_t)P.cap * nf);
+    S.pk16 = nullptr;
+    S.rcell = nullptr;
+    if (P.packed) {
+        S.pk16 = c.take<uint16_t>((int64_t)P.cap * nf);
+        S.rcell = c.take<uint32_t>(nf);
+    }
     S.wcoef = c.take<char>((int64_t)8 * P.cap * nw);
     S.wh = c.take<double>(nw);
     S.wflag = c.take<int32_t>(kind_blocks(P, K_WALL) + 1);
@@ -381,7 +390,7 @@ static void fill_stats(const Control &C, const Params &P, sisph_ppe_stats *out) 
     out->lambda = cv.d;
     out->p_ref = C.p_ref;
     out->dt = C.dt;
-    out->index_bytes = P.compact && !C.wide ? 2 : 4;
+    out->index_bytes = (P.compact && !C.wide) || (P.packed && !C.pk_overflow) ? 2 : 4;
     out->reserved = 0;
     out->beta = P.null_space == SISPH_NULL_PROJECT ? C.beta : 0.0;
 }
@@ -428,6 +437,7 @@ static int32_t init_state(sisph_ctx *ctx, const sisph_case_desc *desc, const dou
     }
     iota_i32(S.id, nf, s);
     iota_i32(S.wid, nw, s);
+    round_state(ctx->T);
     reset_control(ctx->T, RESET_PPE | RESET_NEIGHBOURS | RESET_PREF | RESET_DT);
     if (desc->p_ref_mode == SISPH_PREF_FIXED) {
         Control c0{};
@@ -694,7 +704,7 @@ static void seq_ppe_begin(const Target &T) {
     if (T.null_space) project_rhs(T);
     wall_coef(T);
     if (T.solver == SISPH_BICGSTAB) bicg_begin(T);
-    else if (T.precision == SISPH_MIXED) copy_p32(T);
+    else if (f32_sums(T.precision)) copy_p32(T);
 }
 
 static void seq_ppe_end(const Target &T) {
@@ -1370,6 +1380,16 @@ struct Group {
     Target T{};
     hipGraphExec_t g_pre = nullptr, g_post = nullptr;   // fixed step segments (graph mode)
     int g_maxK = -1;
+    // persistent batched solve of the wall-less Jacobi members: workgroup ->
+    // case and the case's first workgroup over those members only, and the
+    // launch's synchronisation words
+    int32_t *d_powner = nullptr;
+    int64_t *d_pfirst = nullptr;
+    uint32_t *d_bsync = nullptr;
+    size_t powner_cap = 0, bsync_cap = 0, case_cap_p = 0;
+    int64_t ptotal = 0;               // workgroups of those members
+    int32_t pcases = 0;               // how many members
+    std::vector<int> pmembers;        // their indices in members
 };
 
 struct sisph_batch {
@@ -1380,6 +1400,8 @@ struct sisph_batch {
     std::vector<sisph_ctx *> cases;   // attach order
     std::vector<Group> groups;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool use_persistent = true;       // batched persistent solves where they apply
+    int64_t persist_launches = 0, persist_fallbacks = 0;
     std::string err;
 };
 
@@ -1396,9 +1418,17 @@ static void free_group(Group &g) {
     }
     if (g.d_ctl) (void)hipFree(g.d_ctl);
     if (g.h_ctl) (void)hipHostFree(g.h_ctl);
+    if (g.d_powner) (void)hipFree(g.d_powner);
+    if (g.d_pfirst) (void)hipFree(g.d_pfirst);
+    if (g.d_bsync) (void)hipFree(g.d_bsync);
+    g.case_cap_p = 0;
     g.d_tab = nullptr;
     g.d_ctl = nullptr;
     g.h_ctl = nullptr;
+    g.d_powner = nullptr;
+    g.d_pfirst = nullptr;
+    g.d_bsync = nullptr;
+    g.powner_cap = g.bsync_cap = 0;
     g.case_cap = 0;
 }
 
@@ -1479,6 +1509,48 @@ static int32_t rebuild_group(sisph_batch *b, Group &g) {
     for (size_t c = 0; c < n; ++c) {
         tab[c].P = g.members[c]->P;
         tab[c].S = g.members[c]->S;
+    }
+    // the wall-less Jacobi members, for the persistent batched solve
+    {
+        std::vector<int32_t> powner;
+        std::vector<int64_t> pfirst(n, -1);
+        g.pmembers.clear();
+        for (size_t c = 0; c < n; ++c) {
+            const Params &P = g.members[c]->P;
+            if (P.nw > 0 || P.solver != SISPH_JACOBI) continue;
+            const int64_t nb = kind_blocks(P, K_FLUID);
+            pfirst[c] = (int64_t)powner.size();
+            powner.insert(powner.end(), (size_t)nb, (int32_t)c);
+            g.pmembers.push_back((int)c);
+        }
+        g.ptotal = (int64_t)powner.size();
+        g.pcases = (int32_t)g.pmembers.size();
+        if (g.ptotal > 0) {
+            if ((size_t)g.ptotal > g.powner_cap || !g.d_powner) {
+                if (g.d_powner) (void)hipFree(g.d_powner);
+                g.d_powner = nullptr;
+                g.powner_cap = 0;
+                BCHK(b, hipMalloc((void **)&g.d_powner, sizeof(int32_t) * (size_t)g.ptotal));
+                g.powner_cap = (size_t)g.ptotal;
+            }
+            if (!g.d_pfirst || n > g.case_cap_p) {
+                if (g.d_pfirst) (void)hipFree(g.d_pfirst);
+                g.d_pfirst = nullptr;
+                BCHK(b, hipMalloc((void **)&g.d_pfirst, sizeof(int64_t) * n));
+                g.case_cap_p = n;
+            }
+            const size_t words = (size_t)batch_sync_words((int64_t)n);
+            if (words > g.bsync_cap || !g.d_bsync) {
+                if (g.d_bsync) (void)hipFree(g.d_bsync);
+                g.d_bsync = nullptr;
+                g.bsync_cap = 0;
+                BCHK(b, hipMalloc((void **)&g.d_bsync, sizeof(uint32_t) * words));
+                g.bsync_cap = words;
+            }
+            BCHK(b, hipMemcpyAsync(g.d_powner, powner.data(), sizeof(int32_t) * powner.size(), hipMemcpyHostToDevice,
+                                   b->stream));
+            BCHK(b, hipMemcpyAsync(g.d_pfirst, pfirst.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, b->stream));
+        }
     }
     BCHK(b, hipMemcpyAsync(g.d_tab, tab.data(), sizeof(CaseEntry) * n, hipMemcpyHostToDevice, b->stream));
     BCHK(b, hipStreamSynchronize(b->stream));
@@ -1589,10 +1661,55 @@ static int32_t group_step(sisph_batch *b, Group &g) {
         for (size_t c = 0; c < n; ++c) done = done && g.h_ctl[c].done;
         return SISPH_OK;
     };
+    // The wall-less Jacobi members first, in one persistent launch when
+    // their workgroups can all be resident; the others (walls, BiCGStab)
+    // then take per-launch sweeps, in which the finished cases return at once
+    bool persistent_done = false;
+    if (b->use_persistent && g.pcases > 0 && g.ptotal <= ppe_persistent_batch_capacity(T)) {
+        // the starting iterates, kept in each case's binning scratch in case
+        // the launch has to be redone with per-launch sweeps
+        for (int c : g.pmembers) {
+            const sisph_ctx *ctx = g.members[(size_t)c];
+            BCHK(b, hipMemcpyAsync(ctx->S.tmp, ctx->S.p[0], sizeof(double) * (size_t)ctx->P.ntot,
+                                   hipMemcpyDeviceToDevice, b->stream));
+        }
+        const int64_t words = batch_sync_words((int64_t)n);
+        fill_u32(g.d_bsync, 0u, kBatchSyncStop, b->stream);
+        fill_u32(g.d_bsync + kBatchSyncStop, 0xffffffffu, words - kBatchSyncStop, b->stream);
+        uint32_t spins = kBarrierSpins;
+        for (int c : g.pmembers) spins = std::min(spins, g.members[(size_t)c]->P.barrier_spins);
+        const hipError_t e = ppe_persistent_batch(T, g.d_powner, g.d_pfirst, g.ptotal, g.d_bsync, g.pcases,
+                                                  (int)limit, spins);
+        if (e == hipSuccess) {
+            uint32_t late = 0;
+            BCHK(b, hipMemcpyAsync(&late, g.d_bsync, sizeof(uint32_t), hipMemcpyDeviceToHost, b->stream));
+            BCHK(b, hipStreamSynchronize(b->stream));
+            if (late) {
+                // a workgroup never reached a barrier: the starting iterates
+                // back, the solves set up again, per-launch sweeps for all
+                b->persist_fallbacks += 1;
+                for (int c : g.pmembers) {
+                    const sisph_ctx *ctx = g.members[(size_t)c];
+                    BCHK(b, hipMemcpyAsync(ctx->S.p[0], ctx->S.tmp, sizeof(double) * (size_t)ctx->P.ntot,
+                                           hipMemcpyDeviceToDevice, b->stream));
+                }
+                seq_ppe_begin(T);
+                BCHK(b, hipGetLastError());
+            } else {
+                b->persist_launches += 1;
+                persistent_done = true;
+            }
+        } else {
+            (void)hipGetLastError();   // refused: per-launch sweeps this step
+            b->persist_fallbacks += 1;
+        }
+    }
     double sweep_ms = 0.0;
     int64_t launches = 0;
-    int32_t st = ppe_loop(T, predicted, limit, b->e0, b->e1, sweep_ms, launches, poll, b->err);
-    if (st != SISPH_OK) return st;
+    if (!persistent_done || g.pcases < (int32_t)n) {
+        int32_t st = ppe_loop(T, predicted, limit, b->e0, b->e1, sweep_ms, launches, poll, b->err);
+        if (st != SISPH_OK) return st;
+    }
     if (b->use_graphs) BCHK(b, hipGraphLaunch(g.g_post, b->stream));
     else seq_post(T, maxK);
     gather_control(T, g.d_ctl);
@@ -1635,6 +1752,19 @@ extern "C" int32_t sisph_batch_step(sisph_batch *b, sisph_step_stats *per_case) 
 extern "C" int32_t sisph_batch_set_graphs(sisph_batch *b, int32_t on) {
     if (!b) return SISPH_E_INVAL;
     b->use_graphs = on != 0;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_batch_set_persistent(sisph_batch *b, int32_t on) {
+    if (!b) return SISPH_E_INVAL;
+    b->use_persistent = on != 0;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_batch_persistent_info(sisph_batch *b, int64_t *launches, int64_t *fallbacks) {
+    if (!b) return SISPH_E_INVAL;
+    if (launches) *launches = b->persist_launches;
+    if (fallbacks) *fallbacks = b->persist_fallbacks;
     return SISPH_OK;
 }
 

@@ -11,6 +11,10 @@
 namespace sisph {
 
 constexpr int kBlock = 256;   // threads per workgroup for particle kernels
+
+// FP32 neighbour sums and FP32 copies of gathered fields: the mixed mode and
+// the plain FP32 mode.
+__host__ __device__ inline bool f32_sums(int precision) { return precision != SISPH_FP64; }
 constexpr int kXcd = 8;       // MI355X: 8 XCDs, workgroups dealt round-robin
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kBlock * kScanItems;
@@ -33,6 +37,8 @@ struct Params {
     int32_t adaptive_dt;    // next dt from this step's maxima
     int32_t solver;         // SISPH_JACOBI or SISPH_BICGSTAB
     int32_t compact;        // mixed mode without walls: 16-bit neighbour offsets
+    int32_t packed;         // walled Jacobi cases not periodic in x: 16-bit neighbour codes
+                            // (stencil-row range id << 11 | offset in that range)
     uint32_t barrier_spins; // polls before a wait of the persistent solve gives up
     int32_t null_space;     // SISPH_NULL_PROJECT: RHS made compatible before the sweeps
     int64_t nf, nw, ntot;
@@ -67,7 +73,7 @@ struct Control {
     double bicg_rho[2], bicg_alpha[2], bicg_omega[2];
     int32_t bicg_brk;
     int32_t wide;                     // a neighbour offset of this step did not fit 16 bits
-    int32_t pad1;
+    int32_t pk_overflow;              // a 16-bit neighbour code of this step did not fit
     double beta;                      // SISPH_NULL_PROJECT: (y . RHS) / (y . D), y = m rho
 };
 
@@ -103,7 +109,12 @@ struct State {
     int32_t *nbr, *cnt;     // fluid rows: fluid + wall sources
     int32_t *wnbr, *wcnt;   // wall rows: fluid sources
     void *coef;             // cached PPE c_ij, working precision, group-major [cap/4][nf][4]
-    void *cidx;             // their indices (int32) or 16-bit offsets (compact), same layout
+    void *cidx;             // their indices (int32) or 16-bit offsets (compact) or codes (packed), same layout
+    // packed mode: per list slot its 16-bit code, slot-major [cap][nf] like
+    // the lists, and per fluid row its r* cell id (bit 31: the row has wall
+    // neighbours)
+    uint16_t *pk16;
+    uint32_t *rcell;
     void *wcoef;            // cached wall weights W_wf / sum W: (f, FP32) words or FP64 [cap][nw]
     double *wh;             // wall hydrostatic term                 [nw]
     int32_t *wflag;         // wall workgroup has a row with fluid neighbours at r*   [nwb]
@@ -124,6 +135,14 @@ struct State {
 
 // Launch-size kinds: how many workgroups one case needs for a kernel.
 enum Kind { K_FLUID = 0, K_WALL, K_TOT, K_CELL, K_TILE, K_ONE, K_COUNT };
+
+// Packed neighbour codes: the high bits name one of the row's stencil-row
+// ranges (fluid rows 0 .. 3^(D-1)-1, then the same for walls), the low
+// kPackBits the offset of the neighbour from that range's first particle.
+constexpr int kPackBits = 11;
+constexpr uint32_t kPackMask = (1u << kPackBits) - 1u;
+constexpr uint32_t kRcellWalls = 0x80000000u;
+constexpr uint32_t kPackRanges = 18;   // 9 fluid + 9 wall stencil rows (3D)
 
 __host__ __device__ inline int64_t kind_blocks(const Params &P, int kind) {
     switch (kind) {
@@ -220,6 +239,19 @@ constexpr uint32_t kBarrierSpins = 1u << 18;   // polls before a grid barrier gi
 constexpr int kSyncCopies = 8;                 // one posted word per XCD
 constexpr int kSyncBcast = 64, kSyncArrive = 64 * (1 + kSyncCopies);
 constexpr int kSyncWords = kSyncArrive + 1024;   // at most 1024 workgroups
+// The Jacobi solves of a batch's wall-less cases in one cooperative launch:
+// ptotal workgroups, powner / pfirst mapping each to its case (index into
+// the batch table) and to the case's first workgroup; bsync holds the
+// barrier words, the cases stopped so far and per-case stop words (see
+// kBatchSyncWords), prepared by the caller.
+hipError_t ppe_persistent_batch(const Target &T, const int32_t *powner, const int64_t *pfirst, int64_t ptotal,
+                                uint32_t *bsync, int ncase, int limit, uint32_t spins);
+int64_t ppe_persistent_batch_capacity(const Target &T);
+// bsync layout: [0] late flag, [32] cases stopped, [kSyncBcast + 64 x]
+// posted words, [kSyncArrive + b] arrivals, [kSyncArrive + 1024 + c] case c's
+// stop (0xffffffff: running)
+constexpr int64_t kBatchSyncStop = kSyncArrive + 1024;
+inline int64_t batch_sync_words(int64_t ncase) { return kBatchSyncStop + ncase; }
 void wall_pressure_final(const Target &T);
 void pressure_max(const Target &T);
 void correct(const Target &T);
@@ -233,6 +265,8 @@ void gather_control(const Target &T, Control *out);
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void fill_f64(double *p, double v, int64_t n, hipStream_t s);
 void iota_i32(int32_t *p, int64_t n, hipStream_t s);
+// The plain FP32 mode's starting state rounded to FP32 (nothing otherwise).
+void round_state(const Target &T);
 // Row-major [n][dim] device array -> the SoA component arrays dst[k] + at.
 void aos_to_soa(const double *src, double *const dst[3], int64_t at, int dim, int64_t n, hipStream_t s);
 

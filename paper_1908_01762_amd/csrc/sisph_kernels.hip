@@ -264,6 +264,37 @@ __device__ __forceinline__ void block_sum2(double &a, double &b) {
     }
 }
 
+// FP32 counterparts for the plain FP32 mode.
+__device__ __forceinline__ float wave_sum_f(float v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ void block_sum2_f(float &a, float &b) {
+    __shared__ float sh[2][kBlock / 64];
+    a = wave_sum_f(a);
+    b = wave_sum_f(b);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[0][wv] = a;
+        sh[1][wv] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = 0.f;
+        b = 0.f;
+        for (int t = 0; t < kBlock / 64; ++t) {
+            a += sh[0][t];
+            b += sh[1][t];
+        }
+    }
+}
+
+// A per-particle result in the case's precision: rounded to FP32 in the
+// plain FP32 mode, kept otherwise.
+__device__ __forceinline__ bool plain32(const Params &P) { return P.precision == SISPH_FP32; }
+__device__ __forceinline__ double rp(const Params &P, double v) { return plain32(P) ? (double)(float)v : v; }
+
 __device__ __forceinline__ unsigned long long order_key(double v) {
     unsigned long long b = (unsigned long long)__double_as_longlong(v);
     return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
@@ -349,6 +380,7 @@ struct ResetControl {
         if (what & RESET_NEIGHBOURS) {
             c->overflow = 0;
             c->maxcnt = 0;
+            c->pk_overflow = 0;
         }
         if (what & RESET_PREF) {
             c->p_ref_set = 0;
@@ -519,6 +551,62 @@ struct ReorderFluid {
     }
 };
 
+// Reorder of the fluid state into the r* cell order, after the binning at
+// r*: during the second stage the neighbour candidates of one stencil row
+// (three cells along x) are then one contiguous index range.  Every fluid
+// array read later in the step moves through scratch (gathered through the
+// r* permutation, then copied back), in two batches that fit the scratch:
+// batch 0 r^n, u^n, u~^n, r*, u*; batch 1 p^n, m, rho, m / rho^2, the
+// free-surface flag, the original index, the acceleration kept for the
+// adaptive step and the FP32 copies of m and rho.
+template <int D>
+struct ReorderStage2 {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int batch,
+                                               int phase) {
+        ROW;
+        const int64_t n = P.nf;
+        if (i >= n) return;
+        const int64_t s = phase == 0 ? (int64_t)S.perm[i] : 0;
+        int nd = 0;
+        auto mvd = [&](double *col) {
+            double *t = S.tmp + (int64_t)(nd++) * n;
+            if (phase == 0) t[i] = col[s];
+            else col[i] = t[i];
+        };
+        if (batch == 0) {
+            for (int a = 0; a < D; ++a) mvd(S.x[a]);
+            for (int a = 0; a < D; ++a) mvd(S.u[a]);
+            for (int a = 0; a < D; ++a) mvd(S.ut[a]);
+            for (int a = 0; a < D; ++a) mvd(S.xs[a]);
+            for (int a = 0; a < D; ++a) mvd(S.us[a]);
+            return;
+        }
+        mvd(S.p[0]);
+        mvd(S.m);
+        mvd(S.rho);
+        if (P.adaptive_dt)
+            for (int a = 0; a < D; ++a) mvd(S.vk[a]);
+        const bool mixed = f32_sums(P.precision);
+        if (!mixed) mvd((double *)S.mr2);
+        // 4-byte columns after the 8-byte ones
+        uint32_t *wt = (uint32_t *)(S.tmp + (int64_t)nd * n);
+        int nw = 0;
+        auto mvw = [&](void *colv) {
+            uint32_t *col = (uint32_t *)colv;
+            uint32_t *t = wt + (int64_t)(nw++) * n;
+            if (phase == 0) t[i] = col[s];
+            else col[i] = t[i];
+        };
+        mvw(S.fs);
+        mvw(S.id);
+        if (mixed) {
+            mvw(S.mr2);
+            mvw(S.m32);
+            mvw(S.rho32);
+        }
+    }
+};
+
 template <int D>
 struct ReorderWalls {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int phase) {
@@ -546,8 +634,9 @@ struct ReorderWalls {
 // Fluid rows: self in slot 0, then every fluid and wall particle j != i of
 // the stencil cells with |r_ij|^2 < R^2 (exact FP64 predicate), in stencil
 // order (z, y, x) and, within a cell, fluid then walls, each in slot order.
-// At r* the fluid cell slots map to particles through perm (the data stay
-// in r^n order).
+// At r* as at r^n the fluid is in the cell order of the positions the
+// lists are built at (the state is reordered after each binning), so a
+// cell's particles are its slot range.
 //
 // The workgroup's rows (consecutive in cell order) share most stencil
 // cells, so for each stencil row (a, b) the workgroup first stages, in LDS,
@@ -559,11 +648,22 @@ struct ReorderWalls {
 // the same either way.
 constexpr int kStageCap = 1024;
 
+// Packed neighbour code of j in stencil-row range r (fluid, or r + the
+// fluid range count for walls) whose first particle is base; false if the
+// offset does not fit.
+__device__ __forceinline__ bool pack_code(uint32_t r, int64_t j, int64_t base, uint16_t &code) {
+    const int64_t off = j - base;
+    code = (uint16_t)((r << kPackBits) | ((uint32_t)off & kPackMask));
+    return off >= 0 && off <= (int64_t)kPackMask;
+}
+
 template <int D>
 __device__ __forceinline__ void test_cell_global(const Params &P, const State &S, const Pos &x,
                                                  const int32_t *items, int64_t i, const double xi[3],
-                                                 int64_t cell, int &c) {
+                                                 int64_t cell, int &c, uint32_t rr, const int64_t (&pbase)[2],
+                                                 bool &pk_bad, bool &walls) {
     const int64_t nf = P.nf;
+    constexpr uint32_t NR = D == 3 ? 9 : 3;
     for (int pass = 0; pass < 2; ++pass) {
         const uint32_t *start = pass == 0 ? S.fstart : S.wstart;
         const uint32_t t0 = start[cell], t1 = start[cell + 1];
@@ -573,7 +673,15 @@ __device__ __forceinline__ void test_cell_global(const Params &P, const State &S
             double d[3] = {0, 0, 0};
             for (int k = 0; k < D; ++k) d[k] = min_image(xi[k] - x.c[k][j], P.grid, k);
             if (exact_r2<D>(d) < P.R2) {
-                if (c < P.cap) S.nbr[(int64_t)c * nf + i] = (int32_t)j;
+                if (c < P.cap) {
+                    S.nbr[(int64_t)c * nf + i] = (int32_t)j;
+                    if (P.packed) {
+                        uint16_t code;
+                        pk_bad |= !pack_code(rr + (pass ? NR : 0u), j, pbase[pass], code);
+                        S.pk16[(int64_t)c * nf + i] = code;
+                        walls |= pass == 1;
+                    }
+                }
                 ++c;
             }
         }
@@ -593,11 +701,12 @@ struct BuildFluid {
         const Grid &g = P.grid;
         const int64_t nf = P.nf;
         const Pos x = mkpos(which == POS_XS ? S.xs : S.x);
-        const int32_t *items = which == POS_XS ? S.perm : nullptr;
+        const int32_t *items = nullptr;   // the fluid is in the cell order of these positions
         double xi[3] = {0, 0, 0};
         int ci[3] = {0, 0, 0};
         Stencil st;
         int c = 1;
+        bool pk_bad = false, has_walls = false;
         if (live) {
             for (int k = 0; k < D; ++k) {
                 xi[k] = x.c[k][i];
@@ -663,13 +772,24 @@ struct BuildFluid {
                     sj[t] = (int32_t)j;
                 }
                 __syncthreads();
+                // packed codes: this row's range of the stencil row starts at its
+                // first cell (the cells along x are consecutive: x is not periodic)
+                const uint32_t rr = D == 3 ? (uint32_t)(a * 3 + b) : (uint32_t)b;
+                int64_t pbase[2] = {0, 0};
+                if (row_ok && P.packed) {
+                    int e0 = 0;
+                    while (e0 < 2 && !pick3(st.ok[0], e0)) ++e0;
+                    const int64_t c0 = row_base + pick3(st.v[0], e0);
+                    pbase[0] = (int64_t)S.fstart[c0];
+                    pbase[1] = nf + (int64_t)S.wstart[c0];
+                }
                 if (row_ok)
 #pragma unroll
                     for (int e = 0; e < 3; ++e) {
                         if (!st.ok[0][e]) continue;
                         const int64_t cell = row_base + st.v[0][e];
                         if (cell < s_lo || cell > s_hi) {
-                            test_cell_global<D>(P, S, x, items, i, xi, cell, c);
+                            test_cell_global<D>(P, S, x, items, i, xi, cell, c, rr, pbase, pk_bad, has_walls);
                             continue;
                         }
                         // fluid then walls of this cell, from the staged copy
@@ -684,7 +804,16 @@ struct BuildFluid {
                                 double d[3] = {0, 0, 0};
                                 for (int k = 0; k < D; ++k) d[k] = min_image(xi[k] - sx[k][t], g, k);
                                 if (exact_r2<D>(d) < P.R2) {
-                                    if (c < P.cap) S.nbr[(int64_t)c * nf + i] = (int32_t)j;
+                                    if (c < P.cap) {
+                                        S.nbr[(int64_t)c * nf + i] = (int32_t)j;
+                                        if (P.packed) {
+                                            uint16_t code;
+                                            pk_bad |= !pack_code(rr + (pass ? (D == 3 ? 9u : 3u) : 0u), j,
+                                                                 pbase[pass], code);
+                                            S.pk16[(int64_t)c * nf + i] = code;
+                                            has_walls |= pass == 1;
+                                        }
+                                    }
                                     ++c;
                                 }
                             }
@@ -698,6 +827,11 @@ struct BuildFluid {
             atomicMax(&S.ctl->maxcnt, c);
         }
         S.cnt[i] = c < P.cap ? c : P.cap;
+        if (P.packed && which == POS_XS) {
+            if (pk_bad) atomicOr(&S.ctl->pk_overflow, 1);
+            const uint32_t cell = (uint32_t)(((int64_t)ci[2] * g.nc[1] + ci[1]) * g.nc[0] + ci[0]);
+            S.rcell[i] = cell | (has_walls ? kRcellWalls : 0u);
+        }
     }
 };
 
@@ -711,7 +845,7 @@ struct BuildWall {
         const Grid &g = P.grid;
         const int64_t iw = P.nf + w, nw = P.nw;
         const Pos x = mkpos(which == POS_XS ? S.xs : S.x);
-        const int32_t *items = which == POS_XS ? S.perm : nullptr;
+        const int32_t *items = nullptr;   // the fluid is in the cell order of these positions
         double xi[3] = {0, 0, 0};
         int ci[3] = {0, 0, 0};
         for (int k = 0; k < D; ++k) {
@@ -838,7 +972,8 @@ struct Density {
         }
         const double rh = (double)s;
         S.rho[i] = rh;
-        S.fs[i] = (P.free_surface && rh / P.rho0 < P.fs_ratio) ? 1 : 0;
+        const bool low = plain32(P) ? (float)rh / (float)P.rho0 < (float)P.fs_ratio : rh / P.rho0 < P.fs_ratio;
+        S.fs[i] = (P.free_surface && low) ? 1 : 0;
     }
 };
 
@@ -882,6 +1017,18 @@ struct WallVelocity {
             }
         }
         double v[3] = {0, 0, 0}, vn = 0.0;
+        if (plain32(P)) {
+            float vf[3] = {0.f, 0.f, 0.f}, vnf = 0.f;
+            for (int a = 0; a < D; ++a) {
+                const float avg = den > R(0) ? (float)num[a] / (float)den : 0.f;
+                vf[a] = slip ? avg : 2.f * (float)S.wallu[a][w] - avg;
+                vnf += vf[a] * (float)S.nrm[a][w];
+            }
+            if (vnf < 0.f)
+                for (int a = 0; a < D; ++a) vf[a] -= vnf * (float)S.nrm[a][w];
+            for (int a = 0; a < D; ++a) uf[a][iw] = vf[a];
+            return;
+        }
         for (int a = 0; a < D; ++a) {
             const double avg = den > R(0) ? (double)num[a] / (double)den : 0.0;
             v[a] = slip ? avg : 2.0 * S.wallu[a][w] - avg;
@@ -989,14 +1136,20 @@ struct Predictor {
         }
         const double dt = S.ctl->dt;
         for (int a = 0; a < D; ++a) {
-            const double f = (double)(fv[a] + fa[a] + fsr[a]) + P.g[a];
-            double xn;
-            {
+            double f, xn, usn;
+            if (plain32(P)) {
+                const float dtf = (float)dt, ff = (float)(fv[a] + fa[a] + fsr[a]) + (float)P.g[a];
+                f = ff;
+                xn = (float)xi[a] + dtf * (float)ut.c[a][i];
+                usn = (float)u.c[a][i] + dtf * ff;
+            } else {
 #pragma clang fp contract(off)
+                f = (double)(fv[a] + fa[a] + fsr[a]) + P.g[a];
                 xn = xi[a] + dt * ut.c[a][i];
+                usn = u.c[a][i] + dt * f;
             }
-            S.xs[a][i] = wrap_periodic(xn, P.grid, a);
-            S.us[a][i] = u.c[a][i] + dt * f;
+            S.xs[a][i] = rp(P, wrap_periodic(xn, P.grid, a));
+            S.us[a][i] = usn;
             if (P.adaptive_dt) S.vk[a][i] = f;   // completed by the pressure force
         }
     }
@@ -1130,6 +1283,8 @@ struct RhsCoef {
                         else if (o < -(nf / 2)) o += nf;
                         if (o >= -32767 && o <= 32767) oq = (int16_t)o;
                         else wide = true;
+                    } else if (P.packed) {
+                        oq = (int16_t)S.pk16[(int64_t)(k0 + t) * nf + i];
                     }
                     c4[t] = cij;
                     j4[t] = (int32_t)j;
@@ -1143,7 +1298,7 @@ struct RhsCoef {
                 cv.z = c4[2];
                 cv.w = c4[3];
                 ((typename Vec4<R>::T *)S.coef)[at] = cv;
-                if (P.compact) {
+                if (P.compact || P.packed) {
                     Off4 ov;
                     for (int t = 0; t < 4; ++t) ov.o[t] = o4[t];
                     ((Off4 *)S.cidx)[at] = ov;
@@ -1154,7 +1309,9 @@ struct RhsCoef {
             const double rr = (double)s, dd = (double)Dg;
             S.rhs[i] = rr;
             S.dii[i] = dd;
-            if (dd != 0.0 && !S.fs[i]) lam = (unsigned long long)__double_as_longlong(fabs(rr / dd));
+            if (dd != 0.0 && !S.fs[i])
+                lam = (unsigned long long)__double_as_longlong(plain32(P) ? (double)fabsf((float)rr / (float)dd)
+                                                                          : fabs(rr / dd));
             if (P.null_space) {
                 const double y = S.m[i] * S.rho[i];
                 ya = y * rr;
@@ -1197,7 +1354,7 @@ struct ProjectFinish {
             b += pa[nb + k];
         }
         block_sum2(a, b);
-        if (threadIdx.x == 0) S.ctl->beta = b != 0.0 ? a / b : 0.0;
+        if (threadIdx.x == 0) S.ctl->beta = rp(P, b != 0.0 ? a / b : 0.0);
     }
 };
 
@@ -1209,9 +1366,12 @@ struct ProjectRhs {
         if (i < P.nf) {
             const double dd = S.dii[i];
             if (dd != 0.0) {
-                const double rr = S.rhs[i] - S.ctl->beta * dd;
+                const double rr = plain32(P) ? (double)((float)S.rhs[i] - (float)S.ctl->beta * (float)dd)
+                                             : S.rhs[i] - S.ctl->beta * dd;
                 S.rhs[i] = rr;
-                if (!S.fs[i]) lam = (unsigned long long)__double_as_longlong(fabs(rr / dd));
+                if (!S.fs[i])
+                    lam = (unsigned long long)__double_as_longlong(plain32(P) ? (double)fabsf((float)rr / (float)dd)
+                                                                              : fabs(rr / dd));
             }
         }
         lam = wave_max_u64(lam);
@@ -1271,20 +1431,109 @@ __device__ __forceinline__ void load_groups(int64_t i, int64_t nf, int g0, int g
 
 // Offsets to indices; when an offset of the step did not fit, the indices
 // of the group's slots come from the lists instead.
+// Packed codes decode through pb, the row's column of range starts in LDS
+// (stride kBlock; range ids clamped into the table, so stale codes past the
+// row's count read a valid entry and are discarded later).
 template <int NG>
 __device__ __forceinline__ void resolve_groups(int64_t i, int64_t nf, int g0, int npos, const int32_t *nbr,
-                                               bool wide, const Off4 (&oo)[NG], int4 (&jj)[NG]) {
+                                               bool wide, const Off4 (&oo)[NG], int4 (&jj)[NG],
+                                               const int32_t *pb = nullptr, int pstride = 1) {
 #pragma unroll
     for (int t = 0; t < NG; ++t) {
         int32_t j4[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int p = (g0 + t) * 4 + q;
-            if (!wide) j4[q] = offset_index(i, oo[t].o[q], nf);
-            else j4[q] = p < npos ? nbr[(int64_t)(p + 1) * nf + i] : (int32_t)i;
+            if (wide) {
+                j4[q] = p < npos ? nbr[(int64_t)(p + 1) * nf + i] : (int32_t)i;
+            } else if (pb) {
+                const uint32_t code = (uint16_t)oo[t].o[q];
+                const uint32_t r = code >> kPackBits;
+                j4[q] = pb[(r < kPackRanges ? r : kPackRanges - 1) * pstride] + (int32_t)(code & kPackMask);
+            } else {
+                j4[q] = offset_index(i, oo[t].o[q], nf);
+            }
         }
         jj[t] = make_int4(j4[0], j4[1], j4[2], j4[3]);
     }
+}
+
+// The range starts of every cell the workgroup's rows lie in (rows are in
+// cell order, so these cells are one id range [cf, cl]), computed once per
+// workgroup, a few entries per thread, into tbl[cell - cf][range], and the
+// cells' first rows into sfs; a row then finds its cell by a binary search
+// of sfs.  Returns the number of cells, 0 (nothing written) when they are
+// more than kPackCells.  Every thread of the workgroup calls it.
+constexpr int kPackCells = 64;
+
+template <int D>
+__device__ __forceinline__ int pack_table(const Params &P, const State &S, int64_t blk, int32_t *tbl,
+                                          uint32_t *sfs) {
+    __shared__ uint32_t span[2];
+    const int64_t nf = P.nf, r0 = blk * kBlock;
+    const int64_t r1 = (r0 + kBlock < nf ? r0 + kBlock : nf) - 1;
+    if (threadIdx.x == 0) {
+        span[0] = S.rcell[r0] & ~kRcellWalls;
+        span[1] = S.rcell[r1] & ~kRcellWalls;
+    }
+    __syncthreads();
+    const uint32_t cf = span[0];
+    const int ncl = (int)(span[1] - cf) + 1;
+    if (ncl > kPackCells) return 0;
+    const Grid &g = P.grid;
+    constexpr int NR = D == 3 ? 9 : 3;
+    const uint32_t nx = (uint32_t)g.nc[0], ny = (uint32_t)g.nc[1];
+    for (int e = threadIdx.x; e < ncl * NR; e += kBlock) {
+        const int k = e / NR, r = e - k * NR;
+        const uint32_t cell = cf + (uint32_t)k;
+        int ci[3] = {(int)(cell % nx), (int)((cell / nx) % ny), (int)(cell / (nx * ny))};
+        Stencil st;
+        make_stencil<D>(g, ci, st);
+        const int a = D == 3 ? r / 3 : 0, b = D == 3 ? r - 3 * (r / 3) : r;
+        if (!(pick3(st.ok[2], a) && pick3(st.ok[1], b))) continue;
+        int e0 = 0;
+        while (e0 < 2 && !pick3(st.ok[0], e0)) ++e0;
+        const int64_t c0 =
+            ((int64_t)pick3(st.v[2], a) * g.nc[1] + pick3(st.v[1], b)) * g.nc[0] + pick3(st.v[0], e0);
+        tbl[k * (int)kPackRanges + r] = (int32_t)S.fstart[c0];
+        tbl[k * (int)kPackRanges + NR + r] = (int32_t)(nf + (int64_t)S.wstart[c0]);
+    }
+    for (int e = threadIdx.x; e <= ncl; e += kBlock) sfs[e] = S.fstart[cf + (uint32_t)e];
+    __syncthreads();
+    return ncl;
+}
+
+// The start of each of a row's stencil-row ranges (fluid, then walls when
+// the row has wall neighbours) at r*, from its cell, into its LDS column
+// (rows of workgroups whose cells are too many for pack_table).
+template <int D>
+__device__ __forceinline__ void pack_bases(const Params &P, const State &S, int64_t i, int32_t *pb) {
+    const uint32_t rc = S.rcell[i];
+    const bool walls = (rc & kRcellWalls) != 0;
+    const uint32_t cell = rc & ~kRcellWalls;
+    const Grid &g = P.grid;
+    int ci[3] = {0, 0, 0};
+    const uint32_t nx = (uint32_t)g.nc[0], ny = (uint32_t)g.nc[1];
+    ci[0] = (int)(cell % nx);
+    ci[1] = (int)((cell / nx) % ny);
+    ci[2] = (int)(cell / (nx * ny));
+    Stencil st;
+    make_stencil<D>(g, ci, st);
+    constexpr int na = D == 3 ? 3 : 1;
+    constexpr int NR = D == 3 ? 9 : 3;
+    int e0 = 0;
+    while (e0 < 2 && !pick3(st.ok[0], e0)) ++e0;
+    const int x0 = pick3(st.v[0], e0);
+#pragma unroll
+    for (int a = 0; a < na; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const int r = D == 3 ? a * 3 + b : b;
+            if (!(pick3(st.ok[2], a) && pick3(st.ok[1], b))) continue;
+            const int64_t c0 = ((int64_t)pick3(st.v[2], a) * g.nc[1] + pick3(st.v[1], b)) * g.nc[0] + x0;
+            pb[r * kBlock] = (int32_t)S.fstart[c0];
+            if (walls) pb[(NR + r) * kBlock] = (int32_t)(P.nf + (int64_t)S.wstart[c0]);
+        }
 }
 
 template <typename R>
@@ -1362,25 +1611,44 @@ __device__ __forceinline__ void load_partials(const double *partial, int64_t nbl
     }
 }
 
+// The stopping decision of eq. convergence from the partial sums of sweep
+// L-1, in FP64 (the FP32 mode: every sum, the ratio and the test in FP32).
 __device__ __forceinline__ bool stopped_after(const Params &P, const double *partial, int64_t nblk, int L, const PartialLoad &pl,
                               double lam, bool first, Control *ctl) {
     __shared__ double sh[2][kBlock / 64];
     __shared__ int stop_sh;
+    const bool f32 = plain32(P);
     double a = 0.0, b = 0.0;
+    float af = 0.f, bf = 0.f;
 #pragma unroll
     for (int t = 0; t < kPartialRegs; ++t) {
-        a += pl.a[t];
-        b += pl.b[t];
+        if (f32) {
+            af += (float)pl.a[t];
+            bf += (float)pl.b[t];
+        } else {
+            a += pl.a[t];
+            b += pl.b[t];
+        }
     }
     if (nblk > (int64_t)kPartialRegs * kBlock) {   // large grids: the rest, in order
         const double *pa = partial + (int64_t)((L - 1) & 1) * 2 * nblk;
         for (int64_t k = threadIdx.x + (int64_t)kPartialRegs * kBlock; k < nblk; k += kBlock) {
-            a += pa[k];
-            b += pa[nblk + k];
+            if (f32) {
+                af += (float)pa[k];
+                bf += (float)pa[nblk + k];
+            } else {
+                a += pa[k];
+                b += pa[nblk + k];
+            }
         }
     }
-    a = wave_sum(a);
-    b = wave_sum(b);
+    if (f32) {
+        a = wave_sum_f(af);
+        b = wave_sum_f(bf);
+    } else {
+        a = wave_sum(a);
+        b = wave_sum(b);
+    }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) {
         sh[0][wv] = a;
@@ -1388,19 +1656,36 @@ __device__ __forceinline__ bool stopped_after(const Params &P, const double *par
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        a = 0.0;
-        b = 0.0;
-        for (int t = 0; t < kBlock / 64; ++t) {
-            a += sh[0][t];
-            b += sh[1][t];
+        double ratio;
+        if (f32) {
+            float s0 = 0.f, s1 = 0.f;
+            for (int t = 0; t < kBlock / 64; ++t) {
+                s0 += (float)sh[0][t];
+                s1 += (float)sh[1][t];
+            }
+            float lamf = (float)lam;
+            if (P.conv_norm == SISPH_CONV_MEAN) lamf *= (float)P.nf;
+            const float scale = lamf > s1 ? lamf : s1;
+            const float rf = scale > 0.f ? s0 / scale : (s0 > 0.f ? INFINITY : 0.f);
+            a = s0;
+            b = s1;
+            ratio = rf;
+        } else {
+            a = 0.0;
+            b = 0.0;
+            for (int t = 0; t < kBlock / 64; ++t) {
+                a += sh[0][t];
+                b += sh[1][t];
+            }
+            if (P.conv_norm == SISPH_CONV_MEAN) lam *= (double)P.nf;
+            const double scale = lam > b ? lam : b;
+            ratio = scale > 0.0 ? a / scale : (a > 0.0 ? INFINITY : 0.0);
         }
-        if (P.conv_norm == SISPH_CONV_MEAN) lam *= (double)P.nf;
-        const double scale = lam > b ? lam : b;
-        const double ratio = scale > 0.0 ? a / scale : (a > 0.0 ? INFINITY : 0.0);
         const bool bad = !isfinite(a) || !isfinite(b);
+        const bool below = f32 ? (float)ratio < (float)P.tol : ratio < P.tol;
         bool stop;
         if (P.forced_iters > 0) stop = L >= P.forced_iters;
-        else stop = (L >= P.min_iter && ratio < P.tol) || L >= P.max_iter;
+        else stop = (L >= P.min_iter && below) || L >= P.max_iter;
         stop = stop || bad;
         stop_sh = stop ? 1 : 0;
         if (first) {
@@ -1417,6 +1702,33 @@ __device__ __forceinline__ bool stopped_after(const Params &P, const double *par
     }
     __syncthreads();
     return stop_sh != 0;
+}
+
+// The damped Jacobi update of eq. p-sor (FP32 throughout in the FP32 mode)
+// and the row's terms of the two residual sums.
+template <typename R>
+__device__ __forceinline__ double psor(const Params &P, double r, R s, double D, double pold) {
+    if (plain32(P)) {
+        const float w = (float)P.omega;
+        return (double)(w * ((float)r + (float)s) / (float)D + (1.f - w) * (float)pold);
+    }
+    return P.omega * (r + (double)s) / D + (1.0 - P.omega) * pold;
+}
+
+// Partial sums |p^{k+1} - p^k| and |p^{k+1}| of the workgroup's rows, valid
+// in thread 0 (FP32 sums in the FP32 mode).
+__device__ __forceinline__ void residual_partials(const Params &P, bool live, double v, double pold, double &a,
+                                                  double &b) {
+    if (plain32(P)) {
+        float af = live ? fabsf((float)v - (float)pold) : 0.f, bf = live ? fabsf((float)v) : 0.f;
+        block_sum2_f(af, bf);
+        a = af;
+        b = bf;
+        return;
+    }
+    a = live ? fabs(v - pold) : 0.0;
+    b = live ? fabs(v) : 0.0;
+    block_sum2(a, b);
 }
 
 template <typename R, int FIRST, bool PRECHECK>
@@ -1449,11 +1761,39 @@ struct Sweep {
         double *pn = S.p[(L + 1) & 1];
         const float *qc = S.p32 + (L & 1) * P.ntot;
         float *qn = S.p32 + ((L + 1) & 1) * P.ntot;
-        const bool offs = P.compact != 0;
-        const int32_t wide_flag = offs ? ctl->wide : 0;   // set by this step's coefficients
+        const bool packed = P.packed != 0;
+        const bool offs = P.compact != 0 || packed;
+        // set by this step's coefficients (offsets) or neighbour build (codes)
+        const int32_t wide_flag = P.compact ? ctl->wide : (packed ? ctl->pk_overflow : 0);
         const int gmax = P.cap / 4;
         ROW;
         const bool live = i < nf;
+        // packed codes: the range starts of the workgroup's cells in a shared
+        // table, or, when its rows span too many cells, per row in its own
+        // LDS column
+        __shared__ int32_t pbt[kPackRanges * kBlock];
+        __shared__ uint32_t sfs[kPackCells + 1];
+        const int32_t *pb = nullptr;
+        int pstride = 1;
+        if (packed && !wide_flag) {
+            const int ncl = P.dim == 3 ? pack_table<3>(P, S, blk, pbt, sfs) : pack_table<2>(P, S, blk, pbt, sfs);
+            if (ncl > 0) {
+                int lo = 0, hi = ncl - 1;   // the last cell whose first row is <= i
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if ((int64_t)sfs[mid] <= i) lo = mid;
+                    else hi = mid - 1;
+                }
+                pb = pbt + lo * (int)kPackRanges;
+            } else {
+                pb = pbt + threadIdx.x;
+                pstride = kBlock;
+                if (live) {
+                    if (P.dim == 3) pack_bases<3>(P, S, i, pbt + threadIdx.x);
+                    else pack_bases<2>(P, S, i, pbt + threadIdx.x);
+                }
+            }
+        }
         // one round trip: row values and the first FIRST / 4 coefficient and
         // index groups
         constexpr int NG = FIRST / 4;
@@ -1475,7 +1815,7 @@ struct Sweep {
         const int npos = c - 1;   // neighbours besides the row itself
         R pv[NG][4];
         if (live) {
-            if (offs) resolve_groups<NG>(i, nf, 0, npos, S.nbr, wide_flag != 0, oo, jj);
+            if (offs) resolve_groups<NG>(i, nf, 0, npos, S.nbr, wide_flag != 0, oo, jj, pb, pstride);
             issue_gathers<R, NG>(i, 0, npos, jj, pc, qc, pv);
         }
         // (a solve that stopped earlier returned above: its partials are stale)
@@ -1490,19 +1830,18 @@ struct Sweep {
                 int4 jb[kSweepBatchGroups];
                 Off4 ob[kSweepBatchGroups];
                 load_groups<R, kSweepBatchGroups>(i, nf, g0, gmax, S.coef, S.cidx, offs, cb, jb, ob);
-                if (offs) resolve_groups<kSweepBatchGroups>(i, nf, g0, npos, S.nbr, wide_flag != 0, ob, jb);
+                if (offs) resolve_groups<kSweepBatchGroups>(i, nf, g0, npos, S.nbr, wide_flag != 0, ob, jb, pb,
+                                                            pstride);
                 s = gather_groups<R, kSweepBatchGroups>(i, g0, npos, cb, jb, pc, qc, s);
             }
-            if (D != 0.0 && !f) v = P.omega * (r + (double)s) / D + (1.0 - P.omega) * pold;
+            if (D != 0.0 && !f) v = psor<R>(P, r, s, D, pold);
         }
         double a = 0.0, b = 0.0;
         if (live) {
             pn[i] = v;
             if constexpr (sizeof(R) == 4) qn[i] = (float)v;
-            a = fabs(v - pold);
-            b = fabs(v);
         }
-        block_sum2(a, b);
+        residual_partials(P, live, v, pold, a, b);
         if (threadIdx.x == 0) {
             double *pw = S.partial + (int64_t)(L & 1) * 2 * nblk;
             pw[blk] = a;
@@ -1618,7 +1957,7 @@ __global__ __launch_bounds__(kBlock) void k_ppe_persistent(const Params P, const
                 gather_dev<R, kSweepBatchGroups>(i, g0, npos, jb, pc, qc, pb);
                 s = sum_gathers<R, kSweepBatchGroups>(g0, npos, cb, pb, s);
             }
-            if (D != 0.0 && !f) v = P.omega * (r + (double)s) / D + (1.0 - P.omega) * pold;
+            if (D != 0.0 && !f) v = psor<R>(P, r, s, D, pold);
         }
         double a = 0.0, b = 0.0;
         if (live) {
@@ -1628,11 +1967,9 @@ __global__ __launch_bounds__(kBlock) void k_ppe_persistent(const Params P, const
             } else {
                 dev_store(pn + i, v);
             }
-            a = fabs(v - pold);
-            b = fabs(v);
-            pold = v;
         }
-        block_sum2(a, b);
+        residual_partials(P, live, v, pold, a, b);
+        if (live) pold = v;
         if (threadIdx.x == 0) {
             double *pw = S.partial + (int64_t)(L & 1) * 2 * nblk;
             dev_store(pw + blk, a);
@@ -1688,6 +2025,170 @@ __global__ __launch_bounds__(kBlock) void k_ppe_persistent(const Params P, const
     }
 }
 
+// The Jacobi solves of several wall-less cases of a batch in one
+// cooperative launch: one workgroup per fluid block of every such case (all
+// resident), each holding its rows' first FIRST coefficients in registers as
+// the single-case persistent solve does.  Every workgroup meets the others
+// at one grid barrier per sweep (arrival words, workgroup 0 of the launch
+// posting one word per XCD).  Each case keeps its own stopping decision:
+// its first workgroup takes it from the case's partial sums exactly as the
+// per-launch sweep does, and on a stop posts the case's stop word and counts
+// the case as finished; after the barrier the case's workgroups read that
+// word and do no further sweep, while still meeting the barriers.  The
+// launch ends when every case has stopped (the last barrier's word carries
+// the bit), so each case's sums, sweeps and decision are bitwise those it
+// would have alone.  On leaving, each case's stop marker is set below every
+// sweep count, so per-launch sweeps of the other cases of its batch return
+// at once for it.  A wait that does not end within spins polls sets the
+// launch's late flag and every workgroup leaves.
+constexpr int64_t kBatchStopWords = kBatchSyncStop;   // per-case stop words follow the arrivals
+constexpr int kBatchDone = 32;                        // cases stopped so far
+
+template <typename R, int FIRST>
+__global__ __launch_bounds__(kBlock) void k_ppe_persistent_batch(const CaseEntry *__restrict__ tab,
+                                                                 const int32_t *__restrict__ powner,
+                                                                 const int64_t *__restrict__ pfirst, uint32_t *bsync,
+                                                                 int ncase, int limit, uint32_t spins) {
+    const int64_t gb = blockIdx.x, gn = gridDim.x;
+    const int cidx = powner[gb];
+    const Params &P = tab[cidx].P;
+    const State &S = tab[cidx].S;
+    Control *ctl = S.ctl;
+    const int64_t blk = gb - pfirst[cidx], nblk = tab[cidx].nblk[K_FLUID];
+    const int64_t nf = P.nf;
+    const bool offs = P.compact != 0;
+    const int32_t wide_flag = offs ? ctl->wide : 0;
+    const int gmax = P.cap / 4;
+    ROW;
+    const bool live = i < nf;
+    constexpr int NG = FIRST / 4;
+    typename Vec4<R>::T cc[NG];
+    int4 jj[NG];
+    Off4 oo[NG];
+    double D = 0.0, r = 0.0, pold = 0.0;
+    int32_t f = 1, c = 1;
+    if (live) {
+        load_groups<R, NG>(i, nf, 0, gmax, S.coef, S.cidx, offs, cc, jj, oo);
+        D = S.dii[i];
+        r = S.rhs[i];
+        f = S.fs[i];
+        c = S.cnt[i];
+        pold = S.p[0][i];
+        if (offs) resolve_groups<NG>(i, nf, 0, c - 1, S.nbr, wide_flag != 0, oo, jj);
+    }
+    const int npos = c - 1;
+    const double lam = __longlong_as_double((long long)ctl->lambda_bits);   // fixed during the solve
+    uint32_t *const late_flag = bsync;
+    uint32_t *const arrive = bsync + kSyncArrive;
+    uint32_t *const stopw = bsync + kBatchStopWords + cidx;
+    __shared__ int go, cdone_sh;
+    bool stopped = false;   // the case's first workgroup, once it recorded the stop
+    bool cdone = false;     // this workgroup's case has stopped
+    for (int L = 0; L < limit; ++L) {
+        if (!cdone) {
+            if (L > 0 && blk == 0 && !stopped) {
+                PartialLoad pl;
+                const double *pa = S.partial + (int64_t)((L - 1) & 1) * 2 * nblk;
+#pragma unroll
+                for (int t = 0; t < kPartialRegs; ++t) {   // nblk <= kPartialRegs * kBlock here
+                    const int64_t k = threadIdx.x + (int64_t)t * kBlock;
+                    pl.a[t] = k < nblk ? dev_load(pa + k) : 0.0;
+                    pl.b[t] = k < nblk ? dev_load(pa + nblk + k) : 0.0;
+                }
+                stopped = stopped_after(P, S.partial, nblk, L, pl, lam, true, ctl);
+                if (stopped && threadIdx.x == 0) {
+                    dev_store(stopw, (uint32_t)L);
+                    __hip_atomic_fetch_add(bsync + kBatchDone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            const double *pc = S.p[L & 1];
+            double *pn = S.p[(L + 1) & 1];
+            const float *qc = S.p32 + (L & 1) * P.ntot;
+            float *qn = S.p32 + ((L + 1) & 1) * P.ntot;
+            double v = 0.0;
+            if (live) {
+                R pv[NG][4];
+                gather_dev<R, NG>(i, 0, npos, jj, pc, qc, pv);
+                R s = sum_gathers<R, NG>(0, npos, cc, pv, R(0));
+                for (int g0 = NG; 4 * g0 < npos; g0 += kSweepBatchGroups) {
+                    typename Vec4<R>::T cb[kSweepBatchGroups];
+                    int4 jb[kSweepBatchGroups];
+                    Off4 ob[kSweepBatchGroups];
+                    load_groups<R, kSweepBatchGroups>(i, nf, g0, gmax, S.coef, S.cidx, offs, cb, jb, ob);
+                    if (offs) resolve_groups<kSweepBatchGroups>(i, nf, g0, npos, S.nbr, wide_flag != 0, ob, jb);
+                    R pb[kSweepBatchGroups][4];
+                    gather_dev<R, kSweepBatchGroups>(i, g0, npos, jb, pc, qc, pb);
+                    s = sum_gathers<R, kSweepBatchGroups>(g0, npos, cb, pb, s);
+                }
+                if (D != 0.0 && !f) v = psor<R>(P, r, s, D, pold);
+            }
+            double a = 0.0, b = 0.0;
+            if (live) {
+                if constexpr (sizeof(R) == 4) {
+                    pn[i] = v;
+                    dev_store(qn + i, (float)v);
+                } else {
+                    dev_store(pn + i, v);
+                }
+            }
+            residual_partials(P, live, v, pold, a, b);
+            if (live) pold = v;
+            if (threadIdx.x == 0) {
+                double *pw = S.partial + (int64_t)(L & 1) * 2 * nblk;
+                dev_store(pw + blk, a);
+                dev_store(pw + nblk + blk, b);
+                if (blk == 0 && !stopped) ctl->iter = L + 1;
+            }
+        }
+        __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this sweep's stores completed
+        __syncthreads();
+        if (threadIdx.x == 0) dev_store(arrive + gb, (uint32_t)(L + 1));
+        const uint32_t want = 2u * (uint32_t)(L + 1);
+        if (gb == 0) {
+            bool all = false;
+            for (uint32_t sp = 0;; ++sp) {
+                bool ok = true;
+#pragma unroll
+                for (int t = 0; t < kPartialRegs; ++t) {
+                    const int64_t k = threadIdx.x + (int64_t)t * kBlock;
+                    if (k < gn && dev_load(arrive + k) < (uint32_t)(L + 1)) ok = false;
+                }
+                const int give_up = threadIdx.x == 0 && (dev_load(late_flag) != 0u || sp >= spins);
+                all = __syncthreads_and(ok);
+                const bool quit = __syncthreads_or(give_up);
+                if (all || quit) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (threadIdx.x == 0) {
+                if (!all) dev_store(late_flag, 1u);
+                const bool leave = !all || dev_load(bsync + kBatchDone) >= (uint32_t)ncase;
+                const uint32_t word = want + (leave ? 1u : 0u);
+                for (int x = 0; x < kSyncCopies; ++x) dev_store(bsync + kSyncBcast + 64 * x, word);
+                go = leave ? 0 : 1;
+            }
+        } else if (threadIdx.x == 0) {
+            const uint32_t *w = bsync + kSyncBcast + 64 * (gb % kSyncCopies);
+            uint32_t word = dev_load(w);
+            for (uint32_t sp = 0; word < want && dev_load(late_flag) == 0u && sp < spins; ++sp) {
+                __builtin_amdgcn_s_sleep(1);
+                word = dev_load(w);
+            }
+            if (word < want) {
+                dev_store(late_flag, 1u);
+                go = 0;
+            } else {
+                go = (word & 1u) ? 0 : 1;
+            }
+        }
+        if (threadIdx.x == 0) cdone_sh = dev_load(stopw) != 0xffffffffu;
+        __syncthreads();
+        cdone = cdone_sh != 0;
+        if (!go) break;
+    }
+    // later per-launch sweeps of the batch return at once for this case
+    if (blk == 0 && threadIdx.x == 0 && stopped) ctl->stopped_at = -1;
+}
+
 // eq. p-shepard: p_w = [sum_f p_f W_wf + (g - a_w) . sum_f rho_f r_wf W_wf]
 // / sum_f W_wf over fluid neighbours (static wall: a_w = 0); 0 without
 // neighbours; clamped at 0 on free-surface problems.  Positions and
@@ -1725,7 +2226,7 @@ struct WallCoef {
             for (int a = 0; a < D; ++a) gs += P.g[a] * (double)sr[a];
             h = gs / (double)sw;
         }
-        S.wh[w] = h;
+        S.wh[w] = rp(P, h);
         // second pass: the normalised weights (the kernel values again, in
         // the same order, rather than holding them in registers)
         for (int k = 0; k < c; ++k) {
@@ -1846,7 +2347,7 @@ struct WallPressure {
             if (k0 >= c) break;
             wall_words<R>(S, nw, w, k0, P.cap, cb, jr);
         }
-        double pw = (double)sp + S.wh[w];
+        double pw = plain32(P) ? (double)((float)sp + (float)S.wh[w]) : (double)sp + S.wh[w];
         if (P.free_surface && pw < 0.0) pw = 0.0;
         pc[iw] = pw;
         qc[iw] = (float)pw;
@@ -1860,7 +2361,7 @@ struct SettlePressure {
         ROW;
         if (i < P.ntot && (S.ctl->iter & 1)) {
             S.p[0][i] = S.p[1][i];
-            if (P.precision == SISPH_MIXED) S.p32[i] = S.p32[P.ntot + i];
+            if (f32_sums(P.precision)) S.p32[i] = S.p32[P.ntot + i];
         }
     }
 };
@@ -1882,7 +2383,7 @@ struct PrefFinish {
     static __device__ __forceinline__ void run(const Params &, const State &S, int64_t, int64_t, int) {
         Control *c = S.ctl;
         if (threadIdx.x == 0 && !c->p_ref_set) {
-            c->p_ref = 2.0 * order_val(c->pmax_key);
+            c->p_ref = 2.0 * order_val(c->pmax_key);   // exact for an FP32 value too
             c->p_ref_set = 1;
         }
     }
@@ -1936,8 +2437,13 @@ struct Correct {
         }
         const double dt = S.ctl->dt;
         for (int a = 0; a < D; ++a) {
-            S.un[a][i] = S.us[a][i] + dt * (double)f[a];
-            if (P.adaptive_dt) S.vk[a][i] += (double)f[a];   // total acceleration of the step
+            if (plain32(P)) {
+                S.un[a][i] = (float)S.us[a][i] + (float)dt * (float)f[a];
+                if (P.adaptive_dt) S.vk[a][i] = (float)S.vk[a][i] + (float)f[a];
+            } else {
+                S.un[a][i] = S.us[a][i] + dt * (double)f[a];
+                if (P.adaptive_dt) S.vk[a][i] += (double)f[a];   // total acceleration of the step
+            }
         }
     }
 };
@@ -1986,7 +2492,7 @@ struct NextDt {
         double dt = P.dt;
         if (umax > 0.0 && 0.25 * P.h / umax < dt) dt = 0.25 * P.h / umax;
         if (fmax > 0.0 && 0.25 * sqrt(P.h / fmax) < dt) dt = 0.25 * sqrt(P.h / fmax);
-        c->dt_next = dt;
+        c->dt_next = rp(P, dt);
     }
 };
 
@@ -2023,7 +2529,7 @@ struct Gtvf {
         const double pref = S.ctl->p_ref;
         double p0 = pref;
         if (ext) {
-            const double a = 10.0 * fabs(S.p[0][i]);
+            const double a = rp(P, 10.0 * fabs(S.p[0][i]));
             p0 = a < pref ? a : pref;
         }
         R s[3] = {0, 0, 0};
@@ -2048,6 +2554,13 @@ struct Gtvf {
         }
         const double dtau = S.ctl->dt / (double)P.gtvf_K;
         for (int a = 0; a < D; ++a) {
+            if (plain32(P)) {
+                const float dtf = (float)dtau, f = -(float)p0 * (float)s[a];
+                const float v = k == 0 ? 0.f : (float)S.vk[a][i];
+                xdst[a][i] = (float)xi[a] + dtf * v + 0.5f * dtf * dtf * f;
+                S.vk[a][i] = v + dtf * f;
+                continue;
+            }
             const double f = -p0 * (double)s[a];
             const double v = k == 0 ? 0.0 : S.vk[a][i];
             xdst[a][i] = xi[a] + dtau * v + 0.5 * dtau * dtau * f;
@@ -2068,9 +2581,17 @@ struct Advance {
         double *const *xk = kfinal < 0 ? S.xs : S.xk[kfinal & 1];
         const double dt = S.ctl->dt;
         for (int a = 0; a < D; ++a) {
-            const double utn = S.un[a][i] + (xk[a][i] - S.xs[a][i]) / dt;
-            const double xn = S.x[a][i] + 0.5 * dt * (utn + S.ut[a][i]);
-            S.x[a][i] = wrap_periodic(xn, P.grid, a);
+            double utn, xn;
+            if (plain32(P)) {
+                const float dtf = (float)dt;
+                const float u1 = (float)S.un[a][i] + ((float)xk[a][i] - (float)S.xs[a][i]) / dtf;
+                utn = u1;
+                xn = (float)S.x[a][i] + 0.5f * dtf * (u1 + (float)S.ut[a][i]);
+            } else {
+                utn = S.un[a][i] + (xk[a][i] - S.xs[a][i]) / dt;
+                xn = S.x[a][i] + 0.5 * dt * (utn + S.ut[a][i]);
+            }
+            S.x[a][i] = rp(P, wrap_periodic(xn, P.grid, a));
             S.ut[a][i] = utn;
             S.u[a][i] = S.un[a][i];
         }
@@ -2402,7 +2923,7 @@ __global__ void k_iota(int32_t *p, int64_t n) {
 
 #define SISPH_DISPATCH_KDR(T, CALL)                        \
     do {                                                   \
-        if ((T).precision == SISPH_MIXED) {                \
+        if (f32_sums((T).precision)) {                     \
             using R = float;                               \
             SISPH_DISPATCH_KD(T, CALL);                    \
         } else {                                           \
@@ -2430,6 +2951,31 @@ __global__ __launch_bounds__(kBlock) void k_aos_to_soa(const double *__restrict_
     if (dim > 2) d2[i] = src[i * dim + 2];
 }
 
+// The plain FP32 mode starts from the case's state rounded to FP32:
+// positions (fluid and walls), velocities, pressure and mass.
+template <int D>
+struct RoundState {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        ROW;
+        if (i >= P.ntot) return;
+        for (int a = 0; a < D; ++a) {
+            S.x[a][i] = (float)S.x[a][i];
+            if (i < P.nf) {
+                S.u[a][i] = (float)S.u[a][i];
+                S.ut[a][i] = (float)S.ut[a][i];
+            } else {
+                S.wallu[a][i - P.nf] = (float)S.wallu[a][i - P.nf];
+            }
+        }
+        S.p[0][i] = (float)S.p[0][i];
+        S.m[i] = (float)S.m[i];
+    }
+};
+
+void round_state(const Target &T) {
+    if (T.precision == SISPH_FP32) SISPH_DISPATCH_D(T, (launch<RoundState<D>, K_TOT>(T)));
+}
+
 void aos_to_soa(const double *src, double *const dst[3], int64_t at, int dim, int64_t n, hipStream_t s) {
     if (n > 0)
         k_aos_to_soa<<<nblocks(n), kBlock, 0, s>>>(src, dst[0] + at, dim > 1 ? dst[1] + at : nullptr,
@@ -2451,6 +2997,11 @@ void bin_fluid(const Target &T, int which) {
     if (which == POS_X) {
         SISPH_DISPATCH_D(T, (launch<ReorderFluid<D>, K_FLUID>(T, 0)));
         SISPH_DISPATCH_D(T, (launch<ReorderFluid<D>, K_FLUID>(T, 1)));
+    } else {
+        for (int batch = 0; batch < 2; ++batch) {
+            SISPH_DISPATCH_D(T, (launch<ReorderStage2<D>, K_FLUID>(T, batch, 0)));
+            SISPH_DISPATCH_D(T, (launch<ReorderStage2<D>, K_FLUID>(T, batch, 1)));
+        }
     }
 }
 
@@ -2509,7 +3060,7 @@ static void sweep_variant(const Target &T, int L, int v) {
 }
 
 void sweep_only(const Target &T, int L) {
-    if (T.precision == SISPH_MIXED) {
+    if (f32_sums(T.precision)) {
         if (T.precheck) sweep_variant<float, true>(T, L, T.variant);
         else sweep_variant<float, false>(T, L, T.variant);
     } else {
@@ -2543,7 +3094,7 @@ static int64_t persistent_capacity() {
 #define SISPH_PERSISTENT_FIRST(T, CALL)                                       \
     do {                                                                      \
         const int first = kSweepFirsts[(T).variant % 3];                      \
-        if ((T).precision == SISPH_MIXED) {                                   \
+        if (f32_sums((T).precision)) {                                        \
             if (first == 16) { using R = float; constexpr int F = 16; CALL; } \
             else if (first == 20) { using R = float; constexpr int F = 20; CALL; } \
             else { using R = float; constexpr int F = 24; CALL; }            \
@@ -2561,6 +3112,40 @@ hipError_t ppe_persistent(const Target &T, int limit) {
 
 int64_t ppe_persistent_capacity(const Target &T) {
     SISPH_PERSISTENT_FIRST(T, return (persistent_capacity<R, F>()));
+    return 0;
+}
+
+template <typename R, int FIRST>
+static hipError_t persistent_batch_launch(const Target &T, const int32_t *powner, const int64_t *pfirst,
+                                          int64_t ptotal, uint32_t *bsync, int ncase, int limit, uint32_t spins) {
+    const CaseEntry *tab = T.tab;
+    void *args[] = {(void *)&tab, (void *)&powner, (void *)&pfirst, (void *)&bsync,
+                    (void *)&ncase, (void *)&limit, (void *)&spins};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_ppe_persistent_batch<R, FIRST>),
+                                      dim3((unsigned)ptotal), dim3(kBlock), args, 0, T.s);
+}
+
+template <typename R, int FIRST>
+static int64_t persistent_batch_capacity() {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&k_ppe_persistent_batch<R, FIRST>), kBlock, 0) != hipSuccess)
+        return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const int64_t cap = (int64_t)per_cu * cus;
+    return cap < (int64_t)kPartialRegs * kBlock ? cap : (int64_t)kPartialRegs * kBlock;
+}
+
+hipError_t ppe_persistent_batch(const Target &T, const int32_t *powner, const int64_t *pfirst, int64_t ptotal,
+                                uint32_t *bsync, int ncase, int limit, uint32_t spins) {
+    SISPH_PERSISTENT_FIRST(T, return (persistent_batch_launch<R, F>(T, powner, pfirst, ptotal, bsync, ncase, limit,
+                                                                     spins)));
+    return hipErrorInvalidValue;
+}
+
+int64_t ppe_persistent_batch_capacity(const Target &T) {
+    SISPH_PERSISTENT_FIRST(T, return (persistent_batch_capacity<R, F>()));
     return 0;
 }
 
@@ -2587,7 +3172,7 @@ void ppe_iteration(const Target &T, int L) {
 void wall_pressure_iteration(const Target &T, int L) {
     // hardware workgroup order: the listed workgroups, which take the first
     // launch slots, then spread over every XCD
-    if (T.precision == SISPH_MIXED) launch<WallPressure<float>, K_WALL, false>(T, L, 0);
+    if (f32_sums(T.precision)) launch<WallPressure<float>, K_WALL, false>(T, L, 0);
     else launch<WallPressure<double>, K_WALL, false>(T, L, 0);
 }
 
@@ -2604,7 +3189,7 @@ void bicg_settle(const Target &T) { launch<BicgSettle, K_FLUID>(T); }
 void settle_pressure(const Target &T) { launch<SettlePressure, K_TOT>(T); }
 
 void wall_pressure_final(const Target &T) {
-    if (T.precision == SISPH_MIXED) launch<WallPressure<float>, K_WALL>(T, 0, 1);
+    if (f32_sums(T.precision)) launch<WallPressure<float>, K_WALL>(T, 0, 1);
     else launch<WallPressure<double>, K_WALL>(T, 0, 1);
 }
 
@@ -2628,12 +3213,12 @@ void step_maxima(const Target &T) { SISPH_DISPATCH_D(T, (launch<StepMaxima<D>, K
 void next_dt(const Target &T) { launch<NextDt, K_ONE>(T); }
 
 void shadow(const Target &T) {
-    if (T.precision != SISPH_MIXED) return;
+    if (!f32_sums(T.precision)) return;
     launch<Shadow, K_TOT>(T);
 }
 
 void mass_over_rho2(const Target &T) {
-    if (T.precision == SISPH_MIXED) launch<MassOverRho2<float>, K_TOT>(T);
+    if (f32_sums(T.precision)) launch<MassOverRho2<float>, K_TOT>(T);
     else launch<MassOverRho2<double>, K_TOT>(T);
 }
 

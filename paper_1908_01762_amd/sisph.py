@@ -139,6 +139,10 @@ def lib():
         L.sisph_batch_size.argtypes = [C.c_void_p]
         L.sisph_batch_step.restype = C.c_int32
         L.sisph_batch_step.argtypes = [C.c_void_p, C.POINTER(PPEStats)]
+        L.sisph_batch_set_persistent.restype = C.c_int32
+        L.sisph_batch_set_persistent.argtypes = [C.c_void_p, C.c_int32]
+        L.sisph_batch_persistent_info.restype = C.c_int32
+        L.sisph_batch_persistent_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.sisph_batch_destroy.restype = C.c_int32
         L.sisph_batch_destroy.argtypes = [C.c_void_p]
         L.sisph_status_string.restype = C.c_char_p
@@ -415,6 +419,16 @@ class Batch:
         code = lib().sisph_batch_set_graphs(self.h, int(bool(on)))
         if code != OK:
             raise SisphError(code, status_string(code))
+
+    def use_persistent(self, on: bool = True):
+        """Wall-less cases' Jacobi solves in one cooperative launch (default on)."""
+        _check(lib().sisph_batch_set_persistent(self.h, int(bool(on))))
+
+    def persistent_info(self):
+        """Persistent batched launches and fallbacks since creation."""
+        n, f = C.c_int64(), C.c_int64()
+        _check(lib().sisph_batch_persistent_info(self.h, C.byref(n), C.byref(f)))
+        return dict(launches=n.value, fallbacks=f.value)
 
     def attach(self, ctx: Context):
         _check(lib().sisph_batch_attach(self.h, ctx.h), ctx.h)

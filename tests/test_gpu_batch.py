@@ -32,6 +32,8 @@ def _mix():
         cases.dam_break_3d(dx=0.1, lx=0.4, ly=0.4, lz=0.5, tank_x=1.0, tank_y=0.4, tank_z=0.8,
                            precision="mixed"),                            # other group: 3D
         cases.dam_break_2d(dx=0.08, precision="mixed").replace(dt_mode="adaptive"),
+        cases.dam_break_2d(dx=0.1, precision="fp32"),                    # other group: plain FP32
+        cases.taylor_green(20, kernel="wendland", hdx=1.3, precision="fp32", seed=5),
     ]
 
 
@@ -170,3 +172,53 @@ def test_a_failing_case_does_not_disturb_the_others():
     b.detach(cg)
     assert _same(cg.read_state(), ref)
     b.close()
+
+
+def _run_batch(sisph, mix, steps, persistent):
+    ctxs = [sisph.Context(c) for c in mix]
+    b = sisph.Batch(16)
+    b.use_persistent(persistent)
+    for ctx in ctxs:
+        b.attach(ctx)
+    its = [[] for _ in ctxs]
+    for _ in range(steps):
+        for k, s in enumerate(b.step()):
+            its[k].append(s["iters"])
+    info = b.persistent_info()
+    states = []
+    for ctx in ctxs:
+        b.detach(ctx)
+        states.append(ctx.read_state())
+    b.close()
+    for ctx in ctxs:
+        ctx.close()
+    return states, its, info
+
+
+def test_persistent_batch_equals_per_launch():
+    """The wall-less members of a group solved in one cooperative launch
+    (each with its own stopping decision) give bitwise the per-launch
+    results and sweep counts, with a walled member in the same group taking
+    per-launch sweeps after it; and wall-less cases only, in two groups (the
+    quintic and the Wendland kernel), one launch per group and step."""
+    sisph = _gpu()
+    mixes = {
+        "with_walls": (1, [cases.taylor_green(24, kernel="wendland", hdx=1.3, precision="mixed", seed=1),
+                           cases.dam_break_2d(dx=0.1, precision="mixed"),
+                           cases.taylor_green(40, kernel="wendland", hdx=1.3, precision="mixed", seed=2, re=500.0),
+                           cases.taylor_green(17, kernel="wendland", hdx=1.3, precision="mixed", seed=3,
+                                              tol=1e-2)]),
+        "wall_less": (2, [cases.taylor_green(30, precision="fp64", seed=4),
+                          cases.taylor_green(21, precision="fp64", seed=5, tol=1e-3),
+                          cases.cloud_2d(precision="fp64")]),
+    }
+    for name, (groups, mix) in mixes.items():
+        a, ia, pa = _run_batch(sisph, mix, 5, True)
+        b, ib, pb = _run_batch(sisph, mix, 5, False)
+        say(name, "persistent", pa, "iters", ia, "per-launch", ib)
+        if pa["launches"] == 0:
+            pytest.skip(f"persistent batched launch not taken ({pa['fallbacks']} fallbacks)")
+        assert pa["launches"] == 5 * groups and pb["launches"] == 0
+        assert ia == ib
+        for k in range(len(mix)):
+            assert _same(a[k], b[k]), (name, k)

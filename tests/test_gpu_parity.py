@@ -558,3 +558,46 @@ def test_null_space_projection(precision):
     assert all(e < bound for e in errs.values())
     assert abs(s["p"][:nf].mean()) < 0.05 * np.abs(s["p"][:nf]).mean()
     ctx.close()
+
+
+def _round32(case):
+    """The same case with its input arrays rounded to FP32 (the plain FP32
+    mode starts from those values; the oracle then reads the same numbers)."""
+    c = case.copy()
+    for k in ("x", "u", "p", "m"):
+        setattr(c, k, np.ascontiguousarray(getattr(c, k).astype(np.float32).astype(np.float64)))
+    if c.wall_u is not None:
+        c.wall_u = np.ascontiguousarray(c.wall_u.astype(np.float32).astype(np.float64))
+    return c
+
+
+def _is_f32(a):
+    a = np.asarray(a)
+    return np.array_equal(a, a.astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("name", ["tg50_quintic", "tg40_wendland_jitter", "db2d_dx0.05", "ldc30_slip"])
+def test_fp32_plain_steps(name):
+    """The plain FP32 mode (every sum, per-particle result, the residual and
+    the stopping test in FP32) against the FP64 oracle on the same FP32
+    inputs, the oracle following the GPU's sweep counts, over three steps;
+    every state value the GPU holds is an FP32 number."""
+    sisph = _gpu()
+    case = _round32(_cases_small()[name].replace(precision="fp32"))
+    nf = case.n_fluid
+    ctx = sisph.Context(case)
+    ref = oracle.Sim(case.replace(precision="fp64"))
+    its = []
+    for k in range(3):
+        g = ctx.step(1)[0]
+        its.append(g["iters"])
+        ref.step(forced_iters=g["iters"])
+    s = ctx.read_state()
+    for f in ("x", "u", "ut", "p"):
+        assert _is_f32(s[f]), f
+    errs = {"p": rel(s["p"][:nf], ref.p[:nf]), "u": rel(s["u"], ref.u),
+            "displacement": rel(s["x"][:nf] - case.x[:nf], ref.x[:nf] - case.x[:nf])}
+    for k, e in errs.items():
+        say(f"  fp32 {name} {k:12s} rel L2 {e:.3e} (sweeps {its})")
+    assert all(e < 2e-3 for e in errs.values())
+    ctx.close()

@@ -42,6 +42,7 @@ def _cases():
         "cloud_mixed": cases.cloud_2d(precision="mixed"),
         "tg30_eisph": cases.taylor_green(30, jitter=0.1, seed=4).replace(forced_iters=1),
         "tg30_maxiter": cases.taylor_green(30, precision="mixed").replace(tol=1e-300, max_iter=7),
+        "tg40_fp32": cases.taylor_green(40, kernel="wendland", hdx=1.3, precision="fp32"),
         "single_fp64": cases.single_particle(),
     }
 
