@@ -179,26 +179,35 @@ def host_info() -> dict:
 
 def batched_vs_plain(n_cases: int, steps: int, seed: int) -> dict:
     """The same uneven cases (serving mix: Taylor-Green or 2D dam break, N
-    log-uniform in 2.5k-160k, mixed precision, their own tolerances), first
-    stepped one case at a time with their own launches ("plain"), then all
-    together in one batch; both from the same initial state, same number of
-    steps, hence equal tolerance and equal results."""
+    log-uniform in 2.5k-160k, their own tolerances) stepped three ways from
+    the same initial state for the same number of steps: one case at a time
+    with its own launches in the plain FP32 mode (the baseline: every sum,
+    the residual and the stopping test in FP32) and in the mixed mode, and
+    all together as one batch in the mixed mode (FP32 neighbour sums, FP64
+    residual and positions).  The tolerance is the same for all three;
+    mixed plain and batched take identical sweeps."""
     import torch
     from paper_1908_01762_amd import cases, sisph
     mix = [c for _, c in cases.serving_mix(n_cases=n_cases, seed=seed)]
     nf = sum(c.n_fluid for c in mix)
-    ctxs = [sisph.Context(c) for c in mix]
-    for ctx in ctxs:          # one warm step each (first-step p_ref, caches)
-        ctx.step(1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    it_plain = 0
-    for ctx in ctxs:
-        it_plain += sum(s["iters"] * ctx.case.n_fluid for s in ctx.step(steps))
-    torch.cuda.synchronize()
-    plain = time.perf_counter() - t0
-    for ctx in ctxs:
-        ctx.close()
+
+    def per_case(precision):
+        ctxs = [sisph.Context(c.replace(precision=precision)) for c in mix]
+        for ctx in ctxs:          # one warm step each (first-step p_ref, caches)
+            ctx.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = 0
+        for ctx in ctxs:
+            its += sum(s["iters"] * ctx.case.n_fluid for s in ctx.step(steps))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        for ctx in ctxs:
+            ctx.close()
+        return el, its
+
+    plain32_s, it32 = per_case("fp32")
+    plain_s, it_plain = per_case("mixed")
     ctxs = [sisph.Context(c) for c in mix]
     b = sisph.Batch(len(ctxs))
     for ctx in ctxs:
@@ -215,12 +224,16 @@ def batched_vs_plain(n_cases: int, steps: int, seed: int) -> dict:
     for ctx in ctxs:
         ctx.close()
     return {"cases": len(mix), "fluid_particles": nf, "steps": steps,
-            "plain_s": plain, "batched_s": batched, "speedup": plain / batched,
-            "plain_ppe_particle_iters_per_s": it_plain / plain,
+            "plain_fp32_s": plain32_s, "plain_mixed_s": plain_s, "batched_mixed_s": batched,
+            "speedup_vs_plain_fp32": plain32_s / batched, "speedup_vs_plain_mixed": plain_s / batched,
+            "plain_fp32_ppe_particle_iters_per_s": it32 / plain32_s,
+            "plain_mixed_ppe_particle_iters_per_s": it_plain / plain_s,
             "batched_ppe_particle_iters_per_s": it_batch / batched,
-            "same_sweep_counts": it_plain == it_batch,
+            "plain_fp32_particle_steps_per_s": nf * steps / plain32_s,
+            "batched_particle_steps_per_s": nf * steps / batched,
+            "same_sweep_counts_mixed": it_plain == it_batch,
             "workload": "serving mix (seed %d): Taylor-Green / 2D dam break, N log-uniform 2.5k-160k, "
-                        "mixed precision, tol 1e-4 (TG) / 1e-3 (dam break)" % seed}
+                        "tol 1e-4 (TG) / 1e-3 (dam break)" % seed}
 
 
 def copy_reference(sizes_mib=(32, 1024), reps: int = 20) -> list:
@@ -289,7 +302,8 @@ def serving(n_requests: int, steps: int, rate_hz: float, budget_gb: float, seed:
     return rep
 
 
-def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool) -> dict:
+def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool, persistent: bool = True,
+            variant: int = -1) -> dict:
     """Steps one case: warmup steps, the autotuner, then `steps` timed steps
     with every sweep kernel launch timed by its own HIP events."""
     import torch
@@ -298,11 +312,16 @@ def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool)
     ctx = sisph.Context(case, device="cuda:0")
     if launch == "graphs":
         ctx.use_graphs(True)
+    if not persistent:
+        ctx.use_persistent(False)
     print(f"[bench] workload {workload}: {case.n_fluid} fluid + {case.n_wall} wall particles, "
           f"workspace {ctx.nbytes / 1e6:.1f} MB", file=sys.stderr, flush=True)
     warm = ctx.step(warmup) if warmup else []
     tuned = None
-    if warmup and autotune:
+    if variant >= 0:
+        ctx.variant = variant
+        tuned = {"variant": variant, "forced": True}
+    elif warmup and autotune:
         # the project's autotuner picks the sweep launch variant on the live
         # state (outside the timed region; variants change speed only)
         best, us = ctx.autotune(20)
@@ -413,9 +432,14 @@ def main():
     ap.add_argument("--compare-dx", type=float, default=0.01)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default sweep variant instead of autotuning it after the warmup")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="launch the main workload's sweeps with this variant instead of autotuning "
+                         "(counter runs that must replay the benchmark's kernel)")
     ap.add_argument("--launch", choices=("eager", "graphs"), default="eager",
                     help="launch the fixed parts of each step one kernel at a time, or replay them "
                          "from HIP graphs")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="solve wall-less cases with per-sweep launches instead of one persistent launch")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a counter calibration "
                          "reference for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -442,7 +466,8 @@ def main():
         print(f"[bench] copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written",
               file=sys.stderr, flush=True)
         del src, dst
-    primary = measure(args.workload, args.steps, args.warmup, args.launch, not args.no_autotune)
+    primary = measure(args.workload, args.steps, args.warmup, args.launch, not args.no_autotune,
+                      not args.no_persistent, args.variant)
     line = {
         "metric": METRIC,
         "value": primary.pop("value"),
@@ -462,7 +487,7 @@ def main():
     if args.secondary != "none" and args.secondary != args.workload:
         print(f"[bench] secondary workload {args.secondary}", file=sys.stderr, flush=True)
         line["secondary"] = measure(args.secondary, args.secondary_steps, args.warmup, args.launch,
-                                    not args.no_autotune)
+                                    not args.no_autotune, not args.no_persistent)
     if not args.no_batch_compare:
         print("[bench] batched vs plain", file=sys.stderr, flush=True)
         line["batched_vs_plain"] = batched_vs_plain(args.batch_cases, args.batch_steps, seed=0)

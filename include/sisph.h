@@ -330,7 +330,7 @@ int32_t sisph_destroy(sisph_ctx *ctx);
  * *best and the mean launch time of every variant in us[] (microseconds,
  * SISPH_SWEEP_VARIANTS entries, nullable).  A batch launches its group with
  * the variant of its largest case. */
-enum { SISPH_SWEEP_VARIANTS = 6 };
+enum { SISPH_SWEEP_VARIANTS = 8 };
 int32_t sisph_autotune(sisph_ctx *ctx, int32_t reps, int32_t *best, double *us);
 int32_t sisph_set_variant(sisph_ctx *ctx, int32_t variant);
 int32_t sisph_get_variant(sisph_ctx *ctx);

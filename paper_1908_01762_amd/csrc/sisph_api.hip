@@ -41,10 +41,10 @@ struct sisph_ctx {
     int32_t variant;     // Jacobi-sweep launch variant
     bool use_graphs = false;
     bool use_persistent = true;                                // one-launch solves where they apply
-    int64_t persist_cap[3] = {-1, -1, -1};                     // per first-batch size, -1: not asked yet
+    int64_t persist_cap[kSweepFirstCount] = {-1, -1, -1, -1};                     // per first-batch size, -1: not asked yet
     int64_t persist_solves = 0;                                // since the counter reset
     int64_t persist_refused = 0, persist_timeouts = 0;         // fallbacks to per-launch sweeps
-    int32_t persist_refusals[3] = {0, 0, 0};                   // per first-batch size, until it is given up
+    int32_t persist_refusals[kSweepFirstCount] = {0, 0, 0, 0};                   // per first-batch size, until it is given up
     bool persist_last = false;
     // sweep-kernel timing (sisph_set_kernel_timing): one event pair per
     // sweep launch of a chunk, the wall pass left out
@@ -309,6 +309,7 @@ static Target single_target(sisph_ctx *ctx) {
     T.precision = ctx->P.precision;
     T.variant = ctx->variant;
     T.adaptive = ctx->P.adaptive_dt;
+    T.packed = ctx->P.packed;
     T.precheck = ctx->P.nf >= kPrecheckRows ? 1 : 0;
     T.solver = ctx->P.solver;
     T.null_space = ctx->P.null_space;
@@ -887,7 +888,7 @@ static bool persistent_ok(sisph_ctx *ctx) {
     const Params &P = ctx->P;
     if (!ctx->use_persistent || P.nw > 0 || P.solver != SISPH_JACOBI) return false;
     const int64_t nb = kind_blocks(P, K_FLUID);
-    int64_t &cap = ctx->persist_cap[ctx->T.variant % 3];
+    int64_t &cap = ctx->persist_cap[ctx->T.variant % kSweepFirstCount];
     if (cap < 0) cap = ppe_persistent_capacity(ctx->T);
     return nb >= 1 && nb <= cap;
 }
@@ -934,7 +935,8 @@ static int32_t ppe_run(sisph_ctx *ctx, int64_t predicted, int64_t limit) {
         // tried again on later solves, up to kPersistRetries refusals
         (void)hipGetLastError();
         ctx->persist_refused += 1;
-        if (++ctx->persist_refusals[ctx->T.variant % 3] >= kPersistRetries) ctx->persist_cap[ctx->T.variant % 3] = 0;
+        const int fi = ctx->T.variant % kSweepFirstCount;
+        if (++ctx->persist_refusals[fi] >= kPersistRetries) ctx->persist_cap[fi] = 0;
     }
     auto poll = [&](bool &done) -> int32_t {
         int32_t st = read_ctl(ctx);
@@ -1468,6 +1470,7 @@ static int32_t rebuild_group(sisph_batch *b, Group &g) {
     T.s = b->stream;
     for (auto *c : g.members) {
         T.adaptive |= c->P.adaptive_dt;
+        T.packed |= c->P.packed;
         T.null_space |= c->P.null_space;
     }
     T.precheck = 1;

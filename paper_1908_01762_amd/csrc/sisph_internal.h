@@ -176,6 +176,7 @@ struct Target {
     int32_t dim, kernel, precision;
     int32_t variant;                 // Jacobi-sweep variant (speed only)
     int32_t adaptive;                // some case chooses its next dt
+    int32_t packed;                  // some case stores packed neighbour codes
     // the sweep tests the stop flag before its other loads: batches (cases
     // stop at different counts) and large cases (a launch beyond the stop
     // would read every row), see precheck_for()
@@ -227,8 +228,11 @@ void sweep_only(const Target &T, int launch);
 void wall_pressure_iteration(const Target &T, int launch);
 // Fluid rows from which a single case's sweep tests the stop flag first.
 constexpr int64_t kPrecheckRows = int64_t(1) << 19;
-constexpr int kSweepVariants = 6;
-constexpr int kDefaultVariant = 1;
+// Sweep launch variants: kSweepFirstCount first-batch sizes, each with
+// XCD-contiguous (v < kSweepFirstCount) or hardware workgroup order.
+constexpr int kSweepFirstCount = 4;
+constexpr int kSweepVariants = 2 * kSweepFirstCount;
+constexpr int kDefaultVariant = 2;   // 20 neighbours first, XCD-contiguous
 void settle_pressure(const Target &T);
 // The whole Jacobi solve of one wall-less case in one cooperative launch
 // (every workgroup resident); returns the launch's error.  The capacity is

@@ -660,10 +660,8 @@ __device__ __forceinline__ bool pack_code(uint32_t r, int64_t j, int64_t base, u
 template <int D>
 __device__ __forceinline__ void test_cell_global(const Params &P, const State &S, const Pos &x,
                                                  const int32_t *items, int64_t i, const double xi[3],
-                                                 int64_t cell, int &c, uint32_t rr, const int64_t (&pbase)[2],
-                                                 bool &pk_bad, bool &walls) {
+                                                 int64_t cell, int &c) {
     const int64_t nf = P.nf;
-    constexpr uint32_t NR = D == 3 ? 9 : 3;
     for (int pass = 0; pass < 2; ++pass) {
         const uint32_t *start = pass == 0 ? S.fstart : S.wstart;
         const uint32_t t0 = start[cell], t1 = start[cell + 1];
@@ -673,15 +671,7 @@ __device__ __forceinline__ void test_cell_global(const Params &P, const State &S
             double d[3] = {0, 0, 0};
             for (int k = 0; k < D; ++k) d[k] = min_image(xi[k] - x.c[k][j], P.grid, k);
             if (exact_r2<D>(d) < P.R2) {
-                if (c < P.cap) {
-                    S.nbr[(int64_t)c * nf + i] = (int32_t)j;
-                    if (P.packed) {
-                        uint16_t code;
-                        pk_bad |= !pack_code(rr + (pass ? NR : 0u), j, pbase[pass], code);
-                        S.pk16[(int64_t)c * nf + i] = code;
-                        walls |= pass == 1;
-                    }
-                }
+                if (c < P.cap) S.nbr[(int64_t)c * nf + i] = (int32_t)j;
                 ++c;
             }
         }
@@ -706,7 +696,6 @@ struct BuildFluid {
         int ci[3] = {0, 0, 0};
         Stencil st;
         int c = 1;
-        bool pk_bad = false, has_walls = false;
         if (live) {
             for (int k = 0; k < D; ++k) {
                 xi[k] = x.c[k][i];
@@ -772,24 +761,13 @@ struct BuildFluid {
                     sj[t] = (int32_t)j;
                 }
                 __syncthreads();
-                // packed codes: this row's range of the stencil row starts at its
-                // first cell (the cells along x are consecutive: x is not periodic)
-                const uint32_t rr = D == 3 ? (uint32_t)(a * 3 + b) : (uint32_t)b;
-                int64_t pbase[2] = {0, 0};
-                if (row_ok && P.packed) {
-                    int e0 = 0;
-                    while (e0 < 2 && !pick3(st.ok[0], e0)) ++e0;
-                    const int64_t c0 = row_base + pick3(st.v[0], e0);
-                    pbase[0] = (int64_t)S.fstart[c0];
-                    pbase[1] = nf + (int64_t)S.wstart[c0];
-                }
                 if (row_ok)
 #pragma unroll
                     for (int e = 0; e < 3; ++e) {
                         if (!st.ok[0][e]) continue;
                         const int64_t cell = row_base + st.v[0][e];
                         if (cell < s_lo || cell > s_hi) {
-                            test_cell_global<D>(P, S, x, items, i, xi, cell, c, rr, pbase, pk_bad, has_walls);
+                            test_cell_global<D>(P, S, x, items, i, xi, cell, c);
                             continue;
                         }
                         // fluid then walls of this cell, from the staged copy
@@ -804,16 +782,7 @@ struct BuildFluid {
                                 double d[3] = {0, 0, 0};
                                 for (int k = 0; k < D; ++k) d[k] = min_image(xi[k] - sx[k][t], g, k);
                                 if (exact_r2<D>(d) < P.R2) {
-                                    if (c < P.cap) {
-                                        S.nbr[(int64_t)c * nf + i] = (int32_t)j;
-                                        if (P.packed) {
-                                            uint16_t code;
-                                            pk_bad |= !pack_code(rr + (pass ? (D == 3 ? 9u : 3u) : 0u), j,
-                                                                 pbase[pass], code);
-                                            S.pk16[(int64_t)c * nf + i] = code;
-                                            has_walls |= pass == 1;
-                                        }
-                                    }
+                                    if (c < P.cap) S.nbr[(int64_t)c * nf + i] = (int32_t)j;
                                     ++c;
                                 }
                             }
@@ -827,11 +796,73 @@ struct BuildFluid {
             atomicMax(&S.ctl->maxcnt, c);
         }
         S.cnt[i] = c < P.cap ? c : P.cap;
-        if (P.packed && which == POS_XS) {
-            if (pk_bad) atomicOr(&S.ctl->pk_overflow, 1);
-            const uint32_t cell = (uint32_t)(((int64_t)ci[2] * g.nc[1] + ci[1]) * g.nc[0] + ci[0]);
-            S.rcell[i] = cell | (has_walls ? kRcellWalls : 0u);
+    }
+};
+
+// Packed neighbour codes of the lists at r* (walled Jacobi cases whose x
+// axis is not periodic), one pass after the build: each list entry j
+// becomes the id of the row's stencil-row range that holds it (fluid ranges
+// 0 .. NR-1, wall ranges NR .. 2 NR-1) and its offset from that range's
+// first particle.  The three cells of a stencil row are consecutive in the
+// cell order, so a range is one index interval, and the ranges of a row
+// are in ascending order (a list visits them in that order too): the range
+// of j is the last one starting at or below j.  Also the row's cell id with
+// a flag for rows with wall neighbours, read by the sweeps to find the
+// range starts.  The slot-major lists and codes are read and written
+// coalesced (the build's stores are scattered: each row finds its
+// neighbours at its own pace).
+template <int D>
+struct PackCodes {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        ROW;
+        const int64_t nf = P.nf;
+        if (!P.packed || i >= nf) return;   // (batched: the other cases of the group)
+        const Grid &g = P.grid;
+        const Pos x = mkpos(S.xs);
+        int ci[3] = {0, 0, 0};
+        for (int k = 0; k < D; ++k) ci[k] = cell_coord(x.c[k][i], g, k);
+        Stencil st;
+        make_stencil<D>(g, ci, st);
+        constexpr int na = D == 3 ? 3 : 1;
+        constexpr int NR = D == 3 ? 9 : 3;
+        int64_t fs[NR], ws[NR];
+        int e0 = 0;
+        while (e0 < 2 && !pick3(st.ok[0], e0)) ++e0;
+        const int x0 = pick3(st.v[0], e0);
+#pragma unroll
+        for (int a = 0; a < na; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const int r = D == 3 ? a * 3 + b : b;
+                fs[r] = ws[r] = INT64_MAX;   // a stencil row outside the grid holds nothing
+                if (!(pick3(st.ok[2], a) && pick3(st.ok[1], b))) continue;
+                const int64_t c0 = ((int64_t)pick3(st.v[2], a) * g.nc[1] + pick3(st.v[1], b)) * g.nc[0] + x0;
+                fs[r] = (int64_t)S.fstart[c0];
+                ws[r] = nf + (int64_t)S.wstart[c0];
+            }
+        const int cnt = S.cnt[i];
+        bool bad = false, walls = false;
+        for (int c = 1; c < cnt; ++c) {
+            const int64_t j = S.nbr[(int64_t)c * nf + i];
+            const bool w = j >= nf;
+            walls |= w;
+            uint32_t r = 0;
+            int64_t base = w ? ws[0] : fs[0];
+#pragma unroll
+            for (int k = 1; k < NR; ++k) {
+                const int64_t sk = w ? ws[k] : fs[k];
+                if (sk <= j) {
+                    r = (uint32_t)k;
+                    base = sk;
+                }
+            }
+            uint16_t code;
+            bad |= !pack_code(r + (w ? (uint32_t)NR : 0u), j, base, code);
+            S.pk16[(int64_t)c * nf + i] = code;
         }
+        if (bad) atomicOr(&S.ctl->pk_overflow, 1);
+        const uint32_t cell = (uint32_t)(((int64_t)ci[2] * g.nc[1] + ci[1]) * g.nc[0] + ci[0]);
+        S.rcell[i] = cell | (walls ? kRcellWalls : 0u);
     }
 };
 
@@ -1408,7 +1439,9 @@ struct CopyP32 {
 // trip.  Longer rows continue kSweepBatchGroups groups at a time.  The sum runs in slot order whatever
 // FIRST is, so FIRST (chosen by the autotuner among kSweepFirsts) and the
 // workgroup mapping change the speed only, never the result.
-constexpr int kSweepFirsts[3] = {16, 20, 24};   // neighbours in the first round trip (multiples of 4)
+// neighbours in the first round trip (multiples of 4); the persistent solve,
+// which holds them in registers for the whole solve, takes at least 16
+constexpr int kSweepFirsts[kSweepFirstCount] = {8, 16, 20, 24};
 constexpr int kSweepBatchGroups = 2;
 constexpr int kPartialRegs = 4;   // partial sums per thread in the first pass (1024 workgroups)
 
@@ -3020,6 +3053,8 @@ void bin_walls_once(const Target &T) {
 void build_neighbors(const Target &T, int which) {
     SISPH_DISPATCH_D(T, (launch<BuildFluid<D>, K_FLUID>(T, which)));
     SISPH_DISPATCH_D(T, (launch<BuildWall<D>, K_WALL>(T, which)));
+    // the sweeps read the lists at r* only
+    if (which == POS_XS && T.packed) SISPH_DISPATCH_D(T, (launch<PackCodes<D>, K_FLUID>(T)));
 }
 
 void wall_normals(const Target &T) {
@@ -3044,17 +3079,20 @@ void project_rhs(const Target &T) {
 
 void copy_p32(const Target &T) { launch<CopyP32, K_TOT>(T); }
 
-// Sweep variants (numerically identical): first-batch size kSweepFirsts[v % 3],
-// XCD-contiguous workgroup mapping for v < 3, hardware order otherwise.
+// Sweep variants (numerically identical): first-batch size
+// kSweepFirsts[v % kSweepFirstCount], XCD-contiguous workgroup mapping for
+// v < kSweepFirstCount, hardware order otherwise.
 template <typename R, bool PRE>
 static void sweep_variant(const Target &T, int L, int v) {
-    // v = 3 * (hardware workgroup order) + index of FIRST in kSweepFirsts
+    static_assert(kSweepFirstCount == 4 && kSweepVariants == 8, "one case per variant");
     switch (v) {
     case 1: launch<Sweep<R, kSweepFirsts[1], PRE>, K_FLUID, true>(T, L); break;
     case 2: launch<Sweep<R, kSweepFirsts[2], PRE>, K_FLUID, true>(T, L); break;
-    case 3: launch<Sweep<R, kSweepFirsts[0], PRE>, K_FLUID, false>(T, L); break;
-    case 4: launch<Sweep<R, kSweepFirsts[1], PRE>, K_FLUID, false>(T, L); break;
-    case 5: launch<Sweep<R, kSweepFirsts[2], PRE>, K_FLUID, false>(T, L); break;
+    case 3: launch<Sweep<R, kSweepFirsts[3], PRE>, K_FLUID, true>(T, L); break;
+    case 4: launch<Sweep<R, kSweepFirsts[0], PRE>, K_FLUID, false>(T, L); break;
+    case 5: launch<Sweep<R, kSweepFirsts[1], PRE>, K_FLUID, false>(T, L); break;
+    case 6: launch<Sweep<R, kSweepFirsts[2], PRE>, K_FLUID, false>(T, L); break;
+    case 7: launch<Sweep<R, kSweepFirsts[3], PRE>, K_FLUID, false>(T, L); break;
     default: launch<Sweep<R, kSweepFirsts[0], PRE>, K_FLUID, true>(T, L); break;
     }
 }
@@ -3093,13 +3131,13 @@ static int64_t persistent_capacity() {
 
 #define SISPH_PERSISTENT_FIRST(T, CALL)                                       \
     do {                                                                      \
-        const int first = kSweepFirsts[(T).variant % 3];                      \
+        const int first = kSweepFirsts[(T).variant % kSweepFirstCount];       \
         if (f32_sums((T).precision)) {                                        \
-            if (first == 16) { using R = float; constexpr int F = 16; CALL; } \
+            if (first <= 16) { using R = float; constexpr int F = 16; CALL; } \
             else if (first == 20) { using R = float; constexpr int F = 20; CALL; } \
             else { using R = float; constexpr int F = 24; CALL; }            \
         } else {                                                              \
-            if (first == 16) { using R = double; constexpr int F = 16; CALL; } \
+            if (first <= 16) { using R = double; constexpr int F = 16; CALL; } \
             else if (first == 20) { using R = double; constexpr int F = 20; CALL; } \
             else { using R = double; constexpr int F = 24; CALL; }           \
         }                                                                     \

@@ -18,7 +18,7 @@ from . import cases as _cases
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsisph.so")
 
-SWEEP_VARIANTS = 6
+SWEEP_VARIANTS = 8
 STATIC_WORKSPACE_BYTES = 64 << 20
 OK, WARN_MAXITER = 0, 1
 E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_NONFINITE = -1, -2, -3, -4, -5
