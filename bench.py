@@ -37,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "PPE particle-iters/s + HBM GB/s frac; batched vs plain at equal tol; p99 step"
+KT_PERIOD = 8   # sweep launches per timed launch in walled cases
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
@@ -327,7 +328,11 @@ def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool,
         best, us = ctx.autotune(20)
         tuned = {"variant": best, "us_per_variant": [round(t, 3) for t in us]}
         print(f"[bench] autotuned sweep variant {best}", file=sys.stderr, flush=True)
-    ctx.set_kernel_timing(True)
+    # every sweep launch of a walled case timed by its own event pair would
+    # slow the run it measures (a few us per pair): there every KT_PERIOD-th
+    # launch of a solve is timed, and the per-launch average stands for all
+    period = KT_PERIOD if case.n_wall else 1
+    ctx.set_kernel_timing(period)
     torch.cuda.synchronize()
     ctx.sweep_counters(reset=True)
     t0 = time.perf_counter()
@@ -352,15 +357,21 @@ def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool,
     # the dominant kernel: the sweep, one launch per sweep, or one persistent
     # launch per solve holding its sweeps; both are timed by their own events
     n_persistent = kt["persistent"]
-    n_perlaunch = kt["launches"] - n_persistent
+    # every launch when each is timed; else (walled cases: per-sweep
+    # launches only) the sweep counter's launches
+    all_launches = kt["launches"] if period == 1 else cnt["launches"]
+    n_perlaunch = all_launches - n_persistent
     if n_persistent and n_perlaunch:
         mode = "mixed"
     elif n_persistent:
         mode = "persistent"
     else:
         mode = "per-sweep launches"
-    kernel_s = kt["ms"] / 1e3
-    launches = kt["launches"]
+    timed = kt["launches"]
+    avg_launch_s = kt["ms"] / 1e3 / max(timed, 1)
+    # the sampled average over every launch (exact when period is 1)
+    kernel_s = kt["ms"] / 1e3 if period == 1 else avg_launch_s * all_launches
+    launches = all_launches
     eff = cnt["effective"]
     alg_per_sweep = unit * case.n_fluid
     achieved = alg_per_sweep * eff / kernel_s / 1e9 if kernel_s > 0 else 0.0
@@ -375,7 +386,8 @@ def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool,
                 "algorithmic_bytes_per_particle_iter": unit,
                 "algorithmic_bytes_per_sweep": alg_per_sweep,
                 "algorithmic_bytes_per_launch": int(round(alg_per_sweep * eff / max(launches, 1))),
-                "avg_launch_us": round(kernel_s * 1e6 / max(launches, 1), 3), "launches": launches,
+                "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches": launches,
+                "timed_launches": timed, "timing_period": period,
                 "persistent_launches": n_persistent, "per_sweep_launches": n_perlaunch,
                 "effective_sweeps": eff,
                 "avg_us_per_effective_sweep": round(kernel_s * 1e6 / max(eff, 1), 3),
@@ -389,8 +401,8 @@ def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool,
         # sweep kernel: its share of the chunk time and its own bytes
         roofline["wall_pass"] = {"rows": sb["wall_rows"], "pairs": sb["wall_pairs"],
                                  "bytes_per_row": sb["per_wall_row"], "bytes_per_pair": sb["per_wall_pair"],
-                                 "us_per_sweep": round((cnt["sweep_ms"] - kt["ms"]) * 1e3 / max(cnt["launches"], 1),
-                                                       3)}
+                                 "us_per_sweep": round((cnt["sweep_ms"] - kernel_s * 1e3) * 1e3 /
+                                                       max(cnt["launches"], 1), 3)}
     out = {
         "value": value,
         "ms_per_step": elapsed * 1e3 / max(steps, 1),

@@ -264,16 +264,19 @@ int32_t sisph_last_timings(sisph_ctx *ctx, double *ppe_ms, double *step_ms);
 int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_t *launches,
                              int64_t *effective, int32_t reset);
 
-/* Timing of the Jacobi sweep kernel alone.  With on != 0 every sweep
- * launch of a single context is bracketed by its own pair of HIP events on
- * the context's stream (the wall pressure pass before it is left out; a
- * persistent solve's one launch is timed whole), from a pool of
- * 2 (max_iter + 1) events created here; on = 0 frees the pool.  Off by
- * default.  sisph_kernel_timing returns, accumulated since the last reset of
- * sisph_sweep_counters, the summed kernel time in milliseconds, the number
- * of timed launches (launches past a solve's stop included) and how many of
- * them were persistent solves.  Any pointer may be NULL. */
-int32_t sisph_set_kernel_timing(sisph_ctx *ctx, int32_t on);
+/* Timing of the Jacobi sweep kernel alone.  With period > 0 every
+ * period-th sweep launch of each solve of a single context (launches 0,
+ * period, 2 period, ... of the solve; 1: every launch) is bracketed by its
+ * own pair of HIP events on the context's stream (the wall pressure pass
+ * before it is left out; a persistent solve's one launch is timed whole),
+ * from a pool of 2 (max_iter + 1) events created here; period <= 0 frees
+ * the pool.  Off by default.  An event pair costs the stream a few
+ * microseconds, so sampling keeps the timed run's pace.
+ * sisph_kernel_timing returns, accumulated since the last reset of
+ * sisph_sweep_counters, the summed kernel time of the timed launches in
+ * milliseconds, their number (launches past a solve's stop included) and
+ * how many of them were persistent solves.  Any pointer may be NULL. */
+int32_t sisph_set_kernel_timing(sisph_ctx *ctx, int32_t period);
 int32_t sisph_kernel_timing(sisph_ctx *ctx, double *ms, int64_t *launches, int64_t *persistent);
 
 /* Persistent solves (see sisph_set_persistent) since the last counter reset

@@ -44,11 +44,12 @@ struct sisph_ctx {
     int64_t persist_cap[kSweepFirstCount] = {-1, -1, -1, -1};                     // per first-batch size, -1: not asked yet
     int64_t persist_solves = 0;                                // since the counter reset
     int64_t persist_refused = 0, persist_timeouts = 0;         // fallbacks to per-launch sweeps
-    int32_t persist_refusals[kSweepFirstCount] = {0, 0, 0, 0};                   // per first-batch size, until it is given up
+    int32_t persist_refusals[kSweepFirstCount] = {0, 0, 0, 0};   // per first-batch size, until it is given up
     bool persist_last = false;
     // sweep-kernel timing (sisph_set_kernel_timing): one event pair per
-    // sweep launch of a chunk, the wall pass left out
+    // kt_period-th sweep launch of a chunk, the wall pass left out
     std::vector<hipEvent_t> kev;
+    int32_t kt_period = 1;
     double kt_ms = 0.0;
     int64_t kt_launches = 0, kt_persistent = 0;
     bool is_static = false;                                    // lives in a device's static slot
@@ -230,8 +231,8 @@ static void carve(const Params &P, Carver &c, State &S) {
     vec(S.xs, nt);
     vec(S.us, nt);
     vec(S.un, nf);
-    vec(S.xk[0], nt);
-    vec(S.xk[1], nt);
+    S.gk[0] = c.take<double4>(nt);
+    S.gk[1] = c.take<double4>(nt);
     vec(S.vk, nf);
     vec(S.nrm, nw);
     vec(S.wallu, nw);
@@ -461,11 +462,7 @@ static int32_t init_state(sisph_ctx *ctx, const sisph_case_desc *desc, const dou
         fill_f64(S.p[1] + nf, 0.0, nw, s);
         for (int k = 0; k < D; ++k) {
             if (hipMemcpyAsync(S.xs[k] + nf, S.x[k] + nf, sizeof(double) * nw, hipMemcpyDeviceToDevice, s) !=
-                    hipSuccess ||
-                hipMemcpyAsync(S.xk[0][k] + nf, S.x[k] + nf, sizeof(double) * nw, hipMemcpyDeviceToDevice, s) !=
-                    hipSuccess ||
-                hipMemcpyAsync(S.xk[1][k] + nf, S.x[k] + nf, sizeof(double) * nw, hipMemcpyDeviceToDevice, s) !=
-                    hipSuccess) {
+                hipSuccess) {
                 ctx->err = "wall copy failed";
                 return fail_create(SISPH_E_DEVICE);
             }
@@ -721,6 +718,7 @@ static void seq_correct(const Target &T, int maxK) {
         step_maxima(T);   // before the GTVF sub-steps reuse the acceleration buffer
         next_dt(T);
     }
+    if (maxK > 0) gtvf_seed(T);
     for (int k = 0; k < maxK; ++k) gtvf_substep(T, k);
     advance(T);
 }
@@ -818,10 +816,11 @@ static void record_iters(sisph_ctx *ctx, int iters) {
 // (up to the pool's size) between its own pair of events, read after the
 // chunk's poll.
 struct KTimer {
-    hipEvent_t *ev;      // 2 per launch
-    int64_t cap;         // launches the pool covers
+    hipEvent_t *ev;      // 2 per timed launch
+    int64_t cap;         // timed launches the pool covers
     double *ms;
     int64_t *launches;
+    int32_t period;      // every period-th launch of a solve (0, period, 2 period, ...)
 };
 
 template <class Poll>
@@ -835,7 +834,7 @@ static int32_t ppe_loop(const Target &T, int64_t predicted, int64_t limit, hipEv
         if (ev_record(e0, T.s) != hipSuccess) return SISPH_E_DEVICE;
         int64_t timed = 0;
         for (int64_t c = 0; c < chunk; ++c) {
-            if (kt && timed < kt->cap && T.solver == SISPH_JACOBI) {
+            if (kt && timed < kt->cap && T.solver == SISPH_JACOBI && (launched + c) % kt->period == 0) {
                 wall_pressure_iteration(T, (int)(launched + c));
                 if (hipEventRecord(kt->ev[2 * timed], T.s) != hipSuccess) return SISPH_E_DEVICE;
                 sweep_only(T, (int)(launched + c));
@@ -944,7 +943,7 @@ static int32_t ppe_run(sisph_ctx *ctx, int64_t predicted, int64_t limit) {
         done = ctx->h_ctl->done != 0;
         return SISPH_OK;
     };
-    KTimer kt{ctx->kev.data(), (int64_t)ctx->kev.size() / 2, &ctx->kt_ms, &ctx->kt_launches};
+    KTimer kt{ctx->kev.data(), (int64_t)ctx->kev.size() / 2, &ctx->kt_ms, &ctx->kt_launches, ctx->kt_period};
     return ppe_loop(ctx->T, predicted, limit, ctx->evc[0], ctx->evc[1], ctx->sweep_ms, ctx->sweep_launches, poll,
                     ctx->err, ctx->kev.empty() ? nullptr : &kt);
 }
@@ -1313,14 +1312,15 @@ extern "C" int32_t sisph_sweep_counters(sisph_ctx *ctx, double *sweep_ms, int64_
     return SISPH_OK;
 }
 
-extern "C" int32_t sisph_set_kernel_timing(sisph_ctx *ctx, int32_t on) {
+extern "C" int32_t sisph_set_kernel_timing(sisph_ctx *ctx, int32_t period) {
     if (!ctx) return SISPH_E_INVAL;
-    if (!on) {
+    if (period <= 0) {
         for (auto &e : ctx->kev) (void)hipEventDestroy(e);
         ctx->kev.clear();
         return SISPH_OK;
     }
     if (ctx->is_static) return fail(ctx, SISPH_E_STATE, "a context in the static workspace creates no events");
+    ctx->kt_period = period;
     if (!ctx->kev.empty()) return SISPH_OK;
     // one pair per launch a chunk can hold: max_iter + 1 (or forced_iters + 1)
     const int64_t n = 2 * ((int64_t)(ctx->P.forced_iters > 0 ? ctx->P.forced_iters : ctx->P.max_iter) + 1);

@@ -86,7 +86,9 @@ struct State {
     double *xs[3];     // r*                         [ntot]
     double *us[3];     // u* fluid, wall slip u*     [ntot]
     double *un[3];     // u^{n+1}                    [nf]
-    double *xk[2][3];  // GTVF sub-step positions    [ntot] x2
+    // GTVF sub-step records {x, y, z, m/rho^2}: one 32-byte gather per
+    // neighbour; the seed (r*) in gk[1], sub-step k writes gk[k & 1]
+    double4 *gk[2];    // [ntot] x2
     double *vk[3];     // GTVF sub-step velocity     [nf]; before the sub-steps,
                        // the step's total acceleration (adaptive dt)
     double *nrm[3];    // wall unit normals          [nw]
@@ -264,6 +266,7 @@ void step_maxima(const Target &T);
 void next_dt(const Target &T);
 void gtvf_substep(const Target &T, int k);
 void advance(const Target &T);
+void gtvf_seed(const Target &T);
 void gather_control(const Target &T, Control *out);
 
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);

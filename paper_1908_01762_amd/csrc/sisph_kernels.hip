@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
+#include <type_traits>
 
 #include "sisph_internal.h"
 
@@ -314,8 +315,20 @@ __device__ __forceinline__ int64_t logical_block() {
     else return (int64_t)blockIdx.x;
 }
 
+// A body may ask for a minimum occupancy (waves per SIMD) with a
+// kMinWaves member; the compiler then caps its registers to fit.
+template <class F, class = void>
+struct MinWaves {
+    static constexpr int value = 1;
+};
+template <class F>
+struct MinWaves<F, std::void_t<decltype(F::kMinWaves)>> {
+    static constexpr int value = F::kMinWaves;
+};
+
 template <class F, bool XCD, class... A>
-__global__ __launch_bounds__(kBlock) void k_one(const Params P, const State S, A... a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MinWaves<F>::value))) void k_one(
+    const Params P, const State S, A... a) {
     F::run(P, S, logical_block<XCD>(), (int64_t)gridDim.x, 0, a...);
 }
 
@@ -1497,12 +1510,28 @@ __device__ __forceinline__ void resolve_groups(int64_t i, int64_t nf, int g0, in
 // cells' first rows into sfs; a row then finds its cell by a binary search
 // of sfs.  Returns the number of cells, 0 (nothing written) when they are
 // more than kPackCells.  Every thread of the workgroup calls it.
+//
+// When the grid is periodic in no direction, the iterate values every row
+// of the workgroup can gather are also staged in LDS (sp): for each
+// stencil row (dy, dz), the cells of the workgroup's cells shifted by
+// (dy, dz) and widened by one along x form one cell-id interval, so its
+// fluid particles are one index interval, and so are its wall particles.
+// The 2 NR intervals are copied one after the other into sp, and the table
+// then holds each range's position in sp instead of its global start: a
+// code (range, offset) indexes sp directly.  A row's range lies inside its
+// interval (its three cells do), so every code of the workgroup resolves
+// into the staged copy.  *staged tells which form the table holds; it is
+// not staged when the intervals hold more than kStageBytes of values.
 constexpr int kPackCells = 64;
+constexpr int kStageBytes = 16384;
 
-template <int D>
+template <int D, typename R>
 __device__ __forceinline__ int pack_table(const Params &P, const State &S, int64_t blk, int32_t *tbl,
-                                          uint32_t *sfs) {
+                                          uint32_t *sfs, const R *q, R *sp, bool &staged) {
+    constexpr int NR = D == 3 ? 9 : 3;
     __shared__ uint32_t span[2];
+    __shared__ int64_t seg_base[2 * NR];   // global index of each interval's first particle
+    __shared__ int32_t seg_pos[2 * NR + 1];
     const int64_t nf = P.nf, r0 = blk * kBlock;
     const int64_t r1 = (r0 + kBlock < nf ? r0 + kBlock : nf) - 1;
     if (threadIdx.x == 0) {
@@ -1512,10 +1541,38 @@ __device__ __forceinline__ int pack_table(const Params &P, const State &S, int64
     __syncthreads();
     const uint32_t cf = span[0];
     const int ncl = (int)(span[1] - cf) + 1;
+    staged = false;
     if (ncl > kPackCells) return 0;
     const Grid &g = P.grid;
-    constexpr int NR = D == 3 ? 9 : 3;
     const uint32_t nx = (uint32_t)g.nc[0], ny = (uint32_t)g.nc[1];
+    const bool can_stage = !g.per[0] && !g.per[1] && (D == 2 || !g.per[2]);
+    if (can_stage) {
+        if (threadIdx.x < 2 * NR) {
+            const int r = (int)threadIdx.x % NR;
+            const bool wall = (int)threadIdx.x >= NR;
+            const int64_t dz = D == 3 ? r / 3 - 1 : 0, dy = D == 3 ? r % 3 - 1 : r - 1;
+            const int64_t off = (dz * (int64_t)ny + dy) * (int64_t)nx;
+            int64_t lo = (int64_t)cf + off - 1, hi = (int64_t)span[1] + off + 1;
+            lo = lo < 0 ? 0 : lo;
+            hi = hi > g.ncell - 1 ? g.ncell - 1 : hi;
+            int64_t b = 0, n = 0;
+            if (lo <= hi) {
+                const uint32_t *st = wall ? S.wstart : S.fstart;
+                b = (int64_t)st[lo];
+                n = (int64_t)st[hi + 1] - b;
+                if (wall) b += nf;
+            }
+            seg_base[threadIdx.x] = b;
+            seg_pos[threadIdx.x + 1] = (int32_t)n;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            seg_pos[0] = 0;
+            for (int e = 1; e <= 2 * NR; ++e) seg_pos[e] += seg_pos[e - 1];
+        }
+        __syncthreads();
+        staged = seg_pos[2 * NR] <= kStageBytes / (int)sizeof(R);
+    }
     for (int e = threadIdx.x; e < ncl * NR; e += kBlock) {
         const int k = e / NR, r = e - k * NR;
         const uint32_t cell = cf + (uint32_t)k;
@@ -1528,8 +1585,22 @@ __device__ __forceinline__ int pack_table(const Params &P, const State &S, int64
         while (e0 < 2 && !pick3(st.ok[0], e0)) ++e0;
         const int64_t c0 =
             ((int64_t)pick3(st.v[2], a) * g.nc[1] + pick3(st.v[1], b)) * g.nc[0] + pick3(st.v[0], e0);
-        tbl[k * (int)kPackRanges + r] = (int32_t)S.fstart[c0];
-        tbl[k * (int)kPackRanges + NR + r] = (int32_t)(nf + (int64_t)S.wstart[c0]);
+        const int64_t fs0 = (int64_t)S.fstart[c0], ws0 = nf + (int64_t)S.wstart[c0];
+        if (staged) {
+            tbl[k * (int)kPackRanges + r] = seg_pos[r] + (int32_t)(fs0 - seg_base[r]);
+            tbl[k * (int)kPackRanges + NR + r] = seg_pos[NR + r] + (int32_t)(ws0 - seg_base[NR + r]);
+        } else {
+            tbl[k * (int)kPackRanges + r] = (int32_t)fs0;
+            tbl[k * (int)kPackRanges + NR + r] = (int32_t)ws0;
+        }
+    }
+    if (staged) {
+        const int total = seg_pos[2 * NR];
+        for (int e = threadIdx.x; e < total; e += kBlock) {
+            int sg = 0;
+            while (e >= seg_pos[sg + 1]) ++sg;
+            sp[e] = q[seg_base[sg] + (e - seg_pos[sg])];
+        }
     }
     for (int e = threadIdx.x; e <= ncl; e += kBlock) sfs[e] = S.fstart[cf + (uint32_t)e];
     __syncthreads();
@@ -1578,19 +1649,25 @@ __device__ __forceinline__ int32_t iget(const int4 &v, int q) {
 }
 
 // Gathered iterate values of the groups' positions (the row's own value
-// for positions at or past npos).
+// for positions at or past npos); from the workgroup's staged copy sp when
+// there is one (its indices are positions in sp; positions past npos read
+// nothing and get 0).
+template <typename R>
+__device__ __forceinline__ R gather_one(int p, int npos, int32_t j, int64_t i, const double *pc, const float *qc,
+                                        const R *sp) {
+    if (sp) return p < npos ? sp[j] : R(0);
+    const int32_t jj = p < npos ? j : (int32_t)i;
+    if constexpr (sizeof(R) == 4) return qc[jj];
+    else return pc[jj];
+}
+
 template <typename R, int NG>
 __device__ __forceinline__ void issue_gathers(int64_t i, int g0, int npos, const int4 (&jj)[NG], const double *pc,
-                                              const float *qc, R (&pv)[NG][4]) {
+                                              const float *qc, R (&pv)[NG][4], const R *sp = nullptr) {
 #pragma unroll
     for (int t = 0; t < NG; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int p = (g0 + t) * 4 + q;
-            const int32_t j = p < npos ? iget(jj[t], q) : (int32_t)i;
-            if constexpr (sizeof(R) == 4) pv[t][q] = qc[j];
-            else pv[t][q] = pc[j];
-        }
+        for (int q = 0; q < 4; ++q) pv[t][q] = gather_one<R>((g0 + t) * 4 + q, npos, iget(jj[t], q), i, pc, qc, sp);
 }
 
 template <typename R, int NG>
@@ -1609,17 +1686,13 @@ __device__ __forceinline__ R sum_gathers(int g0, int npos, const typename Vec4<R
 // sum over positions p < npos of the groups, in position (= slot) order
 template <typename R, int NG>
 __device__ __forceinline__ R gather_groups(int64_t i, int g0, int npos, const typename Vec4<R>::T (&cc)[NG],
-                                           const int4 (&jj)[NG], const double *pc, const float *qc, R s) {
+                                           const int4 (&jj)[NG], const double *pc, const float *qc, R s,
+                                           const R *sp = nullptr) {
     R pv[NG][4];
 #pragma unroll
     for (int t = 0; t < NG; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int p = (g0 + t) * 4 + q;
-            const int32_t j = p < npos ? iget(jj[t], q) : (int32_t)i;
-            if constexpr (sizeof(R) == 4) pv[t][q] = qc[j];
-            else pv[t][q] = pc[j];
-        }
+        for (int q = 0; q < 4; ++q) pv[t][q] = gather_one<R>((g0 + t) * 4 + q, npos, iget(jj[t], q), i, pc, qc, sp);
 #pragma unroll
     for (int t = 0; t < NG; ++t)
 #pragma unroll
@@ -1766,6 +1839,9 @@ __device__ __forceinline__ void residual_partials(const Params &P, bool live, do
 
 template <typename R, int FIRST, bool PRECHECK>
 struct Sweep {
+    // the gathers' latency is hidden by other waves: the smallest first
+    // batch is built to run eight waves per SIMD
+    static constexpr int kMinWaves = FIRST <= 8 ? 8 : 1;
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int L) {
         Control *ctl = S.ctl;
         // PRECHECK: a finished solve is detected before any other load (one
@@ -1802,14 +1878,27 @@ struct Sweep {
         ROW;
         const bool live = i < nf;
         // packed codes: the range starts of the workgroup's cells in a shared
-        // table, or, when its rows span too many cells, per row in its own
-        // LDS column
-        __shared__ int32_t pbt[kPackRanges * kBlock];
+        // table (and the iterate values they reach staged after it), or,
+        // when its rows span too many cells, per row in its own LDS column
+        constexpr int kTableBytes = kPackCells * kPackRanges * 4;
+        constexpr int kColumnBytes = kPackRanges * kBlock * 4;
+        __shared__ __align__(16) unsigned char lds[kTableBytes + kStageBytes > kColumnBytes
+                                                       ? kTableBytes + kStageBytes
+                                                       : kColumnBytes];
         __shared__ uint32_t sfs[kPackCells + 1];
+        int32_t *pbt = (int32_t *)lds;
+        R *stage = (R *)(lds + kTableBytes);
+        const R *sp = nullptr;
         const int32_t *pb = nullptr;
         int pstride = 1;
         if (packed && !wide_flag) {
-            const int ncl = P.dim == 3 ? pack_table<3>(P, S, blk, pbt, sfs) : pack_table<2>(P, S, blk, pbt, sfs);
+            const R *qsrc;
+            if constexpr (sizeof(R) == 4) qsrc = qc;
+            else qsrc = pc;
+            bool staged = false;
+            const int ncl = P.dim == 3 ? pack_table<3, R>(P, S, blk, pbt, sfs, qsrc, stage, staged)
+                                       : pack_table<2, R>(P, S, blk, pbt, sfs, qsrc, stage, staged);
+            if (staged) sp = stage;
             if (ncl > 0) {
                 int lo = 0, hi = ncl - 1;   // the last cell whose first row is <= i
                 while (lo < hi) {
@@ -1849,7 +1938,7 @@ struct Sweep {
         R pv[NG][4];
         if (live) {
             if (offs) resolve_groups<NG>(i, nf, 0, npos, S.nbr, wide_flag != 0, oo, jj, pb, pstride);
-            issue_gathers<R, NG>(i, 0, npos, jj, pc, qc, pv);
+            issue_gathers<R, NG>(i, 0, npos, jj, pc, qc, pv, sp);
         }
         // (a solve that stopped earlier returned above: its partials are stale)
         if (decides) {
@@ -1865,7 +1954,7 @@ struct Sweep {
                 load_groups<R, kSweepBatchGroups>(i, nf, g0, gmax, S.coef, S.cidx, offs, cb, jb, ob);
                 if (offs) resolve_groups<kSweepBatchGroups>(i, nf, g0, npos, S.nbr, wide_flag != 0, ob, jb, pb,
                                                             pstride);
-                s = gather_groups<R, kSweepBatchGroups>(i, g0, npos, cb, jb, pc, qc, s);
+                s = gather_groups<R, kSweepBatchGroups>(i, g0, npos, cb, jb, pc, qc, s, sp);
             }
             if (D != 0.0 && !f) v = psor<R>(P, r, s, D, pold);
         }
@@ -2543,6 +2632,23 @@ struct MassOverRho2 {
 };
 
 // --------------------------------------------------------- GTVF sub-steps
+// The sub-steps gather a neighbour's position and m/rho^2 as one 32-byte
+// record (two 16-byte loads instead of D + 1 scattered ones): the seed
+// record of every particle at r* goes into gk[1], walls also into gk[0]
+// (they never move); sub-step k reads gk[(k + 1) & 1] and writes its fluid
+// rows into gk[k & 1].
+template <typename R>
+struct GtvfSeed {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        ROW;
+        if (i >= P.ntot || P.gtvf_K <= 0) return;
+        const double4 r = make_double4(S.xs[0][i], P.dim > 1 ? S.xs[1][i] : 0.0, P.dim > 2 ? S.xs[2][i] : 0.0,
+                                       (double)((const R *)S.mr2)[i]);
+        S.gk[1][i] = r;
+        if (i >= P.nf) S.gk[0][i] = r;
+    }
+};
+
 // f = -p0_i sum_j m_j / rho_j^2 grad_i W(r_ij^{k-1}, h~) on the frozen r*
 // neighbour lists (eq. mom:sph:gtvf), walls fixed;
 // r^k = r^{k-1} + dtau u~^{k-1} + dtau^2/2 f, u~^k = u~^{k-1} + dtau f
@@ -2555,10 +2661,10 @@ struct Gtvf {
         const bool ext = P.gtvf == SISPH_GTVF_EXTERNAL;
         Kern<KER, D, R> K(ext ? 0.5 * P.h : P.h);
         const int64_t nf = P.nf;
-        const Pos xsrc = mkpos(k == 0 ? S.xs : S.xk[(k - 1) & 1]);
-        double *const *xdst = S.xk[k & 1];
-        double xi[3] = {0, 0, 0};
-        for (int a = 0; a < D; ++a) xi[a] = xsrc.c[a][i];
+        const double4 *src = S.gk[(k + 1) & 1];
+        double4 *dst = S.gk[k & 1];
+        const double4 own = src[i];
+        const double xi[3] = {own.x, own.y, own.z};
         const double pref = S.ctl->p_ref;
         double p0 = pref;
         if (ext) {
@@ -2569,36 +2675,37 @@ struct Gtvf {
         const int c = S.cnt[i];
         for (int k0 = 1; k0 < c; k0 += kPairBatch) {
             int64_t jb[kPairBatch];
-            double xj[kPairBatch][3];
-            R mr[kPairBatch];
+            double4 rb[kPairBatch];
             batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
-            batch_pos<D>(xsrc, jb, xj);
 #pragma unroll
-            for (int t = 0; t < kPairBatch; ++t) mr[t] = ((const R *)S.mr2)[jb[t]];
+            for (int t = 0; t < kPairBatch; ++t) rb[t] = src[jb[t]];
 #pragma unroll
             for (int t = 0; t < kPairBatch; ++t) {
                 if (k0 + t >= c) break;
+                const double xj[3] = {rb[t].x, rb[t].y, rb[t].z};
                 R d[3], r2;
-                pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
+                pair_diff_v<D, R>(P.grid, xi, xj, d, r2);
                 const R dw = K.dwr(sqrt(r2));
-                const R cf = mr[t] * dw;
+                const R cf = (R)rb[t].w * dw;
                 for (int a = 0; a < D; ++a) s[a] += cf * d[a];
             }
         }
         const double dtau = S.ctl->dt / (double)P.gtvf_K;
+        double xn[3] = {xi[0], xi[1], xi[2]};
         for (int a = 0; a < D; ++a) {
             if (plain32(P)) {
                 const float dtf = (float)dtau, f = -(float)p0 * (float)s[a];
                 const float v = k == 0 ? 0.f : (float)S.vk[a][i];
-                xdst[a][i] = (float)xi[a] + dtf * v + 0.5f * dtf * dtf * f;
+                xn[a] = (float)xi[a] + dtf * v + 0.5f * dtf * dtf * f;
                 S.vk[a][i] = v + dtf * f;
                 continue;
             }
             const double f = -p0 * (double)s[a];
             const double v = k == 0 ? 0.0 : S.vk[a][i];
-            xdst[a][i] = xi[a] + dtau * v + 0.5 * dtau * dtau * f;
+            xn[a] = xi[a] + dtau * v + 0.5 * dtau * dtau * f;
             S.vk[a][i] = v + dtau * f;
         }
+        dst[i] = make_double4(xn[0], xn[1], xn[2], own.w);
     }
 };
 
@@ -2611,17 +2718,25 @@ struct Advance {
         ROW;
         if (i >= P.nf) return;
         const int kfinal = P.gtvf_K - 1;
-        double *const *xk = kfinal < 0 ? S.xs : S.xk[kfinal & 1];
+        double rk[3] = {0, 0, 0};
+        if (kfinal < 0) {
+            for (int a = 0; a < D; ++a) rk[a] = S.xs[a][i];
+        } else {
+            const double4 r = S.gk[kfinal & 1][i];
+            rk[0] = r.x;
+            rk[1] = r.y;
+            rk[2] = r.z;
+        }
         const double dt = S.ctl->dt;
         for (int a = 0; a < D; ++a) {
             double utn, xn;
             if (plain32(P)) {
                 const float dtf = (float)dt;
-                const float u1 = (float)S.un[a][i] + ((float)xk[a][i] - (float)S.xs[a][i]) / dtf;
+                const float u1 = (float)S.un[a][i] + ((float)rk[a] - (float)S.xs[a][i]) / dtf;
                 utn = u1;
                 xn = (float)S.x[a][i] + 0.5f * dtf * (u1 + (float)S.ut[a][i]);
             } else {
-                utn = S.un[a][i] + (xk[a][i] - S.xs[a][i]) / dt;
+                utn = S.un[a][i] + (rk[a] - S.xs[a][i]) / dt;
                 xn = S.x[a][i] + 0.5 * dt * (utn + S.ut[a][i]);
             }
             S.x[a][i] = rp(P, wrap_periodic(xn, P.grid, a));
@@ -3261,6 +3376,11 @@ void mass_over_rho2(const Target &T) {
 }
 
 void gtvf_substep(const Target &T, int k) { SISPH_DISPATCH_KDR(T, (launch<Gtvf<KER, D, R>, K_FLUID>(T, k))); }
+
+void gtvf_seed(const Target &T) {
+    if (f32_sums(T.precision)) launch<GtvfSeed<float>, K_TOT>(T);
+    else launch<GtvfSeed<double>, K_TOT>(T);
+}
 
 void advance(const Target &T) { SISPH_DISPATCH_D(T, (launch<Advance<D>, K_FLUID>(T))); }
 

@@ -356,10 +356,11 @@ class Context:
         _check(lib().sisph_sweep_counters(self.h, C.byref(ms), C.byref(n), C.byref(e), int(reset)), self.h)
         return dict(sweep_ms=ms.value, launches=n.value, effective=e.value)
 
-    def set_kernel_timing(self, on: bool = True):
-        """Bracket every sweep launch with its own HIP events (wall pass
-        left out)."""
-        _check(lib().sisph_set_kernel_timing(self.h, int(bool(on))), self.h)
+    def set_kernel_timing(self, period: int = 1):
+        """Bracket every period-th sweep launch of each solve with its own
+        HIP events (wall pass left out); period 0 (or False) turns it off,
+        True or 1 times every launch."""
+        _check(lib().sisph_set_kernel_timing(self.h, int(period)), self.h)
 
     def kernel_timing(self):
         """Sweep-kernel time (ms), timed launches and persistent ones among

@@ -46,6 +46,9 @@ def test_bench_line_fields():
     # walls: per-sweep launches, each timed on its own, the wall pass apart
     assert rf["mode"] == "per-sweep launches" and rf["persistent_launches"] == 0
     assert rf["launches"] == rf["per_sweep_launches"] >= rf["effective_sweeps"] > 0
+    # every eighth launch of a solve timed (launch 0 of every solve among them)
+    assert rf["timing_period"] == 8 and 0 < rf["timed_launches"] <= rf["launches"]
+    assert rf["timed_launches"] >= rf["launches"] // 8
     assert rf["wall_pass"]["rows"] > 0 and rf["wall_pass"]["us_per_sweep"] > 0
     assert rf["layout"]["bytes_per_sweep"] > 0
     sec = d["secondary"]
@@ -53,6 +56,7 @@ def test_bench_line_fields():
     sr = sec["roofline"]
     assert sr["algorithmic_bytes_per_particle_iter"] == 128
     assert sr["launches"] == sr["persistent_launches"] + sr["per_sweep_launches"]
+    assert sr["timing_period"] == 1 and sr["timed_launches"] == sr["launches"]
     # one persistent launch per solve unless the runtime refused one (for
     # instance while another process holds the device), which is counted
     if sr["per_sweep_launches"]:
