@@ -599,5 +599,10 @@ def test_fp32_plain_steps(name):
             "displacement": rel(s["x"][:nf] - case.x[:nf], ref.x[:nf] - case.x[:nf])}
     for k, e in errs.items():
         say(f"  fp32 {name} {k:12s} rel L2 {e:.3e} (sweeps {its})")
-    assert all(e < 2e-3 for e in errs.values())
+    # measured: p <= 1.5e-5, u <= 3.8e-6 (FP32 sums over up to 1000 sweeps);
+    # the displacement of a dam break's first steps from rest is ~1e-4 of
+    # the positions, each of which FP32 rounds by up to 6e-8 relative per
+    # step: 1.05e-3 there, <= 6e-5 elsewhere
+    bounds = {"p": 5e-5, "u": 2e-5, "displacement": 4e-3 if name.startswith("db") else 2e-4}
+    assert all(errs[k] < bounds[k] for k in errs), errs
     ctx.close()
