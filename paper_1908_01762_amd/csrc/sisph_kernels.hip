@@ -18,7 +18,6 @@
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
-#include <type_traits>
 
 #include "sisph_internal.h"
 
@@ -53,6 +52,20 @@ __device__ __forceinline__ double min_image(double v, const Grid &g, int k) {
         else if (v < -g.Lh[k]) v += g.L[k];
     }
     return v;
+}
+
+// The same without branches (both shifted values formed, one selected), for
+// loops that load several operands before using any; PER false: no
+// direction is periodic.
+template <bool PER>
+__device__ __forceinline__ double min_image_sel(double v, const Grid &g, int k) {
+    if constexpr (!PER) {
+        return v;
+    } else {
+        const double lo = v + g.L[k], hi = v - g.L[k];
+        const double w = v > g.Lh[k] ? hi : (v < -g.Lh[k] ? lo : v);
+        return g.per[k] ? w : v;
+    }
 }
 
 // |d|^2 in exactly the operations of the CPU reference: products rounded,
@@ -315,20 +328,8 @@ __device__ __forceinline__ int64_t logical_block() {
     else return (int64_t)blockIdx.x;
 }
 
-// A body may ask for a minimum occupancy (waves per SIMD) with a
-// kMinWaves member; the compiler then caps its registers to fit.
-template <class F, class = void>
-struct MinWaves {
-    static constexpr int value = 1;
-};
-template <class F>
-struct MinWaves<F, std::void_t<decltype(F::kMinWaves)>> {
-    static constexpr int value = F::kMinWaves;
-};
-
 template <class F, bool XCD, class... A>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MinWaves<F>::value))) void k_one(
-    const Params P, const State S, A... a) {
+__global__ __launch_bounds__(kBlock) void k_one(const Params P, const State S, A... a) {
     F::run(P, S, logical_block<XCD>(), (int64_t)gridDim.x, 0, a...);
 }
 
@@ -691,6 +692,53 @@ __device__ __forceinline__ void test_cell_global(const Params &P, const State &S
     }
 }
 
+// Candidates t0 .. t1-1 of the staged copy against row i, kScanBatch at a
+// time: the batch's indices and coordinates are read before any is
+// tested, so their LDS reads overlap; the set, its order and the counts are
+// those of one candidate at a time.
+constexpr int kScanBatch = 4;
+
+template <int D, bool PER>
+__device__ __forceinline__ bool staged_hit(const Params &P, const Grid &g, const double (*sx)[kStageCap],
+                                           const int32_t *sj, uint32_t t, int32_t self, const double xi[3],
+                                           int32_t &j) {
+    j = sj[t];
+    double xj[3] = {0, 0, 0};
+    for (int k = 0; k < D; ++k) xj[k] = sx[k][t];
+    double d[3] = {0, 0, 0};
+    for (int k = 0; k < D; ++k) d[k] = min_image_sel<PER>(xi[k] - xj[k], g, k);
+    return (j != self) & (exact_r2<D>(d) < P.R2);
+}
+
+template <int D, bool PER>
+__device__ __forceinline__ void scan_staged(const Params &P, const Grid &g, const double (*sx)[kStageCap],
+                                            const int32_t *sj, uint32_t t0, uint32_t t1, int64_t i,
+                                            const double xi[3], int32_t *nbr, int &c) {
+    constexpr int U = kScanBatch;
+    const int64_t nf = P.nf;
+    const int32_t self = (int32_t)i;
+    uint32_t t = t0;
+    for (; t + (U - 1) < t1; t += U) {
+        int32_t jv[U];
+        bool hv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) hv[u] = staged_hit<D, PER>(P, g, sx, sj, t + u, self, xi, jv[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (hv[u]) {
+                if (c < P.cap) nbr[(int64_t)c * nf + i] = jv[u];
+                ++c;
+            }
+    }
+    for (; t < t1; ++t) {
+        int32_t j;
+        if (staged_hit<D, PER>(P, g, sx, sj, t, self, xi, j)) {
+            if (c < P.cap) nbr[(int64_t)c * nf + i] = j;
+            ++c;
+        }
+    }
+}
+
 template <int D>
 struct BuildFluid {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which) {
@@ -705,6 +753,7 @@ struct BuildFluid {
         const int64_t nf = P.nf;
         const Pos x = mkpos(which == POS_XS ? S.xs : S.x);
         const int32_t *items = nullptr;   // the fluid is in the cell order of these positions
+        const bool periodic = g.per[0] || g.per[1] || g.per[2];
         double xi[3] = {0, 0, 0};
         int ci[3] = {0, 0, 0};
         Stencil st;
@@ -789,16 +838,10 @@ struct BuildFluid {
                             const uint32_t base = pass == 0 ? F0 : W0;
                             const uint32_t shift = pass == 0 ? 0u : nF;
                             const uint32_t t0 = start[cell] - base + shift, t1 = start[cell + 1] - base + shift;
-                            for (uint32_t t = t0; t < t1; ++t) {
-                                const int64_t j = sj[t];
-                                if (j == i) continue;
-                                double d[3] = {0, 0, 0};
-                                for (int k = 0; k < D; ++k) d[k] = min_image(xi[k] - sx[k][t], g, k);
-                                if (exact_r2<D>(d) < P.R2) {
-                                    if (c < P.cap) S.nbr[(int64_t)c * nf + i] = (int32_t)j;
-                                    ++c;
-                                }
-                            }
+                            if (periodic)
+                                scan_staged<D, true>(P, g, sx, sj, t0, t1, i, xi, S.nbr, c);
+                            else
+                                scan_staged<D, false>(P, g, sx, sj, t0, t1, i, xi, S.nbr, c);
                         }
                     }
                 __syncthreads();   // the next stencil row overwrites the staged copy
@@ -1839,9 +1882,6 @@ __device__ __forceinline__ void residual_partials(const Params &P, bool live, do
 
 template <typename R, int FIRST, bool PRECHECK>
 struct Sweep {
-    // the gathers' latency is hidden by other waves: the smallest first
-    // batch is built to run eight waves per SIMD
-    static constexpr int kMinWaves = FIRST <= 8 ? 8 : 1;
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int L) {
         Control *ctl = S.ctl;
         // PRECHECK: a finished solve is detected before any other load (one
