@@ -79,33 +79,32 @@ UNIT_BYTES = {(2, "mixed"): 4 * 20 + 8 + 40, (3, "mixed"): 4 * 80 + 60 + 40,
               (2, "fp64"): 8 * 20 + 8 + 40, (3, "fp64"): 8 * 80 + 60 + 40}
 
 
-def sweep_bytes(case, slots: int, index_bytes: int = 4, wall_pairs: int = 0, wall_rows: int = 0) -> dict:
-    """Algorithmic HBM bytes of one Jacobi sweep over the whole case.
+def sweep_bytes(case, slots: int, index_bits: int = 32, wall_pairs: int = 0, wall_rows: int = 0) -> dict:
+    """Bytes the data layout of one Jacobi sweep moves over the whole case.
 
     Per fluid row: neighbour count (4 B), RHS and D_ii (8 + 8), free-surface
     flag (4), own iterate (8), new iterate (8); mixed adds the FP32 copy of
     the new iterate (4) and reads neighbours' FP32 iterate once (4), FP64
     reads it once (8).  Per stored pair (self slot excluded): neighbour index
-    (4, or 2 as a 16-bit offset) and cached coefficient (4 mixed, 8 FP64).
-    Cases with walls run the wall pressure kernel before every sweep, inside
-    the same timed chunks, so its bytes are added: per wall row with fluid
-    neighbours (no sweep reads the others, so the kernel skips them) the
-    count (4), the hydrostatic term (8) and the new wall pressure (8, and its
-    FP32 copy 4 in the mixed mode); per wall pair the cached weight and fluid
-    index (8 mixed, 12 FP64).  The fluid iterate it gathers is counted once,
-    with the sweep's.
+    (index_bits: 32, 16 as an offset, 12 as a position in the workgroup's
+    LDS copy of the iterate) and cached coefficient (4 mixed, 8 FP64).
+    `bytes` is the sweep kernel's.  Cases with walls run the wall pressure
+    kernel before every sweep; its bytes are `wall_bytes`: per wall row with
+    fluid neighbours (no sweep reads the others, so the kernel skips them)
+    the count (4), the hydrostatic term (8) and the new wall pressure (8,
+    and its FP32 copy 4 in the mixed mode); per wall pair the cached weight
+    and fluid index (8 mixed, 12 FP64).
     """
     nf, nw = case.n_fluid, wall_rows
     pairs = slots - nf
     mixed = case.precision == "mixed"
     row = 4 + 8 + 8 + 4 + 8 + 8 + (4 + 4 if mixed else 8)
-    pair = index_bytes + (4 if mixed else 8)
+    pair = index_bits / 8 + (4 if mixed else 8)
     total = nf * row + pairs * pair
     wall_row = 4 + 8 + 8 + (4 if mixed else 0)
     wall_pair = 8 if mixed else 12
-    if nw:
-        total += nw * wall_row + wall_pairs * wall_pair
-    return dict(per_row=row, per_pair=pair, pairs=int(pairs), bytes=int(total),
+    wall = nw * wall_row + wall_pairs * wall_pair if nw else 0
+    return dict(per_row=row, per_pair=pair, pairs=int(pairs), bytes=int(total), wall_bytes=int(wall),
                 wall_rows=int(nw), wall_pairs=int(wall_pairs) if nw else 0,
                 per_wall_row=wall_row if nw else 0, per_wall_pair=wall_pair if nw else 0)
 
@@ -351,7 +350,7 @@ def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool,
     pinfo = ctx.persistent_info()
     fallbacks = ctx.persistent_fallbacks()   # since the reset: the timed steps only
     wall_rows = ctx.rows_with_neighbours(1, 1) if case.n_wall else 0
-    sb = sweep_bytes(case, ctx.pair_count(1, 0), index_bytes=stats[-1]["index_bytes"] if stats else 4,
+    sb = sweep_bytes(case, ctx.pair_count(1, 0), index_bits=stats[-1]["index_bits"] if stats else 32,
                      wall_pairs=ctx.pair_count(1, 1) if case.n_wall else 0, wall_rows=wall_rows)
     unit = UNIT_BYTES[(case.dim, case.precision)]
     # the dominant kernel: the sweep, one launch per sweep, or one persistent
@@ -398,9 +397,11 @@ def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool,
                            "traffic_per_sweep": round(traffic) if traffic is not None else None}}
     if case.n_wall:
         # the wall pressure pass runs before every sweep, outside the timed
-        # sweep kernel: its share of the chunk time and its own bytes
+        # sweep kernel: its share of the chunk time (with the launch gaps)
+        # and its own bytes
         roofline["wall_pass"] = {"rows": sb["wall_rows"], "pairs": sb["wall_pairs"],
                                  "bytes_per_row": sb["per_wall_row"], "bytes_per_pair": sb["per_wall_pair"],
+                                 "bytes_per_sweep": sb["wall_bytes"],
                                  "us_per_sweep": round((cnt["sweep_ms"] - kernel_s * 1e3) * 1e3 /
                                                        max(cnt["launches"], 1), 3)}
     out = {

@@ -152,9 +152,14 @@ typedef struct {
     double lambda;       /* max |RHS_i / D_ii| over non-free-surface fluid   */
     double p_ref;        /* GTVF reference pressure in use                  */
     double dt;           /* this step's time step                          */
-    int32_t index_bytes; /* bytes per neighbour index the sweeps read: 4, or
-                            2 (16-bit offsets: mixed mode, no walls, every
-                            offset of the step within +-32767)            */
+    int32_t index_bits;  /* bits per neighbour index the sweeps read: 32
+                            (the lists); 16 (offsets: mixed mode, no walls,
+                            every offset of the step within +-32767); 12
+                            (walled Jacobi cases on grids periodic in no
+                            direction: the neighbour's position in the
+                            workgroup's LDS copy of the iterate; 32 when a
+                            workgroup's copy would not fit and it reads the
+                            lists)                                         */
     int32_t reserved;
     double beta;         /* SISPH_NULL_PROJECT: the constant removed per unit
                             D_ii from the RHS (else 0)                      */

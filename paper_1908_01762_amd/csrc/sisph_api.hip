@@ -267,11 +267,11 @@ static void carve(const Params &P, Carver &c, State &S) {
     // mixed: (index, FP32 c_ij) 8-byte words; FP64: FP64 c_ij (indices from nbr)
     S.coef = c.take<char>((int64_t)8 * P.cap * nf);
     S.cidx = c.take<int32_t>((int64_t)P.cap * nf);
-    S.pk16 = nullptr;
-    S.rcell = nullptr;
+    S.pk12 = nullptr;
+    S.stagerec = nullptr;
     if (P.packed) {
-        S.pk16 = c.take<uint16_t>((int64_t)P.cap * nf);
-        S.rcell = c.take<uint32_t>(nf);
+        S.pk12 = c.take<uint3>((int64_t)((P.cap + 6) / 8) * nf);
+        S.stagerec = c.take<int32_t>(kind_blocks(P, K_FLUID) * kStageRec);
     }
     S.wcoef = c.take<char>((int64_t)8 * P.cap * nw);
     S.wh = c.take<double>(nw);
@@ -392,7 +392,7 @@ static void fill_stats(const Control &C, const Params &P, sisph_ppe_stats *out) 
     out->lambda = cv.d;
     out->p_ref = C.p_ref;
     out->dt = C.dt;
-    out->index_bytes = (P.compact && !C.wide) || (P.packed && !C.pk_overflow) ? 2 : 4;
+    out->index_bits = P.packed && !C.pk_overflow ? 12 : (P.compact && !C.wide ? 16 : 32);
     out->reserved = 0;
     out->beta = P.null_space == SISPH_NULL_PROJECT ? C.beta : 0.0;
 }

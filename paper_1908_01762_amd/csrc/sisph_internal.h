@@ -73,7 +73,7 @@ struct Control {
     double bicg_rho[2], bicg_alpha[2], bicg_omega[2];
     int32_t bicg_brk;
     int32_t wide;                     // a neighbour offset of this step did not fit 16 bits
-    int32_t pk_overflow;              // a 16-bit neighbour code of this step did not fit
+    int32_t pk_overflow;              // packed mode: some workgroup of this step reads the lists
     double beta;                      // SISPH_NULL_PROJECT: (y . RHS) / (y . D), y = m rho
 };
 
@@ -112,11 +112,11 @@ struct State {
     int32_t *wnbr, *wcnt;   // wall rows: fluid sources
     void *coef;             // cached PPE c_ij, working precision, group-major [cap/4][nf][4]
     void *cidx;             // their indices (int32) or 16-bit offsets (compact) or codes (packed), same layout
-    // packed mode: per list slot its 16-bit code, slot-major [cap][nf] like
-    // the lists, and per fluid row its r* cell id (bit 31: the row has wall
-    // neighbours)
-    uint16_t *pk16;
-    uint32_t *rcell;
+    // packed mode: eight 12-bit staged positions per 12-byte word,
+    // group-major [ceil((cap - 1) / 8)][nf] (word w of a row holds list
+    // slots 8w + 1 .. 8w + 8), and per fluid workgroup its staging record
+    uint3 *pk12;
+    int32_t *stagerec;      // [nblk][kStageRec]
     void *wcoef;            // cached wall weights W_wf / sum W: (f, FP32) words or FP64 [cap][nw]
     double *wh;             // wall hydrostatic term                 [nw]
     int32_t *wflag;         // wall workgroup has a row with fluid neighbours at r*   [nwb]
@@ -138,13 +138,15 @@ struct State {
 // Launch-size kinds: how many workgroups one case needs for a kernel.
 enum Kind { K_FLUID = 0, K_WALL, K_TOT, K_CELL, K_TILE, K_ONE, K_COUNT };
 
-// Packed neighbour codes: the high bits name one of the row's stencil-row
-// ranges (fluid rows 0 .. 3^(D-1)-1, then the same for walls), the low
-// kPackBits the offset of the neighbour from that range's first particle.
-constexpr int kPackBits = 11;
-constexpr uint32_t kPackMask = (1u << kPackBits) - 1u;
-constexpr uint32_t kRcellWalls = 0x80000000u;
-constexpr uint32_t kPackRanges = 18;   // 9 fluid + 9 wall stencil rows (3D)
+// Packed mode (walled Jacobi cases on grids periodic in no direction):
+// each sweep workgroup copies the iterate of the particles its rows can
+// reach into LDS, at most kStageBytes of values, and a neighbour is stored
+// as its 12-bit position in that copy.  The copy is 2 NR index intervals
+// (NR = 3^(D-1) stencil rows, fluid then walls); a workgroup's record holds
+// whether it is staged, each interval's first global index and the
+// intervals' positions in the copy (prefix sums): kStageRec words.
+constexpr int kStageBytes = 16384;
+constexpr int kStageRec = 40;
 
 __host__ __device__ inline int64_t kind_blocks(const Params &P, int kind) {
     switch (kind) {

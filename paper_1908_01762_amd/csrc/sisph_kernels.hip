@@ -662,15 +662,6 @@ struct ReorderWalls {
 // the same either way.
 constexpr int kStageCap = 1024;
 
-// Packed neighbour code of j in stencil-row range r (fluid, or r + the
-// fluid range count for walls) whose first particle is base; false if the
-// offset does not fit.
-__device__ __forceinline__ bool pack_code(uint32_t r, int64_t j, int64_t base, uint16_t &code) {
-    const int64_t off = j - base;
-    code = (uint16_t)((r << kPackBits) | ((uint32_t)off & kPackMask));
-    return off >= 0 && off <= (int64_t)kPackMask;
-}
-
 template <int D>
 __device__ __forceinline__ void test_cell_global(const Params &P, const State &S, const Pos &x,
                                                  const int32_t *items, int64_t i, const double xi[3],
@@ -855,32 +846,87 @@ struct BuildFluid {
     }
 };
 
-// Packed neighbour codes of the lists at r* (walled Jacobi cases whose x
-// axis is not periodic), one pass after the build: each list entry j
-// becomes the id of the row's stencil-row range that holds it (fluid ranges
-// 0 .. NR-1, wall ranges NR .. 2 NR-1) and its offset from that range's
-// first particle.  The three cells of a stencil row are consecutive in the
-// cell order, so a range is one index interval, and the ranges of a row
-// are in ascending order (a list visits them in that order too): the range
-// of j is the last one starting at or below j.  Also the row's cell id with
-// a flag for rows with wall neighbours, read by the sweeps to find the
-// range starts.  The slot-major lists and codes are read and written
-// coalesced (the build's stores are scattered: each row finds its
-// neighbours at its own pace).
+// Packed codes of the lists at r* (walled Jacobi cases on grids periodic in
+// no direction), one pass after the build.  First each workgroup's staging
+// record: its rows are in cell order, so their cells are one id range
+// [cf, cl]; for each stencil row (dy, dz) the cells [cf, cl] shifted by it
+// and widened by one along x are one cell-id interval, whose fluid
+// particles are one index interval, and so are its wall particles.  The
+// 2 NR intervals, one after the other, are what the workgroup's sweep
+// copies into LDS; it is staged when they fit in kStageBytes of iterate
+// values.  Then each list entry j of a staged workgroup's rows becomes its
+// position in that copy: the interval of the row's own stencil row that
+// holds j (the row's three cells lie in it) and the offset into it.  The
+// row's range of stencil row r starts at the cell start of its first cell;
+// the ranges of a row are in ascending order and a list visits them in
+// that order, so the range of j is the last one starting at or below j.
+// Lists and codes are read and written coalesced (the build's stores are
+// scattered: each row finds its neighbours at its own pace).  A workgroup
+// that is not staged keeps no codes; its sweeps read the lists.
+__device__ __forceinline__ void put12(uint32_t (&w)[3], int f, uint32_t code) {
+    const int b = 12 * f, k = b >> 5, o = b & 31;
+    w[k] |= code << o;
+    if (o > 20) w[k + 1] |= code >> (32 - o);
+}
+
 template <int D>
 struct PackCodes {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
-        ROW;
-        const int64_t nf = P.nf;
-        if (!P.packed || i >= nf) return;   // (batched: the other cases of the group)
+        if (!P.packed) return;   // (batched: the other cases of the group)
+        constexpr int NR = D == 3 ? 9 : 3, NQ = 2 * NR;
+        __shared__ int64_t span[2];
+        __shared__ int32_t sb[NQ], sp[NQ + 1];
+        __shared__ int32_t staged;
+        const int64_t nf = P.nf, r0 = blk * kBlock;
+        const int64_t r1 = (r0 + kBlock < nf ? r0 + kBlock : nf) - 1;
         const Grid &g = P.grid;
         const Pos x = mkpos(S.xs);
+        if (threadIdx.x < 2) {
+            const int64_t rr = threadIdx.x == 0 ? r0 : r1;
+            int cc[3] = {0, 0, 0};
+            for (int k = 0; k < D; ++k) cc[k] = cell_coord(x.c[k][rr], g, k);
+            span[threadIdx.x] = ((int64_t)cc[2] * g.nc[1] + cc[1]) * g.nc[0] + cc[0];
+        }
+        __syncthreads();
+        if (threadIdx.x < NQ) {
+            const int r = (int)threadIdx.x % NR;
+            const bool wall = (int)threadIdx.x >= NR;
+            const int64_t dz = D == 3 ? r / 3 - 1 : 0, dy = D == 3 ? r % 3 - 1 : r - 1;
+            const int64_t off = (dz * (int64_t)g.nc[1] + dy) * (int64_t)g.nc[0];
+            int64_t lo = span[0] + off - 1, hi = span[1] + off + 1;
+            lo = lo < 0 ? 0 : lo;
+            hi = hi > g.ncell - 1 ? g.ncell - 1 : hi;
+            int64_t b = 0, n = 0;
+            if (lo <= hi) {
+                const uint32_t *st = wall ? S.wstart : S.fstart;
+                b = (int64_t)st[lo];
+                n = (int64_t)st[hi + 1] - b;
+                if (wall) b += nf;
+            }
+            sb[threadIdx.x] = (int32_t)b;
+            sp[threadIdx.x + 1] = (int32_t)n;
+        }
+        __syncthreads();
+        int32_t *rec = S.stagerec + blk * kStageRec;
+        if (threadIdx.x == 0) {
+            sp[0] = 0;
+            for (int e = 1; e <= NQ; ++e) sp[e] += sp[e - 1];
+            const bool periodic = g.per[0] || g.per[1] || g.per[2];
+            const int cap = kStageBytes / (f32_sums(P.precision) ? 4 : 8);
+            staged = !periodic && sp[NQ] <= cap;
+            if (!staged) atomicOr(&S.ctl->pk_overflow, 1);
+            rec[0] = staged;
+        }
+        __syncthreads();
+        if (threadIdx.x < NQ) rec[1 + threadIdx.x] = sb[threadIdx.x];
+        if (threadIdx.x <= NQ) rec[1 + NQ + threadIdx.x] = sp[threadIdx.x];
+        ROW;
+        if (!staged || i >= nf) return;
         int ci[3] = {0, 0, 0};
         for (int k = 0; k < D; ++k) ci[k] = cell_coord(x.c[k][i], g, k);
         Stencil st;
         make_stencil<D>(g, ci, st);
         constexpr int na = D == 3 ? 3 : 1;
-        constexpr int NR = D == 3 ? 9 : 3;
         int64_t fs[NR], ws[NR];
         int e0 = 0;
         while (e0 < 2 && !pick3(st.ok[0], e0)) ++e0;
@@ -897,28 +943,20 @@ struct PackCodes {
                 ws[r] = nf + (int64_t)S.wstart[c0];
             }
         const int cnt = S.cnt[i];
-        bool bad = false, walls = false;
-        for (int c = 1; c < cnt; ++c) {
-            const int64_t j = S.nbr[(int64_t)c * nf + i];
-            const bool w = j >= nf;
-            walls |= w;
-            uint32_t r = 0;
-            int64_t base = w ? ws[0] : fs[0];
+        for (int c0 = 1; c0 < cnt; c0 += 8) {
+            uint32_t w[3] = {0u, 0u, 0u};
+            for (int f = 0; f < 8 && c0 + f < cnt; ++f) {
+                const int64_t j = S.nbr[(int64_t)(c0 + f) * nf + i];
+                const bool wl = j >= nf;
+                int r = 0;
 #pragma unroll
-            for (int k = 1; k < NR; ++k) {
-                const int64_t sk = w ? ws[k] : fs[k];
-                if (sk <= j) {
-                    r = (uint32_t)k;
-                    base = sk;
-                }
+                for (int k = 1; k < NR; ++k)
+                    if ((wl ? ws[k] : fs[k]) <= j) r = k;
+                const int q = wl ? NR + r : r;
+                put12(w, f, (uint32_t)(sp[q] + (int32_t)(j - sb[q])));
             }
-            uint16_t code;
-            bad |= !pack_code(r + (w ? (uint32_t)NR : 0u), j, base, code);
-            S.pk16[(int64_t)c * nf + i] = code;
+            S.pk12[(int64_t)((c0 - 1) >> 3) * nf + i] = make_uint3(w[0], w[1], w[2]);
         }
-        if (bad) atomicOr(&S.ctl->pk_overflow, 1);
-        const uint32_t cell = (uint32_t)(((int64_t)ci[2] * g.nc[1] + ci[1]) * g.nc[0] + ci[0]);
-        S.rcell[i] = cell | (walls ? kRcellWalls : 0u);
     }
 };
 
@@ -1370,8 +1408,6 @@ struct RhsCoef {
                         else if (o < -(nf / 2)) o += nf;
                         if (o >= -32767 && o <= 32767) oq = (int16_t)o;
                         else wide = true;
-                    } else if (P.packed) {
-                        oq = (int16_t)S.pk16[(int64_t)(k0 + t) * nf + i];
                     }
                     c4[t] = cij;
                     j4[t] = (int32_t)j;
@@ -1385,7 +1421,7 @@ struct RhsCoef {
                 cv.z = c4[2];
                 cv.w = c4[3];
                 ((typename Vec4<R>::T *)S.coef)[at] = cv;
-                if (P.compact || P.packed) {
+                if (P.compact) {
                     Off4 ov;
                     for (int t = 0; t < 4; ++t) ov.o[t] = o4[t];
                     ((Off4 *)S.cidx)[at] = ov;
@@ -1520,13 +1556,9 @@ __device__ __forceinline__ void load_groups(int64_t i, int64_t nf, int g0, int g
 
 // Offsets to indices; when an offset of the step did not fit, the indices
 // of the group's slots come from the lists instead.
-// Packed codes decode through pb, the row's column of range starts in LDS
-// (stride kBlock; range ids clamped into the table, so stale codes past the
-// row's count read a valid entry and are discarded later).
 template <int NG>
 __device__ __forceinline__ void resolve_groups(int64_t i, int64_t nf, int g0, int npos, const int32_t *nbr,
-                                               bool wide, const Off4 (&oo)[NG], int4 (&jj)[NG],
-                                               const int32_t *pb = nullptr, int pstride = 1) {
+                                               bool wide, const Off4 (&oo)[NG], int4 (&jj)[NG]) {
 #pragma unroll
     for (int t = 0; t < NG; ++t) {
         int32_t j4[4];
@@ -1535,10 +1567,6 @@ __device__ __forceinline__ void resolve_groups(int64_t i, int64_t nf, int g0, in
             const int p = (g0 + t) * 4 + q;
             if (wide) {
                 j4[q] = p < npos ? nbr[(int64_t)(p + 1) * nf + i] : (int32_t)i;
-            } else if (pb) {
-                const uint32_t code = (uint16_t)oo[t].o[q];
-                const uint32_t r = code >> kPackBits;
-                j4[q] = pb[(r < kPackRanges ? r : kPackRanges - 1) * pstride] + (int32_t)(code & kPackMask);
             } else {
                 j4[q] = offset_index(i, oo[t].o[q], nf);
             }
@@ -1547,140 +1575,64 @@ __device__ __forceinline__ void resolve_groups(int64_t i, int64_t nf, int g0, in
     }
 }
 
-// The range starts of every cell the workgroup's rows lie in (rows are in
-// cell order, so these cells are one id range [cf, cl]), computed once per
-// workgroup, a few entries per thread, into tbl[cell - cf][range], and the
-// cells' first rows into sfs; a row then finds its cell by a binary search
-// of sfs.  Returns the number of cells, 0 (nothing written) when they are
-// more than kPackCells.  Every thread of the workgroup calls it.
-//
-// When the grid is periodic in no direction, the iterate values every row
-// of the workgroup can gather are also staged in LDS (sp): for each
-// stencil row (dy, dz), the cells of the workgroup's cells shifted by
-// (dy, dz) and widened by one along x form one cell-id interval, so its
-// fluid particles are one index interval, and so are its wall particles.
-// The 2 NR intervals are copied one after the other into sp, and the table
-// then holds each range's position in sp instead of its global start: a
-// code (range, offset) indexes sp directly.  A row's range lies inside its
-// interval (its three cells do), so every code of the workgroup resolves
-// into the staged copy.  *staged tells which form the table holds; it is
-// not staged when the intervals hold more than kStageBytes of values.
-constexpr int kPackCells = 64;
-constexpr int kStageBytes = 16384;
-
-template <int D, typename R>
-__device__ __forceinline__ int pack_table(const Params &P, const State &S, int64_t blk, int32_t *tbl,
-                                          uint32_t *sfs, const R *q, R *sp, bool &staged) {
-    constexpr int NR = D == 3 ? 9 : 3;
-    __shared__ uint32_t span[2];
-    __shared__ int64_t seg_base[2 * NR];   // global index of each interval's first particle
-    __shared__ int32_t seg_pos[2 * NR + 1];
-    const int64_t nf = P.nf, r0 = blk * kBlock;
-    const int64_t r1 = (r0 + kBlock < nf ? r0 + kBlock : nf) - 1;
-    if (threadIdx.x == 0) {
-        span[0] = S.rcell[r0] & ~kRcellWalls;
-        span[1] = S.rcell[r1] & ~kRcellWalls;
+// Packed mode: coefficient groups alone, and the 12-bit code words
+// (eight positions each; word index clamped into the storage, positions at
+// or past the row's count are discarded later).
+template <typename R, int NG>
+__device__ __forceinline__ void load_coef(int64_t i, int64_t nf, int g0, int gmax, const void *coef,
+                                          typename Vec4<R>::T (&cc)[NG]) {
+#pragma unroll
+    for (int t = 0; t < NG; ++t) {
+        const int g = g0 + t < gmax ? g0 + t : gmax - 1;
+        cc[t] = ((const typename Vec4<R>::T *)coef)[group_at(g, nf, i)];
     }
-    __syncthreads();
-    const uint32_t cf = span[0];
-    const int ncl = (int)(span[1] - cf) + 1;
-    staged = false;
-    if (ncl > kPackCells) return 0;
-    const Grid &g = P.grid;
-    const uint32_t nx = (uint32_t)g.nc[0], ny = (uint32_t)g.nc[1];
-    const bool can_stage = !g.per[0] && !g.per[1] && (D == 2 || !g.per[2]);
-    if (can_stage) {
-        if (threadIdx.x < 2 * NR) {
-            const int r = (int)threadIdx.x % NR;
-            const bool wall = (int)threadIdx.x >= NR;
-            const int64_t dz = D == 3 ? r / 3 - 1 : 0, dy = D == 3 ? r % 3 - 1 : r - 1;
-            const int64_t off = (dz * (int64_t)ny + dy) * (int64_t)nx;
-            int64_t lo = (int64_t)cf + off - 1, hi = (int64_t)span[1] + off + 1;
-            lo = lo < 0 ? 0 : lo;
-            hi = hi > g.ncell - 1 ? g.ncell - 1 : hi;
-            int64_t b = 0, n = 0;
-            if (lo <= hi) {
-                const uint32_t *st = wall ? S.wstart : S.fstart;
-                b = (int64_t)st[lo];
-                n = (int64_t)st[hi + 1] - b;
-                if (wall) b += nf;
-            }
-            seg_base[threadIdx.x] = b;
-            seg_pos[threadIdx.x + 1] = (int32_t)n;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            seg_pos[0] = 0;
-            for (int e = 1; e <= 2 * NR; ++e) seg_pos[e] += seg_pos[e - 1];
-        }
-        __syncthreads();
-        staged = seg_pos[2 * NR] <= kStageBytes / (int)sizeof(R);
-    }
-    for (int e = threadIdx.x; e < ncl * NR; e += kBlock) {
-        const int k = e / NR, r = e - k * NR;
-        const uint32_t cell = cf + (uint32_t)k;
-        int ci[3] = {(int)(cell % nx), (int)((cell / nx) % ny), (int)(cell / (nx * ny))};
-        Stencil st;
-        make_stencil<D>(g, ci, st);
-        const int a = D == 3 ? r / 3 : 0, b = D == 3 ? r - 3 * (r / 3) : r;
-        if (!(pick3(st.ok[2], a) && pick3(st.ok[1], b))) continue;
-        int e0 = 0;
-        while (e0 < 2 && !pick3(st.ok[0], e0)) ++e0;
-        const int64_t c0 =
-            ((int64_t)pick3(st.v[2], a) * g.nc[1] + pick3(st.v[1], b)) * g.nc[0] + pick3(st.v[0], e0);
-        const int64_t fs0 = (int64_t)S.fstart[c0], ws0 = nf + (int64_t)S.wstart[c0];
-        if (staged) {
-            tbl[k * (int)kPackRanges + r] = seg_pos[r] + (int32_t)(fs0 - seg_base[r]);
-            tbl[k * (int)kPackRanges + NR + r] = seg_pos[NR + r] + (int32_t)(ws0 - seg_base[NR + r]);
-        } else {
-            tbl[k * (int)kPackRanges + r] = (int32_t)fs0;
-            tbl[k * (int)kPackRanges + NR + r] = (int32_t)ws0;
-        }
-    }
-    if (staged) {
-        const int total = seg_pos[2 * NR];
-        for (int e = threadIdx.x; e < total; e += kBlock) {
-            int sg = 0;
-            while (e >= seg_pos[sg + 1]) ++sg;
-            sp[e] = q[seg_base[sg] + (e - seg_pos[sg])];
-        }
-    }
-    for (int e = threadIdx.x; e <= ncl; e += kBlock) sfs[e] = S.fstart[cf + (uint32_t)e];
-    __syncthreads();
-    return ncl;
 }
 
-// The start of each of a row's stencil-row ranges (fluid, then walls when
-// the row has wall neighbours) at r*, from its cell, into its LDS column
-// (rows of workgroups whose cells are too many for pack_table).
-template <int D>
-__device__ __forceinline__ void pack_bases(const Params &P, const State &S, int64_t i, int32_t *pb) {
-    const uint32_t rc = S.rcell[i];
-    const bool walls = (rc & kRcellWalls) != 0;
-    const uint32_t cell = rc & ~kRcellWalls;
-    const Grid &g = P.grid;
-    int ci[3] = {0, 0, 0};
-    const uint32_t nx = (uint32_t)g.nc[0], ny = (uint32_t)g.nc[1];
-    ci[0] = (int)(cell % nx);
-    ci[1] = (int)((cell / nx) % ny);
-    ci[2] = (int)(cell / (nx * ny));
-    Stencil st;
-    make_stencil<D>(g, ci, st);
-    constexpr int na = D == 3 ? 3 : 1;
-    constexpr int NR = D == 3 ? 9 : 3;
-    int e0 = 0;
-    while (e0 < 2 && !pick3(st.ok[0], e0)) ++e0;
-    const int x0 = pick3(st.v[0], e0);
+template <int NW>
+__device__ __forceinline__ void load_codes(int64_t i, int64_t nf, int w0, int wmax, const uint3 *pk,
+                                           uint3 (&cw)[NW]) {
 #pragma unroll
-    for (int a = 0; a < na; ++a)
+    for (int t = 0; t < NW; ++t) {
+        const int w = w0 + t < wmax ? w0 + t : wmax - 1;
+        cw[t] = pk[(int64_t)w * nf + i];
+    }
+}
+
+__device__ __forceinline__ uint32_t code12(const uint3 &w, int f) {
+    const uint64_t lo = ((uint64_t)w.y << 32) | w.x, hi = ((uint64_t)w.z << 32) | w.y;
+    const int b = 12 * f;
+    return (uint32_t)((b < 32 ? lo >> b : hi >> (b - 32)) & 0xfffu);
+}
+
+// Iterate values of positions g0*4 .. (g0+NG)*4-1: from the staged copy sp
+// by code, or, for a workgroup that is not staged, through the lists; 0 at
+// or past npos.
+template <typename R, int NG>
+__device__ __forceinline__ void packed_gathers(int64_t i, int64_t nf, int g0, int npos, const uint3 *cw,
+                                               const R *sp, const int32_t *nbr, const R *q, R (&pv)[NG][4]) {
+    if (sp) {
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const int r = D == 3 ? a * 3 + b : b;
-            if (!(pick3(st.ok[2], a) && pick3(st.ok[1], b))) continue;
-            const int64_t c0 = ((int64_t)pick3(st.v[2], a) * g.nc[1] + pick3(st.v[1], b)) * g.nc[0] + x0;
-            pb[r * kBlock] = (int32_t)S.fstart[c0];
-            if (walls) pb[(NR + r) * kBlock] = (int32_t)(P.nf + (int64_t)S.wstart[c0]);
-        }
+        for (int t = 0; t < NG; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = t * 4 + u;
+                const uint32_t code = code12(cw[k >> 3], k & 7);
+                pv[t][u] = (g0 + t) * 4 + u < npos ? sp[code] : R(0);
+            }
+    } else {
+        int32_t jv[NG][4];
+#pragma unroll
+        for (int t = 0; t < NG; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int p = (g0 + t) * 4 + u;
+                jv[t][u] = p < npos ? nbr[(int64_t)(p + 1) * nf + i] : (int32_t)i;
+            }
+#pragma unroll
+        for (int t = 0; t < NG; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pv[t][u] = (g0 + t) * 4 + u < npos ? q[jv[t][u]] : R(0);
+    }
 }
 
 template <typename R>
@@ -1692,13 +1644,9 @@ __device__ __forceinline__ int32_t iget(const int4 &v, int q) {
 }
 
 // Gathered iterate values of the groups' positions (the row's own value
-// for positions at or past npos); from the workgroup's staged copy sp when
-// there is one (its indices are positions in sp; positions past npos read
-// nothing and get 0).
+// for positions at or past npos).
 template <typename R>
-__device__ __forceinline__ R gather_one(int p, int npos, int32_t j, int64_t i, const double *pc, const float *qc,
-                                        const R *sp) {
-    if (sp) return p < npos ? sp[j] : R(0);
+__device__ __forceinline__ R gather_one(int p, int npos, int32_t j, int64_t i, const double *pc, const float *qc) {
     const int32_t jj = p < npos ? j : (int32_t)i;
     if constexpr (sizeof(R) == 4) return qc[jj];
     else return pc[jj];
@@ -1706,11 +1654,11 @@ __device__ __forceinline__ R gather_one(int p, int npos, int32_t j, int64_t i, c
 
 template <typename R, int NG>
 __device__ __forceinline__ void issue_gathers(int64_t i, int g0, int npos, const int4 (&jj)[NG], const double *pc,
-                                              const float *qc, R (&pv)[NG][4], const R *sp = nullptr) {
+                                              const float *qc, R (&pv)[NG][4]) {
 #pragma unroll
     for (int t = 0; t < NG; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) pv[t][q] = gather_one<R>((g0 + t) * 4 + q, npos, iget(jj[t], q), i, pc, qc, sp);
+        for (int q = 0; q < 4; ++q) pv[t][q] = gather_one<R>((g0 + t) * 4 + q, npos, iget(jj[t], q), i, pc, qc);
 }
 
 template <typename R, int NG>
@@ -1729,13 +1677,12 @@ __device__ __forceinline__ R sum_gathers(int g0, int npos, const typename Vec4<R
 // sum over positions p < npos of the groups, in position (= slot) order
 template <typename R, int NG>
 __device__ __forceinline__ R gather_groups(int64_t i, int g0, int npos, const typename Vec4<R>::T (&cc)[NG],
-                                           const int4 (&jj)[NG], const double *pc, const float *qc, R s,
-                                           const R *sp = nullptr) {
+                                           const int4 (&jj)[NG], const double *pc, const float *qc, R s) {
     R pv[NG][4];
 #pragma unroll
     for (int t = 0; t < NG; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) pv[t][q] = gather_one<R>((g0 + t) * 4 + q, npos, iget(jj[t], q), i, pc, qc, sp);
+        for (int q = 0; q < 4; ++q) pv[t][q] = gather_one<R>((g0 + t) * 4 + q, npos, iget(jj[t], q), i, pc, qc);
 #pragma unroll
     for (int t = 0; t < NG; ++t)
 #pragma unroll
@@ -1910,93 +1857,113 @@ struct Sweep {
         double *pn = S.p[(L + 1) & 1];
         const float *qc = S.p32 + (L & 1) * P.ntot;
         float *qn = S.p32 + ((L + 1) & 1) * P.ntot;
-        const bool packed = P.packed != 0;
-        const bool offs = P.compact != 0 || packed;
-        // set by this step's coefficients (offsets) or neighbour build (codes)
-        const int32_t wide_flag = P.compact ? ctl->wide : (packed ? ctl->pk_overflow : 0);
         const int gmax = P.cap / 4;
         ROW;
         const bool live = i < nf;
-        // packed codes: the range starts of the workgroup's cells in a shared
-        // table (and the iterate values they reach staged after it), or,
-        // when its rows span too many cells, per row in its own LDS column
-        constexpr int kTableBytes = kPackCells * kPackRanges * 4;
-        constexpr int kColumnBytes = kPackRanges * kBlock * 4;
-        __shared__ __align__(16) unsigned char lds[kTableBytes + kStageBytes > kColumnBytes
-                                                       ? kTableBytes + kStageBytes
-                                                       : kColumnBytes];
-        __shared__ uint32_t sfs[kPackCells + 1];
-        int32_t *pbt = (int32_t *)lds;
-        R *stage = (R *)(lds + kTableBytes);
-        const R *sp = nullptr;
-        const int32_t *pb = nullptr;
-        int pstride = 1;
-        if (packed && !wide_flag) {
-            const R *qsrc;
-            if constexpr (sizeof(R) == 4) qsrc = qc;
-            else qsrc = pc;
-            bool staged = false;
-            const int ncl = P.dim == 3 ? pack_table<3, R>(P, S, blk, pbt, sfs, qsrc, stage, staged)
-                                       : pack_table<2, R>(P, S, blk, pbt, sfs, qsrc, stage, staged);
-            if (staged) sp = stage;
-            if (ncl > 0) {
-                int lo = 0, hi = ncl - 1;   // the last cell whose first row is <= i
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if ((int64_t)sfs[mid] <= i) lo = mid;
-                    else hi = mid - 1;
-                }
-                pb = pbt + lo * (int)kPackRanges;
-            } else {
-                pb = pbt + threadIdx.x;
-                pstride = kBlock;
-                if (live) {
-                    if (P.dim == 3) pack_bases<3>(P, S, i, pbt + threadIdx.x);
-                    else pack_bases<2>(P, S, i, pbt + threadIdx.x);
-                }
-            }
-        }
-        // one round trip: row values and the first FIRST / 4 coefficient and
-        // index groups
-        constexpr int NG = FIRST / 4;
-        typename Vec4<R>::T cc[NG];
-        int4 jj[NG];
-        Off4 oo[NG];
-        double D = 0.0, r = 0.0, pold = 0.0;
+        double D = 0.0, r = 0.0, pold = 0.0, v = 0.0;
         int32_t f = 1, c = 0;
-        if (live) {
-            load_groups<R, NG>(i, nf, 0, gmax, S.coef, S.cidx, offs, cc, jj, oo);
-            D = S.dii[i];
-            r = S.rhs[i];
-            f = S.fs[i];
-            c = S.cnt[i];
-            pold = pc[i];
-        }
-        if (stopped < L) return;   // only earlier launches write values below L
-        double v = 0.0;
-        const int npos = c - 1;   // neighbours besides the row itself
-        R pv[NG][4];
-        if (live) {
-            if (offs) resolve_groups<NG>(i, nf, 0, npos, S.nbr, wide_flag != 0, oo, jj, pb, pstride);
-            issue_gathers<R, NG>(i, 0, npos, jj, pc, qc, pv, sp);
-        }
-        // (a solve that stopped earlier returned above: its partials are stale)
-        if (decides) {
-            const double lam = __longlong_as_double((long long)ctl->lambda_bits);   // fixed during the solve
-            if (stopped_after(P, S.partial, nblk, L, pl, lam, true, ctl)) return;
-        }
-        if (live) {
-            R s = sum_gathers<R, NG>(0, npos, cc, pv, R(0));
-            for (int g0 = NG; 4 * g0 < npos; g0 += kSweepBatchGroups) {
-                typename Vec4<R>::T cb[kSweepBatchGroups];
-                int4 jb[kSweepBatchGroups];
-                Off4 ob[kSweepBatchGroups];
-                load_groups<R, kSweepBatchGroups>(i, nf, g0, gmax, S.coef, S.cidx, offs, cb, jb, ob);
-                if (offs) resolve_groups<kSweepBatchGroups>(i, nf, g0, npos, S.nbr, wide_flag != 0, ob, jb, pb,
-                                                            pstride);
-                s = gather_groups<R, kSweepBatchGroups>(i, g0, npos, cb, jb, pc, qc, s, sp);
+        if (P.packed) {
+            // The workgroup's staging record (one round trip), then its copy
+            // of the iterate its rows reach; codes index the copy.
+            constexpr int kStageVals = kStageBytes / (int)sizeof(R);
+            __shared__ int32_t rec[kStageRec];
+            __shared__ __align__(16) R stage[kStageVals];
+            const int NQ = P.dim == 3 ? 18 : 6;
+            if ((int)threadIdx.x < 2 * NQ + 2) rec[threadIdx.x] = S.stagerec[blk * kStageRec + threadIdx.x];
+            __syncthreads();
+            const bool staged = rec[0] != 0;
+            const R *q;
+            if constexpr (sizeof(R) == 4) q = qc;
+            else q = pc;
+            if (staged) {
+                const int32_t *base = rec + 1, *pos = rec + 1 + NQ;
+                const int total = pos[NQ];
+                for (int e = threadIdx.x; e < total; e += kBlock) {
+                    int sg = 0;
+                    while (e >= pos[sg + 1]) ++sg;
+                    stage[e] = q[(int64_t)base[sg] + (e - pos[sg])];
+                }
             }
-            if (D != 0.0 && !f) v = psor<R>(P, r, s, D, pold);
+            __syncthreads();
+            const R *sp = staged ? stage : nullptr;
+            // first round trip: row values, the first FP coefficients and
+            // their code words (FP: FIRST rounded up to whole code words)
+            constexpr int FP = (FIRST + 7) / 8 * 8, NGP = FP / 4, NWP = FP / 8;
+            const int wmax = (P.cap + 6) / 8;
+            typename Vec4<R>::T cc[NGP];
+            uint3 cw[NWP];
+            if (live) {
+                load_coef<R, NGP>(i, nf, 0, gmax, S.coef, cc);
+                if (staged) load_codes<NWP>(i, nf, 0, wmax, S.pk12, cw);
+                D = S.dii[i];
+                r = S.rhs[i];
+                f = S.fs[i];
+                c = S.cnt[i];
+                pold = pc[i];
+            }
+            if (stopped < L) return;   // only earlier launches write values below L
+            const int npos = c - 1;
+            R pv[NGP][4];
+            if (live) packed_gathers<R, NGP>(i, nf, 0, npos, cw, sp, S.nbr, q, pv);
+            if (decides) {
+                const double lam = __longlong_as_double((long long)ctl->lambda_bits);
+                if (stopped_after(P, S.partial, nblk, L, pl, lam, true, ctl)) return;
+            }
+            if (live) {
+                R s = sum_gathers<R, NGP>(0, npos, cc, pv, R(0));
+                for (int g0 = NGP; 4 * g0 < npos; g0 += 2) {
+                    typename Vec4<R>::T cb[2];
+                    uint3 cn[1];
+                    load_coef<R, 2>(i, nf, g0, gmax, S.coef, cb);
+                    if (staged) load_codes<1>(i, nf, g0 / 2, wmax, S.pk12, cn);
+                    R pb[2][4];
+                    packed_gathers<R, 2>(i, nf, g0, npos, cn, sp, S.nbr, q, pb);
+                    s = sum_gathers<R, 2>(g0, npos, cb, pb, s);
+                }
+                if (D != 0.0 && !f) v = psor<R>(P, r, s, D, pold);
+            }
+        } else {
+            const bool offs = P.compact != 0;
+            // set by this step's coefficients: some offset did not fit
+            const bool wide = P.compact && ctl->wide;
+            // one round trip: row values and the first FIRST / 4 coefficient
+            // and index groups
+            constexpr int NG = FIRST / 4;
+            typename Vec4<R>::T cc[NG];
+            int4 jj[NG];
+            Off4 oo[NG];
+            if (live) {
+                load_groups<R, NG>(i, nf, 0, gmax, S.coef, S.cidx, offs, cc, jj, oo);
+                D = S.dii[i];
+                r = S.rhs[i];
+                f = S.fs[i];
+                c = S.cnt[i];
+                pold = pc[i];
+            }
+            if (stopped < L) return;   // only earlier launches write values below L
+            const int npos = c - 1;    // neighbours besides the row itself
+            R pv[NG][4];
+            if (live) {
+                if (offs) resolve_groups<NG>(i, nf, 0, npos, S.nbr, wide, oo, jj);
+                issue_gathers<R, NG>(i, 0, npos, jj, pc, qc, pv);
+            }
+            // (a solve that stopped earlier returned above: its partials are stale)
+            if (decides) {
+                const double lam = __longlong_as_double((long long)ctl->lambda_bits);   // fixed during the solve
+                if (stopped_after(P, S.partial, nblk, L, pl, lam, true, ctl)) return;
+            }
+            if (live) {
+                R s = sum_gathers<R, NG>(0, npos, cc, pv, R(0));
+                for (int g0 = NG; 4 * g0 < npos; g0 += kSweepBatchGroups) {
+                    typename Vec4<R>::T cb[kSweepBatchGroups];
+                    int4 jb[kSweepBatchGroups];
+                    Off4 ob[kSweepBatchGroups];
+                    load_groups<R, kSweepBatchGroups>(i, nf, g0, gmax, S.coef, S.cidx, offs, cb, jb, ob);
+                    if (offs) resolve_groups<kSweepBatchGroups>(i, nf, g0, npos, S.nbr, wide, ob, jb);
+                    s = gather_groups<R, kSweepBatchGroups>(i, g0, npos, cb, jb, pc, qc, s);
+                }
+                if (D != 0.0 && !f) v = psor<R>(P, r, s, D, pold);
+            }
         }
         double a = 0.0, b = 0.0;
         if (live) {

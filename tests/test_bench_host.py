@@ -14,7 +14,7 @@ from paper_1908_01762_amd import cases  # noqa: E402
 def test_sweep_bytes_rows_and_pairs():
     # 100 rows, 1,600 slots = 100 self slots + 1,500 stored pairs
     mixed = cases.taylor_green(10, precision="mixed")
-    b = bench.sweep_bytes(mixed, slots=1600, index_bytes=2)
+    b = bench.sweep_bytes(mixed, slots=1600, index_bits=16)
     # row: count 4, RHS 8, D_ii 8, flag 4, own p 8, new p 8, new p32 4, gathered p32 4
     assert (b["per_row"], b["per_pair"], b["pairs"]) == (48, 6, 1500)
     assert b["bytes"] == 100 * 48 + 1500 * 6
@@ -27,10 +27,12 @@ def test_sweep_bytes_rows_and_pairs():
 
 def test_sweep_bytes_walls():
     mixed = cases.taylor_green(10, precision="mixed")
-    b = bench.sweep_bytes(mixed, slots=1600, index_bytes=4, wall_pairs=300, wall_rows=20)
+    b = bench.sweep_bytes(mixed, slots=1600, index_bits=32, wall_pairs=300, wall_rows=20)
     # wall row: count 4, hydrostatic term 8, new p 8, its FP32 copy 4; wall pair: weight + index
     assert (b["per_wall_row"], b["per_wall_pair"]) == (24, 8)
-    assert b["bytes"] == 100 * 48 + 1500 * 8 + 20 * 24 + 300 * 8
+    assert b["bytes"] == 100 * 48 + 1500 * 8 and b["wall_bytes"] == 20 * 24 + 300 * 8
+    packed = bench.sweep_bytes(mixed, slots=1600, index_bits=12)
+    assert packed["per_pair"] == 5.5 and packed["bytes"] == 100 * 48 + 1500 * 5.5
     fp64 = cases.taylor_green(10, precision="fp64")
     b = bench.sweep_bytes(fp64, slots=1600, wall_pairs=300, wall_rows=20)
     assert (b["per_wall_row"], b["per_wall_pair"]) == (20, 12)

@@ -292,18 +292,18 @@ def test_index_offsets_compact_and_wide():
     offset of the step fits (Taylor-Green), and the full indices otherwise
     (a long periodic strip); both agree with the FP64 path."""
     sisph = _gpu()
-    for case, expect in ((cases.taylor_green(60, kernel="wendland", hdx=1.3, precision="mixed", seed=2), 2),
-                         (cases.long_strip(), 4)):
+    for case, expect in ((cases.taylor_green(60, kernel="wendland", hdx=1.3, precision="mixed", seed=2), 16),
+                         (cases.long_strip(), 32)):
         a = sisph.Context(case)
         b = sisph.Context(case.replace(precision="fp64"))
         sa = a.step(2)
         sb = b.step(2)
         ra, rb = a.read_state(), b.read_state()
         e = rel(ra["p"], rb["p"])
-        say(f"  {case.name}: index bytes {sa[-1]['index_bytes']}, iters {[s['iters'] for s in sa]} / "
+        say(f"  {case.name}: index bits {sa[-1]['index_bits']}, iters {[s['iters'] for s in sa]} / "
             f"{[s['iters'] for s in sb]}, p rel L2 vs FP64 {e:.3e}, u {rel(ra['u'], rb['u']):.3e}")
-        assert all(s["index_bytes"] == expect for s in sa)
-        assert all(s["index_bytes"] == 4 for s in sb)
+        assert all(s["index_bits"] == expect for s in sa)
+        assert all(s["index_bits"] == 32 for s in sb)
         assert e < 1e-3 and rel(ra["u"], rb["u"]) < 1e-4
         a.close()
         b.close()
