@@ -85,7 +85,8 @@ def sweep_bytes(case, slots: int, index_bits: int = 32, wall_pairs: int = 0, wal
     Per fluid row: neighbour count (4 B), RHS and D_ii (8 + 8), free-surface
     flag (4), own iterate (8), new iterate (8); mixed adds the FP32 copy of
     the new iterate (4) and reads neighbours' FP32 iterate once (4), FP64
-    reads it once (8).  Per stored pair (self slot excluded): neighbour index
+    reads it once (8); the packed mixed sweep reads RHS and D_ii as FP32 and
+    count and flag as one word (36 B).  Per stored pair (self slot excluded): neighbour index
     (index_bits: 32, 16 as an offset, 12 as a position in the workgroup's
     LDS copy of the iterate) and cached coefficient (4 mixed, 8 FP64).
     `bytes` is the sweep kernel's.  Cases with walls run the wall pressure
@@ -99,6 +100,8 @@ def sweep_bytes(case, slots: int, index_bits: int = 32, wall_pairs: int = 0, wal
     pairs = slots - nf
     mixed = case.precision == "mixed"
     row = 4 + 8 + 8 + 4 + 8 + 8 + (4 + 4 if mixed else 8)
+    if mixed and index_bits == 12:
+        row -= 12   # RHS and D_ii as FP32 (exact: FP32 sums), count and flag in one word
     pair = index_bits / 8 + (4 if mixed else 8)
     total = nf * row + pairs * pair
     wall_row = 4 + 8 + 8 + (4 if mixed else 0)

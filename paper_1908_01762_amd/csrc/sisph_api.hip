@@ -269,9 +269,15 @@ static void carve(const Params &P, Carver &c, State &S) {
     S.cidx = c.take<int32_t>((int64_t)P.cap * nf);
     S.pk12 = nullptr;
     S.stagerec = nullptr;
+    S.rd32 = nullptr;
+    S.cf = nullptr;
     if (P.packed) {
         S.pk12 = c.take<uint3>((int64_t)((P.cap + 6) / 8) * nf);
         S.stagerec = c.take<int32_t>(kind_blocks(P, K_FLUID) * kStageRec);
+        if (f32_sums(P.precision)) {
+            S.rd32 = c.take<float2>(nf);
+            S.cf = c.take<int32_t>(nf);
+        }
     }
     S.wcoef = c.take<char>((int64_t)8 * P.cap * nw);
     S.wh = c.take<double>(nw);

@@ -117,6 +117,11 @@ struct State {
     // slots 8w + 1 .. 8w + 8), and per fluid workgroup its staging record
     uint3 *pk12;
     int32_t *stagerec;      // [nblk][kStageRec]
+    // packed mode with FP32 sums: the row words the sweep reads, RHS and
+    // D_ii (FP32 sums, so their FP32 values are exact) and the neighbour
+    // count with the free-surface flag in bit 31                     [nf]
+    float2 *rd32;
+    int32_t *cf;
     void *wcoef;            // cached wall weights W_wf / sum W: (f, FP32) words or FP64 [cap][nw]
     double *wh;             // wall hydrostatic term                 [nw]
     int32_t *wflag;         // wall workgroup has a row with fluid neighbours at r*   [nwb]

@@ -1432,6 +1432,10 @@ struct RhsCoef {
             const double rr = (double)s, dd = (double)Dg;
             S.rhs[i] = rr;
             S.dii[i] = dd;
+            if (P.packed && sizeof(R) == 4) {
+                S.rd32[i] = make_float2((float)rr, (float)dd);   // FP32 sums: exact
+                S.cf[i] = c | (S.fs[i] ? (int32_t)0x80000000 : 0);
+            }
             if (dd != 0.0 && !S.fs[i])
                 lam = (unsigned long long)__double_as_longlong(plain32(P) ? (double)fabsf((float)rr / (float)dd)
                                                                           : fabs(rr / dd));
@@ -1895,10 +1899,19 @@ struct Sweep {
             if (live) {
                 load_coef<R, NGP>(i, nf, 0, gmax, S.coef, cc);
                 if (staged) load_codes<NWP>(i, nf, 0, wmax, S.pk12, cw);
-                D = S.dii[i];
-                r = S.rhs[i];
-                f = S.fs[i];
-                c = S.cnt[i];
+                if constexpr (sizeof(R) == 4) {   // 12 bytes of row words instead of 24
+                    const float2 rd = S.rd32[i];
+                    const int32_t w = S.cf[i];
+                    r = rd.x;
+                    D = rd.y;
+                    c = w & 0x7fffffff;
+                    f = w < 0;
+                } else {
+                    D = S.dii[i];
+                    r = S.rhs[i];
+                    f = S.fs[i];
+                    c = S.cnt[i];
+                }
                 pold = pc[i];
             }
             if (stopped < L) return;   // only earlier launches write values below L

@@ -32,7 +32,8 @@ def test_sweep_bytes_walls():
     assert (b["per_wall_row"], b["per_wall_pair"]) == (24, 8)
     assert b["bytes"] == 100 * 48 + 1500 * 8 and b["wall_bytes"] == 20 * 24 + 300 * 8
     packed = bench.sweep_bytes(mixed, slots=1600, index_bits=12)
-    assert packed["per_pair"] == 5.5 and packed["bytes"] == 100 * 48 + 1500 * 5.5
+    assert packed["per_row"] == 36 and packed["per_pair"] == 5.5
+    assert packed["bytes"] == 100 * 36 + 1500 * 5.5
     fp64 = cases.taylor_green(10, precision="fp64")
     b = bench.sweep_bytes(fp64, slots=1600, wall_pairs=300, wall_rows=20)
     assert (b["per_wall_row"], b["per_wall_pair"]) == (20, 12)
