@@ -79,7 +79,8 @@ UNIT_BYTES = {(2, "mixed"): 4 * 20 + 8 + 40, (3, "mixed"): 4 * 80 + 60 + 40,
               (2, "fp64"): 8 * 20 + 8 + 40, (3, "fp64"): 8 * 80 + 60 + 40}
 
 
-def sweep_bytes(case, slots: int, index_bits: int = 32, wall_pairs: int = 0, wall_rows: int = 0) -> dict:
+def sweep_bytes(case, slots: int, index_bits: int = 32, wall_pairs: int = 0, wall_rows: int = 0,
+                list_frac: float = 0.0) -> dict:
     """Bytes the data layout of one Jacobi sweep moves over the whole case.
 
     Per fluid row: neighbour count (4 B), RHS and D_ii (8 + 8), free-surface
@@ -88,7 +89,9 @@ def sweep_bytes(case, slots: int, index_bits: int = 32, wall_pairs: int = 0, wal
     reads it once (8); the packed mixed sweep reads RHS and D_ii as FP32 and
     count and flag as one word (36 B).  Per stored pair (self slot excluded): neighbour index
     (index_bits: 32, 16 as an offset, 12 as a position in the workgroup's
-    LDS copy of the iterate) and cached coefficient (4 mixed, 8 FP64).
+    LDS copy of the iterate; list_frac of the rows, in workgroups whose copy
+    would not fit, read 32-bit list entries instead) and cached coefficient
+    (4 mixed, 8 FP64).
     `bytes` is the sweep kernel's.  Cases with walls run the wall pressure
     kernel before every sweep; its bytes are `wall_bytes`: per wall row with
     fluid neighbours (no sweep reads the others, so the kernel skips them)
@@ -102,7 +105,7 @@ def sweep_bytes(case, slots: int, index_bits: int = 32, wall_pairs: int = 0, wal
     row = 4 + 8 + 8 + 4 + 8 + 8 + (4 + 4 if mixed else 8)
     if mixed and index_bits == 12:
         row -= 12   # RHS and D_ii as FP32 (exact: FP32 sums), count and flag in one word
-    pair = index_bits / 8 + (4 if mixed else 8)
+    pair = index_bits / 8 * (1.0 - list_frac) + 4 * list_frac + (4 if mixed else 8)
     total = nf * row + pairs * pair
     wall_row = 4 + 8 + 8 + (4 if mixed else 0)
     wall_pair = 8 if mixed else 12
@@ -353,8 +356,11 @@ def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool,
     pinfo = ctx.persistent_info()
     fallbacks = ctx.persistent_fallbacks()   # since the reset: the timed steps only
     wall_rows = ctx.rows_with_neighbours(1, 1) if case.n_wall else 0
+    nblk = -(-case.n_fluid // 256)
+    list_blocks = stats[-1]["list_blocks"] if stats else 0
     sb = sweep_bytes(case, ctx.pair_count(1, 0), index_bits=stats[-1]["index_bits"] if stats else 32,
-                     wall_pairs=ctx.pair_count(1, 1) if case.n_wall else 0, wall_rows=wall_rows)
+                     wall_pairs=ctx.pair_count(1, 1) if case.n_wall else 0, wall_rows=wall_rows,
+                     list_frac=list_blocks / nblk)
     unit = UNIT_BYTES[(case.dim, case.precision)]
     # the dominant kernel: the sweep, one launch per sweep, or one persistent
     # launch per solve holding its sweeps; both are timed by their own events
@@ -395,7 +401,8 @@ def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool,
                 "avg_us_per_effective_sweep": round(kernel_s * 1e6 / max(eff, 1), 3),
                 "persistent_fallbacks": fallbacks,
                 "layout": {"bytes_per_sweep": sb["bytes"], "bytes_per_row": sb["per_row"],
-                           "bytes_per_pair": sb["per_pair"], "pairs": sb["pairs"],
+                           "bytes_per_pair": round(sb["per_pair"], 4), "pairs": sb["pairs"],
+                           "index_bits": stats[-1]["index_bits"] if stats else 32, "list_blocks": list_blocks,
                            "achieved_GBps": round(layout_rate, 1),
                            "traffic_per_sweep": round(traffic) if traffic is not None else None}}
     if case.n_wall:

@@ -157,10 +157,11 @@ typedef struct {
                             every offset of the step within +-32767); 12
                             (walled Jacobi cases on grids periodic in no
                             direction: the neighbour's position in the
-                            workgroup's LDS copy of the iterate; 32 when a
-                            workgroup's copy would not fit and it reads the
-                            lists)                                         */
-    int32_t reserved;
+                            workgroup's LDS copy of the iterate; the
+                            workgroups whose copy would not fit read the
+                            lists, list_blocks below)                      */
+    int32_t list_blocks; /* packed mode: fluid workgroups (of 256 rows)
+                            whose sweeps read the lists this step          */
     double beta;         /* SISPH_NULL_PROJECT: the constant removed per unit
                             D_ii from the RHS (else 0)                      */
 } sisph_ppe_stats;

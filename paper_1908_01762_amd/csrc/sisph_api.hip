@@ -398,8 +398,8 @@ static void fill_stats(const Control &C, const Params &P, sisph_ppe_stats *out) 
     out->lambda = cv.d;
     out->p_ref = C.p_ref;
     out->dt = C.dt;
-    out->index_bits = P.packed && !C.pk_overflow ? 12 : (P.compact && !C.wide ? 16 : 32);
-    out->reserved = 0;
+    out->index_bits = P.packed ? 12 : (P.compact && !C.wide ? 16 : 32);
+    out->list_blocks = P.packed ? C.pk_overflow : 0;
     out->beta = P.null_space == SISPH_NULL_PROJECT ? C.beta : 0.0;
 }
 

@@ -73,7 +73,7 @@ struct Control {
     double bicg_rho[2], bicg_alpha[2], bicg_omega[2];
     int32_t bicg_brk;
     int32_t wide;                     // a neighbour offset of this step did not fit 16 bits
-    int32_t pk_overflow;              // packed mode: some workgroup of this step reads the lists
+    int32_t pk_overflow;              // packed mode: workgroups of this step that read the lists
     double beta;                      // SISPH_NULL_PROJECT: (y . RHS) / (y . D), y = m rho
 };
 

@@ -914,7 +914,7 @@ struct PackCodes {
             const bool periodic = g.per[0] || g.per[1] || g.per[2];
             const int cap = kStageBytes / (f32_sums(P.precision) ? 4 : 8);
             staged = !periodic && sp[NQ] <= cap;
-            if (!staged) atomicOr(&S.ctl->pk_overflow, 1);
+            if (!staged) atomicAdd(&S.ctl->pk_overflow, 1);
             rec[0] = staged;
         }
         __syncthreads();

@@ -52,13 +52,13 @@ class PPEStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("nonfinite", C.c_int32),
                 ("status", C.c_int32), ("ratio", C.c_double), ("lambda_", C.c_double),
                 ("p_ref", C.c_double), ("dt", C.c_double), ("index_bits", C.c_int32),
-                ("reserved", C.c_int32), ("beta", C.c_double)]
+                ("list_blocks", C.c_int32), ("beta", C.c_double)]
 
     def as_dict(self) -> dict:
         return dict(iters=self.iters, converged=bool(self.converged), nonfinite=bool(self.nonfinite),
                     case_status=self.status,
                     ratio=self.ratio, lam=self.lambda_, p_ref=self.p_ref, dt=self.dt,
-                    index_bits=self.index_bits, beta=self.beta)
+                    index_bits=self.index_bits, list_blocks=self.list_blocks, beta=self.beta)
 
 
 _lib = None

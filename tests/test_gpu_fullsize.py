@@ -217,8 +217,16 @@ def test_dam_break_3d_above_2p19_rows_one_step():
         results[precision] = (g, s, ctx.field("rho"), ctx.field("rhs"))
         ctx.close()
     g, s, rho, rhs = results["fp64"]
-    say(f"  sweeps gpu {g['iters']} oracle {out['iters']}")
+    say(f"  sweeps gpu {g['iters']} oracle {out['iters']}; fp64 list workgroups {g['list_blocks']}, "
+        f"mixed {results['mixed'][0]['list_blocks']} of {(base.n_fluid + 255) // 256}")
     assert g["iters"] == out["iters"]
+    # packed codes in both; the FP64 copy holds half the values of the FP32
+    # one, so there most workgroups read the lists instead (both paths are
+    # compared here); in the mixed mode the workgroups whose rows spread
+    # over many cells (near the free surface, 302 of 2,333 measured) do
+    assert g["index_bits"] == 12 and results["mixed"][0]["index_bits"] == 12
+    assert g["list_blocks"] > 0
+    assert results["mixed"][0]["list_blocks"] < 0.2 * ((base.n_fluid + 255) // 256)
     nf = base.n_fluid
     for name, a, b in (("rho", rho, out["rho"]), ("rhs", rhs, out["rhs"]), ("p", s["p"], ref.p),
                        ("u", s["u"], ref.u), ("displacement", s["x"][:nf] - base.x[:nf], ref.x[:nf] - base.x[:nf])):
