@@ -246,6 +246,9 @@ static void carve(const Params &P, Carver &c, State &S) {
     if (f32_sums(P.precision)) {
         S.m32 = c.take<float>(nt);
         S.rho32 = c.take<float>(nt);
+        S.prec = c.take<PredRecF>(nt);
+    } else {
+        S.prec = c.take<PredRecD>(nt);
     }
     S.rhs = c.take<double>(nf);
     S.dii = c.take<double>(nf);

@@ -100,6 +100,8 @@ struct State {
     void *mr2;         // m / rho^2 in the working precision [ntot]
     // FP32 copies for the mixed-mode pair gathers (see Shadow)
     float *m32, *rho32;        // [ntot]
+    // the predictor's gathered fields, one record per particle (PredRec)
+    void *prec;                // [ntot]
     double *rhs, *dii; //                            [nf]
     int32_t *fs;       // free-surface flag          [nf]
     int32_t *id;       // original index of sorted fluid slot [nf]
@@ -138,6 +140,19 @@ struct State {
     // one 256-byte line each) the word workgroup 0 posts after each sweep;
     // at kSyncArrive + b the sweeps workgroup b has finished
     uint32_t *sync;
+};
+
+// The fields the predictor gathers for a neighbour, in one record (five or
+// six 16-byte loads instead of eleven scattered ones): r^n, u^n (walls:
+// the ghost velocity), the transport velocity (fluid; 0 for walls), mass and
+// density in the working precision.
+struct __align__(16) PredRecF {
+    double x[3], u[3], ut[3];
+    float m, rho;
+};
+struct __align__(16) PredRecD {
+    double x[3], u[3], ut[3];
+    double m, rho;
 };
 
 // Launch-size kinds: how many workgroups one case needs for a kernel.

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
+#include <type_traits>
 
 #include "sisph_internal.h"
 
@@ -1194,30 +1195,30 @@ struct Predictor {
         const R eps = (R)P.eps_h, nu4 = (R)(4.0 * P.nu), avc = (R)(P.alpha * P.h * P.c_ref);
         R fv[3] = {0, 0, 0}, fa[3] = {0, 0, 0}, fsr[3] = {0, 0, 0};
         const int c = S.cnt[i];
+        using Rec = typename std::conditional<sizeof(R) == 4, PredRecF, PredRecD>::type;
+        const Rec *prec = (const Rec *)S.prec;
         for (int k0 = 1; k0 < c; k0 += kPairBatch) {
             int64_t jb[kPairBatch];
             double xj[kPairBatch][3], ub[kPairBatch][3], utb[kPairBatch][3];
             R mb[kPairBatch], rhob[kPairBatch];
             batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
-            batch_pos<D>(x, jb, xj);
+            // one record per neighbour: positions, velocities in FP64 in
+            // every mode (their pair differences are small against the
+            // velocities and are formed before any rounding to the working
+            // precision), u~ (0 for walls, whose term is not formed), and
+            // mass and density in the working precision
+            Rec rb[kPairBatch];
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) rb[t] = prec[jb[t]];
 #pragma unroll
             for (int t = 0; t < kPairBatch; ++t) {
-                const int64_t j = jb[t], jf = j < nf ? j : i;   // u~ is held for fluid particles only
-                for (int a = 0; a < 3; ++a) ub[t][a] = utb[t][a] = 0.0;
-                // velocities in FP64 in every mode: their pair differences
-                // are small against the velocities and are formed before
-                // any rounding to the working precision
-                for (int a = 0; a < D; ++a) {
-                    ub[t][a] = u.c[a][j];
-                    utb[t][a] = ut.c[a][jf];
+                for (int a = 0; a < 3; ++a) {
+                    xj[t][a] = rb[t].x[a];
+                    ub[t][a] = rb[t].u[a];
+                    utb[t][a] = rb[t].ut[a];
                 }
-                if constexpr (sizeof(R) == 4) {   // the FP32 copies: the same values, half the bytes
-                    mb[t] = S.m32[j];
-                    rhob[t] = S.rho32[j];
-                } else {
-                    mb[t] = S.m[j];
-                    rhob[t] = S.rho[j];
-                }
+                mb[t] = rb[t].m;
+                rhob[t] = rb[t].rho;
             }
 #pragma unroll
             for (int t = 0; t < kPairBatch; ++t) {
@@ -1323,15 +1324,29 @@ __device__ __forceinline__ int32_t offset_index(int64_t i, int16_t o, int64_t nf
 }
 
 // FP32 copies of the mass and density the mixed-mode pair loops gather
-// (they convert each gathered value to FP32 anyway), after the density.
-// Velocities are gathered in FP64: the loops form their pair differences
-// first.
+// (they convert each gathered value to FP32 anyway), after the density;
+// and the predictor's gather records.  Velocities are gathered in FP64: the
+// loops form their pair differences first.
+template <typename R>
 struct Shadow {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         if (i >= P.ntot) return;
-        S.m32[i] = (float)S.m[i];
-        S.rho32[i] = (float)S.rho[i];
+        using Rec = typename std::conditional<sizeof(R) == 4, PredRecF, PredRecD>::type;
+        Rec rec;
+        for (int a = 0; a < 3; ++a) {
+            const bool on = a < P.dim;
+            rec.x[a] = on ? S.x[a][i] : 0.0;
+            rec.u[a] = on ? S.u[a][i] : 0.0;
+            rec.ut[a] = on && i < P.nf ? S.ut[a][i] : 0.0;
+        }
+        rec.m = (R)S.m[i];
+        rec.rho = (R)S.rho[i];
+        ((Rec *)S.prec)[i] = rec;
+        if constexpr (sizeof(R) == 4) {
+            S.m32[i] = (float)S.m[i];
+            S.rho32[i] = (float)S.rho[i];
+        }
     }
 };
 
@@ -3386,8 +3401,8 @@ void step_maxima(const Target &T) { SISPH_DISPATCH_D(T, (launch<StepMaxima<D>, K
 void next_dt(const Target &T) { launch<NextDt, K_ONE>(T); }
 
 void shadow(const Target &T) {
-    if (!f32_sums(T.precision)) return;
-    launch<Shadow, K_TOT>(T);
+    if (f32_sums(T.precision)) launch<Shadow<float>, K_TOT>(T);
+    else launch<Shadow<double>, K_TOT>(T);
 }
 
 void mass_over_rho2(const Target &T) {
