@@ -707,6 +707,7 @@ static void seq_predict(const Target &T) {
 
 static void seq_ppe_begin(const Target &T) {
     reset_control(T, RESET_PPE);
+    coef_seed(T);
     rhs_coef(T);
     if (T.null_space) project_rhs(T);
     wall_coef(T);
@@ -722,6 +723,7 @@ static void seq_ppe_end(const Target &T) {
 }
 
 static void seq_correct(const Target &T, int maxK) {
+    corr_seed(T);
     correct(T);
     if (T.adaptive) {
         step_maxima(T);   // before the GTVF sub-steps reuse the acceleration buffer

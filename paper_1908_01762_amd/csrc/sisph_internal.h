@@ -100,7 +100,8 @@ struct State {
     void *mr2;         // m / rho^2 in the working precision [ntot]
     // FP32 copies for the mixed-mode pair gathers (see Shadow)
     float *m32, *rho32;        // [ntot]
-    // the predictor's gathered fields, one record per particle (PredRec)
+    // the gathered fields of the predictor, the PPE coefficients or the
+    // pressure force, one record per particle (PredRec, CoefRec, CorrRec)
     void *prec;                // [ntot]
     double *rhs, *dii; //                            [nf]
     int32_t *fs;       // free-surface flag          [nf]
@@ -153,6 +154,21 @@ struct __align__(16) PredRecF {
 struct __align__(16) PredRecD {
     double x[3], u[3], ut[3];
     double m, rho;
+};
+// The same for the PPE coefficients (r*, u* (walls: the slip ghost), mass
+// and density) and for the pressure force (r*, the solved pressure,
+// density in FP64 and mass in the working precision), written into the same
+// buffer before each of them.
+struct __align__(16) CoefRecF {
+    double x[3], u[3];
+    float m, rho;
+};
+struct __align__(16) CoefRecD {
+    double x[3], u[3];
+    double m, rho;
+};
+struct __align__(16) CorrRec {
+    double x[3], p, rho, m;
 };
 
 // Launch-size kinds: how many workgroups one case needs for a kernel.
@@ -289,6 +305,8 @@ void next_dt(const Target &T);
 void gtvf_substep(const Target &T, int k);
 void advance(const Target &T);
 void gtvf_seed(const Target &T);
+void coef_seed(const Target &T);
+void corr_seed(const Target &T);
 void gather_control(const Target &T, Control *out);
 
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);

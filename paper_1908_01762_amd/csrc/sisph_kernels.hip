@@ -1350,6 +1350,38 @@ struct Shadow {
     }
 };
 
+template <typename R>
+struct CoefSeed {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        ROW;
+        if (i >= P.ntot) return;
+        using Rec = typename std::conditional<sizeof(R) == 4, CoefRecF, CoefRecD>::type;
+        Rec rec;
+        for (int a = 0; a < 3; ++a) {
+            const bool on = a < P.dim;
+            rec.x[a] = on ? S.xs[a][i] : 0.0;
+            rec.u[a] = on ? S.us[a][i] : 0.0;
+        }
+        rec.m = (R)S.m[i];
+        rec.rho = (R)S.rho[i];
+        ((Rec *)S.prec)[i] = rec;
+    }
+};
+
+template <typename R>
+struct CorrSeed {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        ROW;
+        if (i >= P.ntot) return;
+        CorrRec rec;
+        for (int a = 0; a < 3; ++a) rec.x[a] = a < P.dim ? S.xs[a][i] : 0.0;
+        rec.p = S.p[0][i];
+        rec.rho = S.rho[i];
+        rec.m = (double)(R)S.m[i];
+        ((CorrRec *)S.prec)[i] = rec;
+    }
+};
+
 // ------------------------------------------------- PPE RHS and coefficients
 // eq. sph-ppe / coeff / coeff1 at r*: RHS_i = sum -m_j/(rho_j dt) u*_ij.gradW,
 // c_ij = 4 m_j / (rho_i (rho_i + rho_j)) (r_ij.gradW) / (r^2 + eta h^2),
@@ -1379,27 +1411,27 @@ struct RhsCoef {
             // a batch of kPairBatch = 4 slots is one group of coefficients
             // (and indices or offsets), written with one store each
             static_assert(kPairBatch == 4, "one coefficient group per batch");
+            using Rec = typename std::conditional<sizeof(R) == 4, CoefRecF, CoefRecD>::type;
+            const Rec *crec = (const Rec *)S.prec;
             for (int k0 = 1; k0 < c; k0 += kPairBatch) {
                 int64_t jb[kPairBatch];
                 double xj[kPairBatch][3], usb[kPairBatch][3];
                 R mb[kPairBatch], rhob[kPairBatch];
                 batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
-                batch_pos<D>(xs, jb, xj);
+                // one record per neighbour; u* in FP64: u*_ij is formed
+                // before rounding (the RHS is the divergence of a nearly
+                // solenoidal field, a sum of terms that mostly cancel)
+                Rec rb[kPairBatch];
+#pragma unroll
+                for (int t = 0; t < kPairBatch; ++t) rb[t] = crec[jb[t]];
 #pragma unroll
                 for (int t = 0; t < kPairBatch; ++t) {
-                    const int64_t j = jb[t];
-                    for (int a = 0; a < 3; ++a) usb[t][a] = 0.0;
-                    // u* in FP64: u*_ij is formed before rounding (the RHS
-                    // is the divergence of a nearly solenoidal field, a sum
-                    // of terms that mostly cancel)
-                    for (int a = 0; a < D; ++a) usb[t][a] = us.c[a][j];
-                    if constexpr (sizeof(R) == 4) {
-                        mb[t] = S.m32[j];
-                        rhob[t] = S.rho32[j];
-                    } else {
-                        mb[t] = S.m[j];
-                        rhob[t] = S.rho[j];
+                    for (int a = 0; a < 3; ++a) {
+                        xj[t][a] = rb[t].x[a];
+                        usb[t][a] = rb[t].u[a];
                     }
+                    mb[t] = rb[t].m;
+                    rhob[t] = rb[t].rho;
                 }
                 R c4[4] = {R(0), R(0), R(0), R(0)};
                 int32_t j4[4] = {(int32_t)i, (int32_t)i, (int32_t)i, (int32_t)i};
@@ -2565,17 +2597,22 @@ struct Correct {
         R f[3] = {0, 0, 0};
         const int c = S.cnt[i];
         const bool symm = P.pgrad == SISPH_SYMM;
+        const CorrRec *crec = (const CorrRec *)S.prec;
         for (int k0 = 1; k0 < c; k0 += kPairBatch) {
             int64_t jb[kPairBatch];
             double xj[kPairBatch][3], rhob[kPairBatch], pb[kPairBatch];
             R mb[kPairBatch];
             batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
-            batch_pos<D>(xs, jb, xj);
+            // one record per neighbour: r*, p, rho, m
+            CorrRec rb[kPairBatch];
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) rb[t] = crec[jb[t]];
 #pragma unroll
             for (int t = 0; t < kPairBatch; ++t) {
-                mb[t] = sizeof(R) == 4 ? (R)S.m32[jb[t]] : (R)S.m[jb[t]];
-                rhob[t] = S.rho[jb[t]];
-                pb[t] = p[jb[t]];
+                for (int a = 0; a < 3; ++a) xj[t][a] = rb[t].x[a];
+                mb[t] = (R)rb[t].m;
+                rhob[t] = rb[t].rho;
+                pb[t] = rb[t].p;
             }
 #pragma unroll
             for (int t = 0; t < kPairBatch; ++t) {
@@ -3399,6 +3436,16 @@ void correct(const Target &T) { SISPH_DISPATCH_KDR(T, (launch<Correct<KER, D, R>
 void step_maxima(const Target &T) { SISPH_DISPATCH_D(T, (launch<StepMaxima<D>, K_FLUID>(T))); }
 
 void next_dt(const Target &T) { launch<NextDt, K_ONE>(T); }
+
+void coef_seed(const Target &T) {
+    if (f32_sums(T.precision)) launch<CoefSeed<float>, K_TOT>(T);
+    else launch<CoefSeed<double>, K_TOT>(T);
+}
+
+void corr_seed(const Target &T) {
+    if (f32_sums(T.precision)) launch<CorrSeed<float>, K_TOT>(T);
+    else launch<CorrSeed<double>, K_TOT>(T);
+}
 
 void shadow(const Target &T) {
     if (f32_sums(T.precision)) launch<Shadow<float>, K_TOT>(T);
