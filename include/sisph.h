@@ -326,6 +326,13 @@ int32_t sisph_set_persistent(sisph_ctx *ctx, int32_t on);
  * solve gives up (0: at once, which exercises the fallback above). */
 int32_t sisph_debug_barrier_spins(sisph_ctx *ctx, uint32_t spins);
 
+/* Test hook: on = 0 makes a single context's sweeps read the neighbour
+ * lists instead of the packed mode's LDS copy and codes (walled Jacobi
+ * cases on grids periodic in no direction), on = 1 restores them; the sums
+ * and their order are the same either way.  SISPH_E_INVAL for on = 1 on a
+ * case without the packed mode. */
+int32_t sisph_debug_packed(sisph_ctx *ctx, int32_t on);
+
 int32_t sisph_destroy(sisph_ctx *ctx);
 
 /* ------------------------------------------------------------- autotuning

@@ -1361,6 +1361,16 @@ extern "C" int32_t sisph_debug_barrier_spins(sisph_ctx *ctx, uint32_t spins) {
     return SISPH_OK;
 }
 
+extern "C" int32_t sisph_debug_packed(sisph_ctx *ctx, int32_t on) {
+    if (!ctx) return SISPH_E_INVAL;
+    const bool can = make_params(&ctx->desc).packed != 0;   // its buffers exist
+    if (on && !can) return fail(ctx, SISPH_E_INVAL, "this case has no packed mode");
+    ctx->P.packed = on && can ? 1 : 0;
+    ctx->T = single_target(ctx);
+    drop_graphs(ctx->g_pre, ctx->g_post);   // captured with the old parameters
+    return SISPH_OK;
+}
+
 extern "C" int32_t sisph_persistent_fallbacks(sisph_ctx *ctx, int64_t *refused, int64_t *timed_out) {
     if (!ctx) return SISPH_E_INVAL;
     if (refused) *refused = ctx->persist_refused;

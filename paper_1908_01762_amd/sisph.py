@@ -103,6 +103,8 @@ def lib():
         L.sisph_set_persistent.argtypes = [C.c_void_p, C.c_int32]
         L.sisph_debug_barrier_spins.restype = C.c_int32
         L.sisph_debug_barrier_spins.argtypes = [C.c_void_p, C.c_uint32]
+        L.sisph_debug_packed.restype = C.c_int32
+        L.sisph_debug_packed.argtypes = [C.c_void_p, C.c_int32]
         L.sisph_persistent_info.restype = C.c_int32
         L.sisph_persistent_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         L.sisph_set_kernel_timing.restype = C.c_int32
@@ -368,6 +370,11 @@ class Context:
         ms, n, p = C.c_double(), C.c_int64(), C.c_int64()
         _check(lib().sisph_kernel_timing(self.h, C.byref(ms), C.byref(n), C.byref(p)), self.h)
         return dict(ms=ms.value, launches=n.value, persistent=p.value)
+
+    def debug_packed(self, on: bool):
+        """Test hook: sweeps through the lists (False) or the packed mode's
+        LDS copy and codes (True, the default where the case has it)."""
+        _check(lib().sisph_debug_packed(self.h, int(bool(on))), self.h)
 
     def debug_barrier_spins(self, spins: int):
         """Test hook: polls before a persistent-solve wait gives up."""
