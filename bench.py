@@ -400,6 +400,10 @@ def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool,
                 "effective_sweeps": eff,
                 "avg_us_per_effective_sweep": round(kernel_s * 1e6 / max(eff, 1), 3),
                 "persistent_fallbacks": fallbacks,
+                "note": ("the cached-coefficient method's bytes over the sweep time; the persistent solve keeps "
+                         "its coefficients in registers and is bound by its grid barrier, not by HBM")
+                if n_persistent else ("the cached-coefficient method's bytes over the sweep kernel's time; "
+                                      "the kernel streams its coefficients and codes from HBM"),
                 "layout": {"bytes_per_sweep": sb["bytes"], "bytes_per_row": sb["per_row"],
                            "bytes_per_pair": round(sb["per_pair"], 4), "pairs": sb["pairs"],
                            "index_bits": stats[-1]["index_bits"] if stats else 32, "list_blocks": list_blocks,

@@ -709,6 +709,9 @@ __device__ __forceinline__ void scan_staged(const Params &P, const Grid &g, cons
     constexpr int U = kScanBatch;
     const int64_t nf = P.nf;
     const int32_t self = (int32_t)i;
+    // the row's next list slot, moved on by a stride per entry (no index
+    // product per entry)
+    int32_t *slot = nbr + (int64_t)c * nf + i;
     uint32_t t = t0;
     for (; t + (U - 1) < t1; t += U) {
         int32_t jv[U];
@@ -718,14 +721,16 @@ __device__ __forceinline__ void scan_staged(const Params &P, const Grid &g, cons
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (hv[u]) {
-                if (c < P.cap) nbr[(int64_t)c * nf + i] = jv[u];
+                if (c < P.cap) *slot = jv[u];
+                slot += nf;
                 ++c;
             }
     }
     for (; t < t1; ++t) {
         int32_t j;
         if (staged_hit<D, PER>(P, g, sx, sj, t, self, xi, j)) {
-            if (c < P.cap) nbr[(int64_t)c * nf + i] = j;
+            if (c < P.cap) *slot = j;
+            slot += nf;
             ++c;
         }
     }
