@@ -88,6 +88,8 @@ static hipError_t ev_sync(hipEvent_t e) { return e ? hipEventSynchronize(e) : hi
 // ----------------------------------------------------------- descriptor
 static double support_of(int kernel) { return kernel == SISPH_QUINTIC ? 3.0 : 2.0; }
 
+static int32_t neighbour_cap(const sisph_case_desc *d);
+
 static const char *check_desc(const sisph_case_desc *d) {
     if (!d) return "null descriptor";
     if (d->dim != 2 && d->dim != 3) return "dim must be 2 or 3";
@@ -117,6 +119,8 @@ static const char *check_desc(const sisph_case_desc *d) {
     if (d->forced_iters < 0 || d->forced_iters >= INT32_MAX - 1) return "forced_iters out of range";
     if (d->gtvf != SISPH_GTVF_OFF && d->gtvf_K < 1) return "gtvf_K must be >= 1";
     if (d->nbr_cap < 0) return "nbr_cap must be >= 0";
+    if ((int64_t)neighbour_cap(d) * d->n_wall >= (int64_t)1 << 32)
+        return "nbr_cap x n_wall reaches 2^32 (wall weight offsets are 32-bit)";
     double R = support_of(d->kernel) * d->h;
     for (int k = 0; k < d->dim; ++k) {
         double L = d->box_hi[k] - d->box_lo[k];
@@ -286,6 +290,9 @@ static void carve(const Params &P, Carver &c, State &S) {
     S.wh = c.take<double>(nw);
     S.wflag = c.take<int32_t>(kind_blocks(P, K_WALL) + 1);
     S.wblk = c.take<int32_t>(kind_blocks(P, K_WALL) + 1);
+    S.wsum = c.take<uint32_t>(2 * kind_blocks(P, K_WALL) + 2);
+    S.wrow = c.take<uint2>(nw + 1);
+    S.woffw = c.take<uint32_t>(nw);
     S.partial = c.take<double>(4 * kind_blocks(P, K_FLUID));
     S.tmp = c.take<double>(16 * nmax);
     S.bx = S.br = S.brh = S.bp = S.bv = S.bs = S.bt = S.bf = S.bh = S.bpart = nullptr;

@@ -125,10 +125,16 @@ struct State {
     // count with the free-surface flag in bit 31                     [nf]
     float2 *rd32;
     int32_t *cf;
-    void *wcoef;            // cached wall weights W_wf / sum W: (f, FP32) words or FP64 [cap][nw]
+    void *wcoef;            // cached wall weights W_wf / sum W: FP32 sums: (f, weight) words, each
+                            // row's run at woffw[w]; FP64: weights [cap][nw] (indices from wnbr)
     double *wh;             // wall hydrostatic term                 [nw]
     int32_t *wflag;         // wall workgroup has a row with fluid neighbours at r*   [nwb]
     int32_t *wblk;          // [0] = count, then those workgroups in order            [1 + nwb]
+    uint32_t *wsum;         // per wall workgroup: rows with fluid neighbours, their entries;
+                            // then exclusive prefixes; [2 nwb] = totals                 [2 nwb + 2]
+    uint2 *wrow;            // rows with fluid neighbours in wall order: (w, first word);
+                            // [rows] = (~0, all words)                                    [nw + 1]
+    uint32_t *woffw;        // each wall row's first word                                 [nw]
     double *partial;        // per-workgroup partial sums of two sweeps [2][2][nblk]
     double *tmp;            // reorder scratch [16][max(nf, nw)]
     // BiCGStab (solver only): x, r, r^, p, v, s, t, scaled RHS f, wall

@@ -2391,11 +2391,47 @@ __global__ __launch_bounds__(kBlock) void k_ppe_persistent_batch(const CaseEntry
 // the fluid index in the mixed mode, FP32 weight) and the hydrostatic term
 // h_w = g . sum rho_f r_wf W_wf / sum W; each sweep then forms
 // p_w = sum_f a_wf p_f + h_w.
+// In the FP32-sum modes the words go where the per-sweep pass reads them
+// with no waste: each wall row with fluid neighbours has its c_w words in
+// one run, the runs one after the other in wall order (a slot-major layout
+// would fetch every line that any row of its sixteen holds a slot in, about
+// three times the words on a walled 3D case).  The workgroup's offsets come
+// from WallBlocks; a row's place within its workgroup is an exclusive scan
+// over its rows of (has neighbours, c_w).
 template <int KER, int D, typename R>
 struct WallCoef {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         const int64_t w = i;
+        uint32_t off = 0;
+        if constexpr (sizeof(R) == 4) {
+            __shared__ uint32_t wave_a[kBlock / 64], wave_c[kBlock / 64];
+            const uint32_t cw = w < P.nw ? (uint32_t)S.wcnt[w] : 0u, aw = cw > 0u;
+            uint32_t ia = aw, ic = cw;   // inclusive scan over the wave
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t ta = __shfl_up(ia, o, 64), tc = __shfl_up(ic, o, 64);
+                if (lane >= o) {
+                    ia += ta;
+                    ic += tc;
+                }
+            }
+            if (lane == 63) {
+                wave_a[wave] = ia;
+                wave_c[wave] = ic;
+            }
+            __syncthreads();
+            uint32_t ba = S.wsum[2 * blk], bc = S.wsum[2 * blk + 1];
+            for (int v = 0; v < wave; ++v) {
+                ba += wave_a[v];
+                bc += wave_c[v];
+            }
+            off = bc + ic - cw;
+            if (w < P.nw) {
+                S.woffw[w] = off;
+                if (aw) S.wrow[ba + ia - aw] = make_uint2((uint32_t)w, off);
+            }
+        }
         if (w >= P.nw) return;
         const int64_t iw = P.nf + w, nw = P.nw;
         Kern<KER, D, R> K(P.h);
@@ -2429,7 +2465,7 @@ struct WallCoef {
             R d[3], r2;
             pair_diff<D, R>(P.grid, xi, xs, f, d, r2);
             const R a = K.w(sqrt(r2)) * inv;
-            if constexpr (sizeof(R) == 4) ((PairF *)S.wcoef)[at] = PairF{(int32_t)f, a};
+            if constexpr (sizeof(R) == 4) ((PairF *)S.wcoef)[(int64_t)off + k] = PairF{(int32_t)f, a};
             else ((double *)S.wcoef)[at] = a;
         }
     }
@@ -2446,12 +2482,33 @@ struct WallCoef {
 // workgroups made only of such rows (the final pass after the solve still
 // covers every wall row).  WallFlags marks each wall workgroup; WallBlocks
 // (one workgroup per case) lists the marked ones in order.
+// WallFlags also counts the workgroup's rows with neighbours and their
+// entries, which WallBlocks turns into exclusive prefixes in place (the
+// placement of the FP32 weight runs).
 struct WallFlags {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
+        __shared__ uint32_t wave_a[kBlock / 64], wave_c[kBlock / 64];
         ROW;
-        const int active = (i < P.nw && S.wcnt[i] > 0) ? 1 : 0;
-        const int any = __syncthreads_or(active);
-        if (threadIdx.x == 0) S.wflag[blk] = any;
+        uint32_t c = i < P.nw ? (uint32_t)S.wcnt[i] : 0u, a = c > 0u;
+        for (int o = 32; o > 0; o >>= 1) {
+            a += __shfl_xor(a, o, 64);
+            c += __shfl_xor(c, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            wave_a[threadIdx.x >> 6] = a;
+            wave_c[threadIdx.x >> 6] = c;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t ta = 0, tc = 0;
+            for (int v = 0; v < kBlock / 64; ++v) {
+                ta += wave_a[v];
+                tc += wave_c[v];
+            }
+            S.wflag[blk] = ta > 0;
+            S.wsum[2 * blk] = ta;
+            S.wsum[2 * blk + 1] = tc;
+        }
     }
 };
 
@@ -2475,42 +2532,157 @@ struct WallBlocks {
         for (int64_t b = b0; b < b1; ++b)
             if (S.wflag[b] != 0) S.wblk[1 + pos++] = (int32_t)b;
         if (threadIdx.x == kBlock - 1) S.wblk[0] = sh[kBlock - 1];
+        // exclusive prefixes of the (rows, entries) counts, chunk by chunk
+        __shared__ uint32_t sa[kBlock], sc[kBlock];
+        uint32_t ta = 0, tc = 0;
+        for (int64_t b = b0; b < b1; ++b) {
+            ta += S.wsum[2 * b];
+            tc += S.wsum[2 * b + 1];
+        }
+        sa[threadIdx.x] = ta;
+        sc[threadIdx.x] = tc;
+        __syncthreads();
+        for (int off = 1; off < kBlock; off <<= 1) {
+            const uint32_t va = threadIdx.x >= off ? sa[threadIdx.x - off] : 0u;
+            const uint32_t vc = threadIdx.x >= off ? sc[threadIdx.x - off] : 0u;
+            __syncthreads();
+            sa[threadIdx.x] += va;
+            sc[threadIdx.x] += vc;
+            __syncthreads();
+        }
+        uint32_t ra = sa[threadIdx.x] - ta, rc = sc[threadIdx.x] - tc;
+        for (int64_t b = b0; b < b1; ++b) {
+            const uint32_t a = S.wsum[2 * b], c = S.wsum[2 * b + 1];
+            S.wsum[2 * b] = ra;
+            S.wsum[2 * b + 1] = rc;
+            ra += a;
+            rc += c;
+        }
+        if (threadIdx.x == kBlock - 1) {
+            S.wsum[2 * nb] = sa[kBlock - 1];
+            S.wsum[2 * nb + 1] = sc[kBlock - 1];
+            S.wrow[sa[kBlock - 1]] = make_uint2(~0u, sc[kBlock - 1]);
+        }
     }
 };
 
-template <typename R>
+// FP64: weights and fluid indices of slots k0 .. k0+kPairBatch-1 of the
+// [cap][nw] weights and lists (slot clamped into the storage).
 __device__ __forceinline__ void wall_words(const State &S, int64_t nw, int64_t w, int k0, int cap,
-                                           R (&cb)[kPairBatch], int32_t (&jr)[kPairBatch]) {
+                                           double (&cb)[kPairBatch], int32_t (&jr)[kPairBatch]) {
 #pragma unroll
     for (int t = 0; t < kPairBatch; ++t) {
         const int k = k0 + t < cap ? k0 + t : cap - 1;
         const int64_t at = (int64_t)k * nw + w;
-        if constexpr (sizeof(R) == 4) {
-            const PairF e = ((const PairF *)S.wcoef)[at];
+        cb[t] = ((const double *)S.wcoef)[at];
+        jr[t] = S.wnbr[at];
+    }
+}
+
+// FP32 sums: sum_f a_wf p_f of one wall row over its run of c words at a0,
+// kWallLanes lanes per row.  Lane q takes words q, q + kWallLanes, ... (the
+// group reads consecutive words), kWallWords of them per batch, and adds
+// its terms in word order; the row's sum is the butterfly over the group
+// ((s0 + s1) + (s2 + s3)) + ..., the same bits on every lane of the group
+// (IEEE addition commutes).  Words past the run are clamped to its last
+// one (word 0 of the buffer for an empty run) and add nothing.
+constexpr int kWallLanes = 4, kWallWords = 8;
+
+__device__ __forceinline__ float wall_run_sum(const State &S, const float *qc, int64_t a0, int c, int q,
+                                              int64_t iw) {
+    const PairF *wd = (const PairF *)S.wcoef + a0;
+    const int last = c > 0 ? c - 1 : 0;
+    float s = 0.0f;
+    for (int b0 = 0;; b0 += kWallLanes * kWallWords) {
+        float cb[kWallWords], v[kWallWords];
+        int32_t jr[kWallWords];
+#pragma unroll
+        for (int t = 0; t < kWallWords; ++t) {
+            const int k = b0 + q + kWallLanes * t;
+            const PairF e = wd[k < c ? k : last];
             cb[t] = e.c;
             jr[t] = e.j;
-        } else {
-            cb[t] = ((const double *)S.wcoef)[at];
-            jr[t] = S.wnbr[at];
         }
+#pragma unroll
+        for (int t = 0; t < kWallWords; ++t) {
+            const int k = b0 + q + kWallLanes * t;
+            v[t] = qc[k < c ? (int64_t)jr[t] : iw];   // iw: a valid index, term not added
+        }
+#pragma unroll
+        for (int t = 0; t < kWallWords; ++t) {
+            const int k = b0 + q + kWallLanes * t;
+            const float acc = fmaf(cb[t], v[t], s);
+            s = k < c ? acc : s;
+        }
+        if (b0 + kWallLanes * kWallWords >= c) break;   // the same on the row's four lanes
     }
+    for (int o = 1; o < kWallLanes; o <<= 1) s += __shfl_xor(s, o);
+    return s;
 }
 
 template <typename R>
 struct WallPressure {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int L, int final) {
+        const int64_t nw = P.nw, nb = (nw + kBlock - 1) / kBlock;
+        // FP32 sums: during the solve the rows with fluid neighbours
+        // (compact, in the first launch slots); the final pass every wall
+        // row.  A workgroup takes kBlock / kWallLanes rows at a time,
+        // striding by the grid.  The row count and the first row's entry
+        // are read with the stop flag rather than after it (wrow has nw + 1
+        // entries; one past the rows is read and not used).
+        const int64_t stride = nb * (kBlock / kWallLanes);
+        int64_t r = blk * (kBlock / kWallLanes) + threadIdx.x / kWallLanes;
+        int64_t listed = 0;
+        uint2 e = make_uint2(0u, 0u), e1 = e;
+        if (sizeof(R) == 4 && !final) {
+            listed = S.wsum[2 * nb];
+            const int64_t rc = r < nw ? r : nw;
+            e = S.wrow[rc];
+            e1 = S.wrow[rc < nw ? rc + 1 : nw];
+        }
+        if (!final && __hip_atomic_load(&S.ctl->stopped_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < L) return;
+        const int par = final ? 0 : (L & 1);
+        double *pc = S.p[par];
+        float *qc = S.p32 + par * P.ntot;
+        if constexpr (sizeof(R) == 4) {
+            const int64_t rows = final ? nw : listed;
+            const int q = threadIdx.x & (kWallLanes - 1);
+            for (; r < rows; r += stride) {
+                int64_t w, a0;
+                int c;
+                if (final) {
+                    w = r;
+                    c = S.wcnt[w];
+                    a0 = c > 0 ? (int64_t)S.woffw[w] : 0;
+                } else {
+                    w = e.x;
+                    a0 = e.y;
+                    c = (int)(e1.y - e.y);
+                    if (r + stride < rows) {
+                        e = S.wrow[r + stride];
+                        e1 = S.wrow[r + stride + 1];
+                    }
+                }
+                const double h = S.wh[w];
+                const int64_t iw = P.nf + w;
+                const float sp = wall_run_sum(S, qc, a0, c, q, iw);
+                double pw = plain32(P) ? (double)(sp + (float)h) : (double)sp + h;
+                if (P.free_surface && pw < 0.0) pw = 0.0;
+                if (q == 0) {
+                    pc[iw] = pw;
+                    qc[iw] = (float)pw;
+                }
+            }
+            return;
+        }
         if (!final) {
-            if (__hip_atomic_load(&S.ctl->stopped_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < L) return;
             if (blk >= S.wblk[0]) return;   // the listed workgroups take the first launch slots
             blk = S.wblk[1 + blk];
         }
         ROW;
         const int64_t w = i;
-        if (w >= P.nw) return;
-        const int par = final ? 0 : (L & 1);
-        double *pc = S.p[par];
-        float *qc = S.p32 + par * P.ntot;
-        const int64_t iw = P.nf + w, nw = P.nw;
+        if (w >= nw) return;
+        const int64_t iw = P.nf + w;
         const int c = S.wcnt[w];
         // kPairBatch slots at a time: weights and indices, then the gathered
         // iterate values, then the terms in slot order; the first batch's
@@ -2520,28 +2692,24 @@ struct WallPressure {
         // selected rather than branched over, so no load waits behind a
         // branch.  sp + 0 leaves sp unchanged (sp starts at +0 and never
         // becomes -0), so the sum is the plain slot-order sum.
-        R sp = R(0);
-        R cb[kPairBatch];
+        double sp = 0.0;
+        double cb[kPairBatch];
         int32_t jr[kPairBatch];
-        wall_words<R>(S, nw, w, 0, P.cap, cb, jr);
+        wall_words(S, nw, w, 0, P.cap, cb, jr);
         for (int k0 = 0;;) {
-            R q[kPairBatch];
+            double q[kPairBatch];
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) q[t] = pc[k0 + t < c ? (int64_t)jr[t] : iw];
 #pragma unroll
             for (int t = 0; t < kPairBatch; ++t) {
-                const int64_t j = k0 + t < c ? (int64_t)jr[t] : iw;   // iw: a valid index, term not added
-                if constexpr (sizeof(R) == 4) q[t] = qc[j];
-                else q[t] = pc[j];
-            }
-#pragma unroll
-            for (int t = 0; t < kPairBatch; ++t) {
-                const R acc = fma(cb[t], q[t], sp);
+                const double acc = fma(cb[t], q[t], sp);
                 sp = k0 + t < c ? acc : sp;
             }
             k0 += kPairBatch;
             if (k0 >= c) break;
-            wall_words<R>(S, nw, w, k0, P.cap, cb, jr);
+            wall_words(S, nw, w, k0, P.cap, cb, jr);
         }
-        double pw = plain32(P) ? (double)((float)sp + (float)S.wh[w]) : (double)sp + S.wh[w];
+        double pw = sp + S.wh[w];
         if (P.free_surface && pw < 0.0) pw = 0.0;
         pc[iw] = pw;
         qc[iw] = (float)pw;
@@ -2923,7 +3091,7 @@ struct BicgWall {
         for (int k = 0; k < c; ++k) {
             const int64_t at = (int64_t)k * nw + i;
             if constexpr (sizeof(R) == 4) {
-                const PairF e = ((const PairF *)S.wcoef)[at];
+                const PairF e = ((const PairF *)S.wcoef)[(int64_t)S.woffw[i] + k];
                 sz += (double)e.c * z[e.j];
             } else {
                 sz += ((const double *)S.wcoef)[at] * z[S.wnbr[at]];
@@ -3426,9 +3594,9 @@ void wall_pressure_final(const Target &T) {
 void wall_coef(const Target &T) {
     const bool walls = T.batched ? T.total[K_WALL] > 0 : kind_blocks(*T.P, K_WALL) > 0;
     if (!walls) return;
-    SISPH_DISPATCH_KDR(T, (launch<WallCoef<KER, D, R>, K_WALL>(T)));
     launch<WallFlags, K_WALL>(T);
     launch<WallBlocks, K_ONE>(T);
+    SISPH_DISPATCH_KDR(T, (launch<WallCoef<KER, D, R>, K_WALL>(T)));
 }
 
 void pressure_max(const Target &T) {
