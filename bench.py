@@ -245,8 +245,9 @@ def batched_vs_plain(n_cases: int, steps: int, seed: int) -> dict:
 def copy_reference(sizes_mib=(32, 1024), reps: int = 20) -> list:
     """Device-to-device copies (torch, i.e. the runtime's copy kernel) of the
     given sizes timed with events: the bandwidth a plain streaming kernel
-    reaches, read + write counted."""
+    reaches, read + write counted; and a plain read of the same buffer."""
     import torch
+    from paper_1908_01762_amd import sisph
     out = []
     for mib in sizes_mib:
         n = mib * (1 << 20) // 4
@@ -261,8 +262,15 @@ def copy_reference(sizes_mib=(32, 1024), reps: int = 20) -> list:
         e1.record()
         torch.cuda.synchronize()
         us = e0.elapsed_time(e1) * 1e3 / reps
-        out.append({"mib": mib, "us": round(us, 3), "GBps": round(2 * n * 4 / (us * 1e-6) / 1e9, 1)})
-        del src, dst
+        # a plain read of the same buffer (the library's read probe): the
+        # rate a kernel that only reads, as the sweep nearly does, can reach
+        grid = 2048
+        out_buf = torch.empty(grid * 256, dtype=torch.float32, device="cuda:0")
+        torch.cuda.synchronize()
+        rus = sisph.read_rate(src.data_ptr(), n * 4, out_buf.data_ptr(), grid, reps)
+        out.append({"mib": mib, "us": round(us, 3), "GBps": round(2 * n * 4 / (us * 1e-6) / 1e9, 1),
+                    "read_us": round(rus, 3), "read_GBps": round(n * 4 / (rus * 1e-6) / 1e9, 1)})
+        del src, dst, out_buf
     return out
 
 
@@ -519,6 +527,12 @@ def main():
         print("[bench] batched vs plain", file=sys.stderr, flush=True)
         line["batched_vs_plain"] = batched_vs_plain(args.batch_cases, args.batch_steps, seed=0)
     line["copy_reference"] = copy_reference()
+    big = [c for c in line["copy_reference"] if c["mib"] == 1024]
+    if big and big[0]["read_GBps"] > 0:
+        # context for frac: the rate a plain read of 1 GiB reaches on this device
+        rf = line["roofline"]
+        rf["read_probe_GBps"] = big[0]["read_GBps"]
+        rf["frac_of_read_probe"] = round(rf["achieved"] / big[0]["read_GBps"], 4)
     if not args.no_solver_compare:
         print("[bench] Jacobi vs BiCGStab", file=sys.stderr, flush=True)
         line["solver_compare"] = solver_compare(args.compare_dx, args.batch_steps)

@@ -333,6 +333,18 @@ int32_t sisph_debug_barrier_spins(sisph_ctx *ctx, uint32_t spins);
  * case without the packed mode. */
 int32_t sisph_debug_packed(sisph_ctx *ctx, int32_t on);
 
+/* Measurement aid, not part of the method: the device's plain read rate,
+ * the ceiling of a kernel that streams its operands once.  Reads the first
+ * `bytes` (a positive multiple of 16) of the device buffer `buf` `reps`
+ * times with a grid-stride kernel of 16-byte loads, `grid` workgroups of 256
+ * threads, each thread writing one float into `out` (device, grid * 256
+ * floats), on the null stream after the work queued there, and stores the
+ * average time of one read in microseconds (HIP events) in *us (host).
+ * Both buffers are the caller's.  SISPH_E_INVAL for a null pointer or a bad
+ * size, grid or reps; SISPH_E_DEVICE on a HIP error. */
+int32_t sisph_debug_read_rate(const void *buf, int64_t bytes, float *out, int32_t grid, int32_t reps,
+                              double *us);
+
 int32_t sisph_destroy(sisph_ctx *ctx);
 
 /* ------------------------------------------------------------- autotuning

@@ -1378,6 +1378,51 @@ extern "C" int32_t sisph_debug_packed(sisph_ctx *ctx, int32_t on) {
     return SISPH_OK;
 }
 
+// Read-rate probe: 16-byte loads, grid-stride, four in flight per thread,
+// one float sum per thread (so no load is dead).
+__global__ __launch_bounds__(kBlock) void k_read_rate(const float4 *__restrict__ a, int64_t n4, float *out) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    float s = 0.0f;
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+        const float4 v0 = a[i], v1 = a[i + stride], v2 = a[i + 2 * stride], v3 = a[i + 3 * stride];
+        s += (v0.x + v0.y + v0.z + v0.w) + (v1.x + v1.y + v1.z + v1.w) + (v2.x + v2.y + v2.z + v2.w) +
+             (v3.x + v3.y + v3.z + v3.w);
+    }
+    for (; i < n4; i += stride) {
+        const float4 v = a[i];
+        s += v.x + v.y + v.z + v.w;
+    }
+    out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+extern "C" int32_t sisph_debug_read_rate(const void *buf, int64_t bytes, float *out, int32_t grid, int32_t reps,
+                                         double *us) {
+    if (!buf || !out || !us || bytes <= 0 || bytes % 16 != 0 || grid < 1 || reps < 1) return SISPH_E_INVAL;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const int64_t n4 = bytes / 16;
+    if (e == hipSuccess) {   // one untimed read, then the timed ones
+        k_read_rate<<<grid, kBlock, 0, nullptr>>>((const float4 *)buf, n4, out);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+    for (int32_t r = 0; e == hipSuccess && r < reps; ++r) {
+        k_read_rate<<<grid, kBlock, 0, nullptr>>>((const float4 *)buf, n4, out);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return SISPH_E_DEVICE;
+    *us = (double)ms * 1e3 / reps;
+    return SISPH_OK;
+}
+
 extern "C" int32_t sisph_persistent_fallbacks(sisph_ctx *ctx, int64_t *refused, int64_t *timed_out) {
     if (!ctx) return SISPH_E_INVAL;
     if (refused) *refused = ctx->persist_refused;

@@ -105,6 +105,9 @@ def lib():
         L.sisph_debug_barrier_spins.argtypes = [C.c_void_p, C.c_uint32]
         L.sisph_debug_packed.restype = C.c_int32
         L.sisph_debug_packed.argtypes = [C.c_void_p, C.c_int32]
+        L.sisph_debug_read_rate.restype = C.c_int32
+        L.sisph_debug_read_rate.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_int32,
+                                            C.POINTER(C.c_double)]
         L.sisph_persistent_info.restype = C.c_int32
         L.sisph_persistent_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         L.sisph_set_kernel_timing.restype = C.c_int32
@@ -196,6 +199,15 @@ def describe(case: "_cases.Case") -> CaseDesc:
 
 def workspace_bytes(case) -> int:
     return int(lib().sisph_workspace_bytes(C.byref(describe(case))))
+
+
+def read_rate(buf_ptr: int, nbytes: int, out_ptr: int, grid: int, reps: int) -> float:
+    """Microseconds per plain read of nbytes of a device buffer
+    (sisph_debug_read_rate); out holds grid * 256 floats."""
+    us = C.c_double()
+    _check(lib().sisph_debug_read_rate(C.c_void_p(buf_ptr), int(nbytes), C.c_void_p(out_ptr), int(grid),
+                                       int(reps), C.byref(us)))
+    return us.value
 
 
 def status_string(code: int) -> str:

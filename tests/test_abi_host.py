@@ -120,6 +120,19 @@ def test_null_context_calls_are_invalid():
     assert L.sisph_step(None, 1, None) == sisph.E_INVAL
 
 
+def test_read_probe_refuses_bad_arguments():
+    """The read-rate probe checks its arguments before any device call."""
+    L = sisph.lib()
+    us = C.c_double()
+    buf = C.c_void_p(0x1000)
+    assert L.sisph_debug_read_rate(None, 16, buf, 1, 1, C.byref(us)) == sisph.E_INVAL
+    assert L.sisph_debug_read_rate(buf, 0, buf, 1, 1, C.byref(us)) == sisph.E_INVAL
+    assert L.sisph_debug_read_rate(buf, 24, buf, 1, 1, C.byref(us)) == sisph.E_INVAL   # not whole 16 B
+    assert L.sisph_debug_read_rate(buf, 16, buf, 0, 1, C.byref(us)) == sisph.E_INVAL
+    assert L.sisph_debug_read_rate(buf, 16, buf, 1, 0, C.byref(us)) == sisph.E_INVAL
+    assert L.sisph_debug_read_rate(buf, 16, buf, 1, 1, None) == sisph.E_INVAL
+
+
 def test_bicgstab_needs_a_free_surface():
     """Without free-surface rows the PPE fixes p only up to a constant:
     BiCGStab cases are refused there, accepted (with extra vectors) else."""

@@ -51,6 +51,10 @@ def test_bench_line_fields():
     assert rf["timed_launches"] >= rf["launches"] // 8
     assert rf["wall_pass"]["rows"] > 0 and rf["wall_pass"]["us_per_sweep"] > 0
     assert rf["layout"]["bytes_per_sweep"] > 0
+    # the plain-read probe of 1 GiB, and the kernel's rate against it
+    big = [c for c in d["copy_reference"] if c["mib"] == 1024][0]
+    assert 0 < big["read_GBps"] < rf["peak"] and rf["read_probe_GBps"] == big["read_GBps"]
+    assert abs(rf["frac_of_read_probe"] - rf["achieved"] / big["read_GBps"]) < 1e-3
     sec = d["secondary"]
     assert sec["config"]["workload"] == "tg400_wendland_mixed"
     sr = sec["roofline"]
