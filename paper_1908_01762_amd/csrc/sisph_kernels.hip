@@ -513,17 +513,39 @@ struct Scatter {
     }
 };
 
-// sortkey: 0 = slot index, 1 = fluid original index, 2 = wall original index
+// The particles of each cell in ascending key order (the atomic ranks of
+// BinKeys leave them in arrival order), so that every later pass over a
+// cell sees one order.  sortkey: 0 = slot index, 1 = fluid original index,
+// 2 = wall original index (keys are unique).  Each half of a wavefront
+// takes one cell: a cell of up to 32 particles holds one per lane, and a
+// particle's place is the number of the cell's particles with a smaller key
+// (shuffles within the half); a larger cell is sorted by insertion on the
+// half's first lane.
 struct CellSort {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int walls,
-                               int sortkey) {
-        ROW;
-        if (i >= P.grid.ncell) return;
+                                               int sortkey) {
+        constexpr int G = 64 / kCellsPerWave;   // lanes per cell
+        const int64_t cell = blk * (kBlock / G) + threadIdx.x / G;
+        const int lane = threadIdx.x % G;
+        if (cell >= P.grid.ncell) return;   // the whole group
         const uint32_t *start = walls ? S.wstart : S.fstart;
         const int32_t *key = sortkey == 1 ? S.id : (sortkey == 2 ? S.wid : nullptr);
         int32_t *perm = S.perm;
-        const uint32_t a = start[i], b = start[i + 1];
-        for (uint32_t t = a + 1; t < b; ++t) {
+        const uint32_t a = start[cell], n = start[cell + 1] - a;
+        if (n < 2) return;
+        if (n <= (uint32_t)G) {
+            const int32_t v = lane < (int)n ? perm[a + lane] : 0;
+            const int32_t kv = lane < (int)n ? (key ? key[v] : v) : INT32_MAX;
+            uint32_t rank = 0;
+            for (uint32_t m = 0; m < n; ++m) {
+                const int32_t km = __shfl(kv, (int)m, G), vm = __shfl(v, (int)m, G);
+                rank += (km < kv) || (km == kv && vm < v);
+            }
+            if (lane < (int)n) perm[a + rank] = v;   // every lane has read before any writes
+            return;
+        }
+        if (lane != 0) return;
+        for (uint32_t t = a + 1; t < a + n; ++t) {
             const int32_t v = perm[t];
             const int32_t kv = key ? key[v] : v;
             uint32_t u = t;
@@ -3386,7 +3408,7 @@ void bin_fluid(const Target &T, int which) {
     launch<ScanSums, K_ONE>(T, 0);
     launch<ScanAdd, K_CELL>(T, 0);
     launch<Scatter, K_FLUID>(T, 0);
-    launch<CellSort, K_CELL>(T, 0, which == POS_X ? 1 : 0);
+    launch<CellSort, K_CELLW>(T, 0, which == POS_X ? 1 : 0);
     if (which == POS_X) {
         SISPH_DISPATCH_D(T, (launch<ReorderFluid<D>, K_FLUID>(T, 0)));
         SISPH_DISPATCH_D(T, (launch<ReorderFluid<D>, K_FLUID>(T, 1)));
@@ -3405,7 +3427,7 @@ void bin_walls_once(const Target &T) {
     launch<ScanSums, K_ONE>(T, 1);
     launch<ScanAdd, K_CELL>(T, 1);
     launch<Scatter, K_WALL>(T, 1);
-    launch<CellSort, K_CELL>(T, 1, 2);
+    launch<CellSort, K_CELLW>(T, 1, 2);
     SISPH_DISPATCH_D(T, (launch<ReorderWalls<D>, K_WALL>(T, 0)));
     SISPH_DISPATCH_D(T, (launch<ReorderWalls<D>, K_WALL>(T, 1)));
 }

@@ -1,6 +1,7 @@
 """The benchmark's JSON line on the GPU, from a short run of bench.py in a
 child process: every field the line promises, with consistent values."""
 import json
+import math
 import os
 import subprocess
 import sys
@@ -49,7 +50,10 @@ def test_bench_line_fields():
     # every eighth launch of a solve timed (launch 0 of every solve among them)
     assert rf["timing_period"] == 8 and 0 < rf["timed_launches"] <= rf["launches"]
     assert rf["timed_launches"] >= rf["launches"] // 8
-    assert rf["wall_pass"]["rows"] > 0 and rf["wall_pass"]["us_per_sweep"] > 0
+    # chunk time less the sweep kernel's (sampled) time, per launch: the wall
+    # pass and the launch gaps; on a two-step run the sampling noise of the
+    # sweep average is of the same size, so only its presence is checked
+    assert rf["wall_pass"]["rows"] > 0 and math.isfinite(rf["wall_pass"]["us_per_sweep"])
     assert rf["layout"]["bytes_per_sweep"] > 0
     # the plain-read probe of 1 GiB, and the kernel's rate against it
     big = [c for c in d["copy_reference"] if c["mib"] == 1024][0]
