@@ -513,46 +513,55 @@ struct Scatter {
     }
 };
 
-// The particles of each cell in ascending key order (the atomic ranks of
-// BinKeys leave them in arrival order), so that every later pass over a
-// cell sees one order.  sortkey: 0 = slot index, 1 = fluid original index,
-// 2 = wall original index (keys are unique).  Each half of a wavefront
-// takes one cell: a cell of up to 32 particles holds one per lane, and a
-// particle's place is the number of the cell's particles with a smaller key
+// The particles of each cell in ascending (x, key) order (the atomic ranks
+// of BinKeys leave them in arrival order): one order for every later pass
+// over a cell, and one in which the neighbour build can skip the far part
+// of the cells left and right of a row's own.  x is the first coordinate
+// of the positions binned (as an order-preserving integer); the key breaks
+// ties.  sortkey: 0 = slot index, 1 = fluid original index, 2 = wall
+// original index (keys are unique).  Each half of a wavefront takes one
+// cell: a cell of up to 32 particles holds one per lane, and a particle's
+// place is the number of the cell's particles that order before it
 // (shuffles within the half); a larger cell is sorted by insertion on the
 // half's first lane.
 struct CellSort {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int walls,
-                                               int sortkey) {
+                                               int sortkey, int which) {
         constexpr int G = 64 / kCellsPerWave;   // lanes per cell
         const int64_t cell = blk * (kBlock / G) + threadIdx.x / G;
         const int lane = threadIdx.x % G;
         if (cell >= P.grid.ncell) return;   // the whole group
         const uint32_t *start = walls ? S.wstart : S.fstart;
         const int32_t *key = sortkey == 1 ? S.id : (sortkey == 2 ? S.wid : nullptr);
+        const double *px = (which == POS_XS ? S.xs : S.x)[0] + (walls ? P.nf : 0);
         int32_t *perm = S.perm;
         const uint32_t a = start[cell], n = start[cell + 1] - a;
         if (n < 2) return;
         if (n <= (uint32_t)G) {
-            const int32_t v = lane < (int)n ? perm[a + lane] : 0;
-            const int32_t kv = lane < (int)n ? (key ? key[v] : v) : INT32_MAX;
+            const bool in = lane < (int)n;
+            const int32_t v = in ? perm[a + lane] : 0;
+            const int32_t kv = in ? (key ? key[v] : v) : INT32_MAX;
+            const unsigned long long xv = in ? order_key(px[v]) : ~0ull;
             uint32_t rank = 0;
             for (uint32_t m = 0; m < n; ++m) {
-                const int32_t km = __shfl(kv, (int)m, G), vm = __shfl(v, (int)m, G);
-                rank += (km < kv) || (km == kv && vm < v);
+                const unsigned long long xm = __shfl(xv, (int)m, G);
+                const int32_t km = __shfl(kv, (int)m, G);
+                rank += (xm < xv) || (xm == xv && km < kv);
             }
-            if (lane < (int)n) perm[a + rank] = v;   // every lane has read before any writes
+            if (in) perm[a + rank] = v;   // every lane has read before any writes
             return;
         }
         if (lane != 0) return;
         for (uint32_t t = a + 1; t < a + n; ++t) {
             const int32_t v = perm[t];
             const int32_t kv = key ? key[v] : v;
+            const unsigned long long xv = order_key(px[v]);
             uint32_t u = t;
             while (u > a) {
                 const int32_t w = perm[u - 1];
                 const int32_t kw = key ? key[w] : w;
-                if (kw <= kv) break;
+                const unsigned long long xw = order_key(px[w]);
+                if (xw < xv || (xw == xv && kw < kv)) break;
                 perm[u] = w;
                 --u;
             }
@@ -758,6 +767,27 @@ __device__ __forceinline__ void scan_staged(const Params &P, const Grid &g, cons
     }
 }
 
+// Within a cell the particles are in ascending x (CellSort).  For a
+// particle j of the cell left of row i's own (x_j <= x_i, the grid not
+// periodic along x), fl(x_i - x_j)^2 does not increase with x_j; once it
+// reaches R^2 so does the exact |d|^2 (the other rounded squares only add
+// to it), so the cell's particles that can be in reach are a suffix: LEFT
+// returns its first position in [t0, t1).  For the cell to the right they
+// are a prefix, and !LEFT returns its end.  Particles cut off are exactly
+// ones the full test rejects, and the rest keep their order.
+template <bool LEFT>
+__device__ __forceinline__ uint32_t reach_cut(const double *sx0, uint32_t t0, uint32_t t1, double xi0, double R2) {
+#pragma clang fp contract(off)
+    while (t0 < t1) {
+        const uint32_t m = t0 + ((t1 - t0) >> 1);
+        const double dx = xi0 - sx0[m];
+        const bool far = dx * dx >= R2;
+        if (LEFT ? far : !far) t0 = m + 1;
+        else t1 = m;
+    }
+    return t0;
+}
+
 template <int D>
 struct BuildFluid {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which) {
@@ -842,7 +872,30 @@ struct BuildFluid {
                     sj[t] = (int32_t)j;
                 }
                 __syncthreads();
-                if (row_ok)
+                // Not periodic along x and the row's cells of this stencil
+                // row all staged: they are consecutive cells, so their fluid
+                // (walls) are one run of the staged copy; the run starts at
+                // the first particle of the left cell that can be in reach
+                // and ends after the last one of the right cell (see
+                // reach_cut), and is scanned in one loop, fluid then walls.
+                const int cx = ci[0];
+                const int64_t c_first = row_base + (cx > 0 ? cx - 1 : cx);
+                const int64_t c_last = row_base + (cx < g.nc[0] - 1 ? cx + 1 : cx);
+                const bool flat = row_ok && !g.per[0] && c_first >= s_lo && c_last <= s_hi;
+                if (flat)
+                    for (int pass = 0; pass < 2; ++pass) {
+                        const uint32_t *start = pass == 0 ? S.fstart : S.wstart;
+                        const uint32_t base = (pass == 0 ? F0 : W0) - (pass == 0 ? 0u : nF);
+                        const int64_t cc = row_base + cx;
+                        uint32_t t0 = start[c_first] - base, t1 = start[c_last + 1] - base;
+                        if (c_first < cc) t0 = reach_cut<true>(sx[0], t0, start[cc] - base, xi[0], P.R2);
+                        if (c_last > cc) t1 = reach_cut<false>(sx[0], start[cc + 1] - base, t1, xi[0], P.R2);
+                        if (periodic)
+                            scan_staged<D, true>(P, g, sx, sj, t0, t1, i, xi, S.nbr, c);
+                        else
+                            scan_staged<D, false>(P, g, sx, sj, t0, t1, i, xi, S.nbr, c);
+                    }
+                else if (row_ok)
 #pragma unroll
                     for (int e = 0; e < 3; ++e) {
                         if (!st.ok[0][e]) continue;
@@ -3408,7 +3461,7 @@ void bin_fluid(const Target &T, int which) {
     launch<ScanSums, K_ONE>(T, 0);
     launch<ScanAdd, K_CELL>(T, 0);
     launch<Scatter, K_FLUID>(T, 0);
-    launch<CellSort, K_CELLW>(T, 0, which == POS_X ? 1 : 0);
+    launch<CellSort, K_CELLW>(T, 0, which == POS_X ? 1 : 0, which);
     if (which == POS_X) {
         SISPH_DISPATCH_D(T, (launch<ReorderFluid<D>, K_FLUID>(T, 0)));
         SISPH_DISPATCH_D(T, (launch<ReorderFluid<D>, K_FLUID>(T, 1)));
@@ -3427,7 +3480,7 @@ void bin_walls_once(const Target &T) {
     launch<ScanSums, K_ONE>(T, 1);
     launch<ScanAdd, K_CELL>(T, 1);
     launch<Scatter, K_WALL>(T, 1);
-    launch<CellSort, K_CELLW>(T, 1, 2);
+    launch<CellSort, K_CELLW>(T, 1, 2, (int)POS_X);
     SISPH_DISPATCH_D(T, (launch<ReorderWalls<D>, K_WALL>(T, 0)));
     SISPH_DISPATCH_D(T, (launch<ReorderWalls<D>, K_WALL>(T, 1)));
 }
