@@ -6,9 +6,11 @@
  * paper's implementation notes split it into two stages (section 3.3):
  *
  *   sisph_bin       cell binning of the particles at r^n and the neighbour
- *                   sets N^n = { j : |r_ij|^2 < R^2 } (R = kernel support)
- *   sisph_predict   summation density (eq. summation_density), free-surface
- *                   flags (section 3), wall ghost velocity (eqs. vf,
+ *                   sets N^n = { j : |r_ij|^2 < R^2 } (R = kernel support),
+ *                   and with them the summation density
+ *                   (eq. summation_density) and free-surface flags
+ *                   (section 3)
+ *   sisph_predict   wall ghost velocity (eqs. vf,
  *                   vg-adami, vg-no-normal), predictor accelerations
  *                   (eqs. mom:sph:visc, mom:sph:av, mom:sph:gtvf:stress, body
  *                   force), r* and u* (eqs. int:rnp1, int:vint), then the

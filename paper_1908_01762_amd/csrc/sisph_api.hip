@@ -702,7 +702,7 @@ static void seq_bin(const Target &T) {
 }
 
 static void seq_predict(const Target &T) {
-    density(T);
+    // (the density and free-surface flag come from the build at r^n)
     mass_over_rho2(T);
     wall_velocity(T, POS_X);
     shadow(T);

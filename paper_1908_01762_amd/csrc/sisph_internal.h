@@ -248,9 +248,10 @@ void reset_control(const Target &T, int what);
 void bin_fluid(const Target &T, int which);
 // Walls of a single case, once at creation.
 void bin_walls_once(const Target &T);
+// Neighbour lists at r^n (POS_X; with them the summation density and
+// free-surface flag) or at r* (POS_XS; then the packed codes).
 void build_neighbors(const Target &T, int which);
 void wall_normals(const Target &T);
-void density(const Target &T);
 void mass_over_rho2(const Target &T);
 // FP32 copies of mass and density (mixed mode), after the density.
 void shadow(const Target &T);

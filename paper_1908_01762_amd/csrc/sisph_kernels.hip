@@ -691,13 +691,69 @@ struct ReorderWalls {
 // instead of one gather per row and candidate).  A cell outside the staged
 // range, or a range too large to stage (periodic wrap, clustering), is read
 // from global memory as before; the visiting order, hence the lists, are
-// the same either way.
-constexpr int kStageCap = 1024;
+// the same either way.  1016 candidates: positions, index and (for the
+// density) mass in 32 bytes each keep five workgroups per CU in FP32 sums.
+constexpr int kStageCap = 1016;
 
-template <int D>
+// The summation density (eq. summation_density: m_i W(0) + sum_j m_j W_ij
+// over fluid and wall neighbours, in list order, in the working precision)
+// formed by the build at r^n as it lists each neighbour: the terms, their
+// order and arithmetic of a pass over the finished list, without that
+// pass's second gather of every neighbour's position and mass.
+// Its arithmetic is written out with no contraction into fused
+// multiply-adds: the compiler's choice of where to fuse could otherwise
+// differ between the kernel instances (one case, a batch) that inline it.
+template <int KER, int D, typename R>
+struct DensAcc {
+    Kern<KER, D, R> K;
+    R s;
+    __device__ explicit DensAcc(double h) : K(h), s(R(0)) {}
+    __device__ __forceinline__ R w(R r) const {
+#pragma clang fp contract(off)
+        const R q = r * K.inv_h;
+        if (KER == SISPH_QUINTIC) {
+            const R a = R(3) - q, b = R(2) - q, c = R(1) - q;
+            R t = R(0);
+            if (a > R(0)) {
+                const R a2 = a * a;
+                t = t + a2 * a2 * a;
+            }
+            if (b > R(0)) {
+                const R b2 = b * b;
+                t = t - R(6) * b2 * b2 * b;
+            }
+            if (c > R(0)) {
+                const R c2 = c * c;
+                t = t + R(15) * c2 * c2 * c;
+            }
+            return K.sig * t;
+        } else {
+            if (q >= R(2)) return R(0);
+            const R a = R(1) - R(0.5) * q, a2 = a * a;
+            return K.sig * a2 * a2 * (R(2) * q + R(1));
+        }
+    }
+    __device__ __forceinline__ void self(R mi) { s = mi * w(R(0)); }
+    __device__ __forceinline__ void add(const Grid &g, const double xi[3], const double xj[3], R mj) {
+#pragma clang fp contract(off)
+        R r2 = R(0);
+        for (int k = 0; k < D; ++k) {
+            const R d = (R)min_image(xi[k] - xj[k], g, k);
+            r2 = r2 + d * d;
+        }
+        s = s + mj * w(sqrt(r2));
+    }
+};
+// (the build at r*: no density)
+struct NoDens {
+    float s;
+    __device__ explicit NoDens(double) : s(0.0f) {}
+};
+
+template <int D, bool DENS, class Acc>
 __device__ __forceinline__ void test_cell_global(const Params &P, const State &S, const Pos &x,
                                                  const int32_t *items, int64_t i, const double xi[3],
-                                                 int64_t cell, int &c) {
+                                                 int64_t cell, int &c, Acc &da) {
     const int64_t nf = P.nf;
     for (int pass = 0; pass < 2; ++pass) {
         const uint32_t *start = pass == 0 ? S.fstart : S.wstart;
@@ -705,11 +761,15 @@ __device__ __forceinline__ void test_cell_global(const Params &P, const State &S
         for (uint32_t t = t0; t < t1; ++t) {
             const int64_t j = pass == 0 ? (items ? (int64_t)items[t] : (int64_t)t) : nf + (int64_t)t;
             if (j == i) continue;
-            double d[3] = {0, 0, 0};
-            for (int k = 0; k < D; ++k) d[k] = min_image(xi[k] - x.c[k][j], P.grid, k);
+            double xj[3] = {0, 0, 0}, d[3] = {0, 0, 0};
+            for (int k = 0; k < D; ++k) {
+                xj[k] = x.c[k][j];
+                d[k] = min_image(xi[k] - xj[k], P.grid, k);
+            }
             if (exact_r2<D>(d) < P.R2) {
                 if (c < P.cap) S.nbr[(int64_t)c * nf + i] = (int32_t)j;
                 ++c;
+                if constexpr (DENS) da.add(P.grid, xi, xj, (decltype(da.s))S.m[j]);
             }
         }
     }
@@ -724,9 +784,9 @@ constexpr int kScanBatch = 4;
 template <int D, bool PER>
 __device__ __forceinline__ bool staged_hit(const Params &P, const Grid &g, const double (*sx)[kStageCap],
                                            const int32_t *sj, uint32_t t, int32_t self, const double xi[3],
-                                           int32_t &j) {
+                                           int32_t &j, double (&xj)[3]) {
     j = sj[t];
-    double xj[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k) xj[k] = 0.0;
     for (int k = 0; k < D; ++k) xj[k] = sx[k][t];
     double d[3] = {0, 0, 0};
     for (int k = 0; k < D; ++k) d[k] = min_image_sel<PER>(xi[k] - xj[k], g, k);
@@ -734,9 +794,19 @@ __device__ __forceinline__ bool staged_hit(const Params &P, const Grid &g, const
 }
 
 template <int D, bool PER>
+__device__ __forceinline__ bool staged_hit(const Params &P, const Grid &g, const double (*sx)[kStageCap],
+                                           const int32_t *sj, uint32_t t, int32_t self, const double xi[3],
+                                           int32_t &j) {
+    double xj[3];
+    return staged_hit<D, PER>(P, g, sx, sj, t, self, xi, j, xj);
+}
+
+// (with DENS, each neighbour's density term is added as it is listed; sm
+// holds the staged masses)
+template <int D, bool PER, bool DENS, class Acc, typename RM>
 __device__ __forceinline__ void scan_staged(const Params &P, const Grid &g, const double (*sx)[kStageCap],
-                                            const int32_t *sj, uint32_t t0, uint32_t t1, int64_t i,
-                                            const double xi[3], int32_t *nbr, int &c) {
+                                            const int32_t *sj, const RM *sm, uint32_t t0, uint32_t t1,
+                                            int64_t i, const double xi[3], int32_t *nbr, int &c, Acc &da) {
     constexpr int U = kScanBatch;
     const int64_t nf = P.nf;
     const int32_t self = (int32_t)i;
@@ -744,25 +814,47 @@ __device__ __forceinline__ void scan_staged(const Params &P, const Grid &g, cons
     // product per entry)
     int32_t *slot = nbr + (int64_t)c * nf + i;
     uint32_t t = t0;
-    for (; t + (U - 1) < t1; t += U) {
-        int32_t jv[U];
-        bool hv[U];
+    if constexpr (DENS) {
+        for (; t + (U - 1) < t1; t += U) {
+            int32_t jv[U];
+            bool hv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) hv[u] = staged_hit<D, PER>(P, g, sx, sj, t + u, self, xi, jv[u]);
+            for (int u = 0; u < U; ++u) hv[u] = staged_hit<D, PER>(P, g, sx, sj, t + u, self, xi, jv[u]);
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (hv[u]) {
-                if (c < P.cap) *slot = jv[u];
-                slot += nf;
-                ++c;
-            }
+            for (int u = 0; u < U; ++u)
+                if (hv[u]) {
+                    if (c < P.cap) *slot = jv[u];
+                    slot += nf;
+                    ++c;
+                    // (the position read again from LDS rather than held)
+                    double xj[3] = {0, 0, 0};
+                    for (int k = 0; k < D; ++k) xj[k] = sx[k][t + u];
+                    da.add(g, xi, xj, sm[t + u]);
+                }
+        }
+    } else {
+        for (; t + (U - 1) < t1; t += U) {
+            int32_t jv[U];
+            bool hv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) hv[u] = staged_hit<D, PER>(P, g, sx, sj, t + u, self, xi, jv[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (hv[u]) {
+                    if (c < P.cap) *slot = jv[u];
+                    slot += nf;
+                    ++c;
+                }
+        }
     }
     for (; t < t1; ++t) {
         int32_t j;
-        if (staged_hit<D, PER>(P, g, sx, sj, t, self, xi, j)) {
+        double xj[3];
+        if (staged_hit<D, PER>(P, g, sx, sj, t, self, xi, j, xj)) {
             if (c < P.cap) *slot = j;
             slot += nf;
             ++c;
+            if constexpr (DENS) da.add(g, xi, xj, sm[t]);
         }
     }
 }
@@ -788,11 +880,14 @@ __device__ __forceinline__ uint32_t reach_cut(const double *sx0, uint32_t t0, ui
     return t0;
 }
 
-template <int D>
+// With DENS (the build at r^n) it also forms the summation density and the
+// free-surface flag of each row (DensAcc).
+template <int KER, int D, typename R, bool DENS>
 struct BuildFluid {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int which) {
         __shared__ double sx[3][kStageCap];
         __shared__ int32_t sj[kStageCap];
+        __shared__ R sm[DENS ? kStageCap : 1];   // masses (density build only)
         __shared__ long long red_lo[kBlock / 64], red_hi[kBlock / 64];
         __shared__ long long seg[2];
         __shared__ uint32_t rng[4];   // fluid [F0, F1), wall [W0, W1) candidate slots
@@ -807,6 +902,7 @@ struct BuildFluid {
         int ci[3] = {0, 0, 0};
         Stencil st;
         int c = 1;
+        typename std::conditional<DENS, DensAcc<KER, D, R>, NoDens>::type da(P.h);
         if (live) {
             for (int k = 0; k < D; ++k) {
                 xi[k] = x.c[k][i];
@@ -814,6 +910,7 @@ struct BuildFluid {
             }
             make_stencil<D>(g, ci, st);
             S.nbr[i] = (int32_t)i;
+            if constexpr (DENS) da.self((R)S.m[i]);
         }
         constexpr int na = D == 3 ? 3 : 1;
         for (int a = 0; a < na; ++a)
@@ -870,6 +967,7 @@ struct BuildFluid {
                                              : nf + (int64_t)(W0 + (t - nF));
                     for (int k = 0; k < D; ++k) sx[k][t] = x.c[k][j];
                     sj[t] = (int32_t)j;
+                    if constexpr (DENS) sm[t] = (R)S.m[j];
                 }
                 __syncthreads();
                 // Not periodic along x and the row's cells of this stencil
@@ -891,9 +989,9 @@ struct BuildFluid {
                         if (c_first < cc) t0 = reach_cut<true>(sx[0], t0, start[cc] - base, xi[0], P.R2);
                         if (c_last > cc) t1 = reach_cut<false>(sx[0], start[cc + 1] - base, t1, xi[0], P.R2);
                         if (periodic)
-                            scan_staged<D, true>(P, g, sx, sj, t0, t1, i, xi, S.nbr, c);
+                            scan_staged<D, true, DENS>(P, g, sx, sj, sm, t0, t1, i, xi, S.nbr, c, da);
                         else
-                            scan_staged<D, false>(P, g, sx, sj, t0, t1, i, xi, S.nbr, c);
+                            scan_staged<D, false, DENS>(P, g, sx, sj, sm, t0, t1, i, xi, S.nbr, c, da);
                     }
                 else if (row_ok)
 #pragma unroll
@@ -901,7 +999,7 @@ struct BuildFluid {
                         if (!st.ok[0][e]) continue;
                         const int64_t cell = row_base + st.v[0][e];
                         if (cell < s_lo || cell > s_hi) {
-                            test_cell_global<D>(P, S, x, items, i, xi, cell, c);
+                            test_cell_global<D, DENS>(P, S, x, items, i, xi, cell, c, da);
                             continue;
                         }
                         // fluid then walls of this cell, from the staged copy
@@ -911,9 +1009,9 @@ struct BuildFluid {
                             const uint32_t shift = pass == 0 ? 0u : nF;
                             const uint32_t t0 = start[cell] - base + shift, t1 = start[cell + 1] - base + shift;
                             if (periodic)
-                                scan_staged<D, true>(P, g, sx, sj, t0, t1, i, xi, S.nbr, c);
+                                scan_staged<D, true, DENS>(P, g, sx, sj, sm, t0, t1, i, xi, S.nbr, c, da);
                             else
-                                scan_staged<D, false>(P, g, sx, sj, t0, t1, i, xi, S.nbr, c);
+                                scan_staged<D, false, DENS>(P, g, sx, sj, sm, t0, t1, i, xi, S.nbr, c, da);
                         }
                     }
                 __syncthreads();   // the next stencil row overwrites the staged copy
@@ -924,6 +1022,14 @@ struct BuildFluid {
             atomicMax(&S.ctl->maxcnt, c);
         }
         S.cnt[i] = c < P.cap ? c : P.cap;
+        if constexpr (DENS) {
+            // eq. summation_density; free-surface flag rho_i / rho0 <
+            // fs_ratio when free_surface is on (section 3)
+            const double rh = (double)da.s;
+            S.rho[i] = rh;
+            const bool low = plain32(P) ? (float)rh / (float)P.rho0 < (float)P.fs_ratio : rh / P.rho0 < P.fs_ratio;
+            S.fs[i] = (P.free_surface && low) ? 1 : 0;
+        }
     }
 };
 
@@ -1147,41 +1253,6 @@ struct WallNormals {
     }
 };
 
-// ----------------------------------------------------- summation density
-// eq. summation_density over fluid + wall neighbours; free-surface flag
-// rho_i / rho0 < fs_ratio when free_surface is on (section 3).
-template <int KER, int D, typename R>
-struct Density {
-    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
-        ROW;
-        if (i >= P.nf) return;
-        Kern<KER, D, R> K(P.h);
-        const Pos x = mkpos(S.x);
-        double xi[3] = {0, 0, 0};
-        for (int k = 0; k < D; ++k) xi[k] = x.c[k][i];
-        const int c = S.cnt[i];
-        R s = (R)S.m[i] * K.w(R(0));
-        for (int k0 = 1; k0 < c; k0 += kPairBatch) {
-            int64_t jb[kPairBatch];
-            double xj[kPairBatch][3], mb[kPairBatch];
-            batch_slots(S.nbr, P.nf, i, k0, c, P.cap, i, jb);
-            batch_pos<D>(x, jb, xj);
-#pragma unroll
-            for (int t = 0; t < kPairBatch; ++t) mb[t] = S.m[jb[t]];
-#pragma unroll
-            for (int t = 0; t < kPairBatch; ++t) {
-                if (k0 + t >= c) break;
-                R d[3], r2;
-                pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
-                s += (R)mb[t] * K.w(sqrt(r2));
-            }
-        }
-        const double rh = (double)s;
-        S.rho[i] = rh;
-        const bool low = plain32(P) ? (float)rh / (float)P.rho0 < (float)P.fs_ratio : rh / P.rho0 < P.fs_ratio;
-        S.fs[i] = (P.free_surface && low) ? 1 : 0;
-    }
-};
 
 // ---------------------------------------------------------- wall velocity
 // eq. vf: Shepard average of the fluid velocity with a kernel of smoothing
@@ -3486,7 +3557,9 @@ void bin_walls_once(const Target &T) {
 }
 
 void build_neighbors(const Target &T, int which) {
-    SISPH_DISPATCH_D(T, (launch<BuildFluid<D>, K_FLUID>(T, which)));
+    // (without the density the kernel and precision do not enter: one instance per dimension)
+    if (which == POS_X) SISPH_DISPATCH_KDR(T, (launch<BuildFluid<KER, D, R, true>, K_FLUID>(T, which)));
+    else SISPH_DISPATCH_D(T, (launch<BuildFluid<SISPH_WENDLAND_C2, D, float, false>, K_FLUID>(T, which)));
     SISPH_DISPATCH_D(T, (launch<BuildWall<D>, K_WALL>(T, which)));
     // the sweeps read the lists at r* only
     if (which == POS_XS && T.packed) SISPH_DISPATCH_D(T, (launch<PackCodes<D>, K_FLUID>(T)));
@@ -3496,8 +3569,6 @@ void wall_normals(const Target &T) {
     SISPH_DISPATCH_KD(T, (launch<WallNormals<KER, D>, K_WALL>(T, 0)));
     SISPH_DISPATCH_KD(T, (launch<WallNormals<KER, D>, K_WALL>(T, 1)));
 }
-
-void density(const Target &T) { SISPH_DISPATCH_KDR(T, (launch<Density<KER, D, R>, K_FLUID>(T))); }
 
 void wall_velocity(const Target &T, int which) {
     SISPH_DISPATCH_KDR(T, (launch<WallVelocity<KER, D, R>, K_WALL>(T, which)));
