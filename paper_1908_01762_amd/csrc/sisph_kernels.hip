@@ -434,7 +434,23 @@ struct BinKeys {
         for (int k = 0; k < D; ++k) c[k] = cell_coord(pos[k][base + i], P.grid, k);
         const uint32_t cell = (uint32_t)(((int64_t)c[2] * P.grid.nc[1] + c[1]) * P.grid.nc[0] + c[0]);
         S.key[i] = cell;
-        S.rank[i] = atomicAdd(&S.count[cell], 1u);
+        // One atomic per distinct cell of the wavefront (its lanes are mostly
+        // in a few cells: the particles are in the last binning's order), the
+        // lanes of a cell ranked by lane order after the cell's base.  Ranks
+        // still depend on the order atomics arrive in; CellSort fixes the
+        // order within each cell.
+        const uint64_t lane_lt = (1ull << (threadIdx.x & 63)) - 1ull;
+        uint64_t todo = __ballot(1);
+        while (todo) {
+            const int lead = __ffsll((unsigned long long)todo) - 1;
+            const uint32_t key = __shfl(cell, lead, 64);
+            const uint64_t same = __ballot(cell == key) & todo;
+            uint32_t first = 0u;
+            if ((int)(threadIdx.x & 63) == lead) first = atomicAdd(&S.count[key], (uint32_t)__popcll(same));
+            first = __shfl(first, lead, 64);
+            if (cell == key) S.rank[i] = first + (uint32_t)__popcll(same & lane_lt);
+            todo &= ~same;
+        }
     }
 };
 
