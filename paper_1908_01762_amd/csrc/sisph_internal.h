@@ -176,6 +176,13 @@ struct __align__(16) CoefRecD {
 struct __align__(16) CorrRec {
     double x[3], p, rho, m;
 };
+// The symmetric form in FP32 sums needs of a neighbour only r*, m and
+// p / rho^2 (formed in FP64, rounded to FP32, as the pair term would):
+// 32 bytes, two loads.
+struct __align__(16) CorrRecS {
+    double x[3];
+    float q, m;
+};
 
 // Launch-size kinds: how many workgroups one case needs for a kernel.
 constexpr int kCellsPerWave = 2;   // cells one wavefront sorts, one per 32 lanes (K_CELLW launches)

@@ -1540,6 +1540,15 @@ struct CorrSeed {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         if (i >= P.ntot) return;
+        if (sizeof(R) == 4 && P.pgrad == SISPH_SYMM) {
+            CorrRecS rec;
+            for (int a = 0; a < 3; ++a) rec.x[a] = a < P.dim ? S.xs[a][i] : 0.0;
+            const double rho = S.rho[i];
+            rec.q = (float)(S.p[0][i] / (rho * rho));
+            rec.m = (float)S.m[i];
+            ((CorrRecS *)S.prec)[i] = rec;
+            return;
+        }
         CorrRec rec;
         for (int a = 0; a < 3; ++a) rec.x[a] = a < P.dim ? S.xs[a][i] : 0.0;
         rec.p = S.p[0][i];
@@ -2932,8 +2941,29 @@ struct Correct {
         R f[3] = {0, 0, 0};
         const int c = S.cnt[i];
         const bool symm = P.pgrad == SISPH_SYMM;
+        if (sizeof(R) == 4 && symm) {
+            // the 32-byte records: -m_j (p_i/rho_i^2 + p_j/rho_j^2) grad W
+            const CorrRecS *srec = (const CorrRecS *)S.prec;
+            for (int k0 = 1; k0 < c; k0 += kPairBatch) {
+                int64_t jb[kPairBatch];
+                batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
+                CorrRecS rb[kPairBatch];
+#pragma unroll
+                for (int t = 0; t < kPairBatch; ++t) rb[t] = srec[jb[t]];
+#pragma unroll
+                for (int t = 0; t < kPairBatch; ++t) {
+                    if (k0 + t >= c) break;
+                    R d[3], r2;
+                    pair_diff_v<D, R>(P.grid, xi, rb[t].x, d, r2);
+                    const R dw = K.dwr(sqrt(r2));
+                    R cf = -(R)rb[t].m * (pi_r + (R)rb[t].q);
+                    cf *= dw;
+                    for (int a = 0; a < D; ++a) f[a] += cf * d[a];
+                }
+            }
+        }
         const CorrRec *crec = (const CorrRec *)S.prec;
-        for (int k0 = 1; k0 < c; k0 += kPairBatch) {
+        for (int k0 = 1; k0 < c && !(sizeof(R) == 4 && symm); k0 += kPairBatch) {
             int64_t jb[kPairBatch];
             double xj[kPairBatch][3], rhob[kPairBatch], pb[kPairBatch];
             R mb[kPairBatch];
