@@ -185,9 +185,10 @@ struct __align__(16) CorrRecS {
 };
 
 // Launch-size kinds: how many workgroups one case needs for a kernel.
+constexpr int kWallRunBlocks = 2048;   // grid of the per-sweep wall pass (K_WALLRUN launches)
 constexpr int kCellsPerWave = 2;   // cells one wavefront sorts, one per 32 lanes (K_CELLW launches)
 
-enum Kind { K_FLUID = 0, K_WALL, K_TOT, K_CELL, K_TILE, K_ONE, K_CELLW, K_COUNT };
+enum Kind { K_FLUID = 0, K_WALL, K_TOT, K_CELL, K_TILE, K_ONE, K_CELLW, K_WALLRUN, K_COUNT };
 
 // Packed mode (walled Jacobi cases on grids periodic in no direction):
 // each sweep workgroup copies the iterate of the particles its rows can
@@ -206,6 +207,10 @@ __host__ __device__ inline int64_t kind_blocks(const Params &P, int kind) {
     case K_TOT: return (P.ntot + kBlock - 1) / kBlock;
     case K_CELL: return (P.grid.ncell + kBlock - 1) / kBlock;
     case K_TILE: return (P.grid.ncell + kScanTile - 1) / kScanTile;
+    case K_WALLRUN: {   // the per-sweep wall pass: a grid-stride loop over the compact rows
+        const int64_t nb = (P.nw + kBlock - 1) / kBlock;
+        return nb < kWallRunBlocks ? nb : kWallRunBlocks;
+    }
     case K_CELLW: return (P.grid.ncell + kBlock / 64 * kCellsPerWave - 1) / (kBlock / 64 * kCellsPerWave);
     default: return 1;
     }

@@ -2793,15 +2793,18 @@ __device__ __forceinline__ float wall_run_sum(const State &S, const float *qc, i
 
 template <typename R>
 struct WallPressure {
-    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int, int L, int final) {
+    static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t nblk, int, int L,
+                                               int final) {
         const int64_t nw = P.nw, nb = (nw + kBlock - 1) / kBlock;
         // FP32 sums: during the solve the rows with fluid neighbours
         // (compact, in the first launch slots); the final pass every wall
         // row.  A workgroup takes kBlock / kWallLanes rows at a time,
-        // striding by the grid.  The row count and the first row's entry
-        // are read with the stop flag rather than after it (wrow has nw + 1
+        // striding by the grid (nblk workgroups: during the solve at most
+        // kWallRunBlocks, enough for the rows near the fluid in one round on
+        // the large cases).  The row count and the first row's entry are
+        // read with the stop flag rather than after it (wrow has nw + 1
         // entries; one past the rows is read and not used).
-        const int64_t stride = nb * (kBlock / kWallLanes);
+        const int64_t stride = nblk * (kBlock / kWallLanes);
         int64_t r = blk * (kBlock / kWallLanes) + threadIdx.x / kWallLanes;
         int64_t listed = 0;
         uint2 e = make_uint2(0u, 0u), e1 = e;
@@ -3762,7 +3765,7 @@ void ppe_iteration(const Target &T, int L) {
 void wall_pressure_iteration(const Target &T, int L) {
     // hardware workgroup order: the listed workgroups, which take the first
     // launch slots, then spread over every XCD
-    if (f32_sums(T.precision)) launch<WallPressure<float>, K_WALL, false>(T, L, 0);
+    if (f32_sums(T.precision)) launch<WallPressure<float>, K_WALLRUN, false>(T, L, 0);
     else launch<WallPressure<double>, K_WALL, false>(T, L, 0);
 }
 

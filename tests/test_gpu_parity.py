@@ -47,6 +47,10 @@ def _cases_small():
                                          precision="fp64"),
         "db3d_quintic": cases.dam_break_3d(dx=0.1, lx=0.5, ly=0.5, lz=0.6, tank_x=1.5, tank_y=0.5, tank_z=1.0,
                                            kernel="quintic", hdx=1.0, precision="fp64"),
+        # support 3.9 dx: cells of about 59 fluid and 45 wall particles, past
+        # the 32 that the cell sort ranks on half a wavefront
+        "db3d_dense_cells": cases.dam_break_3d(dx=0.1, lx=0.5, ly=0.5, lz=0.6, tank_x=1.5, tank_y=0.5,
+                                               tank_z=1.0, kernel="quintic", hdx=1.3, precision="fp64"),
         "ldc30_slip": cases.lid_driven_cavity(30),
         "ldc30_noslip": cases.lid_driven_cavity(30, ustar_wall="noslip"),
     }
