@@ -439,6 +439,10 @@ def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool,
         "sweep_time_frac": cnt["sweep_ms"] / 1e3 / elapsed if elapsed > 0 else 0.0,
         "roofline": roofline,
         "sweep_variant": tuned if tuned is not None else {"variant": ctx.variant},
+        # external-flow GTVF: did the last timed step's sub-steps walk the
+        # short lists (1), the full lists for some sub-step (2), or has the
+        # case none (0)
+        "gtvf_short_lists_last_step": ctx.debug_gtvf_short(),
     }
     ctx.close()
     return out

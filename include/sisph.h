@@ -335,6 +335,21 @@ int32_t sisph_debug_barrier_spins(sisph_ctx *ctx, uint32_t spins);
  * case without the packed mode. */
 int32_t sisph_debug_packed(sisph_ctx *ctx, int32_t on);
 
+/* Test hook.  With the external-flow GTVF (section 2.1: smoothing length
+ * h/2, so the sub-steps of eq. mom:sph:gtvf reach only the closer part of
+ * the neighbours) the neighbour build at r* also lists, per row, the
+ * neighbours closer than the GTVF support plus a margin, and the sub-steps
+ * walk that short list while no particle has moved more than 0.05 dx from
+ * r*; a neighbour it leaves out adds exactly zero, so the sums are the same
+ * bit for bit.  on = 0 makes the sub-steps walk the full lists, on = 1
+ * restores the short lists, on = -1 changes nothing.  *used (host,
+ * nullable) receives, for the last completed step, 0 if the case has no
+ * short lists (or they are off), 1 if every sub-step walked them, 2 if one
+ * walked the full lists (a short list overflowed, or a particle moved past
+ * the bound).  SISPH_E_INVAL for on = 1 on a case without them,
+ * SISPH_E_STATE while attached to a batch. */
+int32_t sisph_debug_gtvf_short(sisph_ctx *ctx, int32_t on, int32_t *used);
+
 /* Measurement aid, not part of the method: the device's plain read rate,
  * the ceiling of a kernel that streams its operands once.  Reads the first
  * `bytes` (a positive multiple of 16) of the device buffer `buf` `reps`

@@ -205,6 +205,24 @@ static Params make_params(const sisph_case_desc *d) {
     P.tol = d->tol;
     const double R = support_of(d->kernel) * d->h;
     P.R2 = R * R;
+    // GTVF short lists: the kernel support at h/2, widened by 1e-5 of it
+    // (the FP32 kernel argument stays at or past the support for any pair
+    // left out) and by twice the displacement bound (0.05 dx)
+    P.g_sub = 0;
+    P.g_cap = 0;
+    P.g_R2 = 0.0;
+    P.g_D2 = 0.0;
+    if (d->gtvf == SISPH_GTVF_EXTERNAL && d->gtvf_K > 0) {
+        const double dmax = 0.05 * d->dx, gR = support_of(d->kernel) * 0.5 * d->h * (1.0 + 1e-5) + 2.0 * dmax;
+        if (gR < R) {
+            const double q = gR / d->dx, pi = 3.14159265358979323846;
+            const double n = d->dim == 2 ? pi * q * q : 4.0 / 3.0 * pi * q * q * q;
+            P.g_sub = 1;
+            P.g_cap = ((int32_t)std::ceil(1.6 * n) + 8 + 3) / 4 * 4;
+            P.g_R2 = gR * gR;
+            P.g_D2 = dmax * dmax;
+        }
+    }
     for (int k = 0; k < 3; ++k) P.g[k] = k < d->dim ? d->gravity[k] : 0.0;
     P.grid = make_grid(d);
     return P;
@@ -237,6 +255,11 @@ static void carve(const Params &P, Carver &c, State &S) {
     vec(S.un, nf);
     S.gk[0] = c.take<double4>(nt);
     S.gk[1] = c.take<double4>(nt);
+    S.gnbr = S.gcnt = nullptr;
+    if (P.g_sub) {
+        S.gnbr = c.take<int32_t>((int64_t)P.g_cap * nf);
+        S.gcnt = c.take<int32_t>(nf);
+    }
     vec(S.vk, nf);
     vec(S.nrm, nw);
     vec(S.wallu, nw);
@@ -1420,6 +1443,27 @@ extern "C" int32_t sisph_debug_read_rate(const void *buf, int64_t bytes, float *
     if (e1) (void)hipEventDestroy(e1);
     if (e != hipSuccess) return SISPH_E_DEVICE;
     *us = (double)ms * 1e3 / reps;
+    return SISPH_OK;
+}
+
+extern "C" int32_t sisph_debug_gtvf_short(sisph_ctx *ctx, int32_t on, int32_t *used) {
+    if (!ctx || on < -1 || on > 1) return SISPH_E_INVAL;
+    if (attached(ctx)) return fail(ctx, SISPH_E_STATE, "context is attached to a batch");
+    const bool can = make_params(&ctx->desc).g_sub != 0;   // its buffers exist
+    if (on == 1 && !can) return fail(ctx, SISPH_E_INVAL, "this case has no GTVF short lists");
+    if (on >= 0) {
+        ctx->P.g_sub = on && can ? 1 : 0;
+        ctx->T = single_target(ctx);
+        drop_graphs(ctx->g_pre, ctx->g_post);   // captured with the old parameters
+    }
+    if (used) {
+        Control C;
+        HIPCHK(ctx, hipMemcpyAsync(&C, ctx->S.ctl, sizeof(Control), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        unsigned long long bound;
+        std::memcpy(&bound, &ctx->P.g_D2, sizeof bound);
+        *used = !ctx->P.g_sub ? 0 : (!C.g_full && C.g_disp_bits <= bound ? 1 : 2);
+    }
     return SISPH_OK;
 }
 

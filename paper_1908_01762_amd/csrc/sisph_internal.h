@@ -37,8 +37,14 @@ struct Params {
     int32_t adaptive_dt;    // next dt from this step's maxima
     int32_t solver;         // SISPH_JACOBI or SISPH_BICGSTAB
     int32_t compact;        // mixed mode without walls: 16-bit neighbour offsets
-    int32_t packed;         // walled Jacobi cases not periodic in x: 16-bit neighbour codes
-                            // (stencil-row range id << 11 | offset in that range)
+    int32_t packed;         // walled Jacobi cases not periodic in x: 12-bit neighbour codes
+                            // (positions in the workgroup's LDS copy of the iterate)
+    // External-flow GTVF (smoothing length h/2, so the sub-steps reach only
+    // part of the neighbours): the sub-steps walk a short list built with
+    // the r* lists, of the neighbours closer than sqrt(g_R2); it holds
+    // while no particle has moved more than sqrt(g_D2) from r*
+    int32_t g_sub, g_cap;
+    double g_R2, g_D2;
     uint32_t barrier_spins; // polls before a wait of the persistent solve gives up
     int32_t null_space;     // SISPH_NULL_PROJECT: RHS made compatible before the sweeps
     int64_t nf, nw, ntot;
@@ -74,6 +80,8 @@ struct Control {
     int32_t bicg_brk;
     int32_t wide;                     // a neighbour offset of this step did not fit 16 bits
     int32_t pk_overflow;              // packed mode: workgroups of this step that read the lists
+    int32_t g_full;                   // the GTVF short list overflowed this step
+    unsigned long long g_disp_bits;   // max |r^k - r*|^2 over the GTVF sub-steps so far
     double beta;                      // SISPH_NULL_PROJECT: (y . RHS) / (y . D), y = m rho
 };
 
@@ -89,6 +97,7 @@ struct State {
     // GTVF sub-step records {x, y, z, m/rho^2}: one 32-byte gather per
     // neighbour; the seed (r*) in gk[1], sub-step k writes gk[k & 1]
     double4 *gk[2];    // [ntot] x2
+    int32_t *gnbr, *gcnt;   // GTVF short lists (g_sub): [g_cap][nf], [nf]
     double *vk[3];     // GTVF sub-step velocity     [nf]; before the sub-steps,
                        // the step's total acceleration (adaptive dt)
     double *nrm[3];    // wall unit normals          [nw]

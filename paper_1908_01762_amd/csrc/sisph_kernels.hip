@@ -372,6 +372,8 @@ struct ResetControl {
             c->dt = c->dt_next;
             c->umax2_bits = 0ull;
             c->fmax2_bits = 0ull;
+            c->g_full = 0;
+            c->g_disp_bits = 0ull;
         }
         if (what & RESET_PPE) {
             c->barrier_late = 0;
@@ -766,10 +768,24 @@ struct NoDens {
     __device__ explicit NoDens(double) : s(0.0f) {}
 };
 
+// The GTVF short list of a row (P.g_sub, at r*): the listed neighbours with
+// |r_ij|^2 < g_R2, in list order, without the row itself.
+struct ShortList {
+    int32_t *slot;   // the next entry (slot-major [g_cap][nf])
+    int c;
+    bool on;
+    __device__ __forceinline__ void add(const Params &P, int32_t j, double r2) {
+        if (!on || !(r2 < P.g_R2)) return;
+        if (c < P.g_cap) *slot = j;
+        slot += P.nf;
+        ++c;
+    }
+};
+
 template <int D, bool DENS, class Acc>
 __device__ __forceinline__ void test_cell_global(const Params &P, const State &S, const Pos &x,
                                                  const int32_t *items, int64_t i, const double xi[3],
-                                                 int64_t cell, int &c, Acc &da) {
+                                                 int64_t cell, int &c, Acc &da, ShortList &sl) {
     const int64_t nf = P.nf;
     for (int pass = 0; pass < 2; ++pass) {
         const uint32_t *start = pass == 0 ? S.fstart : S.wstart;
@@ -782,10 +798,12 @@ __device__ __forceinline__ void test_cell_global(const Params &P, const State &S
                 xj[k] = x.c[k][j];
                 d[k] = min_image(xi[k] - xj[k], P.grid, k);
             }
-            if (exact_r2<D>(d) < P.R2) {
+            const double r2 = exact_r2<D>(d);
+            if (r2 < P.R2) {
                 if (c < P.cap) S.nbr[(int64_t)c * nf + i] = (int32_t)j;
                 ++c;
                 if constexpr (DENS) da.add(P.grid, xi, xj, (decltype(da.s))S.m[j]);
+                else sl.add(P, (int32_t)j, r2);
             }
         }
     }
@@ -800,29 +818,32 @@ constexpr int kScanBatch = 4;
 template <int D, bool PER>
 __device__ __forceinline__ bool staged_hit(const Params &P, const Grid &g, const double (*sx)[kStageCap],
                                            const int32_t *sj, uint32_t t, int32_t self, const double xi[3],
-                                           int32_t &j, double (&xj)[3]) {
+                                           int32_t &j, double (&xj)[3], double &r2) {
     j = sj[t];
     for (int k = 0; k < 3; ++k) xj[k] = 0.0;
     for (int k = 0; k < D; ++k) xj[k] = sx[k][t];
     double d[3] = {0, 0, 0};
     for (int k = 0; k < D; ++k) d[k] = min_image_sel<PER>(xi[k] - xj[k], g, k);
-    return (j != self) & (exact_r2<D>(d) < P.R2);
+    r2 = exact_r2<D>(d);
+    return (j != self) & (r2 < P.R2);
 }
 
 template <int D, bool PER>
 __device__ __forceinline__ bool staged_hit(const Params &P, const Grid &g, const double (*sx)[kStageCap],
                                            const int32_t *sj, uint32_t t, int32_t self, const double xi[3],
-                                           int32_t &j) {
+                                           int32_t &j, double &r2) {
     double xj[3];
-    return staged_hit<D, PER>(P, g, sx, sj, t, self, xi, j, xj);
+    return staged_hit<D, PER>(P, g, sx, sj, t, self, xi, j, xj, r2);
 }
+
 
 // (with DENS, each neighbour's density term is added as it is listed; sm
 // holds the staged masses)
 template <int D, bool PER, bool DENS, class Acc, typename RM>
 __device__ __forceinline__ void scan_staged(const Params &P, const Grid &g, const double (*sx)[kStageCap],
                                             const int32_t *sj, const RM *sm, uint32_t t0, uint32_t t1,
-                                            int64_t i, const double xi[3], int32_t *nbr, int &c, Acc &da) {
+                                            int64_t i, const double xi[3], int32_t *nbr, int &c, Acc &da,
+                                            ShortList &sl) {
     constexpr int U = kScanBatch;
     const int64_t nf = P.nf;
     const int32_t self = (int32_t)i;
@@ -834,8 +855,9 @@ __device__ __forceinline__ void scan_staged(const Params &P, const Grid &g, cons
         for (; t + (U - 1) < t1; t += U) {
             int32_t jv[U];
             bool hv[U];
+            double rv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) hv[u] = staged_hit<D, PER>(P, g, sx, sj, t + u, self, xi, jv[u]);
+            for (int u = 0; u < U; ++u) hv[u] = staged_hit<D, PER>(P, g, sx, sj, t + u, self, xi, jv[u], rv[u]);
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (hv[u]) {
@@ -852,25 +874,28 @@ __device__ __forceinline__ void scan_staged(const Params &P, const Grid &g, cons
         for (; t + (U - 1) < t1; t += U) {
             int32_t jv[U];
             bool hv[U];
+            double rv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) hv[u] = staged_hit<D, PER>(P, g, sx, sj, t + u, self, xi, jv[u]);
+            for (int u = 0; u < U; ++u) hv[u] = staged_hit<D, PER>(P, g, sx, sj, t + u, self, xi, jv[u], rv[u]);
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (hv[u]) {
                     if (c < P.cap) *slot = jv[u];
                     slot += nf;
                     ++c;
+                    sl.add(P, jv[u], rv[u]);
                 }
         }
     }
     for (; t < t1; ++t) {
         int32_t j;
-        double xj[3];
-        if (staged_hit<D, PER>(P, g, sx, sj, t, self, xi, j, xj)) {
+        double xj[3], r2;
+        if (staged_hit<D, PER>(P, g, sx, sj, t, self, xi, j, xj, r2)) {
             if (c < P.cap) *slot = j;
             slot += nf;
             ++c;
             if constexpr (DENS) da.add(g, xi, xj, sm[t]);
+            else sl.add(P, j, r2);
         }
     }
 }
@@ -919,6 +944,8 @@ struct BuildFluid {
         Stencil st;
         int c = 1;
         typename std::conditional<DENS, DensAcc<KER, D, R>, NoDens>::type da(P.h);
+        ShortList sl{nullptr, 0, !DENS && P.g_sub && which == POS_XS && live};
+        if (sl.on) sl.slot = S.gnbr + i;
         if (live) {
             for (int k = 0; k < D; ++k) {
                 xi[k] = x.c[k][i];
@@ -1005,9 +1032,9 @@ struct BuildFluid {
                         if (c_first < cc) t0 = reach_cut<true>(sx[0], t0, start[cc] - base, xi[0], P.R2);
                         if (c_last > cc) t1 = reach_cut<false>(sx[0], start[cc + 1] - base, t1, xi[0], P.R2);
                         if (periodic)
-                            scan_staged<D, true, DENS>(P, g, sx, sj, sm, t0, t1, i, xi, S.nbr, c, da);
+                            scan_staged<D, true, DENS>(P, g, sx, sj, sm, t0, t1, i, xi, S.nbr, c, da, sl);
                         else
-                            scan_staged<D, false, DENS>(P, g, sx, sj, sm, t0, t1, i, xi, S.nbr, c, da);
+                            scan_staged<D, false, DENS>(P, g, sx, sj, sm, t0, t1, i, xi, S.nbr, c, da, sl);
                     }
                 else if (row_ok)
 #pragma unroll
@@ -1015,7 +1042,7 @@ struct BuildFluid {
                         if (!st.ok[0][e]) continue;
                         const int64_t cell = row_base + st.v[0][e];
                         if (cell < s_lo || cell > s_hi) {
-                            test_cell_global<D, DENS>(P, S, x, items, i, xi, cell, c, da);
+                            test_cell_global<D, DENS>(P, S, x, items, i, xi, cell, c, da, sl);
                             continue;
                         }
                         // fluid then walls of this cell, from the staged copy
@@ -1025,9 +1052,9 @@ struct BuildFluid {
                             const uint32_t shift = pass == 0 ? 0u : nF;
                             const uint32_t t0 = start[cell] - base + shift, t1 = start[cell + 1] - base + shift;
                             if (periodic)
-                                scan_staged<D, true, DENS>(P, g, sx, sj, sm, t0, t1, i, xi, S.nbr, c, da);
+                                scan_staged<D, true, DENS>(P, g, sx, sj, sm, t0, t1, i, xi, S.nbr, c, da, sl);
                             else
-                                scan_staged<D, false, DENS>(P, g, sx, sj, sm, t0, t1, i, xi, S.nbr, c, da);
+                                scan_staged<D, false, DENS>(P, g, sx, sj, sm, t0, t1, i, xi, S.nbr, c, da, sl);
                         }
                     }
                 __syncthreads();   // the next stencil row overwrites the staged copy
@@ -1038,6 +1065,10 @@ struct BuildFluid {
             atomicMax(&S.ctl->maxcnt, c);
         }
         S.cnt[i] = c < P.cap ? c : P.cap;
+        if (sl.on) {
+            if (sl.c > P.g_cap) atomicOr(&S.ctl->g_full, 1);   // the sub-steps take the full lists
+            S.gcnt[i] = sl.c < P.g_cap ? sl.c : P.g_cap;
+        }
         if constexpr (DENS) {
             // eq. summation_density; free-surface flag rho_i / rho0 <
             // fs_ratio when free_surface is on (section 3)
@@ -3112,11 +3143,20 @@ struct Gtvf {
             p0 = a < pref ? a : pref;
         }
         R s[3] = {0, 0, 0};
-        const int c = S.cnt[i];
-        for (int k0 = 1; k0 < c; k0 += kPairBatch) {
+        // The short list while every particle is within sqrt(g_D2) of r*
+        // (so far: sub-step k-1 raised g_disp_bits with r^{k-1} before this
+        // launch; a raise by this launch can only select the full list):
+        // a pair left out is then at least the support apart and adds
+        // exactly zero, so the sum is the same bit for bit.
+        const bool short_list = P.g_sub && !S.ctl->g_full &&
+                                S.ctl->g_disp_bits <= (unsigned long long)__double_as_longlong(P.g_D2);
+        const int32_t *list = short_list ? S.gnbr : S.nbr;
+        const int k_first = short_list ? 0 : 1, c = short_list ? S.gcnt[i] : S.cnt[i];
+        const int cap = short_list ? P.g_cap : P.cap;
+        for (int k0 = k_first; k0 < c; k0 += kPairBatch) {
             int64_t jb[kPairBatch];
             double4 rb[kPairBatch];
-            batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
+            batch_slots(list, nf, i, k0, c, cap, i, jb);
 #pragma unroll
             for (int t = 0; t < kPairBatch; ++t) rb[t] = src[jb[t]];
 #pragma unroll
@@ -3146,6 +3186,15 @@ struct Gtvf {
             S.vk[a][i] = v + dtau * f;
         }
         dst[i] = make_double4(xn[0], xn[1], xn[2], own.w);
+        if (P.g_sub && k + 1 < P.gtvf_K) {
+            // |r^k - r*|^2 (non-negative doubles order like their bits)
+            double m2 = 0.0;
+            for (int a = 0; a < D; ++a) {
+                const double e = xn[a] - S.xs[a][i];
+                m2 += e * e;
+            }
+            max_if_larger(&S.ctl->g_disp_bits, (unsigned long long)__double_as_longlong(m2));
+        }
     }
 };
 

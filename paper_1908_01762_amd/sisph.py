@@ -105,6 +105,8 @@ def lib():
         L.sisph_debug_barrier_spins.argtypes = [C.c_void_p, C.c_uint32]
         L.sisph_debug_packed.restype = C.c_int32
         L.sisph_debug_packed.argtypes = [C.c_void_p, C.c_int32]
+        L.sisph_debug_gtvf_short.restype = C.c_int32
+        L.sisph_debug_gtvf_short.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
         L.sisph_debug_read_rate.restype = C.c_int32
         L.sisph_debug_read_rate.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_int32,
                                             C.POINTER(C.c_double)]
@@ -387,6 +389,14 @@ class Context:
         """Test hook: sweeps through the lists (False) or the packed mode's
         LDS copy and codes (True, the default where the case has it)."""
         _check(lib().sisph_debug_packed(self.h, int(bool(on))), self.h)
+
+    def debug_gtvf_short(self, on: Optional[bool] = None) -> int:
+        """Turns the GTVF short lists off (False) or back on (True), or
+        leaves them (None); returns how the last step's sub-steps used them
+        (0 none, 1 all sub-steps, 2 not all)."""
+        used = C.c_int32()
+        _check(lib().sisph_debug_gtvf_short(self.h, -1 if on is None else int(bool(on)), C.byref(used)), self.h)
+        return used.value
 
     def debug_barrier_spins(self, spins: int):
         """Test hook: polls before a persistent-solve wait gives up."""

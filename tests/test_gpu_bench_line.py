@@ -59,6 +59,7 @@ def test_bench_line_fields():
     big = [c for c in d["copy_reference"] if c["mib"] == 1024][0]
     assert 0 < big["read_GBps"] < rf["peak"] and rf["read_probe_GBps"] == big["read_GBps"]
     assert abs(rf["frac_of_read_probe"] - rf["achieved"] / big["read_GBps"]) < 1e-3
+    assert d["gtvf_short_lists_last_step"] == 1   # the dam break's sub-steps walked the short lists
     sec = d["secondary"]
     assert sec["config"]["workload"] == "tg400_wendland_mixed"
     sr = sec["roofline"]
