@@ -1322,20 +1322,28 @@ struct WallVelocity {
         for (int k = 0; k < D; ++k) xi[k] = x.c[k][iw];
         R num[3] = {0, 0, 0}, den = R(0);
         const int c = S.wcnt[w];
+        // The kernel has smoothing length h/2: a fluid neighbour past its
+        // support has W = 0 exactly and adds exact zeros (the sums start at
+        // +0), so its velocity is not gathered; the sums are the same bits.
         for (int k0 = 0; k0 < c; k0 += kPairBatch) {
             int64_t fb[kPairBatch];
             double xj[kPairBatch][3], ub[kPairBatch][3];
             batch_slots(S.wnbr, P.nw, w, k0, c, P.cap, iw, fb);
             batch_pos<D>(x, fb, xj);
+            R Wb[kPairBatch];
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) {
+                R d[3], r2;
+                pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
+                Wb[t] = k0 + t < c ? K.w(sqrt(r2)) : R(0);
+            }
 #pragma unroll
             for (int t = 0; t < kPairBatch; ++t)
-                for (int a = 0; a < D; ++a) ub[t][a] = uf[a][fb[t]];
+                for (int a = 0; a < D; ++a) ub[t][a] = Wb[t] != R(0) ? uf[a][fb[t]] : 0.0;
 #pragma unroll
             for (int t = 0; t < kPairBatch; ++t) {
                 if (k0 + t >= c) break;
-                R d[3], r2;
-                pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
-                const R W = K.w(sqrt(r2));
+                const R W = Wb[t];
                 for (int a = 0; a < D; ++a) num[a] += (R)ub[t][a] * W;
                 den += W;
             }
