@@ -1223,13 +1223,30 @@ struct BuildWall {
                 for (int e = 0; e < 3; ++e) {
                     if (!(st.ok[2][a] && st.ok[1][b] && st.ok[0][e])) continue;
                     const int64_t cell = stencil_cell(g, st, a, b, e);
-                    for (uint32_t t = S.fstart[cell]; t < S.fstart[cell + 1]; ++t) {
-                        const int64_t j = items ? (int64_t)items[t] : (int64_t)t;
-                        double d[3] = {0, 0, 0};
-                        for (int k = 0; k < D; ++k) d[k] = min_image(xi[k] - x.c[k][j], g, k);
-                        if (exact_r2<D>(d) < P.R2) {
-                            if (c < cap) S.wnbr[(int64_t)c * nw + w] = (int32_t)j;
-                            ++c;
+                    // kScanBatch candidates at a time: their positions are
+                    // loaded before any is tested (a dependent round trip
+                    // per candidate made the walls next to the fluid a
+                    // chain of ~475 of them); the set and its order are
+                    // those of one candidate at a time
+                    const uint32_t t1 = S.fstart[cell + 1];
+                    for (uint32_t t = S.fstart[cell]; t < t1; t += kScanBatch) {
+                        double xj[kScanBatch][3];
+#pragma unroll
+                        for (int u = 0; u < kScanBatch; ++u) {
+                            const uint32_t tu = t + u < t1 ? t + u : t;
+                            const int64_t j = items ? (int64_t)items[tu] : (int64_t)tu;
+                            for (int k = 0; k < 3; ++k) xj[u][k] = k < D ? x.c[k][j] : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kScanBatch; ++u) {
+                            if (t + u >= t1) break;
+                            const int64_t j = items ? (int64_t)items[t + u] : (int64_t)(t + u);
+                            double d[3] = {0, 0, 0};
+                            for (int k = 0; k < D; ++k) d[k] = min_image(xi[k] - xj[u][k], g, k);
+                            if (exact_r2<D>(d) < P.R2) {
+                                if (c < cap) S.wnbr[(int64_t)c * nw + w] = (int32_t)j;
+                                ++c;
+                            }
                         }
                     }
                 }
