@@ -2667,14 +2667,25 @@ struct WallCoef {
         for (int k = 0; k < D; ++k) xi[k] = xs.c[k][iw];
         R sr[3] = {0, 0, 0}, sw = R(0);
         const int c = S.wcnt[w];
-        for (int k = 0; k < c; ++k) {
-            const int64_t f = S.wnbr[(int64_t)k * nw + w];
-            R d[3], r2;
-            pair_diff<D, R>(P.grid, xi, xs, f, d, r2);
-            const R W = K.w(sqrt(r2));
-            const R rw = (R)S.rho[f] * W;
-            for (int a = 0; a < D; ++a) sr[a] += rw * d[a];
-            sw += W;
+        // kPairBatch slots at a time (indices, then positions and
+        // densities, then the terms in slot order)
+        for (int k0 = 0; k0 < c; k0 += kPairBatch) {
+            int64_t fb[kPairBatch];
+            double xj[kPairBatch][3], rb[kPairBatch];
+            batch_slots(S.wnbr, nw, w, k0, c, P.cap, iw, fb);
+            batch_pos<D>(xs, fb, xj);
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) rb[t] = S.rho[fb[t]];
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) {
+                if (k0 + t >= c) break;
+                R d[3], r2;
+                pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
+                const R W = K.w(sqrt(r2));
+                const R rw = (R)rb[t] * W;
+                for (int a = 0; a < D; ++a) sr[a] += rw * d[a];
+                sw += W;
+            }
         }
         double h = 0.0;
         const R inv = sw > R(0) ? R(1) / sw : R(0);
@@ -2686,14 +2697,21 @@ struct WallCoef {
         S.wh[w] = rp(P, h);
         // second pass: the normalised weights (the kernel values again, in
         // the same order, rather than holding them in registers)
-        for (int k = 0; k < c; ++k) {
-            const int64_t at = (int64_t)k * nw + w;
-            const int64_t f = S.wnbr[at];
-            R d[3], r2;
-            pair_diff<D, R>(P.grid, xi, xs, f, d, r2);
-            const R a = K.w(sqrt(r2)) * inv;
-            if constexpr (sizeof(R) == 4) ((PairF *)S.wcoef)[(int64_t)off + k] = PairF{(int32_t)f, a};
-            else ((double *)S.wcoef)[at] = a;
+        for (int k0 = 0; k0 < c; k0 += kPairBatch) {
+            int64_t fb[kPairBatch];
+            double xj[kPairBatch][3];
+            batch_slots(S.wnbr, nw, w, k0, c, P.cap, iw, fb);
+            batch_pos<D>(xs, fb, xj);
+#pragma unroll
+            for (int t = 0; t < kPairBatch; ++t) {
+                const int k = k0 + t;
+                if (k >= c) break;
+                R d[3], r2;
+                pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
+                const R a = K.w(sqrt(r2)) * inv;
+                if constexpr (sizeof(R) == 4) ((PairF *)S.wcoef)[(int64_t)off + k] = PairF{(int32_t)fb[t], a};
+                else ((double *)S.wcoef)[(int64_t)k * nw + w] = a;
+            }
         }
     }
 };
