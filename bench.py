@@ -398,6 +398,12 @@ def measure(workload: str, steps: int, warmup: int, launch: str, autotune: bool,
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": round(traffic * eff / max(launches, 1)) if traffic is not None else None,
+                # the counter-measured bytes (the committed summary's, per
+                # sweep) over the same kernel time: the HBM-side rate
+                "traffic_GBps": round(traffic * eff / kernel_s / 1e9, 1) if traffic is not None and kernel_s > 0
+                else None,
+                "traffic_frac": round(traffic * eff / kernel_s / 1e9 / HBM_PEAK_GBS, 4)
+                if traffic is not None and kernel_s > 0 else None,
                 "kernel": kernel, "mode": mode,
                 "algorithmic_bytes_per_particle_iter": unit,
                 "algorithmic_bytes_per_sweep": alg_per_sweep,

@@ -55,6 +55,10 @@ def test_bench_line_fields():
     # sweep average is of the same size, so only its presence is checked
     assert rf["wall_pass"]["rows"] > 0 and math.isfinite(rf["wall_pass"]["us_per_sweep"])
     assert rf["layout"]["bytes_per_sweep"] > 0
+    # the counter-measured bytes and their rate, when the committed counter
+    # summary was taken on the current kernel source
+    if rf["traffic"] is not None:
+        assert rf["traffic"] > 0 and abs(rf["traffic_frac"] - rf["traffic_GBps"] / rf["peak"]) < 1e-3
     # the plain-read probe of 1 GiB, and the kernel's rate against it
     big = [c for c in d["copy_reference"] if c["mib"] == 1024][0]
     assert 0 < big["read_GBps"] < rf["peak"] and rf["read_probe_GBps"] == big["read_GBps"]
