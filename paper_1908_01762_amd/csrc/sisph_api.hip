@@ -458,6 +458,12 @@ static int32_t status_of(const Control &C, const Params &P, std::string *msg) {
 static int32_t init_state(sisph_ctx *ctx, const sisph_case_desc *desc, const double *x, const double *u,
                           const double *p, const double *m, const double *wall_u) {
     auto fail_create = [](int32_t code) { return code; };
+    {   // one mass for every particle (compared bit for bit)
+        bool uni = ctx->P.ntot > 0;
+        for (int64_t k = 1; uni && k < ctx->P.ntot; ++k) uni = std::memcmp(&m[k], &m[0], sizeof(double)) == 0;
+        ctx->P.m_uni = uni ? 1 : 0;
+        ctx->P.m_uni_f = uni ? (float)m[0] : 0.0f;
+    }
     const Params &P = ctx->P;
     State &S = ctx->S;
     const int64_t nf = P.nf, nw = P.nw, nt = P.ntot, D = P.dim;

@@ -45,6 +45,10 @@ struct Params {
     // while no particle has moved more than sqrt(g_D2) from r*
     int32_t g_sub, g_cap;
     double g_R2, g_D2;
+    // every particle has the same mass (m_uni_f: it in FP32): the FP32-sum
+    // predictor's neighbour record then leaves it out (64 bytes, not 80)
+    int32_t m_uni;
+    float m_uni_f;
     uint32_t barrier_spins; // polls before a wait of the persistent solve gives up
     int32_t null_space;     // SISPH_NULL_PROJECT: RHS made compatible before the sweeps
     int64_t nf, nw, ntot;
@@ -169,6 +173,13 @@ struct __align__(16) PredRecF {
 struct __align__(16) PredRecD {
     double x[3], u[3], ut[3];
     double m, rho;
+};
+// The FP32-sum record when every particle has the same mass: r^n and u^n in
+// FP64, u~ - u formed in FP64 and rounded to FP32 (as the pair term did; 0
+// for walls), density in FP32: 64 bytes, four loads instead of five.
+struct __align__(16) PredRecS {
+    double x[3], u[3];
+    float s[3], rho;
 };
 // The same for the PPE coefficients (r*, u* (walls: the slip ghost), mass
 // and density) and for the pressure force (r*, the solved pressure,

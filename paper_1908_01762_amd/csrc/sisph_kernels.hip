@@ -1418,70 +1418,83 @@ struct Predictor {
         const R eps = (R)P.eps_h, nu4 = (R)(4.0 * P.nu), avc = (R)(P.alpha * P.h * P.c_ref);
         R fv[3] = {0, 0, 0}, fa[3] = {0, 0, 0}, fsr[3] = {0, 0, 0};
         const int c = S.cnt[i];
-        using Rec = typename std::conditional<sizeof(R) == 4, PredRecF, PredRecD>::type;
-        const Rec *prec = (const Rec *)S.prec;
-        for (int k0 = 1; k0 < c; k0 += kPairBatch) {
-            int64_t jb[kPairBatch];
-            double xj[kPairBatch][3], ub[kPairBatch][3], utb[kPairBatch][3];
-            R mb[kPairBatch], rhob[kPairBatch];
-            batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
-            // one record per neighbour: positions, velocities in FP64 in
-            // every mode (their pair differences are small against the
-            // velocities and are formed before any rounding to the working
-            // precision), u~ (0 for walls, whose term is not formed), and
-            // mass and density in the working precision
-            Rec rb[kPairBatch];
+        // the pair loop over one record layout (the 64-byte FP32-sum record
+        // when every particle has the same mass)
+        auto pairs = [&](auto tag) {
+            using Rec = decltype(tag);
+            constexpr bool no_mass = std::is_same<Rec, PredRecS>::value;
+            const Rec *prec = (const Rec *)S.prec;
+            for (int k0 = 1; k0 < c; k0 += kPairBatch) {
+                int64_t jb[kPairBatch];
+                double xj[kPairBatch][3], ub[kPairBatch][3];
+                R sb[kPairBatch][3], mb[kPairBatch], rhob[kPairBatch];
+                batch_slots(S.nbr, nf, i, k0, c, P.cap, i, jb);
+                // one record per neighbour: positions, velocities in FP64 in
+                // every mode (their pair differences are small against the
+                // velocities and are formed before any rounding to the working
+                // precision), u~ (0 for walls, whose term is not formed), and
+                // mass and density in the working precision
+                Rec rb[kPairBatch];
 #pragma unroll
-            for (int t = 0; t < kPairBatch; ++t) rb[t] = prec[jb[t]];
+                for (int t = 0; t < kPairBatch; ++t) rb[t] = prec[jb[t]];
 #pragma unroll
-            for (int t = 0; t < kPairBatch; ++t) {
-                for (int a = 0; a < 3; ++a) {
-                    xj[t][a] = rb[t].x[a];
-                    ub[t][a] = rb[t].u[a];
-                    utb[t][a] = rb[t].ut[a];
-                }
-                mb[t] = rb[t].m;
-                rhob[t] = rb[t].rho;
-            }
-#pragma unroll
-            for (int t = 0; t < kPairBatch; ++t) {
-                if (k0 + t >= c) break;
-                const int64_t j = jb[t];
-                R d[3], r2;
-                pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
-                const R r = sqrt(r2);
-                const R dw = K.dwr(r);
-                R gw[3];
-                for (int a = 0; a < 3; ++a) gw[a] = dw * d[a];
-                const R F = dw * r2;
-                const R mj = mb[t], rhoj = rhob[t];
-                R uj[3] = {0, 0, 0};
-                for (int a = 0; a < D; ++a) uj[a] = (R)ub[t][a];
-                R uij[3] = {0, 0, 0};
-                for (int a = 0; a < D; ++a) uij[a] = (R)(ui_d[a] - ub[t][a]);
-                const R inv_den = R(1) / (r2 + eps);
-                const R cv = mj * nu4 / (rhoi + rhoj) * F * inv_den;
-                for (int a = 0; a < D; ++a) fv[a] += cv * uij[a];
-                R vr = R(0);
-                for (int a = 0; a < D; ++a) vr += uij[a] * d[a];
-                if (vr < R(0)) {
-                    const R mu = vr * inv_den;
-                    const R Pi = -avc * mu / (R(0.5) * (rhoi + rhoj));
-                    for (int a = 0; a < D; ++a) fa[a] -= mj * Pi * gw[a];
-                }
-                // artificial stress: sum_b (A_i/rho_i^2 + A_j/rho_j^2)_ab gw_b
-                R sgi = R(0);
-                for (int b = 0; b < D; ++b) sgi += si[b] * gw[b];
-                R sgj = R(0), uj_over[3] = {0, 0, 0};
-                if (j < nf) {
-                    const R inv_rhoj = R(1) / rhoj;
-                    for (int b = 0; b < D; ++b) {
-                        sgj += (R)(utb[t][b] - ub[t][b]) * gw[b];
-                        uj_over[b] = uj[b] * inv_rhoj;
+                for (int t = 0; t < kPairBatch; ++t) {
+                    for (int a = 0; a < 3; ++a) {
+                        xj[t][a] = rb[t].x[a];
+                        ub[t][a] = rb[t].u[a];
+                        if constexpr (no_mass) sb[t][a] = rb[t].s[a];
+                        else sb[t][a] = (R)(rb[t].ut[a] - rb[t].u[a]);   // u~ - u
                     }
+                    if constexpr (no_mass) mb[t] = (R)P.m_uni_f;
+                    else mb[t] = rb[t].m;
+                    rhob[t] = rb[t].rho;
                 }
-                for (int a = 0; a < D; ++a) fsr[a] += mj * (ui[a] * inv_rhoi * sgi + uj_over[a] * sgj);
+#pragma unroll
+                for (int t = 0; t < kPairBatch; ++t) {
+                    if (k0 + t >= c) break;
+                    const int64_t j = jb[t];
+                    R d[3], r2;
+                    pair_diff_v<D, R>(P.grid, xi, xj[t], d, r2);
+                    const R r = sqrt(r2);
+                    const R dw = K.dwr(r);
+                    R gw[3];
+                    for (int a = 0; a < 3; ++a) gw[a] = dw * d[a];
+                    const R F = dw * r2;
+                    const R mj = mb[t], rhoj = rhob[t];
+                    R uj[3] = {0, 0, 0};
+                    for (int a = 0; a < D; ++a) uj[a] = (R)ub[t][a];
+                    R uij[3] = {0, 0, 0};
+                    for (int a = 0; a < D; ++a) uij[a] = (R)(ui_d[a] - ub[t][a]);
+                    const R inv_den = R(1) / (r2 + eps);
+                    const R cv = mj * nu4 / (rhoi + rhoj) * F * inv_den;
+                    for (int a = 0; a < D; ++a) fv[a] += cv * uij[a];
+                    R vr = R(0);
+                    for (int a = 0; a < D; ++a) vr += uij[a] * d[a];
+                    if (vr < R(0)) {
+                        const R mu = vr * inv_den;
+                        const R Pi = -avc * mu / (R(0.5) * (rhoi + rhoj));
+                        for (int a = 0; a < D; ++a) fa[a] -= mj * Pi * gw[a];
+                    }
+                    // artificial stress: sum_b (A_i/rho_i^2 + A_j/rho_j^2)_ab gw_b
+                    R sgi = R(0);
+                    for (int b = 0; b < D; ++b) sgi += si[b] * gw[b];
+                    R sgj = R(0), uj_over[3] = {0, 0, 0};
+                    if (j < nf) {
+                        const R inv_rhoj = R(1) / rhoj;
+                        for (int b = 0; b < D; ++b) {
+                            sgj += sb[t][b] * gw[b];
+                            uj_over[b] = uj[b] * inv_rhoj;
+                        }
+                    }
+                    for (int a = 0; a < D; ++a) fsr[a] += mj * (ui[a] * inv_rhoi * sgi + uj_over[a] * sgj);
+                }
             }
+        };
+        if constexpr (sizeof(R) == 4) {
+            if (P.m_uni) pairs(PredRecS{});
+            else pairs(PredRecF{});
+        } else {
+            pairs(PredRecD{});
         }
         const double dt = S.ctl->dt;
         for (int a = 0; a < D; ++a) {
@@ -1555,17 +1568,29 @@ struct Shadow {
     static __device__ __forceinline__ void run(const Params &P, const State &S, int64_t blk, int64_t, int) {
         ROW;
         if (i >= P.ntot) return;
-        using Rec = typename std::conditional<sizeof(R) == 4, PredRecF, PredRecD>::type;
-        Rec rec;
-        for (int a = 0; a < 3; ++a) {
-            const bool on = a < P.dim;
-            rec.x[a] = on ? S.x[a][i] : 0.0;
-            rec.u[a] = on ? S.u[a][i] : 0.0;
-            rec.ut[a] = on && i < P.nf ? S.ut[a][i] : 0.0;
+        if (sizeof(R) == 4 && P.m_uni) {
+            PredRecS rec;
+            for (int a = 0; a < 3; ++a) {
+                const bool on = a < P.dim;
+                rec.x[a] = on ? S.x[a][i] : 0.0;
+                rec.u[a] = on ? S.u[a][i] : 0.0;
+                rec.s[a] = on && i < P.nf ? (float)(S.ut[a][i] - S.u[a][i]) : 0.0f;
+            }
+            rec.rho = (float)S.rho[i];
+            ((PredRecS *)S.prec)[i] = rec;
+        } else {
+            using Rec = typename std::conditional<sizeof(R) == 4, PredRecF, PredRecD>::type;
+            Rec rec;
+            for (int a = 0; a < 3; ++a) {
+                const bool on = a < P.dim;
+                rec.x[a] = on ? S.x[a][i] : 0.0;
+                rec.u[a] = on ? S.u[a][i] : 0.0;
+                rec.ut[a] = on && i < P.nf ? S.ut[a][i] : 0.0;
+            }
+            rec.m = (R)S.m[i];
+            rec.rho = (R)S.rho[i];
+            ((Rec *)S.prec)[i] = rec;
         }
-        rec.m = (R)S.m[i];
-        rec.rho = (R)S.rho[i];
-        ((Rec *)S.prec)[i] = rec;
         if constexpr (sizeof(R) == 4) {
             S.m32[i] = (float)S.m[i];
             S.rho32[i] = (float)S.rho[i];
