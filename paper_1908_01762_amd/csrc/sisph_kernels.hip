@@ -1179,8 +1179,16 @@ struct PackCodes {
         const int cnt = S.cnt[i];
         for (int c0 = 1; c0 < cnt; c0 += 8) {
             uint32_t w[3] = {0u, 0u, 0u};
+            // the word's eight list entries loaded before any is coded (slots
+            // past the count are clamped into the storage and not coded)
+            int64_t jw[8];
+#pragma unroll
+            for (int f = 0; f < 8; ++f) {
+                const int k = c0 + f < P.cap ? c0 + f : P.cap - 1;
+                jw[f] = S.nbr[(int64_t)k * nf + i];
+            }
             for (int f = 0; f < 8 && c0 + f < cnt; ++f) {
-                const int64_t j = S.nbr[(int64_t)(c0 + f) * nf + i];
+                const int64_t j = jw[f];
                 const bool wl = j >= nf;
                 int r = 0;
 #pragma unroll
